@@ -1,0 +1,218 @@
+"""ctypes binding of the FP64 CPU oracle (``libtsko.so``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg use this module to obtain reference results.  The GPU product
+path never imports it.  Arrays are numpy; inputs are converted to C-contiguous
+float32/float64 as the C routine expects, outputs are float64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("TSKO_LIB") or os.path.join(HERE, "libtsko.so")
+SRC = os.path.join(HERE, "tsko.c")
+
+FLAG_RANKDEF, FLAG_TIE, FLAG_NONFIN = 1, 2, 4
+
+
+def build(force: bool = True, out: str | None = None, mutant: int = 0) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP, no fast-math).
+    ``mutant`` > 0 builds a copy with one planted mistake (mutation test)."""
+    out = out or os.path.join(HERE, "libtsko.so")
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+               f"-DTSKO_MUTANT={int(mutant)}", "-o", tmp, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, out)
+    return out
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int64
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "tsko_gram_f32": [_P, _I, _I, _I, _P],
+            "tsko_gram_f64": [_P, _I, _I, _I, _P],
+            "tsko_eigh": [_P, _I, _P, _P],
+            "tsko_eigh_jacobi": [_P, _I, _P, _P],
+            "tsko_svd": [_P, _I, _I, _P, _P, _P],
+            "tsko_qr": [_P, _I, _I, _P, _P],
+            "tsko_train_f32": [_P, _I, _I, _I, _I, _P, _P, _P],
+            "tsko_train_from_gram": [_P, _I, _I, _P, _P],
+            "tsko_scw": [_P, _I, _I, _P, _I, _I, ctypes.c_int, _P, _P, _P, _P, _P, _P],
+            "tsko_apply_f32": [_P, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P, _P],
+            "tsko_error_f32": [_P, _I, _I, _I, _P, _P, _I, _P],
+            "tsko_opt_f32": [_P, _I, _I, _I, _I, _P, _P],
+            "tsko_threads": [],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _check(st, name):
+    if st < 0:
+        raise ValueError(f"{name}: invalid arguments")
+    return st
+
+
+def threads() -> int:
+    return lib().tsko_threads()
+
+
+def gram(A: np.ndarray) -> np.ndarray:
+    """Mode-1 Gram sum_d A_d A_d^T of a (count, m, n) stack."""
+    A = np.asarray(A)
+    if A.ndim == 2:
+        A = A[None]
+    cnt, m, n = A.shape
+    G = np.empty((m, m))
+    if A.dtype == np.float32:
+        A = _f32(A)
+        _check(lib().tsko_gram_f32(_p(A), cnt, m, n, _p(G)), "gram")
+    else:
+        A = _f64(A)
+        _check(lib().tsko_gram_f64(_p(A), cnt, m, n, _p(G)), "gram")
+    return G
+
+
+def eigh(G: np.ndarray, vectors: bool = True, method: str = "qr"):
+    """Descending eigenvalues (and eigenvector columns) of a symmetric matrix."""
+    G = _f64(G)
+    m = G.shape[0]
+    w = np.empty(m)
+    V = np.empty((m, m)) if vectors else None
+    f = lib().tsko_eigh if method == "qr" else lib().tsko_eigh_jacobi
+    st = _check(f(_p(G), m, _p(w), _p(V)), "eigh")
+    if st:
+        raise RuntimeError("oracle eigensolver did not converge")
+    return (w, V) if vectors else w
+
+
+def svd(A: np.ndarray):
+    """Thin SVD A = U diag(s) Vt (one-sided Jacobi)."""
+    A = _f64(A)
+    m, n = A.shape
+    p = min(m, n)
+    U, s, Vt = np.empty((m, p)), np.empty(p), np.empty((p, n))
+    _check(lib().tsko_svd(_p(A), m, n, _p(U), _p(s), _p(Vt)), "svd")
+    return U, s, Vt
+
+
+def qr(A: np.ndarray):
+    A = _f64(A)
+    m, n = A.shape
+    Q, R = np.empty((m, n)), np.empty((n, n))
+    _check(lib().tsko_qr(_p(A), m, n, _p(Q), _p(R)), "qr")
+    return Q, R
+
+
+def train(A: np.ndarray, k: int, return_fro2: bool = False):
+    """Sketch S (k x m, rows = top-k eigenvectors of the mode-1 Gram) and
+    lambda_1..lambda_{k+1}."""
+    A = _f32(A)
+    cnt, m, n = A.shape
+    S = np.empty((k, m))
+    lam = np.empty(k + 1)
+    fro2 = np.empty(1)
+    st = _check(lib().tsko_train_f32(_p(A), cnt, m, n, k, _p(S), _p(lam), _p(fro2)), "train")
+    if st:
+        raise RuntimeError("oracle eigensolver did not converge")
+    return (S, lam, float(fro2[0])) if return_fro2 else (S, lam)
+
+
+def train_from_gram(G: np.ndarray, k: int):
+    G = _f64(G)
+    m = G.shape[0]
+    S = np.empty((k, m))
+    lam = np.empty(k + 1)
+    st = _check(lib().tsko_train_from_gram(_p(G), m, k, _p(S), _p(lam)), "train_from_gram")
+    if st:
+        raise RuntimeError("oracle eigensolver did not converge")
+    return S, lam
+
+
+def scw(A: np.ndarray, S: np.ndarray, r: int, vmode: int = 0, want_ahat: bool = False):
+    """Algorithm 1 on one matrix.  Returns dict(L, R, sigma, relerr, flags[, Ahat])."""
+    A = _f64(A)
+    S = _f64(S)
+    m, n = A.shape
+    k = S.shape[0]
+    L, R, sig = np.empty((m, r)), np.empty((n, r)), np.empty(r)
+    Ah = np.empty((m, n)) if want_ahat else None
+    e = np.empty(1)
+    fl = np.zeros(1, dtype=np.int32)
+    _check(lib().tsko_scw(_p(A), m, n, _p(S), k, r, vmode, _p(L), _p(R), _p(sig), _p(Ah),
+                          _p(e), _p(fl)), "scw")
+    out = dict(L=L, R=R, sigma=sig, relerr=float(e[0]), flags=int(fl[0]))
+    if want_ahat:
+        out["Ahat"] = Ah
+    return out
+
+
+def apply(A: np.ndarray, S: np.ndarray, r: int, factors: bool = True):
+    """Algorithm 1 over a (count, m, n) float32 stack (OpenMP across slices)."""
+    A = _f32(A)
+    S = _f64(S)
+    cnt, m, n = A.shape
+    k = S.shape[0]
+    L = np.empty((cnt, m, r)) if factors else None
+    R = np.empty((cnt, n, r)) if factors else None
+    sig = np.empty((cnt, r)) if factors else None
+    e = np.empty(cnt)
+    fl = np.zeros(cnt, dtype=np.int32)
+    _check(lib().tsko_apply_f32(_p(A), cnt, m, n, _p(S), k, r, _p(L), _p(R), _p(sig),
+                                _p(e), _p(fl)), "apply")
+    return dict(L=L, R=R, sigma=sig, relerr=e, flags=fl)
+
+
+def error(A: np.ndarray, L: np.ndarray, R: np.ndarray) -> np.ndarray:
+    """Explicit ||A_d - L_d R_d^T||_F / ||A_d||_F per slice."""
+    A = _f32(A)
+    cnt, m, n = A.shape
+    L = _f64(L).reshape(cnt, m, -1)
+    R = _f64(R).reshape(cnt, n, -1)
+    r = L.shape[2]
+    e = np.empty(cnt)
+    _check(lib().tsko_error_f32(_p(A), cnt, m, n, _p(L), _p(R), r, _p(e)), "error")
+    return e
+
+
+def opt_tail(A: np.ndarray, r: int):
+    """||A_d - [A_d]_r||_F and ||A_d||_F per slice (Jacobi SVD)."""
+    A = _f32(A)
+    if A.ndim == 2:
+        A = A[None]
+    cnt, m, n = A.shape
+    t, f = np.empty(cnt), np.empty(cnt)
+    _check(lib().tsko_opt_f32(_p(A), cnt, m, n, r, _p(t), _p(f)), "opt")
+    return t, f

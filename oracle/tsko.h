@@ -1,0 +1,108 @@
+/*
+ * tsko -- FP64 CPU oracle for the tensor-based sketching method
+ * (Liu, Xiao, Ding, Yang: "Tensor-Based Sketching Method for the Low-Rank
+ * Approximation of Data Streams").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain reference that
+ * the GPU path is checked against.  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it; the product path never
+ * calls it and shares no source with it.
+ *
+ * All arithmetic is IEEE double.  Matrices are dense row-major.  Every routine
+ * returns 0 on success and a negative value on bad arguments; none allocates
+ * memory that outlives the call.  OpenMP is used only across independent
+ * outputs (rows of the Gram, test matrices), so results do not depend on the
+ * thread count.
+ *
+ * Parity status of each routine is stated at its declaration.
+ */
+#ifndef TSKO_H
+#define TSKO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* flag bits reported per test matrix */
+#define TSKO_FLAG_RANKDEF 1  /* sigma_k(SA) <= 1e-13 sigma_1(SA): row space of SA has dim < k */
+#define TSKO_FLAG_TIE     2  /* sigma_r(AV) - sigma_{r+1}(AV) <= 1e-12 sigma_1(AV)            */
+#define TSKO_FLAG_NONFIN  4  /* non-finite input entry                                         */
+
+/* Mode-1 Gram of the training tensor (Section 3.1, eqs. 3.2-3.3):
+ *   G = A_(1) A_(1)^T = sum_d A_d A_d^T,   A_(1) = [A_1 | ... | A_D'].
+ * A: count slices of m x n, slice d at A + d*m*n.  G: m x m, full symmetric.
+ * Summation in natural order (slice, then column).  Pinned by exact integer
+ * inputs and trace(G) = ||A||_F^2. */
+int tsko_gram_f32(const float *A, int64_t count, int64_t m, int64_t n, double *G);
+int tsko_gram_f64(const double *A, int64_t count, int64_t m, int64_t n, double *G);
+
+/* Full symmetric eigendecomposition G = V diag(w) V^T by Householder
+ * tridiagonalisation and the implicit-shift symmetric QR iteration
+ * (Golub & Van Loan, Matrix Computations, Sections 8.3.1-8.3.3).
+ * w: m eigenvalues in descending order (ties: lower original index first).
+ * V: m x m row-major, COLUMN j is the eigenvector of w[j], sign-canonical
+ *    (largest-magnitude entry positive, ties to the lowest index).
+ * Returns 1 if the QR iteration failed to converge.
+ * Pinned by planted spectra, residuals, 2x2 closed form, numpy (tests). */
+int tsko_eigh(const double *G, int64_t m, double *w, double *V);
+
+/* Cyclic Jacobi eigensolver (Golub & Van Loan, Section 8.5), same output
+ * convention as tsko_eigh.  Independent cross-check for small m. */
+int tsko_eigh_jacobi(const double *G, int64_t m, double *w, double *V);
+
+/* Thin SVD A = U diag(s) Vt by one-sided (Hestenes) Jacobi on the columns of
+ * A (or of A^T when m < n), Golub & Van Loan Section 8.6.  p = min(m,n).
+ * U: m x p, s: p descending, Vt: p x n.  Any output pointer may be NULL.
+ * Singular vectors of zero singular values are returned as zero vectors. */
+int tsko_svd(const double *A, int64_t m, int64_t n, double *U, double *s, double *Vt);
+
+/* Householder thin QR (Golub & Van Loan Alg. 5.2.1), m >= n.
+ * Q: m x n with orthonormal columns, R: n x n upper triangular. */
+int tsko_qr(const double *A, int64_t m, int64_t n, double *Q, double *R);
+
+/* Training (Algorithm 2, lines 1-2; Section 3.1): S = top-k eigenvectors of
+ * the mode-1 Gram as rows (S S^T = I_k), in descending eigenvalue order,
+ * sign-canonical.  lambda: k+1 leading eigenvalues (lambda_{k+1} is 0 when
+ * k == m).  Also returns ||A||_F^2 in *fro2 (nullable). */
+int tsko_train_f32(const float *A, int64_t count, int64_t m, int64_t n, int64_t k,
+                   double *S, double *lambda, double *fro2);
+int tsko_train_from_gram(const double *G, int64_t m, int64_t k, double *S, double *lambda);
+
+/* SCW (Algorithm 1) on one matrix A (m x n) with sketch S (k x m), r < k:
+ *   1. B = S A;  V = right singular vectors of B (thin SVD, n x k) -- or, with
+ *      vmode = 1, the Q factor of a Householder QR of B^T (the QR variant the
+ *      paper allows in Section 3.2).  Directions with sigma_i(B) below
+ *      1e-13 sigma_1(B) are left out (zero columns), flag RANKDEF.
+ *   2. C = A V (m x k);  C = U Sig Y^T (thin SVD);  [AV]_r = U_r Sig_r Y_r^T.
+ *   3. A_hat = [AV]_r V^T = L R^T with L = U_r Sig_r (m x r), R = V Y_r (n x r).
+ * relerr = ||A - A_hat||_F / ||A||_F, computed from the dense residual.
+ * Any of L, R, sigma (r values), Ahat (m x n) may be NULL. */
+int tsko_scw(const double *A, int64_t m, int64_t n, const double *S, int64_t k, int64_t r,
+             int vmode, double *L, double *R, double *sigma, double *Ahat,
+             double *relerr, int32_t *flags);
+
+/* SCW over a stack of float slices (OpenMP across slices).  Output strides:
+ * L: m*r per slice, R: n*r, sigma: r.  Any output may be NULL. */
+int tsko_apply_f32(const float *A, int64_t count, int64_t m, int64_t n, const double *S,
+                   int64_t k, int64_t r, double *L, double *R, double *sigma,
+                   double *relerr, int32_t *flags);
+
+/* Explicit ||A - L R^T||_F / ||A||_F for a stack of float slices; L, R in
+ * double with strides m*r and n*r. */
+int tsko_error_f32(const float *A, int64_t count, int64_t m, int64_t n, const double *L,
+                   const double *R, int64_t r, double *relerr);
+
+/* Optimal rank-r error (Eckart-Young, Section 1): ||A - [A]_r||_F for each
+ * slice, by the one-sided Jacobi SVD of the slice.  Also ||A||_F in fro
+ * (nullable).  OpenMP across slices. */
+int tsko_opt_f32(const float *A, int64_t count, int64_t m, int64_t n, int64_t r,
+                 double *tail, double *fro);
+
+/* Number of OpenMP threads the library will use. */
+int tsko_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,167 @@
+/*
+ * tsk.h -- C ABI of the MI355X (gfx950) implementation of the tensor-based
+ * sketching method for low-rank approximation of matrix data streams
+ * (Liu, Xiao, Ding, Yang).
+ *
+ * Problem (Section 1, eq. 1.1): for every matrix A_d (m x n) of a stream,
+ *     min_B ||A_d - B||_F   subject to   rank(B) <= r.
+ * Method (Algorithm 2): stack the training matrices into an m x n x N tensor,
+ * take its mode-1 Tucker1 factor as the sketch S (k x m, S S^T = I_k;
+ * Section 3.1, eqs. 3.1-3.3 and the sentence after 3.3), then run SCW
+ * (Algorithm 1) on every test matrix with that S.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every matrix is dense ROW-MAJOR.  Pointers documented "device" must be
+ *   device memory of the context's GPU (for example torch.Tensor.data_ptr()
+ *   of a CUDA tensor); pointers documented "host" are ordinary host memory.
+ * - The caller allocates and owns every input and output.  The library owns
+ *   only the context and its workspace (grown on demand, freed by
+ *   tsk_destroy); it keeps no caller pointer after a call returns.
+ * - All GPU work is enqueued on the context's stream; a call returns after
+ *   enqueueing unless it documents a host output, in which case it
+ *   synchronises that stream before returning.  Device outputs are valid
+ *   once the stream has been synchronised.
+ * - Arguments are validated before anything is launched; a violation returns
+ *   TSK_E_ARG or TSK_E_SHAPE, launches nothing and sets tsk_last_error().
+ * - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef TSK_H
+#define TSK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TSK_OK = 0,
+    TSK_E_ARG = 1,     /* null pointer, bad enum, bad rank/sketch size      */
+    TSK_E_SHAPE = 2,   /* inconsistent shapes, strides or alignment          */
+    TSK_E_NOMEM = 3,   /* workspace allocation failed                         */
+    TSK_E_DEVICE = 4,  /* HIP runtime error (message in tsk_last_error)       */
+    TSK_E_NOCONV = 5   /* eigensolver hit its iteration cap; S still written  */
+} tsk_status;
+
+typedef enum {
+    TSK_F64 = 0,
+    TSK_F32 = 1,
+    TSK_BF16 = 2,
+    TSK_F8E4M3 = 3
+} tsk_dtype;
+
+/* Per-matrix condition bits written to `flags` by tsk_apply. */
+#define TSK_FLAG_RANKDEF 1 /* S A_d numerically rank deficient: V has fewer than k
+                              directions (the missing ones are zero columns)   */
+#define TSK_FLAG_TIE     2 /* sigma_r(A_d V) == sigma_{r+1}(A_d V) to rounding:
+                              the rank-r factor is not unique (the error is)   */
+#define TSK_FLAG_NONFIN  4 /* non-finite value in A_d; outputs are NaN          */
+
+typedef struct tsk_ctx_s *tsk_ctx;
+
+/* A stack of `count` row-major m x n slices (the training tensor of
+ * Section 3.1, or a batch of test matrices).  Element (i, j) of slice d is at
+ * A[d * stride + i * ld + j].  Requirements: m, n, count >= 1, ld >= n,
+ * stride >= m * ld, A 16-byte aligned, ld and stride multiples of 4
+ * elements.  dtype: TSK_F32 in this version.  scale must be NULL. */
+typedef struct {
+    const void *A;     /* device */
+    int32_t dtype;     /* tsk_dtype of the stored elements */
+    const float *scale;/* reserved (per-slice scale of a scaled format); NULL */
+    int64_t m, n, count;
+    int64_t ld, stride;/* in elements */
+} tsk_stack;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on (NULL: the device's null stream).  The context does not own the
+ * stream. */
+tsk_status tsk_create(tsk_ctx *out, int device, void *hip_stream);
+void tsk_destroy(tsk_ctx ctx);
+/* Replace the stream used by later calls (same device). */
+tsk_status tsk_set_stream(tsk_ctx ctx, void *hip_stream);
+/* Message of the last failure on this context ("" when none). */
+const char *tsk_last_error(tsk_ctx ctx);
+
+/* Mode-1 Gram (Section 3.1, eqs. 3.2-3.3; tensor basics in Section 2):
+ *     G = A_(1) A_(1)^T = sum_{d<count} A_d A_d^T,   A_(1) = [A_1|...|A_N].
+ * G: device, m x m FP64, full symmetric matrix.  compute: TSK_F32 (FP32
+ * products with FP32 accumulation inside a slice chunk, FP64 across chunks).
+ * Enqueue only. */
+tsk_status tsk_gram(tsk_ctx ctx, const tsk_stack *train, int32_t compute, double *G);
+
+/* Leading-k eigenvectors of a symmetric m x m matrix (the Tucker1 factor,
+ * S* = (U^(1))_k^T, Section 3.1).  G: device FP64 m x m (full symmetric).
+ * S: device FP32, k x m row-major, rows orthonormal, in descending eigenvalue
+ * order, sign-canonical (largest-magnitude entry of each row positive).
+ * lambda: host, k+1 doubles: the Ritz values theta_1..theta_{k+1} (lambda_{k+1}
+ * is the (k+1)-th Ritz value of the search block).  iters: host, nullable:
+ * subspace iterations used.  Requires 1 <= k < m.  Synchronises the stream.
+ * Returns TSK_E_NOCONV when the residual test was not met within the cap. */
+tsk_status tsk_eig_topk(tsk_ctx ctx, const double *G, int64_t m, int32_t k,
+                        float *S, double *lambda, int32_t *iters);
+
+/* Training, Algorithm 2 lines 1-2: tsk_gram followed by tsk_eig_topk on the
+ * context's workspace.  S: device FP32 k x m.  lambda: host k+1.
+ * iters: host, nullable.  Requires 1 <= k < m.  Synchronises the stream. */
+tsk_status tsk_train(tsk_ctx ctx, const tsk_stack *train, int32_t k, int32_t compute,
+                     float *S, double *lambda, int32_t *iters);
+
+/* SCW, Algorithm 1, on every slice of `test` with the sketch S (k x m,
+ * device FP32, rows orthonormal):
+ *   1. B_d = S A_d (k x n);  V_d = orthonormal basis of the row space of B_d
+ *      (n x k), by CholeskyQR2 -- the QR replacement for the SVD of line 1
+ *      that Section 3.2 allows;
+ *   2. C_d = A_d V_d (m x k) and its rank-r truncation via the eigen-
+ *      decomposition C_d^T C_d = Y diag(sigma^2) Y^T;
+ *   3. A_hat_d = [A_d V_d]_r V_d^T = L_d R_d^T with
+ *      L_d = C_d Y_r = U_r Sigma_r (m x r), R_d = V_d Y_r (n x r).
+ * Outputs (device): L (count*m*r FP32), R (count*n*r FP32),
+ * sigma (count*r FP32, descending), relerr (count FP64, nullable):
+ *      relerr_d = sqrt(max(0, ||A_d||^2 - sum_{i<=r} sigma_i^2)) / ||A_d||
+ * (the Pythagorean identity of the proof of Theorem 1), flags (count int32,
+ * nullable, TSK_FLAG_*).  Requires 1 <= r < k <= min(m, n), k <= 64.
+ * compute: TSK_F32.  Enqueue only. */
+tsk_status tsk_apply(tsk_ctx ctx, const float *S, int32_t k, const tsk_stack *test, int32_t r,
+                     int32_t compute, float *L, float *R, float *sigma, double *relerr,
+                     int32_t *flags);
+
+/* Explicit relative error ||A_d - L_d R_d^T||_F / ||A_d||_F for every slice
+ * (the quantity whose rank-r minimum is problem 1.1).  L, R: device FP32 with
+ * the layout tsk_apply writes.  relerr: device FP64, count values.  r >= 1.
+ * Enqueue only. */
+tsk_status tsk_error(tsk_ctx ctx, const tsk_stack *A, const float *L, const float *R,
+                     int32_t r, double *relerr);
+
+/* Eigensolver controls (defaults in brackets): block = search-block width p
+ * [k + max(12, k/2), rounded up to a multiple of 4, at most m]; max_iter
+ * [600]; tol = residual tolerance relative to theta_1 [1e-10]; check = subspace
+ * iterations between convergence tests [16].  A value <= 0 restores the
+ * default. */
+tsk_status tsk_set_eig_params(tsk_ctx ctx, int32_t block, int32_t max_iter, double tol,
+                              int32_t check);
+
+/* Kernel timing.  When enabled, every launch is bracketed by HIP events on
+ * the context's stream; tsk_timing_read synchronises and returns, for each
+ * kernel class, the number of launches and the summed milliseconds since the
+ * last reset.  Classes: see TSK_KERNEL_*. */
+enum {
+    TSK_KERNEL_GRAM = 0,     /* Gram product kernel          */
+    TSK_KERNEL_GRAM_REDUCE,  /* FP64 reduction of partials    */
+    TSK_KERNEL_EIG_ITER,     /* subspace iteration step       */
+    TSK_KERNEL_EIG_RR,       /* Rayleigh-Ritz / residual      */
+    TSK_KERNEL_SKETCH,       /* B_d = S A_d                   */
+    TSK_KERNEL_QR,           /* CholeskyQR2 of B_d^T          */
+    TSK_KERNEL_PROJECT,      /* C_d = A_d V_d                 */
+    TSK_KERNEL_FINISH,       /* small eigenproblem + outputs  */
+    TSK_KERNEL_ERROR,        /* explicit residual             */
+    TSK_KERNEL_COUNT
+};
+tsk_status tsk_timing_enable(tsk_ctx ctx, int32_t on);
+tsk_status tsk_timing_read(tsk_ctx ctx, int32_t reset, int64_t *launches /* TSK_KERNEL_COUNT */,
+                           double *ms /* TSK_KERNEL_COUNT */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

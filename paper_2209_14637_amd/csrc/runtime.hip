@@ -1,0 +1,306 @@
+// Host runtime of libtsk: context, validation, workspace, timing and the C
+// entry points declared in include/tsk.h.
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "tsk_common.hpp"
+
+tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, double *G);
+tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *S, double *lambda,
+                           int32_t *iters_out);
+tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
+                             float *sigma, double *relerr, int32_t *flags);
+tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, const float *R, int r,
+                             double *relerr);
+
+tsk_status tsk_fail(tsk_ctx c, tsk_status st, const std::string &msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+tsk_status tsk_hip(tsk_ctx c, hipError_t e, const char *what) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: HIP error %d (%s)", what, (int)e, hipGetErrorString(e));
+    return tsk_fail(c, TSK_E_DEVICE, buf);
+}
+
+tsk_status tsk_grow(tsk_ctx c, TskBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return TSK_OK;
+    // work already queued may still use the old buffer
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return tsk_hip(c, e, "workspace sync");
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    const size_t nb = (bytes + (1 << 20) - 1) & ~(size_t)((1 << 20) - 1);
+    if (getenv("TSK_FAULT_NOMEM") || hipMalloc(&b.p, nb) != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        char buf[128];
+        snprintf(buf, sizeof buf, "workspace allocation of %zu bytes failed", nb);
+        return tsk_fail(c, TSK_E_NOMEM, buf);
+    }
+    b.bytes = nb;
+    return TSK_OK;
+}
+
+// The pointer must lie in a device allocation that holds [p, p + bytes).
+tsk_status tsk_check_dev(tsk_ctx c, const void *p, size_t bytes, const char *name) {
+    if (!p) return tsk_fail(c, TSK_E_ARG, std::string(name) + ": null pointer");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    hipError_t e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p);
+    if (e != hipSuccess || !base) {
+        (void)hipGetLastError();
+        return tsk_fail(c, TSK_E_ARG, std::string(name) + ": not a device allocation");
+    }
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) == hipSuccess) {
+        if (attr.type == hipMemoryTypeDevice && attr.device != c->device)
+            return tsk_fail(c, TSK_E_ARG, std::string(name) + ": memory of another device");
+    } else {
+        (void)hipGetLastError();
+    }
+    const char *lo = (const char *)base, *hi = lo + size, *q = (const char *)p;
+    if (q < lo || q + bytes > hi) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "%s: needs %zu bytes, allocation holds %zu from that address", name, bytes,
+                 (size_t)(hi - q));
+        return tsk_fail(c, TSK_E_SHAPE, buf);
+    }
+    return TSK_OK;
+}
+
+static size_t dtype_size(int32_t dt) {
+    switch (dt) {
+        case TSK_F64: return 8;
+        case TSK_F32: return 4;
+        case TSK_BF16: return 2;
+        case TSK_F8E4M3: return 1;
+        default: return 0;
+    }
+}
+
+tsk_status tsk_check_stack(tsk_ctx c, const tsk_stack *s, const char *name) {
+    std::string nm(name);
+    if (!s) return tsk_fail(c, TSK_E_ARG, nm + ": null stack");
+    if (!s->A) return tsk_fail(c, TSK_E_ARG, nm + ": null data pointer");
+    if (s->dtype != TSK_F32) return tsk_fail(c, TSK_E_ARG, nm + ": dtype must be TSK_F32");
+    if (s->scale) return tsk_fail(c, TSK_E_ARG, nm + ": scale must be NULL for TSK_F32");
+    if (s->m < 1 || s->n < 1 || s->count < 1) return tsk_fail(c, TSK_E_SHAPE, nm + ": m, n, count must be >= 1");
+    if (s->ld < s->n) return tsk_fail(c, TSK_E_SHAPE, nm + ": ld < n");
+    if (s->stride < s->m * s->ld) return tsk_fail(c, TSK_E_SHAPE, nm + ": stride < m*ld");
+    if (((uintptr_t)s->A & 15) || (s->ld & 3) || (s->stride & 3))
+        return tsk_fail(c, TSK_E_SHAPE, nm + ": data must be 16-byte aligned with ld, stride multiples of 4");
+    if (s->m > (1 << 20) || s->n > (1 << 20) || s->count > (1 << 24))
+        return tsk_fail(c, TSK_E_SHAPE, nm + ": dimension too large");
+    const size_t es = dtype_size(s->dtype);
+    const size_t need = ((size_t)(s->count - 1) * s->stride + (size_t)(s->m - 1) * s->ld + s->n) * es;
+    return tsk_check_dev(c, s->A, need, (nm + ".A").c_str());
+}
+
+void tsk_ev_begin(tsk_ctx c, hipEvent_t *a) {
+    *a = nullptr;
+    if (!c->timing) return;
+    if (c->pool.empty()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        c->pool.push_back(e);
+    }
+    *a = c->pool.back();
+    c->pool.pop_back();
+    (void)hipEventRecord(*a, c->stream);
+}
+
+void tsk_ev_end(tsk_ctx c, int cls, hipEvent_t a) {
+    if (!c->timing || !a) return;
+    hipEvent_t b;
+    if (c->pool.empty()) {
+        if (hipEventCreate(&b) != hipSuccess) return;
+    } else {
+        b = c->pool.back();
+        c->pool.pop_back();
+    }
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({cls, a, b});
+}
+
+static void drain_events(tsk_ctx c) {
+    for (auto &ev : c->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(ev.b) == hipSuccess && hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
+            c->launches[ev.cls] += 1;
+            c->ms[ev.cls] += ms;
+        }
+        c->pool.push_back(ev.a);
+        c->pool.push_back(ev.b);
+    }
+    c->pending.clear();
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+extern "C" {
+
+tsk_status tsk_create(tsk_ctx *out, int device, void *hip_stream) {
+    if (!out) return TSK_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return TSK_E_DEVICE;
+    }
+    if (device < 0 || device >= ndev) return TSK_E_ARG;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return TSK_E_DEVICE;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TSK_E_DEVICE;
+    tsk_ctx c = new (std::nothrow) tsk_ctx_s();
+    if (!c) return TSK_E_NOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return TSK_OK;
+}
+
+void tsk_destroy(tsk_ctx c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    drain_events(c);
+    TskBuf *bufs[] = {&c->gram_part, &c->gram_G,  &c->eig_Y0,   &c->eig_Y1, &c->eig_Rinv, &c->eig_part,
+                      &c->eig_C,     &c->eig_X,   &c->eig_GX,   &c->eig_small, &c->eig_U, &c->counters,
+                      &c->ap_St,     &c->ap_B,    &c->ap_Vt,    &c->ap_C,   &c->ap_fro,   &c->ap_qflag,
+                      &c->er_part};
+    for (TskBuf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+tsk_status tsk_set_stream(tsk_ctx c, void *hip_stream) {
+    if (!c) return TSK_E_ARG;
+    c->stream = (hipStream_t)hip_stream;
+    return TSK_OK;
+}
+
+const char *tsk_last_error(tsk_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+tsk_status tsk_gram(tsk_ctx c, const tsk_stack *train, int32_t compute, double *G) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    TSK_TRY(tsk_check_stack(c, train, "train"));
+    if (compute != TSK_F32) return tsk_fail(c, TSK_E_ARG, "tsk_gram: compute must be TSK_F32");
+    TSK_TRY(tsk_check_dev(c, G, sizeof(double) * train->m * train->m, "G"));
+    return tsk_gram_enqueue(c, train, G);
+}
+
+tsk_status tsk_eig_topk(tsk_ctx c, const double *G, int64_t m, int32_t k, float *S, double *lambda,
+                        int32_t *iters) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    if (m < 2 || m > (1 << 16)) return tsk_fail(c, TSK_E_SHAPE, "tsk_eig_topk: need 2 <= m <= 65536");
+    if (k < 1 || k >= m) return tsk_fail(c, TSK_E_ARG, "tsk_eig_topk: need 1 <= k < m");
+    if (k > 68) return tsk_fail(c, TSK_E_ARG, "tsk_eig_topk: k > 68 not supported");
+    if (!lambda) return tsk_fail(c, TSK_E_ARG, "tsk_eig_topk: lambda is required");
+    TSK_TRY(tsk_check_dev(c, G, sizeof(double) * m * m, "G"));
+    TSK_TRY(tsk_check_dev(c, S, sizeof(float) * k * m, "S"));
+    tsk_status st = tsk_eig_enqueue(c, G, m, k, S, lambda, iters);
+    return st;
+}
+
+tsk_status tsk_train(tsk_ctx c, const tsk_stack *train, int32_t k, int32_t compute, float *S, double *lambda,
+                     int32_t *iters) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    TSK_TRY(tsk_check_stack(c, train, "train"));
+    if (compute != TSK_F32) return tsk_fail(c, TSK_E_ARG, "tsk_train: compute must be TSK_F32");
+    const int64_t m = train->m;
+    if (k < 1 || k >= m) return tsk_fail(c, TSK_E_ARG, "tsk_train: need 1 <= k < m");
+    if (k > 68) return tsk_fail(c, TSK_E_ARG, "tsk_train: k > 68 not supported");
+    if (!lambda) return tsk_fail(c, TSK_E_ARG, "tsk_train: lambda is required");
+    TSK_TRY(tsk_check_dev(c, S, sizeof(float) * k * m, "S"));
+    TSK_TRY(tsk_grow(c, c->gram_G, sizeof(double) * m * m));
+    double *G = (double *)c->gram_G.p;
+    TSK_TRY(tsk_gram_enqueue(c, train, G));
+    return tsk_eig_enqueue(c, G, m, k, S, lambda, iters);
+}
+
+tsk_status tsk_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test, int32_t r, int32_t compute,
+                     float *L, float *R, float *sigma, double *relerr, int32_t *flags) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    TSK_TRY(tsk_check_stack(c, test, "test"));
+    if (compute != TSK_F32) return tsk_fail(c, TSK_E_ARG, "tsk_apply: compute must be TSK_F32");
+    const int64_t m = test->m, n = test->n, cnt = test->count;
+    if (r < 1 || r >= k) return tsk_fail(c, TSK_E_ARG, "tsk_apply: need 1 <= r < k");
+    if (k > m || k > n) return tsk_fail(c, TSK_E_ARG, "tsk_apply: need k <= min(m, n)");
+    if (k > 64) return tsk_fail(c, TSK_E_ARG, "tsk_apply: k > 64 not supported");
+    TSK_TRY(tsk_check_dev(c, S, sizeof(float) * k * m, "S"));
+    TSK_TRY(tsk_check_dev(c, L, sizeof(float) * cnt * m * r, "L"));
+    TSK_TRY(tsk_check_dev(c, R, sizeof(float) * cnt * n * r, "R"));
+    TSK_TRY(tsk_check_dev(c, sigma, sizeof(float) * cnt * r, "sigma"));
+    if (relerr) TSK_TRY(tsk_check_dev(c, relerr, sizeof(double) * cnt, "relerr"));
+    if (flags) TSK_TRY(tsk_check_dev(c, flags, sizeof(int32_t) * cnt, "flags"));
+    return tsk_apply_enqueue(c, S, k, test, r, L, R, sigma, relerr, flags);
+}
+
+tsk_status tsk_error(tsk_ctx c, const tsk_stack *A, const float *L, const float *R, int32_t r, double *relerr) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    TSK_TRY(tsk_check_stack(c, A, "A"));
+    if (r < 1 || r > 64) return tsk_fail(c, TSK_E_ARG, "tsk_error: need 1 <= r <= 64");
+    const int64_t m = A->m, n = A->n, cnt = A->count;
+    TSK_TRY(tsk_check_dev(c, L, sizeof(float) * cnt * m * r, "L"));
+    TSK_TRY(tsk_check_dev(c, R, sizeof(float) * cnt * n * r, "R"));
+    TSK_TRY(tsk_check_dev(c, relerr, sizeof(double) * cnt, "relerr"));
+    return tsk_error_enqueue(c, A, L, R, r, relerr);
+}
+
+tsk_status tsk_set_eig_params(tsk_ctx c, int32_t block, int32_t max_iter, double tol, int32_t check) {
+    if (!c) return TSK_E_ARG;
+    c->eig_block = block > 0 ? block : 0;
+    c->eig_max_iter = max_iter > 0 ? max_iter : 600;
+    c->eig_tol = tol > 0 ? tol : 1e-10;
+    c->eig_check = check > 0 ? check : 16;
+    return TSK_OK;
+}
+
+tsk_status tsk_timing_enable(tsk_ctx c, int32_t on) {
+    if (!c) return TSK_E_ARG;
+    c->timing = on != 0;
+    return TSK_OK;
+}
+
+tsk_status tsk_timing_read(tsk_ctx c, int32_t reset, int64_t *launches, double *ms) {
+    if (!c) return TSK_E_ARG;
+    DeviceGuard g(c->device);
+    drain_events(c);
+    for (int i = 0; i < TSK_KERNEL_COUNT; ++i) {
+        if (launches) launches[i] = c->launches[i];
+        if (ms) ms[i] = c->ms[i];
+    }
+    if (reset) {
+        memset(c->launches, 0, sizeof c->launches);
+        memset(c->ms, 0, sizeof c->ms);
+    }
+    return TSK_OK;
+}
+
+}  // extern "C"

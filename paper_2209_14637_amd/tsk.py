@@ -1,0 +1,198 @@
+"""Thin ctypes binding of libtsk (include/tsk.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of libtsk.so.  torch is used for device memory and the current stream.  There
+is no fallback: if the library or a gfx950 GPU is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtsk.so")
+
+TSK_OK, TSK_E_ARG, TSK_E_SHAPE, TSK_E_NOMEM, TSK_E_DEVICE, TSK_E_NOCONV = range(6)
+TSK_F64, TSK_F32, TSK_BF16, TSK_F8E4M3 = range(4)
+FLAG_RANKDEF, FLAG_TIE, FLAG_NONFIN = 1, 2, 4
+KERNELS = ["gram", "gram_reduce", "eig_iter", "eig_rr", "sketch", "qr", "project", "finish", "error"]
+
+_STATUS = {0: "TSK_OK", 1: "TSK_E_ARG", 2: "TSK_E_SHAPE", 3: "TSK_E_NOMEM", 4: "TSK_E_DEVICE",
+           5: "TSK_E_NOCONV"}
+
+EXPORTS = ["tsk_create", "tsk_destroy", "tsk_set_stream", "tsk_last_error", "tsk_gram", "tsk_eig_topk",
+           "tsk_train", "tsk_apply", "tsk_error", "tsk_set_eig_params", "tsk_timing_enable",
+           "tsk_timing_read"]
+
+
+class TskError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Stack(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("scale", ctypes.c_void_p),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("count", ctypes.c_int64),
+                ("ld", ctypes.c_int64), ("stride", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libtsk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} not built: run paper_2209_14637_amd/build.py")
+    L = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sp = ctypes.POINTER(Stack)
+    sig = {
+        "tsk_create": ([ctypes.POINTER(P), ctypes.c_int, P], I32),
+        "tsk_destroy": ([P], None),
+        "tsk_set_stream": ([P, P], I32),
+        "tsk_last_error": ([P], ctypes.c_char_p),
+        "tsk_gram": ([P, sp, I32, P], I32),
+        "tsk_eig_topk": ([P, P, I64, I32, P, P, P], I32),
+        "tsk_train": ([P, sp, I32, I32, P, P, P], I32),
+        "tsk_apply": ([P, P, I32, sp, I32, I32, P, P, P, P, P], I32),
+        "tsk_error": ([P, sp, P, P, I32, P], I32),
+        "tsk_set_eig_params": ([P, I32, I32, D, I32], I32),
+        "tsk_timing_enable": ([P, I32], I32),
+        "tsk_timing_read": ([P, I32, P, P], I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _stack(A: torch.Tensor) -> Stack:
+    if not isinstance(A, torch.Tensor) or not A.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if A.dtype != torch.float32:
+        raise TypeError("expected float32 slices")
+    if A.dim() == 2:
+        A = A.unsqueeze(0)
+    if A.dim() != 3 or A.stride(2) != 1:
+        raise ValueError("expected a (count, m, n) stack with unit column stride")
+    cnt, m, n = A.shape
+    return Stack(A.data_ptr(), TSK_F32, None, m, n, cnt, A.stride(1), A.stride(0) if cnt > 1 else m * A.stride(1))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One libtsk context bound to a device; enqueues on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.device = device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            st = self.lib.tsk_create(ctypes.byref(h), device, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        if st != TSK_OK:
+            raise TskError(st, "tsk_create failed (no gfx950 device?)")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tsk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        self.lib.tsk_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _check(self, st: int, allow_noconv: bool = False) -> int:
+        if st == TSK_OK or (allow_noconv and st == TSK_E_NOCONV):
+            return st
+        raise TskError(st, self.lib.tsk_last_error(self.h).decode())
+
+    # --- entry points -----------------------------------------------------
+    def gram(self, A: torch.Tensor, G: torch.Tensor | None = None) -> torch.Tensor:
+        self._sync_stream()
+        s = _stack(A)
+        if G is None:
+            G = torch.empty((s.m, s.m), dtype=torch.float64, device=A.device)
+        self._check(self.lib.tsk_gram(self.h, ctypes.byref(s), TSK_F32, _ptr(G)))
+        return G
+
+    def eig_topk(self, G: torch.Tensor, k: int, S: torch.Tensor | None = None, allow_noconv: bool = False):
+        self._sync_stream()
+        m = G.shape[0]
+        if G.dtype != torch.float64 or G.shape != (m, m) or not G.is_contiguous():
+            raise ValueError("G must be a contiguous (m, m) float64 CUDA tensor")
+        if S is None:
+            S = torch.empty((k, m), dtype=torch.float32, device=G.device)
+        lam = (ctypes.c_double * (k + 1))()
+        it = ctypes.c_int32(0)
+        st = self._check(self.lib.tsk_eig_topk(self.h, _ptr(G), m, k, _ptr(S), lam, ctypes.byref(it)), allow_noconv)
+        return S, list(lam), it.value, st
+
+    def train(self, A: torch.Tensor, k: int, S: torch.Tensor | None = None, allow_noconv: bool = False):
+        self._sync_stream()
+        s = _stack(A)
+        if S is None:
+            S = torch.empty((k, s.m), dtype=torch.float32, device=A.device)
+        lam = (ctypes.c_double * (k + 1))()
+        it = ctypes.c_int32(0)
+        st = self._check(self.lib.tsk_train(self.h, ctypes.byref(s), k, TSK_F32, _ptr(S), lam, ctypes.byref(it)),
+                         allow_noconv)
+        return S, list(lam), it.value, st
+
+    def apply(self, S: torch.Tensor, A: torch.Tensor, r: int, out: dict | None = None, relerr: bool = True,
+              flags: bool = True) -> dict:
+        self._sync_stream()
+        s = _stack(A)
+        k = S.shape[0]
+        if S.dtype != torch.float32 or not S.is_contiguous() or S.shape[1] != s.m:
+            raise ValueError("S must be a contiguous (k, m) float32 CUDA tensor")
+        dev = A.device
+        o = out if out is not None else {}
+        if "L" not in o:
+            o["L"] = torch.empty((s.count, s.m, r), dtype=torch.float32, device=dev)
+            o["R"] = torch.empty((s.count, s.n, r), dtype=torch.float32, device=dev)
+            o["sigma"] = torch.empty((s.count, r), dtype=torch.float32, device=dev)
+            o["relerr"] = torch.empty(s.count, dtype=torch.float64, device=dev) if relerr else None
+            o["flags"] = torch.empty(s.count, dtype=torch.int32, device=dev) if flags else None
+        self._check(self.lib.tsk_apply(self.h, _ptr(S), k, ctypes.byref(s), r, TSK_F32, _ptr(o["L"]), _ptr(o["R"]),
+                                       _ptr(o["sigma"]), _ptr(o.get("relerr")), _ptr(o.get("flags"))))
+        return o
+
+    def error(self, A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, relerr: torch.Tensor | None = None):
+        self._sync_stream()
+        s = _stack(A)
+        r = L.shape[-1]
+        if relerr is None:
+            relerr = torch.empty(s.count, dtype=torch.float64, device=A.device)
+        self._check(self.lib.tsk_error(self.h, ctypes.byref(s), _ptr(L), _ptr(R), r, _ptr(relerr)))
+        return relerr
+
+    def set_eig_params(self, block: int = 0, max_iter: int = 0, tol: float = 0.0, check: int = 0):
+        self._check(self.lib.tsk_set_eig_params(self.h, block, max_iter, tol, check))
+
+    def timing(self, on: bool = True):
+        self._check(self.lib.tsk_timing_enable(self.h, 1 if on else 0))
+
+    def timing_read(self, reset: bool = True) -> dict:
+        n = len(KERNELS)
+        la = (ctypes.c_int64 * n)()
+        ms = (ctypes.c_double * n)()
+        self._check(self.lib.tsk_timing_read(self.h, 1 if reset else 0, la, ms))
+        return {KERNELS[i]: (la[i], ms[i]) for i in range(n)}

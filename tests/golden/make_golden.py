@@ -1,0 +1,51 @@
+"""Writes the oracle's reference values for the full-size workloads to JSON.
+
+Calls only the FP64 CPU oracle (oracle/) and the seeded stream generator; no
+value here comes from the GPU path.  Usage:  python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+from oracle import oracle  # noqa: E402
+from paper_2209_14637_amd import synth  # noqa: E402
+
+
+def golden_stream(spec, name, n_err=64, n_opt=16):
+    st = synth.Stream(spec)
+    t0 = time.time()
+    tr = st.train()
+    S, lam, fro2 = oracle.train(tr, spec.k, return_fro2=True)
+    t_train = time.time() - t0
+    del tr
+    te = st.test(n_err)
+    res = oracle.apply(te, S, spec.r)
+    tail, fro = oracle.opt_tail(te[:n_opt], spec.r)
+    e = res["relerr"]
+    out = {
+        "workload": name,
+        "spec": {k: v for k, v in spec.__dict__.items()},
+        "source": "oracle/tsko.c via tests/golden/make_golden.py",
+        "lambda": lam.tolist(),
+        "train_fro2": fro2,
+        "relerr": e.tolist(),
+        "flags": res["flags"].tolist(),
+        "opt_tail": tail.tolist(),
+        "fro": fro.tolist(),
+        "metric_4_1": ((e[:n_opt] * fro - tail) / tail).tolist(),
+        "oracle_train_seconds": t_train,
+        "threads": oracle.threads(),
+    }
+    with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(name, "lambda_1..3", lam[:3], "e[:3]", e[:3], f"train {t_train:.1f}s")
+
+
+if __name__ == "__main__":
+    golden_stream(synth.spec_hsi_fp32(), "hsi_1024x768_k20_r10")

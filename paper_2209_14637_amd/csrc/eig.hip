@@ -95,7 +95,7 @@ __device__ inline void rowblock_gemm(const double *__restrict__ G, int64_t m, in
     for (int x = 0; x < EIG_MAXPP / 16; ++x) {
         if (x < nt) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) wpart[(wv * 16 + 4 * q + r) * pp + x * 16 + ii] = acc[x][r];
+            for (int r = 0; r < 4; ++r) wpart[(wv * 16 + q + 4 * r) * pp + x * 16 + ii] = acc[x][r];
         }
     }
     __syncthreads();

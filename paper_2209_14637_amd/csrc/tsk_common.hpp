@@ -16,10 +16,11 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // MFMA wrappers.  Operand layout of the 16x16x4 shapes (one wave of 64 lanes,
-// lane = 16*q + i with q = lane/16, i = lane%16):
+// lane = 16*q + i with q = lane/16, i = lane%16), measured on gfx950:
 //   A operand: lane supplies A[i][q]      (16 x 4)
 //   B operand: lane supplies B[q][i]      (4 x 16)
-//   D result : lane holds   D[4q + r][i]  for r = 0..3
+//   D result, f32: lane holds D[4q + r][i]  for r = 0..3
+//   D result, f64: lane holds D[q + 4r][i]  for r = 0..3
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ v4f mfma16x16x4_f32(float a, float b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);

@@ -90,20 +90,24 @@ const char *tsk_last_error(tsk_ctx ctx);
  * Enqueue only. */
 tsk_status tsk_gram(tsk_ctx ctx, const tsk_stack *train, int32_t compute, double *G);
 
-/* Leading-k eigenvectors of a symmetric m x m matrix (the Tucker1 factor,
- * S* = (U^(1))_k^T, Section 3.1).  G: device FP64 m x m (full symmetric).
- * S: device FP32, k x m row-major, rows orthonormal, in descending eigenvalue
- * order, sign-canonical (largest-magnitude entry of each row positive).
- * lambda: host, k+1 doubles: the Ritz values theta_1..theta_{k+1} (lambda_{k+1}
- * is the (k+1)-th Ritz value of the search block).  iters: host, nullable:
- * subspace iterations used.  Requires 1 <= k < m.  Synchronises the stream.
- * Returns TSK_E_NOCONV when the residual test was not met within the cap. */
+/* Leading-k eigenvectors of a symmetric positive semi-definite m x m matrix
+ * (the Tucker1 factor, S* = (U^(1))_k^T, Section 3.1).  G: device FP64 m x m
+ * (full symmetric).  S: device FP32, k x m row-major, rows orthonormal, in
+ * descending eigenvalue order, sign-canonical (largest-magnitude entry of
+ * each row positive).  lambda: host, k+1 doubles: the Ritz values
+ * theta_1..theta_{k+1} of the search block.  iters: host, nullable: number of
+ * block products with G used.  Stops when every one of the first k Ritz pairs
+ * has ||G u - theta u|| <= tol * theta_1 (tol of tsk_set_eig_params).
+ * Requires 1 <= k < m, k <= 52.  Synchronises the stream.
+ * Returns TSK_E_NOCONV when the residual test was not met within the cap
+ * (S and lambda are still written from the last Rayleigh-Ritz step). */
 tsk_status tsk_eig_topk(tsk_ctx ctx, const double *G, int64_t m, int32_t k,
                         float *S, double *lambda, int32_t *iters);
 
 /* Training, Algorithm 2 lines 1-2: tsk_gram followed by tsk_eig_topk on the
  * context's workspace.  S: device FP32 k x m.  lambda: host k+1.
- * iters: host, nullable.  Requires 1 <= k < m.  Synchronises the stream. */
+ * iters: host, nullable.  Requires 1 <= k < m, k <= 52.  Synchronises the
+ * stream. */
 tsk_status tsk_train(tsk_ctx ctx, const tsk_stack *train, int32_t k, int32_t compute,
                      float *S, double *lambda, int32_t *iters);
 
@@ -134,9 +138,11 @@ tsk_status tsk_error(tsk_ctx ctx, const tsk_stack *A, const float *L, const floa
                      int32_t r, double *relerr);
 
 /* Eigensolver controls (defaults in brackets): block = search-block width p
- * [k + max(12, k/2), rounded up to a multiple of 4, at most m]; max_iter
- * [600]; tol = residual tolerance relative to theta_1 [1e-10]; check = subspace
- * iterations between convergence tests [16].  A value <= 0 restores the
+ * [k + max(12, k/2), at most 64 and at most m]; max_iter = cap on filtered
+ * subspace steps [300]; tol = residual tolerance relative to theta_1 [1e-7,
+ * the rounding level of an FP32-accumulated Gram, so the Ritz vectors are
+ * exact eigenvectors of a matrix within that distance of G]; check =
+ * filtered steps between convergence tests [4].  A value <= 0 restores the
  * default. */
 tsk_status tsk_set_eig_params(tsk_ctx ctx, int32_t block, int32_t max_iter, double tol,
                               int32_t check);

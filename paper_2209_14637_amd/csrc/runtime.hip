@@ -214,7 +214,7 @@ tsk_status tsk_eig_topk(tsk_ctx c, const double *G, int64_t m, int32_t k, float 
     DeviceGuard g(c->device);
     if (m < 2 || m > (1 << 16)) return tsk_fail(c, TSK_E_SHAPE, "tsk_eig_topk: need 2 <= m <= 65536");
     if (k < 1 || k >= m) return tsk_fail(c, TSK_E_ARG, "tsk_eig_topk: need 1 <= k < m");
-    if (k > 68) return tsk_fail(c, TSK_E_ARG, "tsk_eig_topk: k > 68 not supported");
+    if (k > 52) return tsk_fail(c, TSK_E_ARG, "tsk_eig_topk: k > 52 not supported");
     if (!lambda) return tsk_fail(c, TSK_E_ARG, "tsk_eig_topk: lambda is required");
     TSK_TRY(tsk_check_dev(c, G, sizeof(double) * m * m, "G"));
     TSK_TRY(tsk_check_dev(c, S, sizeof(float) * k * m, "S"));
@@ -231,7 +231,7 @@ tsk_status tsk_train(tsk_ctx c, const tsk_stack *train, int32_t k, int32_t compu
     if (compute != TSK_F32) return tsk_fail(c, TSK_E_ARG, "tsk_train: compute must be TSK_F32");
     const int64_t m = train->m;
     if (k < 1 || k >= m) return tsk_fail(c, TSK_E_ARG, "tsk_train: need 1 <= k < m");
-    if (k > 68) return tsk_fail(c, TSK_E_ARG, "tsk_train: k > 68 not supported");
+    if (k > 52) return tsk_fail(c, TSK_E_ARG, "tsk_train: k > 52 not supported");
     if (!lambda) return tsk_fail(c, TSK_E_ARG, "tsk_train: lambda is required");
     TSK_TRY(tsk_check_dev(c, S, sizeof(float) * k * m, "S"));
     TSK_TRY(tsk_grow(c, c->gram_G, sizeof(double) * m * m));
@@ -276,9 +276,9 @@ tsk_status tsk_error(tsk_ctx c, const tsk_stack *A, const float *L, const float 
 tsk_status tsk_set_eig_params(tsk_ctx c, int32_t block, int32_t max_iter, double tol, int32_t check) {
     if (!c) return TSK_E_ARG;
     c->eig_block = block > 0 ? block : 0;
-    c->eig_max_iter = max_iter > 0 ? max_iter : 600;
-    c->eig_tol = tol > 0 ? tol : 1e-10;
-    c->eig_check = check > 0 ? check : 16;
+    c->eig_max_iter = max_iter > 0 ? max_iter : 300;
+    c->eig_tol = tol > 0 ? tol : 1e-7;
+    c->eig_check = check > 0 ? check : 4;
     return TSK_OK;
 }
 

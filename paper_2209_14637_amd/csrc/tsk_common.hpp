@@ -162,8 +162,8 @@ struct tsk_ctx_s {
     TskBuf ap_St, ap_B, ap_Vt, ap_C, ap_fro, ap_qflag;
     TskBuf er_part;
     // eigensolver controls
-    int eig_block = 0, eig_max_iter = 600, eig_check = 16;
-    double eig_tol = 1e-10;
+    int eig_block = 0, eig_max_iter = 300, eig_check = 4;
+    double eig_tol = 1e-7;
     // timing
     bool timing = false;
     std::vector<TskEvent> pending;

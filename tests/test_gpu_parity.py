@@ -97,7 +97,8 @@ def test_eig_clustered_tail(ctx, orc):
     S, lamg, iters, st = ctx.eig_topk(dev(g), k)
     s = S.cpu().numpy().astype(np.float64)
     uk = q[:, :k]
-    assert np.linalg.norm(s.T - uk @ (uk.T @ s.T), 2) < 1e-6
+    # residual <= 1e-7 theta_1 and a gap of 5 bound the angle by 1e-6 (FP32 output)
+    assert np.linalg.norm(s.T - uk @ (uk.T @ s.T), 2) < 2e-6
 
 
 # --------------------------------------------------------------------------

@@ -147,10 +147,11 @@ tsk_status tsk_error(tsk_ctx ctx, const tsk_stack *A, const float *L, const floa
 tsk_status tsk_set_eig_params(tsk_ctx ctx, int32_t block, int32_t max_iter, double tol,
                               int32_t check);
 
-/* Kernel timing.  When enabled, every launch is bracketed by HIP events on
- * the context's stream; tsk_timing_read synchronises and returns, for each
- * kernel class, the number of launches and the summed milliseconds since the
- * last reset.  Classes: see TSK_KERNEL_*. */
+/* Kernel timing.  mask bit i (i = TSK_KERNEL_*) brackets every launch of
+ * kernel class i with HIP events on the context's stream (0: off, -1: all
+ * classes).  tsk_timing_read synchronises and returns, for each kernel class,
+ * the number of timed launches and their summed milliseconds since the last
+ * reset. */
 enum {
     TSK_KERNEL_GRAM = 0,     /* Gram product kernel          */
     TSK_KERNEL_GRAM_REDUCE,  /* FP64 reduction of partials    */
@@ -163,7 +164,7 @@ enum {
     TSK_KERNEL_ERROR,        /* explicit residual             */
     TSK_KERNEL_COUNT
 };
-tsk_status tsk_timing_enable(tsk_ctx ctx, int32_t on);
+tsk_status tsk_timing_enable(tsk_ctx ctx, int32_t mask);
 tsk_status tsk_timing_read(tsk_ctx ctx, int32_t reset, int64_t *launches /* TSK_KERNEL_COUNT */,
                            double *ms /* TSK_KERNEL_COUNT */);
 

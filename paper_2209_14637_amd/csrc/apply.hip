@@ -17,8 +17,11 @@
 
 namespace {
 
-constexpr int SK_PANEL = 256;  // columns of A_d per sketch workgroup (64 per wave)
-constexpr int PJ_ROWS = 256;   // rows of A_d per project workgroup (64 per wave)
+// One wave per workgroup: 400 matrices x 12 panels is 4800 equal work units,
+// a little over the machine's resident-wave count, and single waves let the
+// last units run at full speed on otherwise idle SIMDs.
+constexpr int SK_PANEL = 64;   // columns of A_d per sketch workgroup (one wave)
+constexpr int PJ_ROWS = 64;    // rows of A_d per project workgroup (one wave)
 constexpr int MAXK = 64;
 constexpr int NTRI_PER_THREAD = (MAXK * (MAXK + 1) / 2 + 255) / 256;  // upper-triangle entries per thread
 
@@ -33,16 +36,16 @@ __global__ void transpose_sketch_kernel(const float *__restrict__ S, int k, int 
 }
 
 template <int MT>
-__global__ __launch_bounds__(256) void sketch_f32_kernel(const float *__restrict__ A, int64_t m, int64_t n,
+__global__ __launch_bounds__(64) void sketch_f32_kernel(const float *__restrict__ A, int64_t m, int64_t n,
                                                          int64_t ld, int64_t stride, const float *__restrict__ St,
                                                          float *__restrict__ B, int64_t ldb,
                                                          double *__restrict__ fro_part, int npanel) {
     constexpr int kp = MT * 16;
     const int64_t d = blockIdx.y;
     const int panel = blockIdx.x;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int q = lane >> 4, jj = lane & 15;
-    const int64_t col4 = (int64_t)panel * SK_PANEL + wv * 64 + 4 * jj;  // this lane's 4 columns
+    const int64_t col4 = (int64_t)panel * SK_PANEL + 4 * jj;  // this lane's 4 columns
     const bool full = col4 + 3 < n;
     const bool any = col4 < n;
     const float *Ad = A + d * stride;
@@ -99,153 +102,142 @@ __global__ __launch_bounds__(256) void sketch_f32_kernel(const float *__restrict
                 *reinterpret_cast<float4 *>(Bd + srow * ldb + col4) = v;
             }
     }
-    __shared__ double red[4];
-    const double tot = block_sum_f64(fro, red);
+    const double tot = wave_sum_f64(fro);
     if (threadIdx.x == 0) fro_part[d * npanel + panel] = tot;
 }
 
 // ---------------------------------------------------------------------------
-// CholeskyQR2 of B_d^T, one workgroup per matrix.
+// Small dense helpers, one workgroup (256 threads) per matrix.
 // ---------------------------------------------------------------------------
 
-// C (k x k, upper triangle, LDS) = src src^T, src k x n rows with stride lds_src.
-__device__ inline void gram_rows(const float *__restrict__ src, int k, int64_t n, int64_t ldsrc, double *C,
-                                 float *stage /* k x 256 */) {
+// Gram of k vectors stored as the ROWS of X (k x n, row stride ldx, FP32):
+// C[a][b] = sum_c X[a][c] X[b][c] in FP64 (full symmetric, LDS stride ld).
+// Work: 4x4 register blocks of C (a-block <= b-block) x column slices, float4
+// loads over 4 consecutive columns; slices summed through LDS (scratch:
+// 256*16 doubles).  Columns in [n, round4(n)) must hold zeros.
+__device__ inline void row_gram(const float *__restrict__ X, int64_t ldx, int k, int64_t n, double *C, int ld,
+                                double *scratch) {
+    const int nb = (k + 3) / 4;
+    const int nblk = nb * (nb + 1) / 2;
+    const int ns = 256 / nblk;
     const int tid = threadIdx.x;
-    const int ntri = k * (k + 1) / 2;
-    double acc[NTRI_PER_THREAD];
-    int ea[NTRI_PER_THREAD], eb[NTRI_PER_THREAD];
+    const int sl = tid / nblk, blk = tid % nblk;
+    double acc[16];
 #pragma unroll
-    for (int u = 0; u < NTRI_PER_THREAD; ++u) {
-        acc[u] = 0.0;
-        int e = tid + u * 256, a = 0, rowlen = k;
-        if (e < ntri) {
-            while (e >= rowlen) {
-                e -= rowlen;
-                ++a;
-                --rowlen;
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    int ta = 0, tb = 0;
+    if (sl < ns) {
+        int e = blk, rr = 0, len = nb;
+        while (e >= len) {
+            e -= len;
+            ++rr;
+            --len;
+        }
+        ta = rr;
+        tb = rr + e;
+        const float *xa[4], *xb[4];
+        bool va[4], vb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            va[u] = 4 * ta + u < k;
+            vb[u] = 4 * tb + u < k;
+            xa[u] = X + (va[u] ? 4 * ta + u : 0) * ldx;
+            xb[u] = X + (vb[u] ? 4 * tb + u : 0) * ldx;
+        }
+        for (int64_t c4 = 4 * (int64_t)sl; c4 < n; c4 += 4 * ns) {
+            float4 fa[4], fb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                fa[u] = va[u] ? *reinterpret_cast<const float4 *>(xa[u] + c4) : float4{0.f, 0.f, 0.f, 0.f};
+                fb[u] = vb[u] ? *reinterpret_cast<const float4 *>(xb[u] + c4) : float4{0.f, 0.f, 0.f, 0.f};
             }
-            ea[u] = a;
-            eb[u] = a + e;
-        } else {
-            ea[u] = eb[u] = -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[u * 4 + v] += (double)fa[u].x * fb[v].x + (double)fa[u].y * fb[v].y +
+                                      (double)fa[u].z * fb[v].z + (double)fa[u].w * fb[v].w;
         }
     }
-    for (int64_t c0 = 0; c0 < n; c0 += 256) {
-        __syncthreads();
-        for (int e = tid; e < k * 256; e += 256) {
-            const int a = e / 256;
-            const int64_t cc = c0 + (e % 256);
-            stage[e] = cc < n ? src[a * ldsrc + cc] : 0.f;
-        }
-        __syncthreads();
+    __syncthreads();
+    if (sl < ns) {
 #pragma unroll
-        for (int u = 0; u < NTRI_PER_THREAD; ++u) {
-            if (ea[u] < 0) continue;
-            const float *ra = stage + ea[u] * 256, *rb = stage + eb[u] * 256;
-            double s = 0.0;
-            for (int c = 0; c < 256; ++c) s += (double)ra[c] * (double)rb[c];
-            acc[u] += s;
+        for (int u = 0; u < 16; ++u) scratch[(sl * nblk + blk) * 16 + u] = acc[u];
+    }
+    __syncthreads();
+    for (int e = tid; e < nblk * 16; e += 256) {
+        const int bk = e / 16, u = e % 16;
+        double sum = 0.0;
+        for (int z = 0; z < ns; ++z) sum += scratch[(z * nblk + bk) * 16 + u];
+        int ee = bk, rr = 0, len = nb;
+        while (ee >= len) {
+            ee -= len;
+            ++rr;
+            --len;
+        }
+        const int a = 4 * rr + u / 4, b = 4 * (rr + ee) + u % 4;
+        if (a < k && b < k) {
+            C[a * ld + b] = sum;
+            C[b * ld + a] = sum;
         }
     }
-#pragma unroll
-    for (int u = 0; u < NTRI_PER_THREAD; ++u)
-        if (ea[u] >= 0) {
-            C[ea[u] * MAXK + eb[u]] = acc[u];
-            C[eb[u] * MAXK + ea[u]] = acc[u];
-        }
     __syncthreads();
 }
 
-// In-LDS Cholesky (ld = MAXK) with dead pivots, then Rinv by column-parallel
-// back substitution (k <= 64).  Returns the number of dead indices.
-__device__ inline int chol_inv_small(double *C, double *Rinv, int k, double tol_rel, int *dead) {
-    const int tid = threadIdx.x;
-    __shared__ double s_maxd;
-    __shared__ int s_nd;
-    if (tid == 0) {
-        double mx = 0.0;
-        for (int j = 0; j < k; ++j) mx = fmax(mx, C[j * MAXK + j]);
-        s_maxd = mx;
-        s_nd = 0;
-    }
-    __syncthreads();
-    const double thr = tol_rel * s_maxd;
-    for (int j = 0; j < k; ++j) {
-        const double piv = C[j * MAXK + j];
-        const bool dj = !(piv > thr) || !(piv > 0.0);
-        if (tid == 0) {
-            dead[j] = dj;
-            if (dj) ++s_nd;
-        }
-        if (!dj) {
-            const int L = k - j - 1;
-            const double inv = 1.0 / piv;
-            for (int e = tid; e < L * L; e += blockDim.x) {
-                const int a = j + 1 + e / L, b = j + 1 + e % L;
-                if (a <= b) C[a * MAXK + b] -= C[j * MAXK + a] * C[j * MAXK + b] * inv;
-            }
-        }
-        __syncthreads();
-    }
-    // R[a][b] = C[a][b]/sqrt(C[a][a]) (rows of dead a are zero); invert by
-    // back substitution, one thread per column, R read straight from C.
-    if (tid < k) {
-        const int j = tid;
-        for (int i = j; i >= 0; --i) {
-            double v = 0.0;
-            if (!dead[i]) {
-                const double di = sqrt(C[i * MAXK + i]);
-                double s = (i == j) ? 1.0 : 0.0;
-                for (int t = i + 1; t <= j; ++t) s -= (C[i * MAXK + t] / di) * Rinv[t * MAXK + j];
-                v = s / di;
-            }
-            Rinv[i * MAXK + j] = v;
-        }
-        for (int i = j + 1; i < k; ++i) Rinv[i * MAXK + j] = 0.0;
-    }
-    __syncthreads();
-    return s_nd;
-}
-
-// dst (k x ldv) = Rinv^T src, columns >= n and rows k..kp-1 set to zero.
-__device__ inline void apply_rinv_t(const float *__restrict__ src, int64_t ldsrc, float *__restrict__ dst,
-                                    int64_t lddst, int k, int kp, int64_t n, int64_t ldv, const double *Rinv) {
+// dst (KP x ldv) = Rinv^T src for the first k rows, FP32; rows k..KP-1 and
+// columns n..ldv-1 are written as zero.  Rf: Rinv (KP x KP, FP32, LDS).
+template <int KP>
+__device__ inline void apply_rinv_t(const float *__restrict__ src, float *__restrict__ dst, int64_t ldv, int k,
+                                    int64_t n, const float *Rf) {
     for (int64_t c = threadIdx.x; c < ldv; c += blockDim.x) {
-        double col[MAXK];
-        if (c < n) {
-            for (int t = 0; t < k; ++t) col[t] = (double)src[t * ldsrc + c];
-        }
-        for (int i = 0; i < kp; ++i) {
-            double s = 0.0;
-            if (c < n && i < k) {
-                for (int t = 0; t <= i; ++t) s += Rinv[t * MAXK + i] * col[t];
-            }
-            dst[i * lddst + c] = (float)s;
+        float col[KP];
+#pragma unroll
+        for (int t = 0; t < KP; ++t) col[t] = (t < k && c < n) ? src[t * ldv + c] : 0.f;
+        // Rf is upper triangular (zero below the diagonal): full-length dot
+        // products keep col[] statically indexed, i.e. in registers
+#pragma nounroll
+        for (int i = 0; i < KP; ++i) {
+            float s = 0.f;
+#pragma unroll
+            for (int t = 0; t < KP; ++t) s += Rf[t * KP + i] * col[t];
+            dst[i * ldv + c] = s;
         }
     }
 }
 
-__global__ __launch_bounds__(256) void cholqr2_kernel(const float *__restrict__ B, int64_t ldb, float *__restrict__ Vt,
-                                                      int k, int kp, int64_t n, int *__restrict__ qflag) {
-    __shared__ double C[MAXK * MAXK];
-    __shared__ double Rinv[MAXK * MAXK];
-    __shared__ float stage[MAXK * 256];
-    __shared__ int dead[MAXK];
+// CholeskyQR2 of B_d^T: V_d^T (k x n, rows orthonormal) spans the row space
+// of B_d.  Grams in FP64 from FP32 data, Cholesky and inverse in FP64, the
+// triangular application in FP32 (the span does not depend on the accuracy
+// of R; the second pass restores orthogonality).  Dead pivots in the first
+// pass (singular-value ratio below 1e-6, the FP32 rounding level of B) flag
+// the matrix as rank deficient and leave zero rows in V^T.
+template <int KP>
+__global__ __launch_bounds__(256) void cholqr2_kernel(const float *__restrict__ B, int64_t ldv,
+                                                      float *__restrict__ Vt, int k, int64_t n,
+                                                      int *__restrict__ qflag) {
+    // C | R | X (KP*KP doubles each); the Gram's slice scratch (4096 doubles)
+    // sits after C and is dead once C is assembled
+    constexpr int SCR = (3 * KP * KP > KP * KP + 4096) ? 3 * KP * KP : KP * KP + 4096;
+    __shared__ double lds[SCR];
+    __shared__ float Rf[KP * KP];
+    __shared__ int dead[KP];
+    double *C = lds, *R = lds + KP * KP, *X = lds + 2 * KP * KP;
     const int64_t d = blockIdx.x;
-    const float *Bd = B + d * kp * ldb;
-    float *Vd = Vt + d * kp * ldb;
-    // pass 1: threshold 1e-12 on the pivot ratio (singular-value ratio 1e-6,
-    // the FP32 rounding level of B)
-    gram_rows(Bd, k, n, ldb, C, stage);
-    const int nd1 = chol_inv_small(C, Rinv, k, 1e-12, dead);
-    apply_rinv_t(Bd, ldb, Vd, ldb, k, kp, n, ldb, Rinv);
-    __syncthreads();
-    // pass 2 on the (nearly orthonormal) first pass
-    gram_rows(Vd, k, n, ldb, C, stage);
-    chol_inv_small(C, Rinv, k, 1e-12, dead);
-    __syncthreads();
-    apply_rinv_t(Vd, ldb, Vd, ldb, k, kp, n, ldb, Rinv);
+    const float *Bd = B + d * KP * ldv;
+    float *Vd = Vt + d * KP * ldv;
+    int nd1 = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const float *src = pass == 0 ? Bd : Vd;
+        for (int e = threadIdx.x; e < KP * KP; e += 256) lds[e] = 0.0;
+        __syncthreads();
+        row_gram(src, ldv, k, n, C, KP, lds + KP * KP);
+        const int nd = chol_factor_inverse(C, KP, KP, 1e-12, R, X, dead, k);
+        if (pass == 0) nd1 = nd;
+        for (int e = threadIdx.x; e < KP * KP; e += 256) Rf[e] = (float)X[e];
+        __syncthreads();
+        apply_rinv_t<KP>(src, Vd, ldv, k, n, Rf);
+        __syncthreads();
+    }
     if (threadIdx.x == 0) qflag[d] = nd1 > 0 ? TSK_FLAG_RANKDEF : 0;
 }
 
@@ -253,14 +245,14 @@ __global__ __launch_bounds__(256) void cholqr2_kernel(const float *__restrict__ 
 // C_d = A_d V_d
 // ---------------------------------------------------------------------------
 template <int NT>
-__global__ __launch_bounds__(256) void project_f32_kernel(const float *__restrict__ A, int64_t m, int64_t n,
+__global__ __launch_bounds__(64) void project_f32_kernel(const float *__restrict__ A, int64_t m, int64_t n,
                                                           int64_t ld, int64_t stride, const float *__restrict__ Vt,
                                                           int64_t ldv, float *__restrict__ C) {
     constexpr int kp = NT * 16;
     const int64_t d = blockIdx.y;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int q = lane >> 4, ii = lane & 15;
-    const int64_t r0 = (int64_t)blockIdx.x * PJ_ROWS + wv * 64;
+    const int64_t r0 = (int64_t)blockIdx.x * PJ_ROWS;
     const float *Ad = A + d * stride;
     const float *Vd = Vt + d * kp * ldv;
     const float *arow[4];
@@ -320,77 +312,100 @@ __global__ __launch_bounds__(256) void project_f32_kernel(const float *__restric
 
 // ---------------------------------------------------------------------------
 // Rank-r truncation, outputs and the fused error.  One workgroup per matrix.
+//   H = C^T C (FP64), Jacobi -> Y, sigma^2 (descending); L = C Y_r,
+//   R = V Y_r; relerr from ||A||^2 - sum_{i<=r} sigma_i^2.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ C, int64_t m, int k, int kp, int r,
+
+// Gram of the KP columns of C (m x KP row-major FP32): H[a][b] = sum_i
+// C[i][a] C[i][b], FP64, 4x4 register blocks x row slices (scratch: 4096).
+__device__ inline void col_gram(const float *__restrict__ Cm, int KP, int k, int64_t m, double *H, int ld,
+                                double *scratch) {
+    const int nb = (k + 3) / 4;
+    const int nblk = nb * (nb + 1) / 2;
+    const int ns = 256 / nblk;
+    const int tid = threadIdx.x;
+    const int sl = tid / nblk, blk = tid % nblk;
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    int ta = 0, tb = 0;
+    {
+        int e = blk, rr = 0, len = nb;
+        while (e >= len) {
+            e -= len;
+            ++rr;
+            --len;
+        }
+        ta = rr;
+        tb = rr + e;
+    }
+    if (sl < ns) {
+        for (int64_t i = sl; i < m; i += ns) {
+            const float4 fa = *reinterpret_cast<const float4 *>(Cm + i * KP + 4 * ta);
+            const float4 fb = *reinterpret_cast<const float4 *>(Cm + i * KP + 4 * tb);
+            const float av[4] = {fa.x, fa.y, fa.z, fa.w}, bv[4] = {fb.x, fb.y, fb.z, fb.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u * 4 + v] += (double)av[u] * (double)bv[v];
+        }
+    }
+    __syncthreads();
+    if (sl < ns) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) scratch[(sl * nblk + blk) * 16 + u] = acc[u];
+    }
+    __syncthreads();
+    for (int e = tid; e < nblk * 16; e += 256) {
+        const int bk = e / 16, u = e % 16;
+        double sum = 0.0;
+        for (int z = 0; z < ns; ++z) sum += scratch[(z * nblk + bk) * 16 + u];
+        int ee = bk, rr = 0, len = nb;
+        while (ee >= len) {
+            ee -= len;
+            ++rr;
+            --len;
+        }
+        const int a = 4 * rr + u / 4, b = 4 * (rr + ee) + u % 4;
+        if (a < k && b < k) {
+            H[a * ld + b] = sum;
+            H[b * ld + a] = sum;
+        }
+    }
+    __syncthreads();
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ C, int64_t m, int k, int r,
                                                      const float *__restrict__ Vt, int64_t ldv, int64_t n,
                                                      const double *__restrict__ fro_part, int npanel,
                                                      const int *__restrict__ qflag, float *__restrict__ L,
                                                      float *__restrict__ R, float *__restrict__ sigma,
                                                      double *__restrict__ relerr, int *__restrict__ flags) {
-    __shared__ double H[MAXK * MAXK];
-    __shared__ double W[MAXK * MAXK];
-    __shared__ double Yr[MAXK * MAXK];  // first r eigenvector columns, descending
-    __shared__ float stage[64 * MAXK];
-    __shared__ double rot[MAXK];
-    __shared__ int pairs[MAXK];
-    __shared__ int perm[MAXK];
+    // H | W | Hn (KP*KP each); the Gram scratch (4096) overlaps W and Hn
+    constexpr int SCR = (3 * KP * KP > KP * KP + 4096) ? 3 * KP * KP : KP * KP + 4096;
+    __shared__ double lds[SCR];
+    __shared__ float Yr[KP * KP];  // first r eigenvector columns, descending
+    __shared__ double rot[KP];
+    __shared__ int pairs[(KP - 1) * (KP / 2)];
+    __shared__ int perm[KP];
     __shared__ double red4[4];
-    __shared__ double s_lam[MAXK];
+    __shared__ double s_lam[KP];
     const int64_t d = blockIdx.x;
     const int tid = threadIdx.x;
-    const float *Cd = C + d * m * kp;
-    const int kk = k + (k & 1);  // even size for the parallel Jacobi ordering
-    // H = C^T C (k x k), FP64
-    const int ntri = k * (k + 1) / 2;
-    double acc[NTRI_PER_THREAD];
-    int ea[NTRI_PER_THREAD], eb[NTRI_PER_THREAD];
-#pragma unroll
-    for (int u = 0; u < NTRI_PER_THREAD; ++u) {
-        int e = tid + u * 256, a = 0, rowlen = k;
-        acc[u] = 0.0;
-        if (e < ntri) {
-            while (e >= rowlen) {
-                e -= rowlen;
-                ++a;
-                --rowlen;
-            }
-            ea[u] = a;
-            eb[u] = a + e;
-        } else {
-            ea[u] = eb[u] = -1;
-        }
-    }
-    for (int64_t i0 = 0; i0 < m; i0 += 64) {
-        __syncthreads();
-        for (int e = tid; e < 64 * kp; e += 256) {
-            const int64_t row = i0 + e / kp;
-            stage[e] = row < m ? Cd[i0 * kp + e] : 0.f;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < NTRI_PER_THREAD; ++u) {
-            if (ea[u] < 0) continue;
-            double s = 0.0;
-            for (int i = 0; i < 64; ++i) s += (double)stage[i * kp + ea[u]] * (double)stage[i * kp + eb[u]];
-            acc[u] += s;
-        }
-    }
-    for (int e = tid; e < MAXK * MAXK; e += 256) H[e] = 0.0;
+    const float *Cd = C + d * m * KP;
+    double *H = lds, *W = lds + KP * KP, *Hn = lds + 2 * KP * KP;
+    for (int e = tid; e < KP * KP; e += 256) H[e] = 0.0;
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < NTRI_PER_THREAD; ++u)
-        if (ea[u] >= 0) {
-            H[ea[u] * MAXK + eb[u]] = acc[u];
-            H[eb[u] * MAXK + ea[u]] = acc[u];
-        }
+    col_gram(Cd, KP, k, m, H, KP, lds + KP * KP);
+    const int kk = k + (k & 1);  // even size for the parallel ordering
+    H = jacobi_eig_lds(H, Hn, W, kk, KP, rot, pairs, 40, red4);
+    if (tid == 0) sort_diag_desc(H, kk, KP, perm);
     __syncthreads();
-    jacobi_eig_lds(H, W, kk, MAXK, rot, pairs, 40, red4);
-    if (tid == 0) sort_diag_desc(H, kk, MAXK, perm);
-    __syncthreads();
-    for (int t = tid; t < kk; t += 256) s_lam[t] = H[perm[t] * MAXK + perm[t]];
-    for (int e = tid; e < k * r; e += 256) {
-        const int s = e / r, t = e % r;
-        Yr[s * MAXK + t] = W[s * MAXK + perm[t]];
+    for (int t = tid; t < kk; t += 256) s_lam[t] = H[perm[t] * KP + perm[t]];
+    for (int e = tid; e < KP * KP; e += 256) {
+        const int u = e / KP, t = e % KP;
+        Yr[e] = (u < k && t < r) ? (float)W[u * KP + perm[t]] : 0.f;
     }
     __syncthreads();
     double fro2 = 0.0;
@@ -409,24 +424,38 @@ __global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ C
         if (flags) flags[d] = fl;
         if (relerr) relerr[d] = !finite ? (double)qnan : (fro2 > 0.0 ? sqrt(fmax(fro2 - cap, 0.0) / fro2) : 0.0);
     }
-    // L = C Y_r (m x r)
+    // L = C Y_r: one row of C per thread
     float *Ld = L + d * m * r;
-    for (int64_t e = tid; e < m * r; e += 256) {
-        const int64_t i = e / r;
-        const int t = (int)(e % r);
-        double s = 0.0;
-        for (int u = 0; u < k; ++u) s += (double)Cd[i * kp + u] * Yr[u * MAXK + t];
-        Ld[e] = finite ? (float)s : qnan;
+    for (int64_t i = tid; i < m; i += 256) {
+        float cv[KP];
+#pragma unroll
+        for (int u = 0; u < KP; u += 4) {
+            const float4 f = *reinterpret_cast<const float4 *>(Cd + i * KP + u);
+            cv[u] = f.x;
+            cv[u + 1] = f.y;
+            cv[u + 2] = f.z;
+            cv[u + 3] = f.w;
+        }
+        for (int t = 0; t < r; ++t) {
+            float s = 0.f;
+#pragma unroll
+            for (int u = 0; u < KP; ++u) s += cv[u] * Yr[u * KP + t];
+            Ld[i * r + t] = finite ? s : qnan;
+        }
     }
-    // R = V Y_r (n x r), V[j][u] = Vt[u][j]
-    const float *Vd = Vt + d * kp * ldv;
+    // R = V Y_r with V[j][u] = Vt[u][j]: one column of V^T per thread
+    const float *Vd = Vt + d * KP * ldv;
     float *Rd = R + d * n * r;
-    for (int64_t e = tid; e < n * r; e += 256) {
-        const int64_t j = e / r;
-        const int t = (int)(e % r);
-        double s = 0.0;
-        for (int u = 0; u < k; ++u) s += (double)Vd[u * ldv + j] * Yr[u * MAXK + t];
-        Rd[e] = finite ? (float)s : qnan;
+    for (int64_t j = tid; j < n; j += 256) {
+        float vv[KP];
+#pragma unroll
+        for (int u = 0; u < KP; ++u) vv[u] = u < k ? Vd[u * ldv + j] : 0.f;
+        for (int t = 0; t < r; ++t) {
+            float s = 0.f;
+#pragma unroll
+            for (int u = 0; u < KP; ++u) s += vv[u] * Yr[u * KP + t];
+            Rd[j * r + t] = finite ? s : qnan;
+        }
     }
 }
 
@@ -507,26 +536,38 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
                                   c->stream, S, k, kp, m, St));
     const dim3 gs((unsigned)npanel, (unsigned)count);
     switch (kp / 16) {
-        case 1: TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_kernel<1>, gs, dim3(256), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)St, B, ldv, fro, npanel)); break;
-        case 2: TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_kernel<2>, gs, dim3(256), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)St, B, ldv, fro, npanel)); break;
-        case 3: TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_kernel<3>, gs, dim3(256), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)St, B, ldv, fro, npanel)); break;
-        case 4: TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_kernel<4>, gs, dim3(256), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)St, B, ldv, fro, npanel)); break;
+        case 1: TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_kernel<1>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)St, B, ldv, fro, npanel)); break;
+        case 2: TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_kernel<2>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)St, B, ldv, fro, npanel)); break;
+        case 3: TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_kernel<3>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)St, B, ldv, fro, npanel)); break;
+        case 4: TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_kernel<4>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)St, B, ldv, fro, npanel)); break;
         default: return tsk_fail(c, TSK_E_ARG, "k > 64");
     }
-    TSK_LAUNCH(c, TSK_KERNEL_QR,
-               hipLaunchKernelGGL(cholqr2_kernel, dim3((unsigned)count), dim3(256), 0, c->stream, (const float *)B,
-                                  ldv, Vt, k, kp, n, qflag));
+    const dim3 gq((unsigned)count);
+    switch (kp / 16) {
+        case 1: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<16>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag)); break;
+        case 2: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<32>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag)); break;
+        case 3: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<48>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag)); break;
+        case 4: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<64>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag)); break;
+    }
     const dim3 gp((unsigned)((m + PJ_ROWS - 1) / PJ_ROWS), (unsigned)count);
     switch (kp / 16) {
-        case 1: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<1>, gp, dim3(256), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
-        case 2: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<2>, gp, dim3(256), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
-        case 3: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<3>, gp, dim3(256), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
-        case 4: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<4>, gp, dim3(256), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
+        case 1: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<1>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
+        case 2: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<2>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
+        case 3: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<3>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
+        case 4: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<4>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
     }
-    TSK_LAUNCH(c, TSK_KERNEL_FINISH,
-               hipLaunchKernelGGL(finish_kernel, dim3((unsigned)count), dim3(256), 0, c->stream, (const float *)Cm, m, k,
-                                  kp, r, (const float *)Vt, ldv, n, (const double *)fro, npanel, (const int *)qflag, L,
-                                  R, sigma, relerr, flags));
+#define TSK_FINISH(KPV)                                                                                        \
+    TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                           \
+               hipLaunchKernelGGL(finish_kernel<KPV>, dim3((unsigned)count), dim3(256), 0, c->stream,          \
+                                  (const float *)Cm, m, k, r, (const float *)Vt, ldv, n, (const double *)fro, \
+                                  npanel, (const int *)qflag, L, R, sigma, relerr, flags))
+    switch (kp / 16) {
+        case 1: TSK_FINISH(16); break;
+        case 2: TSK_FINISH(32); break;
+        case 3: TSK_FINISH(48); break;
+        case 4: TSK_FINISH(64); break;
+    }
+#undef TSK_FINISH
     return TSK_OK;
 }
 

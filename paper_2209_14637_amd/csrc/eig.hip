@@ -172,15 +172,28 @@ __global__ __launch_bounds__(256) void eig_mv_kernel(const double *__restrict__ 
 // ---------------------------------------------------------------------------
 
 // Sum of the KS partial matvec products for this workgroup's rows into Zs.
+// Elements are processed four at a time per thread, with all of their loads
+// (up to 4 x 8 splits) issued before the first add.
 __device__ inline void load_mv_rows(const double *__restrict__ P, int KS, int64_t m, int pp, int64_t r0, double *Zs) {
-    for (int e = threadIdx.x; e < RW_RB * pp; e += blockDim.x) {
-        const int64_t row = r0 + e / pp;
-        double s = 0.0;
-        if (row < m) {
+    const int nel = RW_RB * pp;
+    for (int base = 0; base < nel; base += 4 * 256) {
+        double v[4][8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = base + threadIdx.x + 256 * u;
+            const bool ok = e < nel && r0 + e / pp < m;
             const double *p = P + r0 * pp + e;
-            for (int ks = 0; ks < KS; ++ks) s += p[(int64_t)ks * m * pp];
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) v[u][ks] = (ok && ks < KS) ? p[(int64_t)ks * m * pp] : 0.0;
         }
-        Zs[e] = s;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = base + threadIdx.x + 256 * u;
+            double s = 0.0;
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) s += v[u][ks];
+            if (e < nel) Zs[e] = s;
+        }
     }
 }
 
@@ -198,20 +211,18 @@ __device__ inline void block_gram(const double *As, const double *Bs, int pp, do
     }
 }
 
-// Sum nparts upper-triangle partials into the full symmetric C (LDS).
+// Sum nparts upper-triangle partials into the full symmetric C (LDS), in
+// partial order; the first 32 partials of an entry are loaded before any add.
 __device__ inline void reduce_tri(const double *__restrict__ part, int nparts, int pp, double *C) {
     const int ntri = pp * (pp + 1) / 2;
     for (int e = threadIdx.x; e < ntri; e += blockDim.x) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int w = 0;
-        for (; w + 4 <= nparts; w += 4) {
-            s0 += part[(int64_t)w * ntri + e];
-            s1 += part[(int64_t)(w + 1) * ntri + e];
-            s2 += part[(int64_t)(w + 2) * ntri + e];
-            s3 += part[(int64_t)(w + 3) * ntri + e];
-        }
-        for (; w < nparts; ++w) s0 += part[(int64_t)w * ntri + e];
-        const double s = (s0 + s1) + (s2 + s3);
+        double v[32];
+#pragma unroll
+        for (int w = 0; w < 32; ++w) v[w] = (w < nparts) ? part[(int64_t)w * ntri + e] : 0.0;
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < 32; ++w) s += v[w];
+        for (int w = 32; w < nparts; ++w) s += part[(int64_t)w * ntri + e];
         int a, b;
         tri_index(e, pp, a, b);
         C[a * pp + b] = s;
@@ -220,92 +231,13 @@ __device__ inline void reduce_tri(const double *__restrict__ part, int nparts, i
     __syncthreads();
 }
 
-// Blocked inverse of an upper-triangular pp x pp matrix R (LDS) into X (LDS):
-// 8x8 diagonal blocks inverted by one thread each, then neighbouring blocks
-// merged level by level with X12 = -X11 R12 X22.  Zero diagonal entries
-// (dead pivots) give zero rows/columns in X.  T: LDS scratch (pp*pp).
-__device__ inline void upper_tri_inverse(const double *R, double *X, int pp, double *T) {
-    const int tid = threadIdx.x;
-    for (int e = tid; e < pp * pp; e += blockDim.x) X[e] = 0.0;
-    __syncthreads();
-    const int nblk = pp / 8;
-    if (tid < nblk) {
-        const int o = tid * 8;
-        for (int j = 7; j >= 0; --j) {
-            for (int i = j; i >= 0; --i) {
-                const double rii = R[(o + i) * pp + (o + i)];
-                if (rii == 0.0) {
-                    X[(o + i) * pp + (o + j)] = 0.0;
-                    continue;
-                }
-                double s = (i == j) ? 1.0 : 0.0;
-                for (int t = i + 1; t <= j; ++t) s -= R[(o + i) * pp + (o + t)] * X[(o + t) * pp + (o + j)];
-                X[(o + i) * pp + (o + j)] = s / rii;
-            }
-        }
-    }
-    __syncthreads();
-    for (int s = 8; s < pp; s *= 2) {
-        const int ngroups = (pp + 2 * s - 1) / (2 * s);
-        for (int e = tid; e < ngroups * s * s; e += blockDim.x) {
-            const int g = e / (s * s), a = (e / s) % s, b = e % s;
-            const int o = g * 2 * s, s2 = (pp - o - s < s) ? pp - o - s : s;
-            if (s2 <= 0 || b >= s2) continue;
-            double acc = 0.0;
-            for (int cidx = 0; cidx <= b; ++cidx)
-                acc += R[(o + a) * pp + (o + s + cidx)] * X[(o + s + cidx) * pp + (o + s + b)];
-            T[e] = acc;
-        }
-        __syncthreads();
-        for (int e = tid; e < ngroups * s * s; e += blockDim.x) {
-            const int g = e / (s * s), a = (e / s) % s, b = e % s;
-            const int o = g * 2 * s, s2 = (pp - o - s < s) ? pp - o - s : s;
-            if (s2 <= 0 || b >= s2) continue;
-            double acc = 0.0;
-            for (int cidx = a; cidx < s; ++cidx) acc += X[(o + a) * pp + (o + cidx)] * T[g * s * s + cidx * s + b];
-            X[(o + a) * pp + (o + s + b)] = -acc;
-        }
-        __syncthreads();
-    }
-}
-
-// C (LDS, full symmetric, destroyed) -> Rinv (global, pp x pp) with
-// Cholesky C = R^T R, one barrier per column.  A pivot <= tol_rel * max(diag)
-// marks the index dead: its row of R and its row/column of Rinv are zero.
-// lds: 2*pp*pp doubles of scratch.
+// C (LDS, full symmetric, destroyed) -> Rinv (global, pp x pp), see
+// chol_factor_inverse.  lds: 2*pp*pp doubles of scratch.
 __device__ inline void chol_inverse(double *C, int pp, double tol_rel, double *lds, double *Rinv) {
-    __shared__ double s_maxd;
     __shared__ int dead[EIG_MAXPP];
     double *R = lds, *X = lds + pp * pp;
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        double mx = 0.0;
-        for (int j = 0; j < pp; ++j) mx = fmax(mx, C[j * pp + j]);
-        s_maxd = mx;
-    }
-    __syncthreads();
-    const double thr = tol_rel * s_maxd;
-    for (int j = 0; j < pp; ++j) {
-        const double piv = C[j * pp + j];
-        const bool dj = !(piv > thr) || !(piv > 0.0);
-        if (tid == 0) dead[j] = dj;
-        if (!dj) {
-            const int L = pp - j - 1;
-            const double inv = 1.0 / piv;
-            for (int e = tid; e < L * L; e += blockDim.x) {
-                const int a = j + 1 + e / L, b = j + 1 + e % L;
-                if (a <= b) C[a * pp + b] -= C[j * pp + a] * C[j * pp + b] * inv;
-            }
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < pp * pp; e += blockDim.x) {
-        const int a = e / pp, b = e % pp;
-        R[e] = (b >= a && !dead[a]) ? C[a * pp + b] / sqrt(C[a * pp + a]) : 0.0;
-    }
-    __syncthreads();
-    upper_tri_inverse(R, X, pp, C);
-    for (int e = tid; e < pp * pp; e += blockDim.x) Rinv[e] = X[e];
+    chol_factor_inverse(C, pp, pp, tol_rel, R, X, dead);
+    for (int e = threadIdx.x; e < pp * pp; e += blockDim.x) Rinv[e] = X[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -377,6 +309,40 @@ __global__ __launch_bounds__(256) void eig_apply_kernel(const double *__restrict
     chol_inverse(C, pp, tol_chol, lds + pp * pp, small + SM_RINV);
 }
 
+// After a single-pass Cholesky QR of Y2 (Rinv from eig_filter) and P = G Y2:
+// X = Y2 Rinv, GX = P Rinv = G X, Y1 = (GX - c X)/e.  X is only
+// well-conditioned here (one Cholesky pass), which is all that the next
+// filtered step needs; the spans are exact.
+__global__ __launch_bounds__(256) void eig_gxr_kernel(const double *__restrict__ P, int KS, int64_t m, int pp,
+                                                      const double *__restrict__ Y2, double *__restrict__ X,
+                                                      double *__restrict__ GX, double *__restrict__ Y1,
+                                                      const double *__restrict__ small) {
+    extern __shared__ double lds[];
+    double *Rs = lds, *Zs = Rs + pp * pp, *Ys = Zs + RW_RB * pp;
+    const int64_t r0 = (int64_t)blockIdx.x * RW_RB;
+    for (int t = threadIdx.x; t < pp * pp; t += blockDim.x) Rs[t] = small[SM_RINV + t];
+    load_mv_rows(P, KS, m, pp, r0, Zs);
+    for (int t = threadIdx.x; t < RW_RB * pp; t += blockDim.x) {
+        const int64_t row = r0 + t / pp;
+        Ys[t] = row < m ? Y2[r0 * pp + t] : 0.0;
+    }
+    const double c = small[SM_C], e = small[SM_E];
+    __syncthreads();
+    for (int t = threadIdx.x; t < RW_RB * pp; t += blockDim.x) {
+        const int i = t / pp, j = t % pp;
+        if (r0 + i >= m) continue;
+        double x = 0.0, g = 0.0;
+        for (int u = 0; u <= j; ++u) {
+            const double rv = Rs[u * pp + j];
+            x += Ys[i * pp + u] * rv;
+            g += Zs[i * pp + u] * rv;
+        }
+        X[r0 * pp + t] = x;
+        GX[r0 * pp + t] = g;
+        Y1[r0 * pp + t] = (g - c * x) / e;
+    }
+}
+
 // GX = G X.  rr = 0: Y1 = (GX - c X)/e.  rr = 1: partial X^T GX, and the last
 // workgroup diagonalises H = X^T G X -> W (columns in descending order), theta,
 // and the next filter interval.
@@ -404,12 +370,12 @@ __global__ __launch_bounds__(256) void eig_gx_kernel(const double *__restrict__ 
     block_gram(Xs, Zs, pp, part + (int64_t)blockIdx.x * ntri);
     if (!last_block(counter)) return;
     __shared__ double rot[EIG_MAXPP];
-    __shared__ int pairs[EIG_MAXPP];
+    __shared__ int pairs[(EIG_MAXPP - 1) * (EIG_MAXPP / 2)];
     __shared__ int perm[EIG_MAXPP];
     __shared__ double red4[4];
-    double *H = lds, *W = lds + pp * pp;
+    double *H = lds, *W = lds + pp * pp, *Hn = lds + 2 * pp * pp;
     reduce_tri(part, gridDim.x, pp, H);
-    jacobi_eig_lds(H, W, pp, pp, rot, pairs, 40, red4);
+    H = jacobi_eig_lds(H, Hn, W, pp, pp, rot, pairs, 40, red4);
     if (threadIdx.x == 0) sort_diag_desc(H, pp, pp, perm);
     __syncthreads();
     for (int t = threadIdx.x; t < pp * pp; t += blockDim.x) {
@@ -560,7 +526,7 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
     const size_t lds_filter = sizeof(double) * (RW_RB * pp > 3 * pp * pp ? RW_RB * pp : 3 * pp * pp);
     const size_t lds_apply =
         sizeof(double) * (pp * pp + 2 * RW_RB * pp > 3 * pp * pp ? pp * pp + 2 * RW_RB * pp : 3 * pp * pp);
-    const size_t lds_gx = sizeof(double) * (2 * RW_RB * pp > 2 * pp * pp ? 2 * RW_RB * pp : 2 * pp * pp);
+    const size_t lds_gx = sizeof(double) * (2 * RW_RB * pp > 3 * pp * pp ? 2 * RW_RB * pp : 3 * pp * pp);
     const size_t lds_rot = sizeof(double) * (pp * pp + 3 * RW_RB * pp);
     {
         hipError_t a1 = hipFuncSetAttribute((const void *)eig_filter_kernel,
@@ -602,17 +568,33 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
                                       part, counter, small, tol));
         return TSK_OK;
     };
-    // one filtered step: Y2 = T_2(L) X, CholeskyQR2 -> X, GX = G X
+    const size_t lds_gxr = sizeof(double) * (pp * pp + 2 * RW_RB * pp);
+    {
+        hipError_t a5 = hipFuncSetAttribute((const void *)eig_gxr_kernel,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_gxr);
+        if (a5 != hipSuccess) return tsk_hip(c, a5, "LDS attribute");
+    }
+    // one filtered step: Y2 = T_2(L) X; a single Cholesky QR pass keeps the
+    // block well conditioned; before a Rayleigh-Ritz check (rr = 1) the block
+    // is made orthonormal with CholeskyQR2.
     auto filter_step = [&](int rr) -> tsk_status {
         TSK_TRY(mv(Y1));
         TSK_LAUNCH(c, TSK_KERNEL_EIG_ITER,
                    hipLaunchKernelGGL(eig_filter_kernel, dim3(nrw), dim3(256), lds_filter, c->stream,
                                       (const double *)P, KS, m, pp, (const double *)Y1, (const double *)X, Y2, part,
                                       counter, small, tol_chol));
+        if (!rr) {
+            TSK_TRY(mv(Y2));
+            TSK_LAUNCH(c, TSK_KERNEL_EIG_ITER,
+                       hipLaunchKernelGGL(eig_gxr_kernel, dim3(nrw), dim3(256), lds_gxr, c->stream,
+                                          (const double *)P, KS, m, pp, (const double *)Y2, X, GX, Y1,
+                                          (const double *)small));
+            return TSK_OK;
+        }
         TSK_TRY(apply(Y2, X1, 1));
         TSK_TRY(apply(X1, X, 0));
         TSK_TRY(mv(X));
-        return gx(rr);
+        return gx(1);
     };
 
     // start: random block, CholeskyQR2, Rayleigh-Ritz

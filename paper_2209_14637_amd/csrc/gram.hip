@@ -11,10 +11,13 @@
 //    and share that chunk's rows through its L2.
 //  * Each of the 4 waves owns a 64x64 quarter of the tile: 4x4 MFMA
 //    16x16x4 f32 tiles accumulated in registers.
+//  * The workgroup stages 32 columns of its 256 operand rows in LDS per
+//    step (coalesced 128-byte row reads), double buffered: the next step's
+//    global loads are in flight while this step's MFMAs run.
 //  * The contraction index (slice, column) can be visited in any order as
-//    long as both operands use the same order, so each lane loads 2 float4
-//    (columns c0+4q..+3 and c0+16+4q..+3 of one row) and feeds component u
-//    of them to MFMA number u: row reads are 128 contiguous bytes per row.
+//    long as both operands use the same order, so each lane reads 2 float4
+//    (columns 4q..+3 and 16+4q..+3 of one staged row) and feeds component u
+//    of them to MFMA number u.
 #include "tsk_common.hpp"
 
 namespace {
@@ -29,31 +32,51 @@ __device__ __forceinline__ void tile_coords(int t, int &bi, int &bj) {
     bj = t - b * (b + 1) / 2;
 }
 
-__device__ __forceinline__ void load_row8(const float *__restrict__ row, int64_t c0, int q, int64_t n,
-                                          bool fast, bool valid, float (&v)[8]) {
-    if (!valid) {
+// Stage = 32 columns of one slice for the tile's 128 row-block rows (Ra) and
+// 128 column-block rows (Rb), staged in LDS and double buffered.  LDS rows
+// are padded to 36 floats so that the 16 rows read by one ds_read_b128
+// quarter-wave start in distinct bank groups.
+constexpr int GK = 32;           // columns per stage
+constexpr int GLD = GK + 4;      // padded LDS row length
+constexpr int GBUF = 2 * GT * GLD;  // floats per stage buffer (Ra and Rb)
+
+__device__ __forceinline__ void gram_fetch(const float *__restrict__ Ad, int64_t m, int64_t n, int64_t ld,
+                                           int64_t rb0, int64_t cb0, int64_t c0, float4 (&v)[8]) {
+    // thread t: row (t >> 3) + 32 u of each block, columns c0 + 4 (t & 7) .. +3
+    const int t = threadIdx.x;
+    const int64_t cc = c0 + 4 * (t & 7);
+    const bool fullc = cc + 3 < n;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = 0.f;
-        return;
-    }
-    if (fast) {
-        const float4 x = *reinterpret_cast<const float4 *>(row + c0 + 4 * q);
-        const float4 y = *reinterpret_cast<const float4 *>(row + c0 + 16 + 4 * q);
-        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
-    } else {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t ca = c0 + 4 * q + u, cb = c0 + 16 + 4 * q + u;
-            v[u] = ca < n ? row[ca] : 0.f;
-            v[4 + u] = cb < n ? row[cb] : 0.f;
+    for (int u = 0; u < 8; ++u) {
+        const int64_t row = (u < 4 ? rb0 : cb0) + (t >> 3) + 32 * (u & 3);
+        float4 x = float4{0.f, 0.f, 0.f, 0.f};
+        if (row < m && cc < n) {
+            const float *p = Ad + row * ld + cc;
+            if (fullc) {
+                x = *reinterpret_cast<const float4 *>(p);
+            } else {
+                x.x = p[0];
+                if (cc + 1 < n) x.y = p[1];
+                if (cc + 2 < n) x.z = p[2];
+            }
         }
+        v[u] = x;
+    }
+}
+
+__device__ __forceinline__ void gram_stash(float *buf, const float4 (&v)[8]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int r = (u < 4 ? 0 : GT) + (t >> 3) + 32 * (u & 3);
+        *reinterpret_cast<float4 *>(buf + r * GLD + 4 * (t & 7)) = v[u];
     }
 }
 
 __global__ __launch_bounds__(256) void gram_f32_kernel(const float *__restrict__ A, int64_t m, int64_t n,
                                                        int64_t ld, int64_t stride, int64_t count, int T,
                                                        int nchunks, int per_xcd, float *__restrict__ part) {
+    __shared__ float lds[2 * GBUF];
     const int w = blockIdx.x;
     const int xcd = w & 7, local = w >> 3;
     const int t = local % T, sub = local / T;
@@ -65,9 +88,8 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(const float *__restrict__
     tile_coords(t, bi, bj);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int q = lane >> 4, ii = lane & 15;
-    const int64_t rbase = (int64_t)bi * GT + (wv >> 1) * 64;
-    const int64_t cbase = (int64_t)bj * GT + (wv & 1) * 64;
-    const bool same = (rbase == cbase);
+    const int64_t rb0 = (int64_t)bi * GT, cb0 = (int64_t)bj * GT;
+    const int wr = (wv >> 1) * 64, wc = GT + (wv & 1) * 64;  // LDS row offsets of this wave's operands
 
     v4f acc[4][4];
 #pragma unroll
@@ -75,39 +97,40 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(const float *__restrict__
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    for (int64_t d = d0; d < d1; ++d) {
-        const float *Ad = A + d * stride;
-        const float *ra[4], *rb[4];
-        bool va[4], vb[4];
+    const int64_t spd = (n + GK - 1) / GK;  // stages per slice
+    const int64_t nst = (d1 - d0) * spd;
+    float4 pre[8];
+    gram_fetch(A + d0 * stride, m, n, ld, rb0, cb0, 0, pre);
+    gram_stash(lds, pre);
+    __syncthreads();
+    for (int64_t st = 0; st < nst; ++st) {
+        const float *cur = lds + (st & 1) * GBUF;
+        const bool more = st + 1 < nst;
+        if (more) {
+            const int64_t s1 = st + 1;
+            const int64_t d = d0 + s1 / spd;
+            gram_fetch(A + d * stride, m, n, ld, rb0, cb0, (s1 % spd) * GK, pre);
+        }
+        float a[4][8], b[4][8];
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-            const int64_t r = rbase + x * 16 + ii, c = cbase + x * 16 + ii;
-            va[x] = r < m;
-            vb[x] = c < m;
-            ra[x] = Ad + (va[x] ? r : 0) * ld;
-            rb[x] = Ad + (vb[x] ? c : 0) * ld;
+            const float *ra = cur + (wr + x * 16 + ii) * GLD + 4 * q;
+            const float *rc = cur + (wc + x * 16 + ii) * GLD + 4 * q;
+            const float4 a0 = *reinterpret_cast<const float4 *>(ra), a1 = *reinterpret_cast<const float4 *>(ra + 16);
+            const float4 b0 = *reinterpret_cast<const float4 *>(rc), b1 = *reinterpret_cast<const float4 *>(rc + 16);
+            a[x][0] = a0.x; a[x][1] = a0.y; a[x][2] = a0.z; a[x][3] = a0.w;
+            a[x][4] = a1.x; a[x][5] = a1.y; a[x][6] = a1.z; a[x][7] = a1.w;
+            b[x][0] = b0.x; b[x][1] = b0.y; b[x][2] = b0.z; b[x][3] = b0.w;
+            b[x][4] = b1.x; b[x][5] = b1.y; b[x][6] = b1.z; b[x][7] = b1.w;
         }
-        for (int64_t c0 = 0; c0 < n; c0 += 32) {
-            const bool fast = (c0 + 32 <= n);
-            float a[4][8], b[4][8];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) load_row8(ra[x], c0, q, n, fast, va[x], a[x]);
-            if (same) {
+        for (int u = 0; u < 8; ++u)
 #pragma unroll
-                for (int x = 0; x < 4; ++x)
+            for (int x = 0; x < 4; ++x)
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) b[x][u] = a[x][u];
-            } else {
-#pragma unroll
-                for (int x = 0; x < 4; ++x) load_row8(rb[x], c0, q, n, fast, vb[x], b[x]);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4_f32(a[x][u], b[y][u], acc[x][y]);
-        }
+                for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4_f32(a[x][u], b[y][u], acc[x][y]);
+        if (more) gram_stash(lds + ((st + 1) & 1) * GBUF, pre);
+        __syncthreads();
     }
     float *P = part + ((int64_t)chunk * T + t) * (GT * GT);
 #pragma unroll

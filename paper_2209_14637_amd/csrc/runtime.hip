@@ -101,9 +101,9 @@ tsk_status tsk_check_stack(tsk_ctx c, const tsk_stack *s, const char *name) {
     return tsk_check_dev(c, s->A, need, (nm + ".A").c_str());
 }
 
-void tsk_ev_begin(tsk_ctx c, hipEvent_t *a) {
+void tsk_ev_begin(tsk_ctx c, int cls, hipEvent_t *a) {
     *a = nullptr;
-    if (!c->timing) return;
+    if (!(c->timing >> cls & 1u)) return;
     if (c->pool.empty()) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return;
@@ -115,7 +115,7 @@ void tsk_ev_begin(tsk_ctx c, hipEvent_t *a) {
 }
 
 void tsk_ev_end(tsk_ctx c, int cls, hipEvent_t a) {
-    if (!c->timing || !a) return;
+    if (!a) return;
     hipEvent_t b;
     if (c->pool.empty()) {
         if (hipEventCreate(&b) != hipSuccess) return;
@@ -282,9 +282,9 @@ tsk_status tsk_set_eig_params(tsk_ctx c, int32_t block, int32_t max_iter, double
     return TSK_OK;
 }
 
-tsk_status tsk_timing_enable(tsk_ctx c, int32_t on) {
+tsk_status tsk_timing_enable(tsk_ctx c, int32_t mask) {
     if (!c) return TSK_E_ARG;
-    c->timing = on != 0;
+    c->timing = (uint32_t)mask & ((1u << TSK_KERNEL_COUNT) - 1u);
     return TSK_OK;
 }
 

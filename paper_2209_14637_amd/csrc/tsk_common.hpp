@@ -48,78 +48,137 @@ __device__ __forceinline__ double block_sum_f64(double v, double *scratch4) {
 // ---------------------------------------------------------------------------
 // Cyclic Jacobi eigensolver for a symmetric p x p FP64 matrix held in LDS,
 // run by one whole workgroup.  Parallel (round-robin) ordering: each round
-// rotates p/2 disjoint index pairs, p-1 rounds per sweep, so the rotations of
-// a round commute and are applied together.  On exit H is (numerically)
-// diagonal and W holds the eigenvectors as columns (H_in = W diag W^T).
-// p must be even (pad with a zero row/column); ld is the LDS row stride.
-// rot: LDS scratch of 4*(p/2) entries.
+// rotates p/2 disjoint index pairs, p-1 rounds per sweep; the pairing of
+// every round is tabulated once in LDS.  Because the pairs are disjoint,
+// H' = J^T H J splits into independent 2x2 blocks J_P^T H_PQ J_Q.  A round
+// is: the p/2 rotations (one thread each) into LDS, barrier, every 2x2 block
+// of H' written into Hn and W <- W J, barrier, swap H and Hn.  The Frobenius
+// norm is invariant, so the stopping test needs only the off-diagonal mass.
+// On exit the returned buffer is (numerically) diagonal and W holds the
+// eigenvectors as columns (H_in = W diag W^T).  p must be even (pad with a
+// zero row/column), p <= 64; ld is the row stride of H, Hn and W.
+// LDS scratch: rot (p doubles), ptab ((p-1)*(p/2) ints).
 // ---------------------------------------------------------------------------
-__device__ inline void jacobi_eig_lds(double *H, double *W, int p, int ld, double *rot,
-                                      int *pairs, int max_sweeps, double *red4) {
-    const int tid = threadIdx.x, nth = blockDim.x;
-    for (int e = tid; e < p * p; e += nth) {
-        int i = e / p, j = e % p;
-        W[i * ld + j] = (i == j) ? 1.0 : 0.0;
+// Reciprocal and reciprocal square root from the hardware FP64 estimates
+// refined by Newton-Raphson steps (each step squares the relative error).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = r * fma(-x, r, 2.0);
+    r = r * fma(-x, r, 2.0);
+    return r;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y;
+}
+
+// Rotation (c, s) that zeroes H[a][b] in J^T H J.  t only has to be accurate
+// enough for the sweep to converge; c = (1+t^2)^-1/2 and s = t c are what
+// make the rotation orthogonal, so c is refined to full precision.
+__device__ __forceinline__ void jacobi_rot(const double *H, int ld, int a, int b, double &c, double &s) {
+    const double haa = H[a * ld + a], hbb = H[b * ld + b], hab = H[a * ld + b];
+    c = 1.0;
+    s = 0.0;
+    if (hab != 0.0 && fabs(hab) > 1e-18 * sqrt(fabs(haa * hbb))) {
+        const double tau = (hbb - haa) * rcp_nr(2.0 * hab);
+        const double q = 1.0 + tau * tau;
+        const double root = q * rsq_nr(q);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + root);
+        c = rsq_nr(1.0 + t * t);
+        s = t * c;
     }
-    __syncthreads();
+}
+
+__device__ inline double *jacobi_eig_lds(double *H, double *Hn, double *W, int p, int ld, double *rot, int *ptab,
+                                         int max_sweeps, double *red4) {
+    const int tid = threadIdx.x, nth = blockDim.x;
     const int half = p / 2;
+    // pairing table: round r, slot t -> (a, b), a < b; player 0 fixed, the
+    // others rotated by r
+    for (int e = tid; e < (p - 1) * half; e += nth) {
+        const int r = e / half, t = e % half;
+        const int ia = (t == 0) ? 0 : 1 + ((t - 1 + r) % (p - 1));
+        const int ib = 1 + ((p - 2 - t + r) % (p - 1));
+        ptab[e] = ia < ib ? (ia | (ib << 8)) : (ib | (ia << 8));
+    }
+    double tot = 0.0;
+    for (int e = tid; e < p * p; e += nth) {
+        const int i = e / p, j = e % p;
+        W[i * ld + j] = (i == j) ? 1.0 : 0.0;
+        const double h = H[i * ld + j];
+        tot += h * h;
+    }
+    tot = block_sum_f64(tot, red4);  // includes a barrier: ptab and W ready
+    // this thread's 2x2 blocks (P, Q) and W items (row i, pair Q): fixed
+    constexpr int MAXB = 4;  // (64/2)^2 / 256 blocks per thread at most
+    int bP[MAXB], bQ[MAXB], wI[MAXB * 2], wQ[MAXB * 2];
+#pragma unroll
+    for (int u = 0; u < MAXB; ++u) {
+        const int e = tid + nth * u;
+        bP[u] = e < half * half ? e / half : -1;
+        bQ[u] = e < half * half ? e % half : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 2 * MAXB; ++u) {
+        const int e = tid + nth * u;
+        wI[u] = e < p * half ? e / half : -1;
+        wQ[u] = e < p * half ? e % half : 0;
+    }
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        // convergence: off-diagonal mass vs total mass
-        double off = 0.0, tot = 0.0;
+        double off = 0.0;
         for (int e = tid; e < p * p; e += nth) {
-            int i = e / p, j = e % p;
-            double h = H[i * ld + j];
-            tot += h * h;
+            const int i = e / p, j = e % p;
+            const double h = H[i * ld + j];
             if (i != j) off += h * h;
         }
         off = block_sum_f64(off, red4);
-        tot = block_sum_f64(tot, red4);
         if (off <= 1e-30 * tot || tot == 0.0) break;
         for (int round = 0; round < p - 1; ++round) {
+            const int *pr = ptab + round * half;
             if (tid < half) {
-                // player list: 0 fixed, the rest rotated by `round`
-                int ia = (tid == 0) ? 0 : 1 + ((tid - 1 + round) % (p - 1));
-                int ib = 1 + ((p - 2 - tid + round) % (p - 1));
-                int a = ia < ib ? ia : ib, b = ia < ib ? ib : ia;
-                double haa = H[a * ld + a], hbb = H[b * ld + b], hab = H[a * ld + b];
-                double c = 1.0, s = 0.0;
-                if (hab != 0.0 && fabs(hab) > 1e-18 * sqrt(fabs(haa * hbb))) {
-                    double tau = (hbb - haa) / (2.0 * hab);
-                    double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
-                }
-                rot[2 * tid] = c;
-                rot[2 * tid + 1] = s;
-                pairs[2 * tid] = a;
-                pairs[2 * tid + 1] = b;
+                const int ab = pr[tid];
+                double cc, ss;
+                jacobi_rot(H, ld, ab & 255, ab >> 8, cc, ss);
+                rot[2 * tid] = cc;
+                rot[2 * tid + 1] = ss;
             }
             __syncthreads();
-            // H <- H J and W <- W J (columns a, b)
-            for (int e = tid; e < p * half; e += nth) {
-                int i = e / half, t = e % half;
-                int a = pairs[2 * t], b = pairs[2 * t + 1];
-                double c = rot[2 * t], s = rot[2 * t + 1];
-                double ha = H[i * ld + a], hb = H[i * ld + b];
-                H[i * ld + a] = c * ha - s * hb;
-                H[i * ld + b] = s * ha + c * hb;
-                double wa = W[i * ld + a], wb = W[i * ld + b];
-                W[i * ld + a] = c * wa - s * wb;
-                W[i * ld + b] = s * wa + c * wb;
+#pragma unroll
+            for (int u = 0; u < MAXB; ++u) {
+                if (bP[u] < 0) continue;
+                const int ab = pr[bP[u]], xy = pr[bQ[u]];
+                const int a = ab & 255, b = ab >> 8, x = xy & 255, y = xy >> 8;
+                const double cp = rot[2 * bP[u]], sp = rot[2 * bP[u] + 1];
+                const double cq = rot[2 * bQ[u]], sq = rot[2 * bQ[u] + 1];
+                const double hax = H[a * ld + x], hay = H[a * ld + y], hbx = H[b * ld + x], hby = H[b * ld + y];
+                // columns: x' = cq x - sq y, y' = sq x + cq y
+                const double tax = cq * hax - sq * hay, tay = sq * hax + cq * hay;
+                const double tbx = cq * hbx - sq * hby, tby = sq * hbx + cq * hby;
+                // rows: a' = cp a - sp b, b' = sp a + cp b
+                Hn[a * ld + x] = cp * tax - sp * tbx;
+                Hn[a * ld + y] = cp * tay - sp * tby;
+                Hn[b * ld + x] = sp * tax + cp * tbx;
+                Hn[b * ld + y] = sp * tay + cp * tby;
+            }
+#pragma unroll
+            for (int u = 0; u < 2 * MAXB; ++u) {
+                if (wI[u] < 0) continue;
+                const int xy = pr[wQ[u]], i = wI[u];
+                const int x = xy & 255, y = xy >> 8;
+                const double cq = rot[2 * wQ[u]], sq = rot[2 * wQ[u] + 1];
+                const double wx = W[i * ld + x], wy = W[i * ld + y];
+                W[i * ld + x] = cq * wx - sq * wy;
+                W[i * ld + y] = sq * wx + cq * wy;
             }
             __syncthreads();
-            // H <- J^T H (rows a, b)
-            for (int e = tid; e < p * half; e += nth) {
-                int j = e / half, t = e % half;
-                int a = pairs[2 * t], b = pairs[2 * t + 1];
-                double c = rot[2 * t], s = rot[2 * t + 1];
-                double ha = H[a * ld + j], hb = H[b * ld + j];
-                H[a * ld + j] = c * ha - s * hb;
-                H[b * ld + j] = s * ha + c * hb;
-            }
-            __syncthreads();
+            double *t = H;
+            H = Hn;
+            Hn = t;
         }
     }
+    return H;
 }
 
 // Stable descending order of the diagonal of H (p entries) into perm; run by
@@ -136,6 +195,138 @@ __device__ inline void sort_diag_desc(const double *H, int p, int ld, int *perm)
         }
         perm[j + 1] = v;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Blocked inverse of an upper-triangular pp x pp matrix R (LDS) into X (LDS),
+// pp a multiple of 8: 8x8 diagonal blocks inverted by one thread each, then
+// neighbouring blocks merged level by level with X12 = -X11 R12 X22.  Zero
+// diagonal entries (dead pivots) give zero rows/columns in X.  T: LDS scratch
+// of pp*pp doubles.
+// ---------------------------------------------------------------------------
+__device__ inline void upper_tri_inverse(const double *R, double *X, int pp, double *T) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < pp * pp; e += blockDim.x) X[e] = 0.0;
+    __syncthreads();
+    // reciprocal diagonal, kept on the diagonal of X until the leaves use it
+    for (int i = tid; i < pp; i += blockDim.x) {
+        const double rii = R[i * pp + i];
+        X[i * pp + i] = rii == 0.0 ? 0.0 : 1.0 / rii;
+    }
+    __syncthreads();
+    // 8x8 diagonal blocks: one thread per (block, column); back substitution.
+    // All reads of X's reciprocal diagonal happen before the barrier, all
+    // writes after it; the barriers sit outside the branches.
+    const int nblk = pp / 8;
+    const bool act = tid < nblk * 8;
+    const int o = (tid >> 3) * 8, j = tid & 7;
+    double col[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) col[i] = 0.0;
+    if (act) {
+        const double dj = X[(o + j) * pp + (o + j)];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) col[i] = (i == j) ? dj : 0.0;
+#pragma unroll
+        for (int i = 7; i >= 0; --i) {
+            if (i < j) {
+                double s = 0.0;
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (t > i && t <= j) s += R[(o + i) * pp + (o + t)] * col[t];
+                col[i] = -s * X[(o + i) * pp + (o + i)];
+            }
+        }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) X[(o + i) * pp + (o + j)] = (i <= j) ? col[i] : 0.0;
+    }
+    __syncthreads();
+    for (int s = 8; s < pp; s *= 2) {
+        const int ngroups = (pp + 2 * s - 1) / (2 * s);
+        for (int e = tid; e < ngroups * s * s; e += blockDim.x) {
+            const int g = e / (s * s), a = (e / s) % s, b = e % s;
+            const int o = g * 2 * s, s2 = (pp - o - s < s) ? pp - o - s : s;
+            if (s2 <= 0 || b >= s2) continue;
+            double acc = 0.0;
+            for (int cidx = 0; cidx <= b; ++cidx)
+                acc += R[(o + a) * pp + (o + s + cidx)] * X[(o + s + cidx) * pp + (o + s + b)];
+            T[e] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < ngroups * s * s; e += blockDim.x) {
+            const int g = e / (s * s), a = (e / s) % s, b = e % s;
+            const int o = g * 2 * s, s2 = (pp - o - s < s) ? pp - o - s : s;
+            if (s2 <= 0 || b >= s2) continue;
+            double acc = 0.0;
+            for (int cidx = a; cidx < s; ++cidx) acc += X[(o + a) * pp + (o + cidx)] * T[g * s * s + cidx * s + b];
+            X[(o + a) * pp + (o + s + b)] = -acc;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky C = R^T R of a symmetric positive semi-definite pp x pp matrix in
+// LDS (row stride ld; only the upper triangle is read, C is destroyed), one
+// barrier per column, then X = R^-1 (LDS, stride pp).  A pivot <=
+// tol_rel * max(diag) marks the index dead: its row of R and its row and
+// column of X are zero.  R, X: LDS pp*pp each; dead: LDS pp ints.  Returns (in
+// every thread) the number of dead indices below `live`.
+// ---------------------------------------------------------------------------
+__device__ inline int chol_factor_inverse(double *C, int ld, int pp, double tol_rel, double *R, double *X, int *dead,
+                                          int live = 1 << 30) {
+    __shared__ double s_maxd;
+    __shared__ int s_nd;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        double mx = 0.0;
+        for (int j = 0; j < pp; ++j) mx = fmax(mx, C[j * ld + j]);
+        s_maxd = mx;
+        s_nd = 0;
+    }
+    __syncthreads();
+    const double thr = tol_rel * s_maxd;
+    // each thread owns the upper-triangle entries e = tid + 256 u of the
+    // pp x pp matrix (u < 16 covers pp <= 64)
+    int ea[16], eb[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = tid + (int)blockDim.x * u;
+        const int a = e / pp, b = e % pp;
+        const bool own = e < pp * pp && a <= b;
+        ea[u] = own ? a : -1;
+        eb[u] = own ? b : 0;
+    }
+    for (int j = 0; j < pp; ++j) {
+        const double piv = C[j * ld + j];
+        const bool dj = !(piv > thr) || !(piv > 0.0);
+        if (tid == 0) {
+            dead[j] = dj;
+            if (dj && j < live) ++s_nd;
+        }
+        if (!dj) {
+            const double inv = 1.0 / piv;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                if (ea[u] > j) {
+                    const int a = ea[u], b = eb[u];
+                    C[a * ld + b] -= C[j * ld + a] * C[j * ld + b] * inv;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < pp * pp; e += blockDim.x) {
+        const int a = e / pp, b = e % pp;
+        R[e] = (b >= a && !dead[a]) ? C[a * ld + b] / sqrt(C[a * ld + a]) : 0.0;
+    }
+    __syncthreads();
+    // C is free now: scratch of the inverse (needs ld >= pp)
+    upper_tri_inverse(R, X, pp, C);
+    return s_nd;
 }
 
 // ---------------------------------------------------------------------------
@@ -165,7 +356,7 @@ struct tsk_ctx_s {
     int eig_block = 0, eig_max_iter = 300, eig_check = 4;
     double eig_tol = 1e-7;
     // timing
-    bool timing = false;
+    uint32_t timing = 0;  // bit i: bracket launches of kernel class i with events
     std::vector<TskEvent> pending;
     std::vector<hipEvent_t> pool;
     int64_t launches[TSK_KERNEL_COUNT] = {};
@@ -178,14 +369,14 @@ tsk_status tsk_hip(tsk_ctx c, hipError_t e, const char *what);
 tsk_status tsk_grow(tsk_ctx c, TskBuf &b, size_t bytes);
 tsk_status tsk_check_dev(tsk_ctx c, const void *p, size_t bytes, const char *name);
 tsk_status tsk_check_stack(tsk_ctx c, const tsk_stack *s, const char *name);
-void tsk_ev_begin(tsk_ctx c, hipEvent_t *a);
+void tsk_ev_begin(tsk_ctx c, int cls, hipEvent_t *a);
 void tsk_ev_end(tsk_ctx c, int cls, hipEvent_t a);
 
 // Launch wrapper: optional event bracket + launch error check.
 #define TSK_LAUNCH(ctx, cls, ...)                                           \
     do {                                                                    \
         hipEvent_t _ev_a = nullptr;                                         \
-        tsk_ev_begin((ctx), &_ev_a);                                        \
+        tsk_ev_begin((ctx), (cls), &_ev_a);                                 \
         __VA_ARGS__;                                                        \
         hipError_t _e = hipGetLastError();                                  \
         tsk_ev_end((ctx), (cls), _ev_a);                                    \

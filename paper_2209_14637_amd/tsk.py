@@ -187,8 +187,18 @@ class Context:
     def set_eig_params(self, block: int = 0, max_iter: int = 0, tol: float = 0.0, check: int = 0):
         self._check(self.lib.tsk_set_eig_params(self.h, block, max_iter, tol, check))
 
-    def timing(self, on: bool = True):
-        self._check(self.lib.tsk_timing_enable(self.h, 1 if on else 0))
+    def timing(self, on=True):
+        """True: time every kernel class; False: off; or an iterable of class
+        names (see KERNELS) to time only those."""
+        if on is True:
+            mask = -1
+        elif not on:
+            mask = 0
+        else:
+            mask = 0
+            for name in on:
+                mask |= 1 << KERNELS.index(name)
+        self._check(self.lib.tsk_timing_enable(self.h, mask))
 
     def timing_read(self, reset: bool = True) -> dict:
         n = len(KERNELS)

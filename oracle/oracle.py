@@ -58,6 +58,9 @@ def lib():
             "tsko_error_f32": [_P, _I, _I, _I, _P, _P, _I, _P],
             "tsko_opt_f32": [_P, _I, _I, _I, _I, _P, _P],
             "tsko_threads": [],
+            "tsko_round_bf16": [_P, _I, _P],
+            "tsko_round_e4m3": [_P, _I, ctypes.c_float, _P],
+            "tsko_e4m3_scale": [_P, _I, _P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -216,3 +219,28 @@ def opt_tail(A: np.ndarray, r: int):
     t, f = np.empty(cnt), np.empty(cnt)
     _check(lib().tsko_opt_f32(_p(A), cnt, m, n, r, _p(t), _p(f)), "opt")
     return t, f
+
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Values of x rounded to bfloat16 (nearest, ties to even), as float32."""
+    x = _f32(x)
+    y = np.empty_like(x)
+    _check(lib().tsko_round_bf16(_p(x), x.size, _p(y)), "round_bf16")
+    return y
+
+
+def round_e4m3(x: np.ndarray, scale: float = 1.0) -> np.ndarray:
+    """Values of x * scale rounded to e4m3 (nearest, ties to even, saturating
+    at 448), as float32."""
+    x = _f32(x)
+    y = np.empty_like(x)
+    _check(lib().tsko_round_e4m3(_p(x), x.size, ctypes.c_float(scale), _p(y)), "round_e4m3")
+    return y
+
+
+def e4m3_scale(x: np.ndarray) -> float:
+    """Power-of-two scale 2^floor(log2(448 / max|x|)) of one matrix."""
+    x = _f32(x)
+    s = np.empty(1, dtype=np.float32)
+    _check(lib().tsko_e4m3_scale(_p(x), x.size, _p(s)), "e4m3_scale")
+    return float(s[0])

@@ -614,6 +614,59 @@ int tsko_error_f32(const float *A, int64_t count, int64_t m, int64_t n, const do
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Number formats of the reduced-precision forms (no precision is fixed by  */
+/* the paper).  Written from the format definitions: the value is scaled    */
+/* by its quantum (a power of two, so the division is exact), rounded to an */
+/* integer with ties to even (rint in the default rounding mode) and scaled */
+/* back.  No bit manipulation.                                               */
+/* ------------------------------------------------------------------------ */
+static double round_to_format(double x, int p, int emin, double maxfin, int saturate) {
+    if (isnan(x) || x == 0.0) return x;
+    if (isinf(x)) return saturate ? copysign(maxfin, x) : x;
+    int e;
+    frexp(x, &e);              /* |x| = f 2^e, 1/2 <= f < 1: leading bit weighs 2^(e-1) */
+    int lead = e - 1;
+    if (lead < emin) lead = emin;  /* subnormal range: fixed quantum */
+    const double q = ldexp(1.0, lead - (p - 1 - MUT(14)));
+    const double t = x / q;
+    const double y = (MUT(13) ? round(t) : rint(t)) * q;
+    if (fabs(y) > maxfin) return saturate ? copysign(maxfin, x) : copysign(INFINITY, x);
+    return y;
+}
+
+int tsko_round_bf16(const float *x, int64_t n, float *y) {
+    if ((!x || !y) && n > 0) return -1;
+    const double maxfin = ldexp(2.0 - ldexp(1.0, -7), 127);
+    for (int64_t i = 0; i < n; i++) y[i] = (float)round_to_format((double)x[i], 8, -126, maxfin, 0);
+    return 0;
+}
+
+int tsko_round_e4m3(const float *x, int64_t n, float scale, float *y) {
+    if ((!x || !y) && n > 0) return -1;
+    for (int64_t i = 0; i < n; i++)
+        y[i] = (float)round_to_format((double)x[i] * (double)scale, 4, -6, 448.0, 1);
+    return 0;
+}
+
+int tsko_e4m3_scale(const float *x, int64_t n, float *scale) {
+    if ((!x && n > 0) || !scale) return -1;
+    double amax = 0.0;
+    for (int64_t i = 0; i < n; i++)
+        if (fabs((double)x[i]) > amax) amax = fabs((double)x[i]);
+    if (amax == 0.0) {
+        *scale = 1.0f;
+        return 0;
+    }
+    int e;
+    frexp(448.0 / amax, &e);   /* 448/amax = f 2^e, 1/2 <= f < 1: floor(log2) = e - 1 */
+    int j = e - 1 + MUT(15);
+    if (j > 127) j = 127;
+    if (j < -126) j = -126;
+    *scale = (float)ldexp(1.0, j);
+    return 0;
+}
+
 int tsko_opt_f32(const float *A, int64_t count, int64_t m, int64_t n, int64_t r,
                  double *tail, double *fro) {
     if (!A || !tail || count < 0 || m <= 0 || n <= 0 || r < 0) return -1;

@@ -99,6 +99,25 @@ int tsko_error_f32(const float *A, int64_t count, int64_t m, int64_t n, const do
 int tsko_opt_f32(const float *A, int64_t count, int64_t m, int64_t n, int64_t r,
                  double *tail, double *fro);
 
+/* Storage formats of the reduced-precision forms.  The paper fixes no number
+ * format; the reading used is round to nearest with ties to the even
+ * significand, into
+ *   bf16 : 8 significant bits, binary32 exponent range (smallest normal
+ *          2^-126, subnormals below it), overflow to +-infinity;
+ *   e4m3 : 4 significant bits, smallest normal 2^-6 (subnormal quantum 2^-9),
+ *          largest finite 448, saturating to +-448, no infinity.
+ * y[i] is the rounded value of x[i] (for e4m3: of x[i] * scale) as a float.
+ * NaN stays NaN.  Pinned by exhaustive nearest-value search over every code
+ * of the format (tests). */
+int tsko_round_bf16(const float *x, int64_t n, float *y);
+int tsko_round_e4m3(const float *x, int64_t n, float scale, float *y);
+
+/* Per-matrix power-of-two scale of the e4m3 form: s = 2^j with
+ * j = floor(log2(448 / amax)), amax = max |x[i]| over the n values, clamped
+ * to -126 <= j <= 127; amax == 0 gives s = 1.  So amax * s <= 448 and,
+ * unless clamped, 2 * amax * s > 448. */
+int tsko_e4m3_scale(const float *x, int64_t n, float *scale);
+
 /* Number of OpenMP threads the library will use. */
 int tsko_threads(void);
 

@@ -25,6 +25,9 @@ MUTANTS = {
     10: "rank-(r+1) output instead of rank-r truncation",
     11: "sketch product reads S as a transposed (m x k) operand",
     12: "QR keeps |R_jj| but not the reflector's sign",
+    13: "format rounding breaks ties away from zero",
+    14: "format rounding keeps one significant bit too few",
+    15: "e4m3 scale one power of two too large",
 }
 
 
@@ -33,6 +36,7 @@ def test_pins_catch_mutant(tmp_path, mutant):
     so = oracle.build(force=True, out=str(tmp_path / f"libtsko_m{mutant}.so"), mutant=mutant)
     env = dict(os.environ, TSKO_LIB=so, OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle.py")],
+                        os.path.join(ROOT, "tests", "test_oracle.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_formats.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"pins missed mutant {mutant}: {MUTANTS[mutant]}\n{r.stdout[-2000:]}"

@@ -63,12 +63,16 @@ typedef struct tsk_ctx_s *tsk_ctx;
 /* A stack of `count` row-major m x n slices (the training tensor of
  * Section 3.1, or a batch of test matrices).  Element (i, j) of slice d is at
  * A[d * stride + i * ld + j].  Requirements: m, n, count >= 1, ld >= n,
- * stride >= m * ld, A 16-byte aligned, ld and stride multiples of 4
- * elements.  dtype: TSK_F32 in this version.  scale must be NULL. */
+ * stride >= m * ld, A 16-byte aligned, ld and stride multiples of 16 bytes
+ * (4 FP32, 8 bf16 or 16 e4m3 elements).
+ * dtype: TSK_F32, TSK_BF16 (bfloat16 bits), or TSK_F8E4M3 (OCP e4m3 bytes,
+ * largest finite 448); scale: NULL except for TSK_F8E4M3, where it is a
+ * device array of `count` floats and slice d holds A_d * scale[d]
+ * (tsk_stage writes such stacks). */
 typedef struct {
     const void *A;     /* device */
     int32_t dtype;     /* tsk_dtype of the stored elements */
-    const float *scale;/* reserved (per-slice scale of a scaled format); NULL */
+    const float *scale;/* device, count values, TSK_F8E4M3 only; else NULL */
     int64_t m, n, count;
     int64_t ld, stride;/* in elements */
 } tsk_stack;
@@ -83,10 +87,27 @@ tsk_status tsk_set_stream(tsk_ctx ctx, void *hip_stream);
 /* Message of the last failure on this context ("" when none). */
 const char *tsk_last_error(tsk_ctx ctx);
 
+/* Staging into a reduced-precision storage format (the precision forms; the
+ * paper fixes no number format).  src: an FP32 stack.  dtype: TSK_BF16
+ * (round to nearest even) or TSK_F8E4M3 (slice d is multiplied by the
+ * power of two s_d = 2^floor(log2(448 / max|A_d|)), clamped to
+ * [2^-126, 2^127], 1 for an all-zero slice, then rounded to nearest even;
+ * no value saturates).  dst: device, element (i, j) of slice d at
+ * dst[d * stride + i * ld + j] in the new format; ld >= n, stride >= m * ld,
+ * both multiples of 16 bytes, dst 16-byte aligned; columns n..ld-1 are not
+ * written.  scale: device, count floats (written: s_d), required for
+ * TSK_F8E4M3, must be NULL for TSK_BF16.  norm2: device, count doubles,
+ * nullable: ||A_d||_F^2 of the FP32 source in FP64.  Enqueue only. */
+tsk_status tsk_stage(tsk_ctx ctx, const tsk_stack *src, int32_t dtype, void *dst, int64_t ld,
+                     int64_t stride, float *scale, double *norm2);
+
 /* Mode-1 Gram (Section 3.1, eqs. 3.2-3.3; tensor basics in Section 2):
  *     G = A_(1) A_(1)^T = sum_{d<count} A_d A_d^T,   A_(1) = [A_1|...|A_N].
- * G: device, m x m FP64, full symmetric matrix.  compute: TSK_F32 (FP32
- * products with FP32 accumulation inside a slice chunk, FP64 across chunks).
+ * G: device, m x m FP64, full symmetric matrix.  Products accumulate in FP32
+ * inside a chunk of slices and in FP64 across chunks.  compute:
+ *   TSK_F32  : FP32 stack, FP32 products;
+ *   TSK_BF16 : bf16 products, from a TSK_BF16 stack as stored or from an
+ *              FP32 stack rounded to bf16 (nearest even) as it is loaded.
  * Enqueue only. */
 tsk_status tsk_gram(tsk_ctx ctx, const tsk_stack *train, int32_t compute, double *G);
 
@@ -104,10 +125,10 @@ tsk_status tsk_gram(tsk_ctx ctx, const tsk_stack *train, int32_t compute, double
 tsk_status tsk_eig_topk(tsk_ctx ctx, const double *G, int64_t m, int32_t k,
                         float *S, double *lambda, int32_t *iters);
 
-/* Training, Algorithm 2 lines 1-2: tsk_gram followed by tsk_eig_topk on the
- * context's workspace.  S: device FP32 k x m.  lambda: host k+1.
- * iters: host, nullable.  Requires 1 <= k < m, k <= 52.  Synchronises the
- * stream. */
+/* Training, Algorithm 2 lines 1-2: tsk_gram (same stack/compute rules)
+ * followed by tsk_eig_topk on the context's workspace.  S: device FP32
+ * k x m.  lambda: host k+1.  iters: host, nullable.  Requires 1 <= k < m,
+ * k <= 52.  Synchronises the stream. */
 tsk_status tsk_train(tsk_ctx ctx, const tsk_stack *train, int32_t k, int32_t compute,
                      float *S, double *lambda, int32_t *iters);
 
@@ -125,15 +146,22 @@ tsk_status tsk_train(tsk_ctx ctx, const tsk_stack *train, int32_t k, int32_t com
  *      relerr_d = sqrt(max(0, ||A_d||^2 - sum_{i<=r} sigma_i^2)) / ||A_d||
  * (the Pythagorean identity of the proof of Theorem 1), flags (count int32,
  * nullable, TSK_FLAG_*).  Requires 1 <= r < k <= min(m, n), k <= 64.
- * compute: TSK_F32.  Enqueue only. */
+ * compute must match the stack's dtype:
+ *   TSK_F32  : FP32 products S A_d and A_d V_d;
+ *   TSK_BF16 : bf16 stack; products with bf16 A_d and S, V_d each split
+ *              into a bf16 pair (hi + lo), so the only rounding beyond FP32
+ *              is that of the stored A_d; ||A_d|| is that of the stored
+ *              values.
+ * The small factorizations (CholeskyQR2, C^T C eigenproblem) are FP64 in
+ * every form.  Enqueue only. */
 tsk_status tsk_apply(tsk_ctx ctx, const float *S, int32_t k, const tsk_stack *test, int32_t r,
                      int32_t compute, float *L, float *R, float *sigma, double *relerr,
                      int32_t *flags);
 
 /* Explicit relative error ||A_d - L_d R_d^T||_F / ||A_d||_F for every slice
- * (the quantity whose rank-r minimum is problem 1.1).  L, R: device FP32 with
- * the layout tsk_apply writes.  relerr: device FP64, count values.  r >= 1.
- * Enqueue only. */
+ * (the quantity whose rank-r minimum is problem 1.1).  A: an FP32 stack.
+ * L, R: device FP32 with the layout tsk_apply writes.  relerr: device FP64,
+ * count values.  r >= 1.  Enqueue only. */
 tsk_status tsk_error(tsk_ctx ctx, const tsk_stack *A, const float *L, const float *R,
                      int32_t r, double *relerr);
 
@@ -162,6 +190,7 @@ enum {
     TSK_KERNEL_PROJECT,      /* C_d = A_d V_d                 */
     TSK_KERNEL_FINISH,       /* small eigenproblem + outputs  */
     TSK_KERNEL_ERROR,        /* explicit residual             */
+    TSK_KERNEL_STAGE,        /* format conversion (tsk_stage) */
     TSK_KERNEL_COUNT
 };
 tsk_status tsk_timing_enable(tsk_ctx ctx, int32_t mask);

@@ -188,7 +188,7 @@ __device__ inline void row_gram(const float *__restrict__ X, int64_t ldx, int k,
 // columns n..ldv-1 are written as zero.  Rf: Rinv (KP x KP, FP32, LDS).
 template <int KP>
 __device__ inline void apply_rinv_t(const float *__restrict__ src, float *__restrict__ dst, int64_t ldv, int k,
-                                    int64_t n, const float *Rf) {
+                                    int64_t n, const float *Rf, uint16_t *__restrict__ vb = nullptr) {
     for (int64_t c = threadIdx.x; c < ldv; c += blockDim.x) {
         float col[KP];
 #pragma unroll
@@ -201,6 +201,13 @@ __device__ inline void apply_rinv_t(const float *__restrict__ src, float *__rest
 #pragma unroll
             for (int t = 0; t < KP; ++t) s += Rf[t * KP + i] * col[t];
             dst[i * ldv + c] = s;
+            if (vb) {
+                // bf16 pair: hi = RNE(s), lo = RNE(s - hi) (s - hi is exact)
+                const unsigned h = pack_bf16(s, 0.f) & 0xffffu;
+                const unsigned l = pack_bf16(s - bf16_lo(h), 0.f) & 0xffffu;
+                vb[i * ldv + c] = (uint16_t)h;
+                vb[(KP + i) * ldv + c] = (uint16_t)l;
+            }
         }
     }
 }
@@ -214,7 +221,7 @@ __device__ inline void apply_rinv_t(const float *__restrict__ src, float *__rest
 template <int KP>
 __global__ __launch_bounds__(256) void cholqr2_kernel(const float *__restrict__ B, int64_t ldv,
                                                       float *__restrict__ Vt, int k, int64_t n,
-                                                      int *__restrict__ qflag) {
+                                                      int *__restrict__ qflag, uint16_t *__restrict__ Vb) {
     // C | R | X (KP*KP doubles each); the Gram's slice scratch (4096 doubles)
     // sits after C and is dead once C is assembled
     constexpr int SCR = (3 * KP * KP > KP * KP + 4096) ? 3 * KP * KP : KP * KP + 4096;
@@ -235,7 +242,7 @@ __global__ __launch_bounds__(256) void cholqr2_kernel(const float *__restrict__ 
         if (pass == 0) nd1 = nd;
         for (int e = threadIdx.x; e < KP * KP; e += 256) Rf[e] = (float)X[e];
         __syncthreads();
-        apply_rinv_t<KP>(src, Vd, ldv, k, n, Rf);
+        apply_rinv_t<KP>(src, Vd, ldv, k, n, Rf, (pass == 1 && Vb) ? Vb + d * 2 * KP * ldv : nullptr);
         __syncthreads();
     }
     if (threadIdx.x == 0) qflag[d] = nd1 > 0 ? TSK_FLAG_RANKDEF : 0;
@@ -300,6 +307,190 @@ __global__ __launch_bounds__(64) void project_f32_kernel(const float *__restrict
     float *Cd = C + d * m * kp;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = r0 + a * 16 + 4 * q + r;
+            if (row < m) {
+#pragma unroll
+                for (int b = 0; b < NT; ++b) Cd[row * kp + b * 16 + ii] = acc[a][b][r];
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// bf16 form.  A_d is stored in bf16; S and V_d are each split into a bf16
+// pair (hi + lo), two MFMAs per product, so the products carry about 16
+// significant bits of S and V and the only extra rounding is that of A_d.
+// ---------------------------------------------------------------------------
+constexpr int SKB_PANEL = 128;  // columns per sketch wave (16 lanes x 8)
+constexpr int PJB_ROWS = 128;   // rows per project wave (8 row tiles)
+
+// Sb = [S_hi; S_lo], each kp x mp bf16 with zero padding (rows >= k,
+// columns >= m).
+__global__ void prep_sketch_bf16_kernel(const float *__restrict__ S, int k, int kp, int64_t m, int64_t mp,
+                                        uint16_t *__restrict__ Sb) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)kp * mp) return;
+    const int s = (int)(e / mp);
+    const int64_t i = e % mp;
+    const float x = (s < k && i < m) ? S[(int64_t)s * m + i] : 0.f;
+    const unsigned h = pack_bf16(x, 0.f) & 0xffffu;
+    const unsigned l = pack_bf16(x - bf16_lo(h), 0.f) & 0xffffu;
+    Sb[e] = (uint16_t)h;
+    Sb[(int64_t)kp * mp + e] = (uint16_t)l;
+}
+
+__device__ __forceinline__ v4u load_bf16x8(const uint16_t *p, int64_t c, int64_t n) {
+    if (c + 7 < n) return *reinterpret_cast<const v4u *>(p);
+    unsigned w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if (c + e < n) w[e >> 1] |= (unsigned)p[e] << (16 * (e & 1));
+    return v4u{w[0], w[1], w[2], w[3]};
+}
+
+// B_d = S A_d.  The contraction runs over the rows of A_d, but an MFMA lane
+// needs 8 consecutive contraction indices: lane (q, i) loads 16 bytes (8
+// columns) from each of the 8 rows r0 + 8q + e and transposes the 8 x 8
+// block in registers, so that MFMA u (u = 0..7) takes column c0 + 8i + u
+// of those 8 rows.  One wave covers 128 columns, 32 rows per step; the next
+// step's rows are in flight during the MFMAs.  ||A_d||^2 is accumulated from
+// the same registers (FP32 per step, FP64 across steps).
+template <int MT>
+__global__ __launch_bounds__(64) void sketch_bf16_kernel(const uint16_t *__restrict__ A, int64_t m, int64_t n,
+                                                          int64_t ld, int64_t stride, const uint16_t *__restrict__ Sb,
+                                                          int64_t mp, float *__restrict__ B, int64_t ldb,
+                                                          double *__restrict__ fro_part, int npanel) {
+    constexpr int kp = MT * 16;
+    const int64_t d = blockIdx.y;
+    const int panel = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int q = lane >> 4, ii = lane & 15;
+    const int64_t c8 = (int64_t)panel * SKB_PANEL + 8 * ii;
+    const bool any = c8 < n;
+    const uint16_t *Ad = A + d * stride + (any ? c8 : 0);
+    const uint16_t *Sh = Sb + (int64_t)ii * mp + 8 * q;
+    const uint16_t *Sl = Sh + (int64_t)kp * mp;
+    v4f acc[MT][8];
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[a][u] = v4f{0.f, 0.f, 0.f, 0.f};
+    double fro = 0.0;
+    v4u x[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t row = 8 * q + e;
+        x[e] = (any && row < m) ? load_bf16x8(Ad + row * ld, c8, n) : v4u{0u, 0u, 0u, 0u};
+    }
+    for (int64_t r0 = 0; r0 < m; r0 += 32) {
+        const bool more = r0 + 32 < m;
+        v4u nx[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t row = r0 + 32 + 8 * q + e;
+            nx[e] = (more && any && row < m) ? load_bf16x8(Ad + row * ld, c8, n) : v4u{0u, 0u, 0u, 0u};
+        }
+        v4u sh[MT], sl[MT];
+#pragma unroll
+        for (int a = 0; a < MT; ++a) {
+            sh[a] = *reinterpret_cast<const v4u *>(Sh + (int64_t)a * 16 * mp + r0);
+            sl[a] = *reinterpret_cast<const v4u *>(Sl + (int64_t)a * 16 * mp + r0);
+        }
+        float f = 0.f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) f += sumsq_bf16x8(x[e]);
+        fro += (double)f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = u >> 1;
+            v4u bt;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const unsigned lo = x[2 * t][j], hi = x[2 * t + 1][j];
+                bt[t] = (u & 1) ? ((lo >> 16) | (hi & 0xffff0000u)) : ((lo & 0xffffu) | (hi << 16));
+            }
+#pragma unroll
+            for (int a = 0; a < MT; ++a) {
+                acc[a][u] = mfma16x16x32_bf16(sh[a], bt, acc[a][u]);
+                acc[a][u] = mfma16x16x32_bf16(sl[a], bt, acc[a][u]);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = nx[e];
+    }
+    // lane holds B[a*16 + 4q + r][c8 + u] in acc[a][u][r]
+    if (any) {
+        float *Bd = B + d * kp * ldb + c8;
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float *o = Bd + (int64_t)(a * 16 + 4 * q + r) * ldb;
+                *reinterpret_cast<float4 *>(o) = float4{acc[a][0][r], acc[a][1][r], acc[a][2][r], acc[a][3][r]};
+                *reinterpret_cast<float4 *>(o + 4) = float4{acc[a][4][r], acc[a][5][r], acc[a][6][r], acc[a][7][r]};
+            }
+    }
+    const double tot = wave_sum_f64(fro);
+    if (threadIdx.x == 0) fro_part[d * npanel + panel] = tot;
+}
+
+// C_d = A_d V_d: contraction over the columns of A_d (contiguous), so lane
+// (q, i) reads 8 consecutive columns of row i of each of 8 row tiles; V_d^T
+// rows give the other operand directly.  One wave covers 128 rows.
+template <int NT>
+__global__ __launch_bounds__(64) void project_bf16_kernel(const uint16_t *__restrict__ A, int64_t m, int64_t n,
+                                                           int64_t ld, int64_t stride, const uint16_t *__restrict__ Vb,
+                                                           int64_t ldv, float *__restrict__ C) {
+    constexpr int kp = NT * 16;
+    const int64_t d = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int q = lane >> 4, ii = lane & 15;
+    const int64_t r0 = (int64_t)blockIdx.x * PJB_ROWS;
+    const uint16_t *Ad = A + d * stride;
+    const uint16_t *arow[8];
+    bool av[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const int64_t row = r0 + a * 16 + ii;
+        av[a] = row < m;
+        arow[a] = Ad + (av[a] ? row : 0) * ld + 8 * q;
+    }
+    const uint16_t *Vh = Vb + d * 2 * kp * ldv + (int64_t)ii * ldv + 8 * q;
+    const uint16_t *Vl = Vh + (int64_t)kp * ldv;
+    v4f acc[8][NT];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    v4u xa[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) xa[a] = (av[a] && 8 * q < n) ? load_bf16x8(arow[a], 8 * q, n) : v4u{0u, 0u, 0u, 0u};
+    for (int64_t c0 = 0; c0 < n; c0 += 32) {
+        const int64_t cn = c0 + 32 + 8 * q;  // this lane's columns in the next step
+        v4u nxa[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+            nxa[a] = (av[a] && cn < n) ? load_bf16x8(arow[a] + c0 + 32, cn, n) : v4u{0u, 0u, 0u, 0u};
+        v4u vh[NT], vl[NT];
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+            vh[b] = *reinterpret_cast<const v4u *>(Vh + (int64_t)b * 16 * ldv + c0);
+            vl[b] = *reinterpret_cast<const v4u *>(Vl + (int64_t)b * 16 * ldv + c0);
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int b = 0; b < NT; ++b) {
+                acc[a][b] = mfma16x16x32_bf16(xa[a], vh[b], acc[a][b]);
+                acc[a][b] = mfma16x16x32_bf16(xa[a], vl[b], acc[a][b]);
+            }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) xa[a] = nxa[a];
+    }
+    float *Cd = C + d * m * kp;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t row = r0 + a * 16 + 4 * q + r;
@@ -544,10 +735,10 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
     }
     const dim3 gq((unsigned)count);
     switch (kp / 16) {
-        case 1: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<16>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag)); break;
-        case 2: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<32>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag)); break;
-        case 3: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<48>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag)); break;
-        case 4: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<64>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag)); break;
+        case 1: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<16>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag, (uint16_t *)nullptr)); break;
+        case 2: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<32>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag, (uint16_t *)nullptr)); break;
+        case 3: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<48>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag, (uint16_t *)nullptr)); break;
+        case 4: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<64>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag, (uint16_t *)nullptr)); break;
     }
     const dim3 gp((unsigned)((m + PJ_ROWS - 1) / PJ_ROWS), (unsigned)count);
     switch (kp / 16) {
@@ -556,6 +747,79 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
         case 3: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<3>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
         case 4: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<4>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
     }
+#define TSK_FINISH(KPV)                                                                                        \
+    TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                           \
+               hipLaunchKernelGGL(finish_kernel<KPV>, dim3((unsigned)count), dim3(256), 0, c->stream,          \
+                                  (const float *)Cm, m, k, r, (const float *)Vt, ldv, n, (const double *)fro, \
+                                  npanel, (const int *)qflag, L, R, sigma, relerr, flags))
+    switch (kp / 16) {
+        case 1: TSK_FINISH(16); break;
+        case 2: TSK_FINISH(32); break;
+        case 3: TSK_FINISH(48); break;
+        case 4: TSK_FINISH(64); break;
+    }
+#undef TSK_FINISH
+    return TSK_OK;
+}
+
+tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
+                                  float *sigma, double *relerr, int32_t *flags) {
+    const int64_t m = s->m, n = s->n, count = s->count;
+    const int kp = (k + 15) / 16 * 16;
+    const int64_t mp = (m + 31) / 32 * 32;
+    const int64_t ldv = (n + 63) / 64 * 64;
+    const int npanel = (int)((n + SKB_PANEL - 1) / SKB_PANEL);
+    TSK_TRY(tsk_grow(c, c->ap_Sb, sizeof(uint16_t) * 2 * kp * mp));
+    TSK_TRY(tsk_grow(c, c->ap_B, sizeof(float) * count * kp * ldv));
+    TSK_TRY(tsk_grow(c, c->ap_Vt, sizeof(float) * count * kp * ldv));
+    TSK_TRY(tsk_grow(c, c->ap_Vb, sizeof(uint16_t) * count * 2 * kp * ldv));
+    TSK_TRY(tsk_grow(c, c->ap_C, sizeof(float) * count * m * kp));
+    TSK_TRY(tsk_grow(c, c->ap_fro, sizeof(double) * count * npanel));
+    TSK_TRY(tsk_grow(c, c->ap_qflag, sizeof(int) * count));
+    uint16_t *Sb = (uint16_t *)c->ap_Sb.p, *Vb = (uint16_t *)c->ap_Vb.p;
+    float *B = (float *)c->ap_B.p, *Vt = (float *)c->ap_Vt.p, *Cm = (float *)c->ap_C.p;
+    double *fro = (double *)c->ap_fro.p;
+    int *qflag = (int *)c->ap_qflag.p;
+    const uint16_t *A = (const uint16_t *)s->A;
+    TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
+               hipLaunchKernelGGL(prep_sketch_bf16_kernel, dim3((unsigned)((kp * mp + 255) / 256)), dim3(256), 0,
+                                  c->stream, S, k, kp, m, mp, Sb));
+    const dim3 gs((unsigned)npanel, (unsigned)count);
+#define TSK_SKB(MTV)                                                                                              \
+    TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                              \
+               hipLaunchKernelGGL(sketch_bf16_kernel<MTV>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, \
+                                  (const uint16_t *)Sb, mp, B, ldv, fro, npanel))
+    switch (kp / 16) {
+        case 1: TSK_SKB(1); break;
+        case 2: TSK_SKB(2); break;
+        case 3: TSK_SKB(3); break;
+        case 4: TSK_SKB(4); break;
+        default: return tsk_fail(c, TSK_E_ARG, "k > 64");
+    }
+#undef TSK_SKB
+    const dim3 gq((unsigned)count);
+#define TSK_QRB(KPV)                                                                                  \
+    TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<KPV>, gq, dim3(256), 0, c->stream, \
+                                                    (const float *)B, ldv, Vt, k, n, qflag, Vb))
+    switch (kp / 16) {
+        case 1: TSK_QRB(16); break;
+        case 2: TSK_QRB(32); break;
+        case 3: TSK_QRB(48); break;
+        case 4: TSK_QRB(64); break;
+    }
+#undef TSK_QRB
+    const dim3 gp((unsigned)((m + PJB_ROWS - 1) / PJB_ROWS), (unsigned)count);
+#define TSK_PJB(NTV)                                                                                     \
+    TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                    \
+               hipLaunchKernelGGL(project_bf16_kernel<NTV>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, \
+                                  s->stride, (const uint16_t *)Vb, ldv, Cm))
+    switch (kp / 16) {
+        case 1: TSK_PJB(1); break;
+        case 2: TSK_PJB(2); break;
+        case 3: TSK_PJB(3); break;
+        case 4: TSK_PJB(4); break;
+    }
+#undef TSK_PJB
 #define TSK_FINISH(KPV)                                                                                        \
     TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                           \
                hipLaunchKernelGGL(finish_kernel<KPV>, dim3((unsigned)count), dim3(256), 0, c->stream,          \

@@ -145,6 +145,164 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(const float *__restrict__
             }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 products (the precision form): same tiling, chunking and partial
+// layout as the FP32 kernel; a stage is 64 bf16 columns (128 bytes of every
+// staged row, the same LDS geometry), and each lane feeds the 16x16x32 bf16
+// MFMA with two 16-byte reads per staged row.  The source is either bf16
+// (read as stored) or FP32 rounded to bf16 (nearest-even) on the way into
+// LDS, so training can consume an FP32 stack directly.
+// ---------------------------------------------------------------------------
+constexpr int HK = 64;            // bf16 columns per stage
+constexpr int HLD = HK + 8;       // padded LDS row, bf16 elements (144 bytes)
+constexpr int HBUF = 2 * GT * HLD;  // bf16 elements per stage buffer
+
+// Per-thread staged data: 8 row chunks of 8 columns (thread t: chunk t & 7,
+// rows (t >> 3) + 32 u of the row block (u < 4) or column block (u >= 4)).
+template <typename SrcT> struct HRaw;
+template <> struct HRaw<uint16_t> { v4u v[8]; };
+template <> struct HRaw<float> { float4 v[16]; };
+
+__device__ __forceinline__ void hfetch(const uint16_t *__restrict__ Ad, int64_t m, int64_t n, int64_t ld,
+                                       int64_t rb0, int64_t cb0, int64_t c0, HRaw<uint16_t> &raw) {
+    const int t = threadIdx.x;
+    const int64_t cc = c0 + 8 * (t & 7);
+    const bool fullc = cc + 7 < n;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int64_t row = (u < 4 ? rb0 : cb0) + (t >> 3) + 32 * (u & 3);
+        v4u x = v4u{0u, 0u, 0u, 0u};
+        if (row < m && cc < n) {
+            const uint16_t *p = Ad + row * ld + cc;
+            if (fullc) {
+                x = *reinterpret_cast<const v4u *>(p);
+            } else {
+                unsigned w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (cc + e < n) w[e >> 1] |= (unsigned)p[e] << (16 * (e & 1));
+                x = v4u{w[0], w[1], w[2], w[3]};
+            }
+        }
+        raw.v[u] = x;
+    }
+}
+
+__device__ __forceinline__ void hfetch(const float *__restrict__ Ad, int64_t m, int64_t n, int64_t ld, int64_t rb0,
+                                       int64_t cb0, int64_t c0, HRaw<float> &raw) {
+    const int t = threadIdx.x;
+    const int64_t cc = c0 + 8 * (t & 7);
+    const bool fullc = cc + 7 < n;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int64_t row = (u < 4 ? rb0 : cb0) + (t >> 3) + 32 * (u & 3);
+        float4 x0 = float4{0.f, 0.f, 0.f, 0.f}, x1 = x0;
+        if (row < m && cc < n) {
+            const float *p = Ad + row * ld + cc;
+            if (fullc) {
+                x0 = *reinterpret_cast<const float4 *>(p);
+                x1 = *reinterpret_cast<const float4 *>(p + 4);
+            } else {
+                float w[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (cc + e < n) w[e] = p[e];
+                x0 = float4{w[0], w[1], w[2], w[3]};
+                x1 = float4{w[4], w[5], w[6], w[7]};
+            }
+        }
+        raw.v[2 * u] = x0;
+        raw.v[2 * u + 1] = x1;
+    }
+}
+
+__device__ __forceinline__ v4u hpack(const HRaw<uint16_t> &raw, int u) { return raw.v[u]; }
+__device__ __forceinline__ v4u hpack(const HRaw<float> &raw, int u) {
+    const float4 a = raw.v[2 * u], b = raw.v[2 * u + 1];
+    return v4u{pack_bf16(a.x, a.y), pack_bf16(a.z, a.w), pack_bf16(b.x, b.y), pack_bf16(b.z, b.w)};
+}
+
+template <typename SrcT>
+__device__ __forceinline__ void hstash(uint16_t *buf, const HRaw<SrcT> &raw) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int r = (u < 4 ? 0 : GT) + (t >> 3) + 32 * (u & 3);
+        *reinterpret_cast<v4u *>(buf + r * HLD + 8 * (t & 7)) = hpack(raw, u);
+    }
+}
+
+template <typename SrcT>
+__global__ __launch_bounds__(256) void gram_bf16_kernel(const SrcT *__restrict__ A, int64_t m, int64_t n,
+                                                        int64_t ld, int64_t stride, int64_t count, int T,
+                                                        int nchunks, int per_xcd, float *__restrict__ part) {
+    __shared__ uint16_t lds[2 * HBUF];
+    const int w = blockIdx.x;
+    const int xcd = w & 7, local = w >> 3;
+    const int t = local % T, sub = local / T;
+    const int chunk = xcd * per_xcd + sub;
+    const int64_t d0 = (int64_t)chunk * count / nchunks;
+    const int64_t d1 = (int64_t)(chunk + 1) * count / nchunks;
+    if (d0 >= d1) return;
+    int bi, bj;
+    tile_coords(t, bi, bj);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = lane >> 4, ii = lane & 15;
+    const int64_t rb0 = (int64_t)bi * GT, cb0 = (int64_t)bj * GT;
+    const int wr = (wv >> 1) * 64, wc = GT + (wv & 1) * 64;
+
+    v4f acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    const int64_t spd = (n + HK - 1) / HK;
+    const int64_t nst = (d1 - d0) * spd;
+    HRaw<SrcT> pre;
+    hfetch(A + d0 * stride, m, n, ld, rb0, cb0, 0, pre);
+    hstash(lds, pre);
+    __syncthreads();
+    for (int64_t st = 0; st < nst; ++st) {
+        const uint16_t *cur = lds + (st & 1) * HBUF;
+        const bool more = st + 1 < nst;
+        if (more) {
+            const int64_t s1 = st + 1;
+            const int64_t d = d0 + s1 / spd;
+            hfetch(A + d * stride, m, n, ld, rb0, cb0, (s1 % spd) * HK, pre);
+        }
+        v4u a[4][2], b[4][2];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const uint16_t *ra = cur + (wr + x * 16 + ii) * HLD + 8 * q;
+            const uint16_t *rc = cur + (wc + x * 16 + ii) * HLD + 8 * q;
+            a[x][0] = *reinterpret_cast<const v4u *>(ra);
+            a[x][1] = *reinterpret_cast<const v4u *>(ra + 32);
+            b[x][0] = *reinterpret_cast<const v4u *>(rc);
+            b[x][1] = *reinterpret_cast<const v4u *>(rc + 32);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x32_bf16(a[x][h], b[y][h], acc[x][y]);
+        if (more) hstash(lds + ((st + 1) & 1) * HBUF, pre);
+        __syncthreads();
+    }
+    float *P = part + ((int64_t)chunk * T + t) * (GT * GT);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int lr = (wv >> 1) * 64 + x * 16 + 4 * q + r;
+                const int lc = (wv & 1) * 64 + y * 16 + ii;
+                P[lr * GT + lc] = acc[x][y][r];
+            }
+}
+
 // G[i][j] = sum over non-empty chunks (in chunk order) of the partial tiles,
 // in FP64; diagonal tiles use their lower entry for both (i,j) and (j,i).
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const float *__restrict__ part, int64_t m,
@@ -170,8 +328,10 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const float *__restric
 
 }  // namespace
 
-// Enqueue the Gram of a validated FP32 stack into device G (m x m FP64).
-tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, double *G) {
+// Enqueue the Gram of a validated stack into device G (m x m FP64).
+// compute TSK_F32: FP32 stack, FP32 products.  compute TSK_BF16: FP32 stack
+// rounded to bf16 on load, or a bf16 stack as stored.
+tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *G) {
     const int64_t m = s->m, count = s->count;
     const int nb = (int)((m + GT - 1) / GT);
     const int T = nb * (nb + 1) / 2;
@@ -184,10 +344,22 @@ tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, double *G) {
     TSK_TRY(tsk_grow(c, c->gram_part, part_bytes));
     float *part = (float *)c->gram_part.p;
     const unsigned grid = (unsigned)(8 * per_xcd * T);
-    TSK_LAUNCH(c, TSK_KERNEL_GRAM,
-               hipLaunchKernelGGL(gram_f32_kernel, dim3(grid), dim3(256), 0, c->stream,
-                                  (const float *)s->A, m, s->n, s->ld, s->stride, count, T, nchunks,
-                                  per_xcd, part));
+    if (compute == TSK_F32) {
+        TSK_LAUNCH(c, TSK_KERNEL_GRAM,
+                   hipLaunchKernelGGL(gram_f32_kernel, dim3(grid), dim3(256), 0, c->stream,
+                                      (const float *)s->A, m, s->n, s->ld, s->stride, count, T, nchunks,
+                                      per_xcd, part));
+    } else if (s->dtype == TSK_F32) {
+        TSK_LAUNCH(c, TSK_KERNEL_GRAM,
+                   hipLaunchKernelGGL(gram_bf16_kernel<float>, dim3(grid), dim3(256), 0, c->stream,
+                                      (const float *)s->A, m, s->n, s->ld, s->stride, count, T, nchunks,
+                                      per_xcd, part));
+    } else {
+        TSK_LAUNCH(c, TSK_KERNEL_GRAM,
+                   hipLaunchKernelGGL(gram_bf16_kernel<uint16_t>, dim3(grid), dim3(256), 0, c->stream,
+                                      (const uint16_t *)s->A, m, s->n, s->ld, s->stride, count, T, nchunks,
+                                      per_xcd, part));
+    }
     TSK_LAUNCH(c, TSK_KERNEL_GRAM_REDUCE,
                hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)(T * (GT * GT / 256))), dim3(256), 0,
                                   c->stream, (const float *)part, m, count, T, nchunks, G));

@@ -6,11 +6,15 @@
 
 #include "tsk_common.hpp"
 
-tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, double *G);
+tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *G);
+tsk_status tsk_stage_enqueue(tsk_ctx c, const tsk_stack *s, int dtype, void *dst, int64_t ldd, int64_t strided,
+                             float *scale, double *norm2);
 tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *S, double *lambda,
                            int32_t *iters_out);
 tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
                              float *sigma, double *relerr, int32_t *flags);
+tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
+                                  float *sigma, double *relerr, int32_t *flags);
 tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, const float *R, int r,
                              double *relerr);
 
@@ -87,18 +91,38 @@ tsk_status tsk_check_stack(tsk_ctx c, const tsk_stack *s, const char *name) {
     std::string nm(name);
     if (!s) return tsk_fail(c, TSK_E_ARG, nm + ": null stack");
     if (!s->A) return tsk_fail(c, TSK_E_ARG, nm + ": null data pointer");
-    if (s->dtype != TSK_F32) return tsk_fail(c, TSK_E_ARG, nm + ": dtype must be TSK_F32");
-    if (s->scale) return tsk_fail(c, TSK_E_ARG, nm + ": scale must be NULL for TSK_F32");
+    const size_t es = dtype_size(s->dtype);
+    if (s->dtype != TSK_F32 && s->dtype != TSK_BF16 && s->dtype != TSK_F8E4M3)
+        return tsk_fail(c, TSK_E_ARG, nm + ": dtype must be TSK_F32, TSK_BF16 or TSK_F8E4M3");
+    if (s->dtype == TSK_F8E4M3 && !s->scale) return tsk_fail(c, TSK_E_ARG, nm + ": TSK_F8E4M3 needs scale");
+    if (s->dtype != TSK_F8E4M3 && s->scale) return tsk_fail(c, TSK_E_ARG, nm + ": scale must be NULL");
     if (s->m < 1 || s->n < 1 || s->count < 1) return tsk_fail(c, TSK_E_SHAPE, nm + ": m, n, count must be >= 1");
     if (s->ld < s->n) return tsk_fail(c, TSK_E_SHAPE, nm + ": ld < n");
     if (s->stride < s->m * s->ld) return tsk_fail(c, TSK_E_SHAPE, nm + ": stride < m*ld");
-    if (((uintptr_t)s->A & 15) || (s->ld & 3) || (s->stride & 3))
-        return tsk_fail(c, TSK_E_SHAPE, nm + ": data must be 16-byte aligned with ld, stride multiples of 4");
+    const int64_t q = (int64_t)(16 / es);  // elements per 16 bytes
+    if (((uintptr_t)s->A & 15) || (s->ld % q) || (s->stride % q))
+        return tsk_fail(c, TSK_E_SHAPE, nm + ": data must be 16-byte aligned with ld, stride multiples of 16 bytes");
     if (s->m > (1 << 20) || s->n > (1 << 20) || s->count > (1 << 24))
         return tsk_fail(c, TSK_E_SHAPE, nm + ": dimension too large");
-    const size_t es = dtype_size(s->dtype);
     const size_t need = ((size_t)(s->count - 1) * s->stride + (size_t)(s->m - 1) * s->ld + s->n) * es;
-    return tsk_check_dev(c, s->A, need, (nm + ".A").c_str());
+    TSK_TRY(tsk_check_dev(c, s->A, need, (nm + ".A").c_str()));
+    if (s->scale) TSK_TRY(tsk_check_dev(c, s->scale, sizeof(float) * s->count, (nm + ".scale").c_str()));
+    return TSK_OK;
+}
+
+// Gram compute rules shared by tsk_gram and tsk_train.
+static tsk_status check_gram_compute(tsk_ctx c, const tsk_stack *s, int32_t compute, const char *who) {
+    std::string w(who);
+    if (compute == TSK_F32) {
+        if (s->dtype != TSK_F32) return tsk_fail(c, TSK_E_ARG, w + ": compute TSK_F32 needs an FP32 stack");
+        return TSK_OK;
+    }
+    if (compute == TSK_BF16) {
+        if (s->dtype != TSK_F32 && s->dtype != TSK_BF16)
+            return tsk_fail(c, TSK_E_ARG, w + ": compute TSK_BF16 needs an FP32 or bf16 stack");
+        return TSK_OK;
+    }
+    return tsk_fail(c, TSK_E_ARG, w + ": compute must be TSK_F32 or TSK_BF16");
 }
 
 void tsk_ev_begin(tsk_ctx c, int cls, hipEvent_t *a) {
@@ -182,7 +206,7 @@ void tsk_destroy(tsk_ctx c) {
     TskBuf *bufs[] = {&c->gram_part, &c->gram_G,  &c->eig_Y0,   &c->eig_Y1, &c->eig_Rinv, &c->eig_part,
                       &c->eig_C,     &c->eig_X,   &c->eig_GX,   &c->eig_small, &c->eig_U, &c->counters,
                       &c->ap_St,     &c->ap_B,    &c->ap_Vt,    &c->ap_C,   &c->ap_fro,   &c->ap_qflag,
-                      &c->er_part};
+                      &c->ap_Sb,     &c->ap_Vb,   &c->er_part,  &c->st_part};
     for (TskBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
@@ -202,9 +226,31 @@ tsk_status tsk_gram(tsk_ctx c, const tsk_stack *train, int32_t compute, double *
     c->err.clear();
     DeviceGuard g(c->device);
     TSK_TRY(tsk_check_stack(c, train, "train"));
-    if (compute != TSK_F32) return tsk_fail(c, TSK_E_ARG, "tsk_gram: compute must be TSK_F32");
+    TSK_TRY(check_gram_compute(c, train, compute, "tsk_gram"));
     TSK_TRY(tsk_check_dev(c, G, sizeof(double) * train->m * train->m, "G"));
-    return tsk_gram_enqueue(c, train, G);
+    return tsk_gram_enqueue(c, train, compute, G);
+}
+
+tsk_status tsk_stage(tsk_ctx c, const tsk_stack *src, int32_t dtype, void *dst, int64_t ld, int64_t stride,
+                     float *scale, double *norm2) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    TSK_TRY(tsk_check_stack(c, src, "src"));
+    if (src->dtype != TSK_F32) return tsk_fail(c, TSK_E_ARG, "tsk_stage: src must be an FP32 stack");
+    if (dtype != TSK_BF16 && dtype != TSK_F8E4M3)
+        return tsk_fail(c, TSK_E_ARG, "tsk_stage: dtype must be TSK_BF16 or TSK_F8E4M3");
+    if (dtype == TSK_F8E4M3 && !scale) return tsk_fail(c, TSK_E_ARG, "tsk_stage: TSK_F8E4M3 needs scale");
+    if (dtype == TSK_BF16 && scale) return tsk_fail(c, TSK_E_ARG, "tsk_stage: scale must be NULL for TSK_BF16");
+    tsk_stack d = *src;
+    d.A = dst;
+    d.dtype = dtype;
+    d.scale = scale;
+    d.ld = ld;
+    d.stride = stride;
+    TSK_TRY(tsk_check_stack(c, &d, "dst"));
+    if (norm2) TSK_TRY(tsk_check_dev(c, norm2, sizeof(double) * src->count, "norm2"));
+    return tsk_stage_enqueue(c, src, dtype, dst, ld, stride, scale, norm2);
 }
 
 tsk_status tsk_eig_topk(tsk_ctx c, const double *G, int64_t m, int32_t k, float *S, double *lambda,
@@ -228,7 +274,7 @@ tsk_status tsk_train(tsk_ctx c, const tsk_stack *train, int32_t k, int32_t compu
     c->err.clear();
     DeviceGuard g(c->device);
     TSK_TRY(tsk_check_stack(c, train, "train"));
-    if (compute != TSK_F32) return tsk_fail(c, TSK_E_ARG, "tsk_train: compute must be TSK_F32");
+    TSK_TRY(check_gram_compute(c, train, compute, "tsk_train"));
     const int64_t m = train->m;
     if (k < 1 || k >= m) return tsk_fail(c, TSK_E_ARG, "tsk_train: need 1 <= k < m");
     if (k > 52) return tsk_fail(c, TSK_E_ARG, "tsk_train: k > 52 not supported");
@@ -236,7 +282,7 @@ tsk_status tsk_train(tsk_ctx c, const tsk_stack *train, int32_t k, int32_t compu
     TSK_TRY(tsk_check_dev(c, S, sizeof(float) * k * m, "S"));
     TSK_TRY(tsk_grow(c, c->gram_G, sizeof(double) * m * m));
     double *G = (double *)c->gram_G.p;
-    TSK_TRY(tsk_gram_enqueue(c, train, G));
+    TSK_TRY(tsk_gram_enqueue(c, train, compute, G));
     return tsk_eig_enqueue(c, G, m, k, S, lambda, iters);
 }
 
@@ -246,7 +292,9 @@ tsk_status tsk_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test
     c->err.clear();
     DeviceGuard g(c->device);
     TSK_TRY(tsk_check_stack(c, test, "test"));
-    if (compute != TSK_F32) return tsk_fail(c, TSK_E_ARG, "tsk_apply: compute must be TSK_F32");
+    if (compute != TSK_F32 && compute != TSK_BF16)
+        return tsk_fail(c, TSK_E_ARG, "tsk_apply: compute must be TSK_F32 or TSK_BF16");
+    if (test->dtype != compute) return tsk_fail(c, TSK_E_ARG, "tsk_apply: compute must match the stack's dtype");
     const int64_t m = test->m, n = test->n, cnt = test->count;
     if (r < 1 || r >= k) return tsk_fail(c, TSK_E_ARG, "tsk_apply: need 1 <= r < k");
     if (k > m || k > n) return tsk_fail(c, TSK_E_ARG, "tsk_apply: need k <= min(m, n)");
@@ -257,6 +305,7 @@ tsk_status tsk_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test
     TSK_TRY(tsk_check_dev(c, sigma, sizeof(float) * cnt * r, "sigma"));
     if (relerr) TSK_TRY(tsk_check_dev(c, relerr, sizeof(double) * cnt, "relerr"));
     if (flags) TSK_TRY(tsk_check_dev(c, flags, sizeof(int32_t) * cnt, "flags"));
+    if (compute == TSK_BF16) return tsk_apply_bf16_enqueue(c, S, k, test, r, L, R, sigma, relerr, flags);
     return tsk_apply_enqueue(c, S, k, test, r, L, R, sigma, relerr, flags);
 }
 
@@ -265,6 +314,7 @@ tsk_status tsk_error(tsk_ctx c, const tsk_stack *A, const float *L, const float 
     c->err.clear();
     DeviceGuard g(c->device);
     TSK_TRY(tsk_check_stack(c, A, "A"));
+    if (A->dtype != TSK_F32) return tsk_fail(c, TSK_E_ARG, "tsk_error: A must be an FP32 stack");
     if (r < 1 || r > 64) return tsk_fail(c, TSK_E_ARG, "tsk_error: need 1 <= r <= 64");
     const int64_t m = A->m, n = A->n, cnt = A->count;
     TSK_TRY(tsk_check_dev(c, L, sizeof(float) * cnt * m * r, "L"));

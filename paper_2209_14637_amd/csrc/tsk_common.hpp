@@ -29,6 +29,39 @@ __device__ __forceinline__ v4d mfma16x16x4_f64(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// 16x16x32 bf16 (FP32 accumulate), measured on gfx950: lane 16*q + i
+// supplies A[i][8q .. 8q+7] and B[8q .. 8q+7][i] (8 consecutive bf16 in 4
+// dwords, element 2t in the low half of dword t); D as for the f32 shape.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4f mfma16x16x32_bf16(v4u a, v4u b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
+                                                   0, 0);
+}
+
+// bf16 bits <-> float (bf16 is the upper half of a binary32).
+__device__ __forceinline__ float bf16_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+// Round-to-nearest-even float -> bf16 of two values packed into one dword
+// (x in the low half), by the hardware conversion.
+__device__ __forceinline__ unsigned pack_bf16(float x, float y) {
+    typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    const v2bf h = __builtin_convertvector(v2f{x, y}, v2bf);
+    return __builtin_bit_cast(unsigned, h);
+}
+// Sum of squares of the 8 bf16 values of a 16-byte vector, in FP32.
+__device__ __forceinline__ float sumsq_bf16x8(v4u v) {
+    float s = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float a = bf16_lo(v[t]), b = bf16_hi(v[t]);
+        s = fmaf(a, a, s);
+        s = fmaf(b, b, s);
+    }
+    return s;
+}
+
 __device__ __forceinline__ double wave_sum_f64(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
@@ -351,7 +384,8 @@ struct tsk_ctx_s {
     TskBuf eig_Y0, eig_Y1, eig_Rinv, eig_part, eig_C, eig_X, eig_GX, eig_small, eig_U;
     TskBuf counters;
     TskBuf ap_St, ap_B, ap_Vt, ap_C, ap_fro, ap_qflag;
-    TskBuf er_part;
+    TskBuf ap_Sb, ap_Vb;  // bf16 hi/lo copies of S and V^T (bf16 path)
+    TskBuf er_part, st_part;
     // eigensolver controls
     int eig_block = 0, eig_max_iter = 300, eig_check = 4;
     double eig_tol = 1e-7;

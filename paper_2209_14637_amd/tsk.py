@@ -17,14 +17,16 @@ LIB_PATH = os.path.join(HERE, "libtsk.so")
 TSK_OK, TSK_E_ARG, TSK_E_SHAPE, TSK_E_NOMEM, TSK_E_DEVICE, TSK_E_NOCONV = range(6)
 TSK_F64, TSK_F32, TSK_BF16, TSK_F8E4M3 = range(4)
 FLAG_RANKDEF, FLAG_TIE, FLAG_NONFIN = 1, 2, 4
-KERNELS = ["gram", "gram_reduce", "eig_iter", "eig_rr", "sketch", "qr", "project", "finish", "error"]
+KERNELS = ["gram", "gram_reduce", "eig_iter", "eig_rr", "sketch", "qr", "project", "finish", "error", "stage"]
 
 _STATUS = {0: "TSK_OK", 1: "TSK_E_ARG", 2: "TSK_E_SHAPE", 3: "TSK_E_NOMEM", 4: "TSK_E_DEVICE",
            5: "TSK_E_NOCONV"}
 
-EXPORTS = ["tsk_create", "tsk_destroy", "tsk_set_stream", "tsk_last_error", "tsk_gram", "tsk_eig_topk",
-           "tsk_train", "tsk_apply", "tsk_error", "tsk_set_eig_params", "tsk_timing_enable",
+EXPORTS = ["tsk_create", "tsk_destroy", "tsk_set_stream", "tsk_last_error", "tsk_stage", "tsk_gram",
+           "tsk_eig_topk", "tsk_train", "tsk_apply", "tsk_error", "tsk_set_eig_params", "tsk_timing_enable",
            "tsk_timing_read"]
+
+_DTYPES = {"f32": TSK_F32, "bf16": TSK_BF16, "e4m3": TSK_F8E4M3}
 
 
 class TskError(RuntimeError):
@@ -58,6 +60,7 @@ def load(path: str | None = None):
         "tsk_destroy": ([P], None),
         "tsk_set_stream": ([P, P], I32),
         "tsk_last_error": ([P], ctypes.c_char_p),
+        "tsk_stage": ([P, sp, I32, P, I64, I64, P, P], I32),
         "tsk_gram": ([P, sp, I32, P], I32),
         "tsk_eig_topk": ([P, P, I64, I32, P, P, P], I32),
         "tsk_train": ([P, sp, I32, I32, P, P, P], I32),
@@ -75,17 +78,41 @@ def load(path: str | None = None):
     return L
 
 
-def _stack(A: torch.Tensor) -> Stack:
+class Staged:
+    """A stack in a reduced-precision storage format: `data` holds the raw
+    elements (torch.bfloat16 for bf16, torch.uint8 bytes for e4m3) as
+    (count, m, ld); `scale` is the per-slice e4m3 scale (None for bf16)."""
+
+    def __init__(self, data: torch.Tensor, n: int, dtype: str, scale: torch.Tensor | None = None):
+        self.data, self.n, self.dtype, self.scale = data, n, dtype, scale
+
+    @property
+    def shape(self):
+        return (self.data.shape[0], self.data.shape[1], self.n)
+
+
+def _stack(A) -> Stack:
+    if isinstance(A, Staged):
+        t = A.data
+        if not t.is_cuda or t.dim() != 3 or t.stride(2) != 1:
+            raise ValueError("staged data must be a (count, m, ld) CUDA tensor")
+        cnt, m, _ = t.shape
+        return Stack(t.data_ptr(), _DTYPES[A.dtype], _ptr(A.scale), m, A.n, cnt, t.stride(1),
+                     t.stride(0) if cnt > 1 else m * t.stride(1))
     if not isinstance(A, torch.Tensor) or not A.is_cuda:
         raise TypeError("expected a CUDA tensor")
-    if A.dtype != torch.float32:
-        raise TypeError("expected float32 slices")
+    if A.dtype == torch.float32:
+        dt = TSK_F32
+    elif A.dtype == torch.bfloat16:
+        dt = TSK_BF16
+    else:
+        raise TypeError("expected float32 or bfloat16 slices")
     if A.dim() == 2:
         A = A.unsqueeze(0)
     if A.dim() != 3 or A.stride(2) != 1:
         raise ValueError("expected a (count, m, n) stack with unit column stride")
     cnt, m, n = A.shape
-    return Stack(A.data_ptr(), TSK_F32, None, m, n, cnt, A.stride(1), A.stride(0) if cnt > 1 else m * A.stride(1))
+    return Stack(A.data_ptr(), dt, None, m, n, cnt, A.stride(1), A.stride(0) if cnt > 1 else m * A.stride(1))
 
 
 def _ptr(t):
@@ -125,12 +152,32 @@ class Context:
         raise TskError(st, self.lib.tsk_last_error(self.h).decode())
 
     # --- entry points -----------------------------------------------------
-    def gram(self, A: torch.Tensor, G: torch.Tensor | None = None) -> torch.Tensor:
+    def stage(self, A: torch.Tensor, dtype: str = "bf16", norm2: bool = False):
+        """Round an FP32 stack into a storage format ("bf16" or "e4m3");
+        returns a Staged stack (and ||A_d||^2 of the source when norm2)."""
         self._sync_stream()
         s = _stack(A)
+        if s.dtype != TSK_F32:
+            raise TypeError("stage() takes an FP32 stack")
+        per16 = 8 if dtype == "bf16" else 16
+        ld = (s.n + per16 - 1) // per16 * per16
+        tdt = torch.bfloat16 if dtype == "bf16" else torch.uint8
+        dev = A.device
+        out = torch.empty((s.count, s.m, ld), dtype=tdt, device=dev)
+        scale = torch.empty(s.count, dtype=torch.float32, device=dev) if dtype == "e4m3" else None
+        nrm = torch.empty(s.count, dtype=torch.float64, device=dev) if norm2 else None
+        self._check(self.lib.tsk_stage(self.h, ctypes.byref(s), _DTYPES[dtype], _ptr(out), ld, s.m * ld,
+                                       _ptr(scale), _ptr(nrm)))
+        st = Staged(out, s.n, dtype, scale)
+        return (st, nrm) if norm2 else st
+
+    def gram(self, A, G: torch.Tensor | None = None, compute: str = "f32") -> torch.Tensor:
+        self._sync_stream()
+        s = _stack(A)
+        dev = (A.data if isinstance(A, Staged) else A).device
         if G is None:
-            G = torch.empty((s.m, s.m), dtype=torch.float64, device=A.device)
-        self._check(self.lib.tsk_gram(self.h, ctypes.byref(s), TSK_F32, _ptr(G)))
+            G = torch.empty((s.m, s.m), dtype=torch.float64, device=dev)
+        self._check(self.lib.tsk_gram(self.h, ctypes.byref(s), _DTYPES[compute], _ptr(G)))
         return G
 
     def eig_topk(self, G: torch.Tensor, k: int, S: torch.Tensor | None = None, allow_noconv: bool = False):
@@ -145,25 +192,28 @@ class Context:
         st = self._check(self.lib.tsk_eig_topk(self.h, _ptr(G), m, k, _ptr(S), lam, ctypes.byref(it)), allow_noconv)
         return S, list(lam), it.value, st
 
-    def train(self, A: torch.Tensor, k: int, S: torch.Tensor | None = None, allow_noconv: bool = False):
+    def train(self, A, k: int, S: torch.Tensor | None = None, allow_noconv: bool = False, compute: str = "f32"):
         self._sync_stream()
         s = _stack(A)
+        dev = (A.data if isinstance(A, Staged) else A).device
         if S is None:
-            S = torch.empty((k, s.m), dtype=torch.float32, device=A.device)
+            S = torch.empty((k, s.m), dtype=torch.float32, device=dev)
         lam = (ctypes.c_double * (k + 1))()
         it = ctypes.c_int32(0)
-        st = self._check(self.lib.tsk_train(self.h, ctypes.byref(s), k, TSK_F32, _ptr(S), lam, ctypes.byref(it)),
-                         allow_noconv)
+        st = self._check(self.lib.tsk_train(self.h, ctypes.byref(s), k, _DTYPES[compute], _ptr(S), lam,
+                                            ctypes.byref(it)), allow_noconv)
         return S, list(lam), it.value, st
 
-    def apply(self, S: torch.Tensor, A: torch.Tensor, r: int, out: dict | None = None, relerr: bool = True,
+    def apply(self, S: torch.Tensor, A, r: int, out: dict | None = None, relerr: bool = True,
               flags: bool = True) -> dict:
+        """SCW on every slice; the arithmetic follows the stack's format
+        (FP32 tensor, bfloat16 tensor or a Staged stack)."""
         self._sync_stream()
         s = _stack(A)
         k = S.shape[0]
         if S.dtype != torch.float32 or not S.is_contiguous() or S.shape[1] != s.m:
             raise ValueError("S must be a contiguous (k, m) float32 CUDA tensor")
-        dev = A.device
+        dev = S.device
         o = out if out is not None else {}
         if "L" not in o:
             o["L"] = torch.empty((s.count, s.m, r), dtype=torch.float32, device=dev)
@@ -171,7 +221,7 @@ class Context:
             o["sigma"] = torch.empty((s.count, r), dtype=torch.float32, device=dev)
             o["relerr"] = torch.empty(s.count, dtype=torch.float64, device=dev) if relerr else None
             o["flags"] = torch.empty(s.count, dtype=torch.int32, device=dev) if flags else None
-        self._check(self.lib.tsk_apply(self.h, _ptr(S), k, ctypes.byref(s), r, TSK_F32, _ptr(o["L"]), _ptr(o["R"]),
+        self._check(self.lib.tsk_apply(self.h, _ptr(S), k, ctypes.byref(s), r, s.dtype, _ptr(o["L"]), _ptr(o["R"]),
                                        _ptr(o["sigma"]), _ptr(o.get("relerr")), _ptr(o.get("flags"))))
         return o
 

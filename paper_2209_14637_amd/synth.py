@@ -29,6 +29,7 @@ the oracle reads exactly (upcast to float64) and the GPU path reads as stored.
 from __future__ import annotations
 
 import dataclasses
+import mmap
 import os
 from concurrent.futures import ThreadPoolExecutor
 
@@ -39,6 +40,14 @@ PURPOSE_U0, PURPOSE_UPERP, PURPOSE_W, PURPOSE_E = 0, 1, 2, 3
 
 def _rng(*key: int) -> np.random.Generator:
     return np.random.default_rng(np.random.SeedSequence([int(x) for x in key]))
+
+
+def _single_thread_blas():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
 
 
 def _orth(x: np.ndarray) -> np.ndarray:
@@ -116,9 +125,17 @@ class Stream:
             a = a + s.eta * self.noise(d)
         return a.astype(np.float32)
 
-    def slices(self, ds, out: np.ndarray | None = None, threads: int | None = None) -> np.ndarray:
+    def slices(self, ds, out: np.ndarray | None = None, threads: int | None = None,
+               procs: int | None = None) -> np.ndarray:
+        """Slices ds as a (len(ds), m, n) float32 array.  Large requests are
+        split over forked worker processes writing into shared anonymous
+        memory (the draws are per-slice, so the result does not depend on
+        the split); call it before the process starts GPU work."""
         ds = list(ds)
         s = self.spec
+        nproc = procs if procs is not None else min(16, len(os.sched_getaffinity(0)))
+        if out is None and nproc > 1 and len(ds) * s.m * s.n >= (1 << 26) and hasattr(os, "fork"):
+            return self._slices_forked(ds, nproc)
         if out is None:
             out = np.empty((len(ds), s.m, s.n), dtype=np.float32)
         nthr = threads or min(16, len(os.sched_getaffinity(0)))
@@ -133,6 +150,34 @@ class Stream:
             with ThreadPoolExecutor(nthr) as ex:
                 list(ex.map(work, range(len(ds))))
         return out
+
+    def _slices_forked(self, ds, nproc):
+        s = self.spec
+        per = s.m * s.n
+        mm = mmap.mmap(-1, len(ds) * per * 4)
+        arr = np.frombuffer(mm, dtype=np.float32).reshape(len(ds), s.m, s.n)
+        nproc = min(nproc, len(ds))
+        bounds = [len(ds) * p // nproc for p in range(nproc + 1)]
+        pids = []
+        for p in range(nproc):
+            pid = os.fork()
+            if pid == 0:  # child: numpy only, then leave without cleanup
+                code = 0
+                try:
+                    _single_thread_blas()
+                    for i in range(bounds[p], bounds[p + 1]):
+                        arr[i] = self.slice(ds[i])
+                except BaseException:
+                    code = 1
+                os._exit(code)
+            pids.append(pid)
+        bad = 0
+        for pid in pids:
+            _, st = os.waitpid(pid, 0)
+            bad |= st != 0
+        if bad:
+            raise RuntimeError("slice generation worker failed")
+        return arr  # backed by the anonymous mapping, released with the array
 
     def train(self, count: int | None = None, **kw) -> np.ndarray:
         c = self.spec.n_train if count is None else count

@@ -1,18 +1,24 @@
-// SCW (Algorithm 1) on a stack of test matrices, FP32 path.
+// SCW (Algorithm 1) on a stack of test matrices.
 //
 //  sketch  : B_d = S A_d (k x n), the 1-mode product of Section 2 slice by
-//            slice, FP32 MFMA; also ||A_d||_F^2 in FP64.
-//  cholqr2 : V_d^T = orthonormal basis of the row space of B_d (k x n) by
-//            CholeskyQR2 in FP64 -- Section 3.2 allows QR in place of the SVD
-//            of line 1 because only the orthogonalisation is used.
-//  project : C_d = A_d V_d (m x k), FP32 MFMA (second pass over A_d).
-//  finish  : C_d^T C_d = Y diag(sigma^2) Y^T (FP64 Jacobi), rank-r truncation,
-//            L_d = C_d Y_r, R_d = V_d Y_r, sigma, and the error from the
+//            slice, MFMA; also ||A_d||_F^2 in FP64.
+//  project : C_d = A_d B_d^T (m x k), MFMA (second pass over A_d).
+//  finish  : one workgroup per matrix.  Section 3.2 notes that only the
+//            orthogonalisation of line 1 matters (QR may replace the SVD), so
+//            V_d is kept implicit: with B_d B_d^T = R^T R (Cholesky, FP64),
+//            V_d = B_d^T R^-1 is an orthonormal basis of the row space of
+//            S A_d, A_d V_d = C_d R^-1, and
+//                (A_d V_d)^T (A_d V_d) = R^-T (C_d^T C_d) R^-1 = Y diag(s^2) Y^T
+//            (FP64 Jacobi).  With Z = R^-1 Y_r:
+//                L_d = C_d Z = U_r Sigma_r,  R_d = B_d^T Z = V_d Y_r,
+//            so L_d R_d^T = [A_d V_d]_r V_d^T, and the error follows from the
 //            Pythagorean identity of the proof of Theorem 1.
 //  error   : explicit ||A_d - L_d R_d^T||_F / ||A_d||_F (tsk_error).
 //
-// MFMA operand layout: see tsk_common.hpp.  kp = k rounded up to 16; the
-// padded rows of S / columns of V are zero so no masking is needed on them.
+// Two forms of the streaming kernels: FP32 (FP32 MFMA) and bf16 (A_d stored
+// in bf16, B_d split into a bf16 pair hi + lo; every later use of B_d takes
+// B_d = hi + lo, so all factors refer to the same row space).  kp = k rounded
+// up to 16; rows k..kp-1 of S, B are zero, so no masking is needed on them.
 #include "tsk_common.hpp"
 
 namespace {
@@ -23,7 +29,6 @@ namespace {
 constexpr int SK_PANEL = 64;   // columns of A_d per sketch workgroup (one wave)
 constexpr int PJ_ROWS = 64;    // rows of A_d per project workgroup (one wave)
 constexpr int MAXK = 64;
-constexpr int NTRI_PER_THREAD = (MAXK * (MAXK + 1) / 2 + 255) / 256;  // upper-triangle entries per thread
 
 // St (m x kp) = S^T with zero columns k..kp-1
 __global__ void transpose_sketch_kernel(const float *__restrict__ S, int k, int kp, int64_t m,
@@ -90,8 +95,9 @@ __global__ __launch_bounds__(64) void sketch_f32_kernel(const float *__restrict_
             }
         }
     }
-    // lane holds B[a*16 + 4q + r][col4 + t] in acc[a][t][r]
-    if (any) {
+    // lane holds B[a*16 + 4q + r][col4 + t] in acc[a][t][r]; the whole panel
+    // is written (columns >= n are zero), so B's padding is defined
+    {
         float *Bd = B + d * kp * ldb;
 #pragma unroll
         for (int a = 0; a < MT; ++a)
@@ -107,153 +113,11 @@ __global__ __launch_bounds__(64) void sketch_f32_kernel(const float *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Small dense helpers, one workgroup (256 threads) per matrix.
-// ---------------------------------------------------------------------------
-
-// Gram of k vectors stored as the ROWS of X (k x n, row stride ldx, FP32):
-// C[a][b] = sum_c X[a][c] X[b][c] in FP64 (full symmetric, LDS stride ld).
-// Work: 4x4 register blocks of C (a-block <= b-block) x column slices, float4
-// loads over 4 consecutive columns; slices summed through LDS (scratch:
-// 256*16 doubles).  Columns in [n, round4(n)) must hold zeros.
-__device__ inline void row_gram(const float *__restrict__ X, int64_t ldx, int k, int64_t n, double *C, int ld,
-                                double *scratch) {
-    const int nb = (k + 3) / 4;
-    const int nblk = nb * (nb + 1) / 2;
-    const int ns = 256 / nblk;
-    const int tid = threadIdx.x;
-    const int sl = tid / nblk, blk = tid % nblk;
-    double acc[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-    int ta = 0, tb = 0;
-    if (sl < ns) {
-        int e = blk, rr = 0, len = nb;
-        while (e >= len) {
-            e -= len;
-            ++rr;
-            --len;
-        }
-        ta = rr;
-        tb = rr + e;
-        const float *xa[4], *xb[4];
-        bool va[4], vb[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            va[u] = 4 * ta + u < k;
-            vb[u] = 4 * tb + u < k;
-            xa[u] = X + (va[u] ? 4 * ta + u : 0) * ldx;
-            xb[u] = X + (vb[u] ? 4 * tb + u : 0) * ldx;
-        }
-        for (int64_t c4 = 4 * (int64_t)sl; c4 < n; c4 += 4 * ns) {
-            float4 fa[4], fb[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                fa[u] = va[u] ? *reinterpret_cast<const float4 *>(xa[u] + c4) : float4{0.f, 0.f, 0.f, 0.f};
-                fb[u] = vb[u] ? *reinterpret_cast<const float4 *>(xb[u] + c4) : float4{0.f, 0.f, 0.f, 0.f};
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    acc[u * 4 + v] += (double)fa[u].x * fb[v].x + (double)fa[u].y * fb[v].y +
-                                      (double)fa[u].z * fb[v].z + (double)fa[u].w * fb[v].w;
-        }
-    }
-    __syncthreads();
-    if (sl < ns) {
-#pragma unroll
-        for (int u = 0; u < 16; ++u) scratch[(sl * nblk + blk) * 16 + u] = acc[u];
-    }
-    __syncthreads();
-    for (int e = tid; e < nblk * 16; e += 256) {
-        const int bk = e / 16, u = e % 16;
-        double sum = 0.0;
-        for (int z = 0; z < ns; ++z) sum += scratch[(z * nblk + bk) * 16 + u];
-        int ee = bk, rr = 0, len = nb;
-        while (ee >= len) {
-            ee -= len;
-            ++rr;
-            --len;
-        }
-        const int a = 4 * rr + u / 4, b = 4 * (rr + ee) + u % 4;
-        if (a < k && b < k) {
-            C[a * ld + b] = sum;
-            C[b * ld + a] = sum;
-        }
-    }
-    __syncthreads();
-}
-
-// dst (KP x ldv) = Rinv^T src for the first k rows, FP32; rows k..KP-1 and
-// columns n..ldv-1 are written as zero.  Rf: Rinv (KP x KP, FP32, LDS).
-template <int KP>
-__device__ inline void apply_rinv_t(const float *__restrict__ src, float *__restrict__ dst, int64_t ldv, int k,
-                                    int64_t n, const float *Rf, uint16_t *__restrict__ vb = nullptr) {
-    for (int64_t c = threadIdx.x; c < ldv; c += blockDim.x) {
-        float col[KP];
-#pragma unroll
-        for (int t = 0; t < KP; ++t) col[t] = (t < k && c < n) ? src[t * ldv + c] : 0.f;
-        // Rf is upper triangular (zero below the diagonal): full-length dot
-        // products keep col[] statically indexed, i.e. in registers
-#pragma nounroll
-        for (int i = 0; i < KP; ++i) {
-            float s = 0.f;
-#pragma unroll
-            for (int t = 0; t < KP; ++t) s += Rf[t * KP + i] * col[t];
-            dst[i * ldv + c] = s;
-            if (vb) {
-                // bf16 pair: hi = RNE(s), lo = RNE(s - hi) (s - hi is exact)
-                const unsigned h = pack_bf16(s, 0.f) & 0xffffu;
-                const unsigned l = pack_bf16(s - bf16_lo(h), 0.f) & 0xffffu;
-                vb[i * ldv + c] = (uint16_t)h;
-                vb[(KP + i) * ldv + c] = (uint16_t)l;
-            }
-        }
-    }
-}
-
-// CholeskyQR2 of B_d^T: V_d^T (k x n, rows orthonormal) spans the row space
-// of B_d.  Grams in FP64 from FP32 data, Cholesky and inverse in FP64, the
-// triangular application in FP32 (the span does not depend on the accuracy
-// of R; the second pass restores orthogonality).  Dead pivots in the first
-// pass (singular-value ratio below 1e-6, the FP32 rounding level of B) flag
-// the matrix as rank deficient and leave zero rows in V^T.
-template <int KP>
-__global__ __launch_bounds__(256) void cholqr2_kernel(const float *__restrict__ B, int64_t ldv,
-                                                      float *__restrict__ Vt, int k, int64_t n,
-                                                      int *__restrict__ qflag, uint16_t *__restrict__ Vb) {
-    // C | R | X (KP*KP doubles each); the Gram's slice scratch (4096 doubles)
-    // sits after C and is dead once C is assembled
-    constexpr int SCR = (3 * KP * KP > KP * KP + 4096) ? 3 * KP * KP : KP * KP + 4096;
-    __shared__ double lds[SCR];
-    __shared__ float Rf[KP * KP];
-    __shared__ int dead[KP];
-    double *C = lds, *R = lds + KP * KP, *X = lds + 2 * KP * KP;
-    const int64_t d = blockIdx.x;
-    const float *Bd = B + d * KP * ldv;
-    float *Vd = Vt + d * KP * ldv;
-    int nd1 = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-        const float *src = pass == 0 ? Bd : Vd;
-        for (int e = threadIdx.x; e < KP * KP; e += 256) lds[e] = 0.0;
-        __syncthreads();
-        row_gram(src, ldv, k, n, C, KP, lds + KP * KP);
-        const int nd = chol_factor_inverse(C, KP, KP, 1e-12, R, X, dead, k);
-        if (pass == 0) nd1 = nd;
-        for (int e = threadIdx.x; e < KP * KP; e += 256) Rf[e] = (float)X[e];
-        __syncthreads();
-        apply_rinv_t<KP>(src, Vd, ldv, k, n, Rf, (pass == 1 && Vb) ? Vb + d * 2 * KP * ldv : nullptr);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) qflag[d] = nd1 > 0 ? TSK_FLAG_RANKDEF : 0;
-}
-
-// ---------------------------------------------------------------------------
-// C_d = A_d V_d
+// C_d = A_d B_d^T (FP32)
 // ---------------------------------------------------------------------------
 template <int NT>
 __global__ __launch_bounds__(64) void project_f32_kernel(const float *__restrict__ A, int64_t m, int64_t n,
-                                                          int64_t ld, int64_t stride, const float *__restrict__ Vt,
+                                                          int64_t ld, int64_t stride, const float *__restrict__ Bm,
                                                           int64_t ldv, float *__restrict__ C) {
     constexpr int kp = NT * 16;
     const int64_t d = blockIdx.y;
@@ -261,7 +125,7 @@ __global__ __launch_bounds__(64) void project_f32_kernel(const float *__restrict
     const int q = lane >> 4, ii = lane & 15;
     const int64_t r0 = (int64_t)blockIdx.x * PJ_ROWS;
     const float *Ad = A + d * stride;
-    const float *Vd = Vt + d * kp * ldv;
+    const float *Vd = Bm + d * kp * ldv;
     const float *arow[4];
     bool av[4];
 #pragma unroll
@@ -318,9 +182,9 @@ __global__ __launch_bounds__(64) void project_f32_kernel(const float *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// bf16 form.  A_d is stored in bf16; S and V_d are each split into a bf16
+// bf16 form.  A_d is stored in bf16; S and B_d are each split into a bf16
 // pair (hi + lo), two MFMAs per product, so the products carry about 16
-// significant bits of S and V and the only extra rounding is that of A_d.
+// significant bits of S and B and the only extra rounding is that of A_d.
 // ---------------------------------------------------------------------------
 constexpr int SKB_PANEL = 128;  // columns per sketch wave (16 lanes x 8)
 constexpr int PJB_ROWS = 128;   // rows per project wave (8 row tiles)
@@ -359,8 +223,8 @@ __device__ __forceinline__ v4u load_bf16x8(const uint16_t *p, int64_t c, int64_t
 template <int MT>
 __global__ __launch_bounds__(64) void sketch_bf16_kernel(const uint16_t *__restrict__ A, int64_t m, int64_t n,
                                                           int64_t ld, int64_t stride, const uint16_t *__restrict__ Sb,
-                                                          int64_t mp, float *__restrict__ B, int64_t ldb,
-                                                          double *__restrict__ fro_part, int npanel) {
+                                                          int64_t mp, float *__restrict__ B, uint16_t *__restrict__ Bb,
+                                                          int64_t ldb, double *__restrict__ fro_part, int npanel) {
     constexpr int kp = MT * 16;
     const int64_t d = blockIdx.y;
     const int panel = blockIdx.x;
@@ -419,28 +283,47 @@ __global__ __launch_bounds__(64) void sketch_bf16_kernel(const uint16_t *__restr
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = nx[e];
     }
-    // lane holds B[a*16 + 4q + r][c8 + u] in acc[a][u][r]
-    if (any) {
+    // lane holds B[a*16 + 4q + r][c8 + u] in acc[a][u][r].  Each value is
+    // split into hi = RNE(b), lo = RNE(b - hi); B' = hi + lo (exact in FP32)
+    // is what every later step uses.  The whole panel is written.
+    {
         float *Bd = B + d * kp * ldb + c8;
+        uint16_t *Bh = Bb + d * 2 * kp * ldb + c8;
+        uint16_t *Bl = Bh + (int64_t)kp * ldb;
 #pragma unroll
         for (int a = 0; a < MT; ++a)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                float *o = Bd + (int64_t)(a * 16 + 4 * q + r) * ldb;
-                *reinterpret_cast<float4 *>(o) = float4{acc[a][0][r], acc[a][1][r], acc[a][2][r], acc[a][3][r]};
-                *reinterpret_cast<float4 *>(o + 4) = float4{acc[a][4][r], acc[a][5][r], acc[a][6][r], acc[a][7][r]};
+                const int64_t row = (int64_t)(a * 16 + 4 * q + r) * ldb;
+                float bp[8];
+                unsigned hw[4], lw[4];
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                    const unsigned h2 = pack_bf16(acc[a][u][r], acc[a][u + 1][r]);
+                    const float h0 = bf16_lo(h2), h1 = bf16_hi(h2);
+                    const unsigned l2 = pack_bf16(acc[a][u][r] - h0, acc[a][u + 1][r] - h1);
+                    bp[u] = h0 + bf16_lo(l2);
+                    bp[u + 1] = h1 + bf16_hi(l2);
+                    hw[u >> 1] = h2;
+                    lw[u >> 1] = l2;
+                }
+                *reinterpret_cast<float4 *>(Bd + row) = float4{bp[0], bp[1], bp[2], bp[3]};
+                *reinterpret_cast<float4 *>(Bd + row + 4) = float4{bp[4], bp[5], bp[6], bp[7]};
+                *reinterpret_cast<v4u *>(Bh + row) = v4u{hw[0], hw[1], hw[2], hw[3]};
+                *reinterpret_cast<v4u *>(Bl + row) = v4u{lw[0], lw[1], lw[2], lw[3]};
             }
     }
     const double tot = wave_sum_f64(fro);
     if (threadIdx.x == 0) fro_part[d * npanel + panel] = tot;
 }
 
-// C_d = A_d V_d: contraction over the columns of A_d (contiguous), so lane
-// (q, i) reads 8 consecutive columns of row i of each of 8 row tiles; V_d^T
-// rows give the other operand directly.  One wave covers 128 rows.
+// C_d = A_d B_d^T: contraction over the columns of A_d (contiguous), so lane
+// (q, i) reads 8 consecutive columns of row i of each of 8 row tiles; the rows
+// of the bf16 pair of B_d give the other operand directly.  One wave covers
+// 128 rows.
 template <int NT>
 __global__ __launch_bounds__(64) void project_bf16_kernel(const uint16_t *__restrict__ A, int64_t m, int64_t n,
-                                                           int64_t ld, int64_t stride, const uint16_t *__restrict__ Vb,
+                                                           int64_t ld, int64_t stride, const uint16_t *__restrict__ Bb,
                                                            int64_t ldv, float *__restrict__ C) {
     constexpr int kp = NT * 16;
     const int64_t d = blockIdx.y;
@@ -456,8 +339,8 @@ __global__ __launch_bounds__(64) void project_bf16_kernel(const uint16_t *__rest
         av[a] = row < m;
         arow[a] = Ad + (av[a] ? row : 0) * ld + 8 * q;
     }
-    const uint16_t *Vh = Vb + d * 2 * kp * ldv + (int64_t)ii * ldv + 8 * q;
-    const uint16_t *Vl = Vh + (int64_t)kp * ldv;
+    const uint16_t *Bh = Bb + d * 2 * kp * ldv + (int64_t)ii * ldv + 8 * q;
+    const uint16_t *Bl = Bh + (int64_t)kp * ldv;
     v4f acc[8][NT];
 #pragma unroll
     for (int a = 0; a < 8; ++a)
@@ -475,8 +358,8 @@ __global__ __launch_bounds__(64) void project_bf16_kernel(const uint16_t *__rest
         v4u vh[NT], vl[NT];
 #pragma unroll
         for (int b = 0; b < NT; ++b) {
-            vh[b] = *reinterpret_cast<const v4u *>(Vh + (int64_t)b * 16 * ldv + c0);
-            vl[b] = *reinterpret_cast<const v4u *>(Vl + (int64_t)b * 16 * ldv + c0);
+            vh[b] = *reinterpret_cast<const v4u *>(Bh + (int64_t)b * 16 * ldv + c0);
+            vl[b] = *reinterpret_cast<const v4u *>(Bl + (int64_t)b * 16 * ldv + c0);
         }
 #pragma unroll
         for (int a = 0; a < 8; ++a)
@@ -502,101 +385,168 @@ __global__ __launch_bounds__(64) void project_bf16_kernel(const uint16_t *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Rank-r truncation, outputs and the fused error.  One workgroup per matrix.
-//   H = C^T C (FP64), Jacobi -> Y, sigma^2 (descending); L = C Y_r,
-//   R = V Y_r; relerr from ||A||^2 - sum_{i<=r} sigma_i^2.
+// finish: one workgroup (256 threads) per matrix.
 // ---------------------------------------------------------------------------
 
-// Gram of the KP columns of C (m x KP row-major FP32): H[a][b] = sum_i
-// C[i][a] C[i][b], FP64, 4x4 register blocks x row slices (scratch: 4096).
-__device__ inline void col_gram(const float *__restrict__ Cm, int KP, int k, int64_t m, double *H, int ld,
-                                double *scratch) {
-    const int nb = (k + 3) / 4;
-    const int nblk = nb * (nb + 1) / 2;
-    const int ns = 256 / nblk;
-    const int tid = threadIdx.x;
-    const int sl = tid / nblk, blk = tid % nblk;
-    double acc[16];
+// T += Gram of the KP vectors (KP = 16 NT), FP64, by FP64 MFMA 16x16x4 with
+// FP32 data converted on load.  ROWS: the vectors are the rows of X
+// (KP x len, row stride ldx, entries in [len, round16(len)) zero and
+// addressable); otherwise the columns of X (len x KP, row stride KP).  The
+// four waves split the summation index; their tiles are added into T (LDS,
+// stride ld, zero-initialised by the caller) one wave after another, so the
+// result is reproducible.  Vectors k..KP-1 must be zero.
+template <int NT, bool ROWS>
+__device__ inline void gram_mfma_acc(const float *__restrict__ X, int64_t ldx, int64_t len, double *T, int ld) {
+    constexpr int KP = NT * 16, NPAIR = NT * (NT + 1) / 2;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = lane >> 4, ii = lane & 15;
+    v4d acc[NPAIR];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-    int ta = 0, tb = 0;
-    {
-        int e = blk, rr = 0, len = nb;
-        while (e >= len) {
-            e -= len;
-            ++rr;
-            --len;
+    for (int t = 0; t < NPAIR; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    if (ROWS) {
+        // K-steps of 16 columns: lane (q, i) holds columns c + 4q .. +3 of row
+        // t*16 + i; component u feeds MFMA u (same order on both operands)
+        const int64_t nst = (len + 15) / 16;
+        const int64_t s0 = nst * wv / 4, s1 = nst * (wv + 1) / 4;
+        for (int64_t st = s0; st < s1; ++st) {
+            const int64_t c = st * 16 + 4 * q;
+            float4 x[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) x[t] = *reinterpret_cast<const float4 *>(X + (int64_t)(t * 16 + ii) * ldx + c);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                double xv[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) xv[t] = (double)(u == 0 ? x[t].x : u == 1 ? x[t].y : u == 2 ? x[t].z : x[t].w);
+                int pr = 0;
+#pragma unroll
+                for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+                    for (int tb = ta; tb < NT; ++tb) {
+                        acc[pr] = mfma16x16x4_f64(xv[ta], xv[tb], acc[pr]);
+                        ++pr;
+                    }
+            }
         }
-        ta = rr;
-        tb = rr + e;
+    } else {
+        // K-steps of 4 rows: lane (q, i) holds row r + q, columns t*16 + i
+        const int64_t nst = (len + 3) / 4;
+        const int64_t s0 = nst * wv / 4, s1 = nst * (wv + 1) / 4;
+        constexpr int UH = 8;  // K-steps per iteration (all their loads issued first)
+        for (int64_t st = s0; st < s1; st += UH) {
+            float xf[UH][NT];
+#pragma unroll
+            for (int h = 0; h < UH; ++h) {
+                const int64_t row = (st + h) * 4 + q;
+                const bool ok = st + h < s1 && row < len;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) xf[h][t] = ok ? X[row * KP + t * 16 + ii] : 0.f;
+            }
+            double xv[UH][NT];
+#pragma unroll
+            for (int h = 0; h < UH; ++h)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) xv[h][t] = (double)xf[h][t];
+#pragma unroll
+            for (int h = 0; h < UH; ++h) {
+                int pr = 0;
+#pragma unroll
+                for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+                    for (int tb = ta; tb < NT; ++tb) {
+                        acc[pr] = mfma16x16x4_f64(xv[h][ta], xv[h][tb], acc[pr]);
+                        ++pr;
+                    }
+            }
+        }
     }
-    if (sl < ns) {
-        for (int64_t i = sl; i < m; i += ns) {
-            const float4 fa = *reinterpret_cast<const float4 *>(Cm + i * KP + 4 * ta);
-            const float4 fb = *reinterpret_cast<const float4 *>(Cm + i * KP + 4 * tb);
-            const float av[4] = {fa.x, fa.y, fa.z, fa.w}, bv[4] = {fb.x, fb.y, fb.z, fb.w};
+    // f64 result layout: lane holds D[q + 4r][i]
+    for (int w = 0; w < 4; ++w) {
+        if (wv == w) {
+            int pr = 0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int ta = 0; ta < NT; ++ta)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u * 4 + v] += (double)av[u] * (double)bv[v];
+                for (int tb = ta; tb < NT; ++tb) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int a = ta * 16 + q + 4 * r, b = tb * 16 + ii;
+                        T[a * ld + b] += acc[pr][r];
+                        if (ta != tb) T[b * ld + a] += acc[pr][r];
+                    }
+                    ++pr;
+                }
         }
+        __syncthreads();
     }
-    __syncthreads();
-    if (sl < ns) {
-#pragma unroll
-        for (int u = 0; u < 16; ++u) scratch[(sl * nblk + blk) * 16 + u] = acc[u];
-    }
-    __syncthreads();
-    for (int e = tid; e < nblk * 16; e += 256) {
-        const int bk = e / 16, u = e % 16;
-        double sum = 0.0;
-        for (int z = 0; z < ns; ++z) sum += scratch[(z * nblk + bk) * 16 + u];
-        int ee = bk, rr = 0, len = nb;
-        while (ee >= len) {
-            ee -= len;
-            ++rr;
-            --len;
-        }
-        const int a = 4 * rr + u / 4, b = 4 * (rr + ee) + u % 4;
-        if (a < k && b < k) {
-            H[a * ld + b] = sum;
-            H[b * ld + a] = sum;
-        }
+}
+
+// Y = op(X) M for KP x KP FP64 matrices in LDS (op = transpose when TA).
+template <int KP, bool TA>
+__device__ inline void small_mm(const double *X, const double *M, double *Y) {
+    for (int e = threadIdx.x; e < KP * KP; e += 256) {
+        const int i = e / KP, j = e % KP;
+        double s = 0.0;
+#pragma unroll 8
+        for (int u = 0; u < KP; ++u) s += (TA ? X[u * KP + i] : X[i * KP + u]) * M[u * KP + j];
+        Y[e] = s;
     }
     __syncthreads();
 }
 
 template <int KP>
-__global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ C, int64_t m, int k, int r,
-                                                     const float *__restrict__ Vt, int64_t ldv, int64_t n,
+__global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ B, int64_t ldb, int64_t n,
+                                                     const float *__restrict__ C, int64_t m, int k, int r,
                                                      const double *__restrict__ fro_part, int npanel,
-                                                     const int *__restrict__ qflag, float *__restrict__ L,
-                                                     float *__restrict__ R, float *__restrict__ sigma,
-                                                     double *__restrict__ relerr, int *__restrict__ flags) {
-    // H | W | Hn (KP*KP each); the Gram scratch (4096) overlaps W and Hn
-    constexpr int SCR = (3 * KP * KP > KP * KP + 4096) ? 3 * KP * KP : KP * KP + 4096;
-    __shared__ double lds[SCR];
-    __shared__ float Yr[KP * KP];  // first r eigenvector columns, descending
+                                                     float *__restrict__ L, float *__restrict__ R,
+                                                     float *__restrict__ sigma, double *__restrict__ relerr,
+                                                     int *__restrict__ flags) {
+    constexpr int SZ = KP * KP;
+    __shared__ double buf[3 * SZ];
+    __shared__ float Zs[KP * KP];          // Z = R^-1 Y_r (k x r, row stride KP)
     __shared__ double rot[KP];
-    __shared__ int pairs[(KP - 1) * (KP / 2)];
-    __shared__ int perm[KP];
     __shared__ double red4[4];
+    __shared__ int dead[KP];
+    __shared__ int perm[KP];
     __shared__ double s_lam[KP];
     const int64_t d = blockIdx.x;
     const int tid = threadIdx.x;
+    const float *Bd = B + d * KP * ldb;
     const float *Cd = C + d * m * KP;
-    double *H = lds, *W = lds + KP * KP, *Hn = lds + 2 * KP * KP;
-    for (int e = tid; e < KP * KP; e += 256) H[e] = 0.0;
+    double *b0 = buf, *b1 = buf + SZ, *b2 = buf + 2 * SZ;
+    // 1. B B^T = R^T R; X = R^-1 in b2 (b0 scratch, b1 = R)
+    for (int e = tid; e < SZ; e += 256) b0[e] = 0.0;
     __syncthreads();
-    col_gram(Cd, KP, k, m, H, KP, lds + KP * KP);
+    gram_mfma_acc<KP / 16, true>(Bd, ldb, n, b0, KP);
+    const int nd = chol_factor_inverse(b0, KP, KP, 1e-12, b1, b2, dead, k);
+    // 2. H = X^T (C^T C) X in b0
+    for (int e = tid; e < SZ; e += 256) b0[e] = 0.0;
+    __syncthreads();
+    gram_mfma_acc<KP / 16, false>(Cd, KP, m, b0, KP);
+    small_mm<KP, false>(b0, b2, b1);  // b1 = (C^T C) X
+    small_mm<KP, true>(b2, b1, b0);   // b0 = X^T b1
+    // 3. H = Y diag Y^T (Y^T in b1)
     const int kk = k + (k & 1);  // even size for the parallel ordering
-    H = jacobi_eig_lds(H, Hn, W, kk, KP, rot, pairs, 40, red4);
-    if (tid == 0) sort_diag_desc(H, kk, KP, perm);
+    jacobi_eig_wg<(KP * (KP + 2) / 8 + 255) / 256, (KP * KP / 2 + 255) / 256>(b0, b1, kk, KP, rot, 40, red4);
+    // descending order: rank of each diagonal entry (ties by index)
+    for (int i = tid; i < kk; i += 256) {
+        const double hi = b0[i * KP + i];
+        int rank = 0;
+        for (int j = 0; j < kk; ++j) {
+            const double hj = b0[j * KP + j];
+            rank += (hj > hi) || (hj == hi && j < i);
+        }
+        perm[rank] = i;
+    }
     __syncthreads();
-    for (int t = tid; t < kk; t += 256) s_lam[t] = H[perm[t] * KP + perm[t]];
-    for (int e = tid; e < KP * KP; e += 256) {
-        const int u = e / KP, t = e % KP;
-        Yr[e] = (u < k && t < r) ? (float)W[u * KP + perm[t]] : 0.f;
+    for (int t = tid; t < kk; t += 256) s_lam[t] = b0[perm[t] * KP + perm[t]];
+    // 4. Z = X Y_r (FP32 for the output products)
+    for (int e = tid; e < SZ; e += 256) {
+        const int i = e / KP, t = e % KP;
+        double z = 0.0;
+        if (i < k && t < r)
+            for (int u = 0; u < k; ++u) z += b2[i * KP + u] * b1[perm[t] * KP + u];
+        Zs[e] = (float)z;
     }
     __syncthreads();
     double fro2 = 0.0;
@@ -607,7 +557,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ C
     if (tid == 0) {
         double cap = 0.0;
         for (int t = 0; t < r; ++t) cap += fmax(s_lam[t], 0.0);
-        int fl = qflag[d];
+        int fl = nd > 0 ? TSK_FLAG_RANKDEF : 0;
         if (!finite) fl |= TSK_FLAG_NONFIN;
         const double sr = sqrt(fmax(s_lam[r - 1], 0.0)), sr1 = sqrt(fmax(s_lam[r], 0.0));
         const double s1 = sqrt(fmax(s_lam[0], 0.0));
@@ -615,7 +565,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ C
         if (flags) flags[d] = fl;
         if (relerr) relerr[d] = !finite ? (double)qnan : (fro2 > 0.0 ? sqrt(fmax(fro2 - cap, 0.0) / fro2) : 0.0);
     }
-    // L = C Y_r: one row of C per thread
+    // 5. L = C Z: one row of C per thread
     float *Ld = L + d * m * r;
     for (int64_t i = tid; i < m; i += 256) {
         float cv[KP];
@@ -630,21 +580,20 @@ __global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ C
         for (int t = 0; t < r; ++t) {
             float s = 0.f;
 #pragma unroll
-            for (int u = 0; u < KP; ++u) s += cv[u] * Yr[u * KP + t];
+            for (int u = 0; u < KP; ++u) s += cv[u] * Zs[u * KP + t];
             Ld[i * r + t] = finite ? s : qnan;
         }
     }
-    // R = V Y_r with V[j][u] = Vt[u][j]: one column of V^T per thread
-    const float *Vd = Vt + d * KP * ldv;
+    // 6. R = B^T Z: one column of B per thread
     float *Rd = R + d * n * r;
     for (int64_t j = tid; j < n; j += 256) {
         float vv[KP];
 #pragma unroll
-        for (int u = 0; u < KP; ++u) vv[u] = u < k ? Vd[u * ldv + j] : 0.f;
+        for (int u = 0; u < KP; ++u) vv[u] = u < k ? Bd[u * ldb + j] : 0.f;
         for (int t = 0; t < r; ++t) {
             float s = 0.f;
 #pragma unroll
-            for (int u = 0; u < KP; ++u) s += vv[u] * Yr[u * KP + t];
+            for (int u = 0; u < KP; ++u) s += vv[u] * Zs[u * KP + t];
             Rd[j * r + t] = finite ? s : qnan;
         }
     }
@@ -658,7 +607,7 @@ __global__ __launch_bounds__(256) void error_part_kernel(const float *__restrict
                                                          int64_t ld, int64_t stride, const float *__restrict__ L,
                                                          const float *__restrict__ R, int r,
                                                          double *__restrict__ part) {
-    __shared__ double Ls[16 * MAXK];
+    __shared__ double Ls[MAXK * 16];  // Ls[t * 16 + i] = L[i0 + i][t]
     __shared__ double red[4];
     const int64_t d = blockIdx.y;
     const int64_t i0 = (int64_t)blockIdx.x * 16;
@@ -666,21 +615,27 @@ __global__ __launch_bounds__(256) void error_part_kernel(const float *__restrict
     const float *Ld = L + d * m * r;
     const float *Rd = R + d * n * r;
     for (int e = threadIdx.x; e < 16 * r; e += 256) {
-        const int64_t i = i0 + e / r;
-        Ls[e] = i < m ? (double)Ld[i0 * r + e] : 0.0;
+        const int i = e / r, t = e % r;
+        Ls[t * 16 + i] = i0 + i < m ? (double)Ld[(i0 + i) * r + t] : 0.0;
     }
     __syncthreads();
     double res2 = 0.0, fro2 = 0.0;
     for (int64_t j = threadIdx.x; j < n; j += 256) {
-        double rj[MAXK];
-        for (int t = 0; t < r; ++t) rj[t] = (double)Rd[j * r + t];
+        double ah[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) ah[i] = 0.0;
+        for (int t = 0; t < r; ++t) {
+            const double rv = (double)Rd[j * r + t];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) ah[i] += Ls[t * 16 + i] * rv;
+        }
+#pragma unroll
         for (int i = 0; i < 16; ++i) {
-            if (i0 + i >= m) break;
-            double ah = 0.0;
-            for (int t = 0; t < r; ++t) ah += Ls[i * r + t] * rj[t];
-            const double a = (double)Ad[(i0 + i) * ld + j];
-            res2 += (a - ah) * (a - ah);
-            fro2 += a * a;
+            if (i0 + i < m) {
+                const double a = (double)Ad[(i0 + i) * ld + j];
+                res2 += (a - ah[i]) * (a - ah[i]);
+                fro2 += a * a;
+            }
         }
     }
     res2 = block_sum_f64(res2, red);
@@ -706,60 +661,59 @@ __global__ void error_final_kernel(const double *__restrict__ part, int nblk, in
 
 }  // namespace
 
+#define TSK_KP_SWITCH(KP16, M1, M2, M3, M4) \
+    switch (KP16) {                        \
+        case 1: M1; break;                 \
+        case 2: M2; break;                 \
+        case 3: M3; break;                 \
+        case 4: M4; break;                 \
+        default: return tsk_fail(c, TSK_E_ARG, "k > 64"); \
+    }
+
+static tsk_status finish_enqueue(tsk_ctx c, int kp, const float *B, int64_t ldv, int64_t n, const float *Cm,
+                                 int64_t m, int k, int r, const double *fro, int npanel, int64_t count, float *L,
+                                 float *R, float *sigma, double *relerr, int32_t *flags) {
+    const dim3 g((unsigned)count);
+#define TSK_FIN(KPV)                                                                                        \
+    TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                        \
+               hipLaunchKernelGGL(finish_kernel<KPV>, g, dim3(256), 0, c->stream, B, ldv, n, Cm, m, k, r, fro, \
+                                  npanel, L, R, sigma, relerr, flags))
+    TSK_KP_SWITCH(kp / 16, TSK_FIN(16), TSK_FIN(32), TSK_FIN(48), TSK_FIN(64))
+#undef TSK_FIN
+    return TSK_OK;
+}
+
 tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
                              float *sigma, double *relerr, int32_t *flags) {
     const int64_t m = s->m, n = s->n, count = s->count;
     const int kp = (k + 15) / 16 * 16;
-    const int64_t ldv = (n + 63) / 64 * 64;
     const int npanel = (int)((n + SK_PANEL - 1) / SK_PANEL);
+    const int64_t ldv = (int64_t)npanel * SK_PANEL;  // whole panels
     TSK_TRY(tsk_grow(c, c->ap_St, sizeof(float) * m * kp));
     TSK_TRY(tsk_grow(c, c->ap_B, sizeof(float) * count * kp * ldv));
-    TSK_TRY(tsk_grow(c, c->ap_Vt, sizeof(float) * count * kp * ldv));
     TSK_TRY(tsk_grow(c, c->ap_C, sizeof(float) * count * m * kp));
     TSK_TRY(tsk_grow(c, c->ap_fro, sizeof(double) * count * npanel));
-    TSK_TRY(tsk_grow(c, c->ap_qflag, sizeof(int) * count));
-    float *St = (float *)c->ap_St.p, *B = (float *)c->ap_B.p, *Vt = (float *)c->ap_Vt.p, *Cm = (float *)c->ap_C.p;
+    float *St = (float *)c->ap_St.p, *B = (float *)c->ap_B.p, *Cm = (float *)c->ap_C.p;
     double *fro = (double *)c->ap_fro.p;
-    int *qflag = (int *)c->ap_qflag.p;
     const float *A = (const float *)s->A;
     TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
                hipLaunchKernelGGL(transpose_sketch_kernel, dim3((unsigned)((m * kp + 255) / 256)), dim3(256), 0,
                                   c->stream, S, k, kp, m, St));
     const dim3 gs((unsigned)npanel, (unsigned)count);
-    switch (kp / 16) {
-        case 1: TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_kernel<1>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)St, B, ldv, fro, npanel)); break;
-        case 2: TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_kernel<2>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)St, B, ldv, fro, npanel)); break;
-        case 3: TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_kernel<3>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)St, B, ldv, fro, npanel)); break;
-        case 4: TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_kernel<4>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)St, B, ldv, fro, npanel)); break;
-        default: return tsk_fail(c, TSK_E_ARG, "k > 64");
-    }
-    const dim3 gq((unsigned)count);
-    switch (kp / 16) {
-        case 1: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<16>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag, (uint16_t *)nullptr)); break;
-        case 2: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<32>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag, (uint16_t *)nullptr)); break;
-        case 3: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<48>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag, (uint16_t *)nullptr)); break;
-        case 4: TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<64>, gq, dim3(256), 0, c->stream, (const float *)B, ldv, Vt, k, n, qflag, (uint16_t *)nullptr)); break;
-    }
+#define TSK_SK(MTV)                                                                                             \
+    TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                            \
+               hipLaunchKernelGGL(sketch_f32_kernel<MTV>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, \
+                                  (const float *)St, B, ldv, fro, npanel))
+    TSK_KP_SWITCH(kp / 16, TSK_SK(1), TSK_SK(2), TSK_SK(3), TSK_SK(4))
+#undef TSK_SK
     const dim3 gp((unsigned)((m + PJ_ROWS - 1) / PJ_ROWS), (unsigned)count);
-    switch (kp / 16) {
-        case 1: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<1>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
-        case 2: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<2>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
-        case 3: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<3>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
-        case 4: TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_kernel<4>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, (const float *)Vt, ldv, Cm)); break;
-    }
-#define TSK_FINISH(KPV)                                                                                        \
-    TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                           \
-               hipLaunchKernelGGL(finish_kernel<KPV>, dim3((unsigned)count), dim3(256), 0, c->stream,          \
-                                  (const float *)Cm, m, k, r, (const float *)Vt, ldv, n, (const double *)fro, \
-                                  npanel, (const int *)qflag, L, R, sigma, relerr, flags))
-    switch (kp / 16) {
-        case 1: TSK_FINISH(16); break;
-        case 2: TSK_FINISH(32); break;
-        case 3: TSK_FINISH(48); break;
-        case 4: TSK_FINISH(64); break;
-    }
-#undef TSK_FINISH
-    return TSK_OK;
+#define TSK_PJ(NTV)                                                                                           \
+    TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                         \
+               hipLaunchKernelGGL(project_f32_kernel<NTV>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, \
+                                  (const float *)B, ldv, Cm))
+    TSK_KP_SWITCH(kp / 16, TSK_PJ(1), TSK_PJ(2), TSK_PJ(3), TSK_PJ(4))
+#undef TSK_PJ
+    return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags);
 }
 
 tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
@@ -767,19 +721,16 @@ tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_st
     const int64_t m = s->m, n = s->n, count = s->count;
     const int kp = (k + 15) / 16 * 16;
     const int64_t mp = (m + 31) / 32 * 32;
-    const int64_t ldv = (n + 63) / 64 * 64;
     const int npanel = (int)((n + SKB_PANEL - 1) / SKB_PANEL);
+    const int64_t ldv = (int64_t)npanel * SKB_PANEL;  // whole panels
     TSK_TRY(tsk_grow(c, c->ap_Sb, sizeof(uint16_t) * 2 * kp * mp));
     TSK_TRY(tsk_grow(c, c->ap_B, sizeof(float) * count * kp * ldv));
-    TSK_TRY(tsk_grow(c, c->ap_Vt, sizeof(float) * count * kp * ldv));
-    TSK_TRY(tsk_grow(c, c->ap_Vb, sizeof(uint16_t) * count * 2 * kp * ldv));
+    TSK_TRY(tsk_grow(c, c->ap_Bb, sizeof(uint16_t) * count * 2 * kp * ldv));
     TSK_TRY(tsk_grow(c, c->ap_C, sizeof(float) * count * m * kp));
     TSK_TRY(tsk_grow(c, c->ap_fro, sizeof(double) * count * npanel));
-    TSK_TRY(tsk_grow(c, c->ap_qflag, sizeof(int) * count));
-    uint16_t *Sb = (uint16_t *)c->ap_Sb.p, *Vb = (uint16_t *)c->ap_Vb.p;
-    float *B = (float *)c->ap_B.p, *Vt = (float *)c->ap_Vt.p, *Cm = (float *)c->ap_C.p;
+    uint16_t *Sb = (uint16_t *)c->ap_Sb.p, *Bb = (uint16_t *)c->ap_Bb.p;
+    float *B = (float *)c->ap_B.p, *Cm = (float *)c->ap_C.p;
     double *fro = (double *)c->ap_fro.p;
-    int *qflag = (int *)c->ap_qflag.p;
     const uint16_t *A = (const uint16_t *)s->A;
     TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
                hipLaunchKernelGGL(prep_sketch_bf16_kernel, dim3((unsigned)((kp * mp + 255) / 256)), dim3(256), 0,
@@ -788,51 +739,17 @@ tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_st
 #define TSK_SKB(MTV)                                                                                              \
     TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                              \
                hipLaunchKernelGGL(sketch_bf16_kernel<MTV>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, \
-                                  (const uint16_t *)Sb, mp, B, ldv, fro, npanel))
-    switch (kp / 16) {
-        case 1: TSK_SKB(1); break;
-        case 2: TSK_SKB(2); break;
-        case 3: TSK_SKB(3); break;
-        case 4: TSK_SKB(4); break;
-        default: return tsk_fail(c, TSK_E_ARG, "k > 64");
-    }
+                                  (const uint16_t *)Sb, mp, B, Bb, ldv, fro, npanel))
+    TSK_KP_SWITCH(kp / 16, TSK_SKB(1), TSK_SKB(2), TSK_SKB(3), TSK_SKB(4))
 #undef TSK_SKB
-    const dim3 gq((unsigned)count);
-#define TSK_QRB(KPV)                                                                                  \
-    TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(cholqr2_kernel<KPV>, gq, dim3(256), 0, c->stream, \
-                                                    (const float *)B, ldv, Vt, k, n, qflag, Vb))
-    switch (kp / 16) {
-        case 1: TSK_QRB(16); break;
-        case 2: TSK_QRB(32); break;
-        case 3: TSK_QRB(48); break;
-        case 4: TSK_QRB(64); break;
-    }
-#undef TSK_QRB
     const dim3 gp((unsigned)((m + PJB_ROWS - 1) / PJB_ROWS), (unsigned)count);
 #define TSK_PJB(NTV)                                                                                     \
     TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                    \
                hipLaunchKernelGGL(project_bf16_kernel<NTV>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, \
-                                  s->stride, (const uint16_t *)Vb, ldv, Cm))
-    switch (kp / 16) {
-        case 1: TSK_PJB(1); break;
-        case 2: TSK_PJB(2); break;
-        case 3: TSK_PJB(3); break;
-        case 4: TSK_PJB(4); break;
-    }
+                                  s->stride, (const uint16_t *)Bb, ldv, Cm))
+    TSK_KP_SWITCH(kp / 16, TSK_PJB(1), TSK_PJB(2), TSK_PJB(3), TSK_PJB(4))
 #undef TSK_PJB
-#define TSK_FINISH(KPV)                                                                                        \
-    TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                           \
-               hipLaunchKernelGGL(finish_kernel<KPV>, dim3((unsigned)count), dim3(256), 0, c->stream,          \
-                                  (const float *)Cm, m, k, r, (const float *)Vt, ldv, n, (const double *)fro, \
-                                  npanel, (const int *)qflag, L, R, sigma, relerr, flags))
-    switch (kp / 16) {
-        case 1: TSK_FINISH(16); break;
-        case 2: TSK_FINISH(32); break;
-        case 3: TSK_FINISH(48); break;
-        case 4: TSK_FINISH(64); break;
-    }
-#undef TSK_FINISH
-    return TSK_OK;
+    return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags);
 }
 
 tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, const float *R, int r, double *relerr) {

@@ -205,8 +205,8 @@ void tsk_destroy(tsk_ctx c) {
     drain_events(c);
     TskBuf *bufs[] = {&c->gram_part, &c->gram_G,  &c->eig_Y0,   &c->eig_Y1, &c->eig_Rinv, &c->eig_part,
                       &c->eig_C,     &c->eig_X,   &c->eig_GX,   &c->eig_small, &c->eig_U, &c->counters,
-                      &c->ap_St,     &c->ap_B,    &c->ap_Vt,    &c->ap_C,   &c->ap_fro,   &c->ap_qflag,
-                      &c->ap_Sb,     &c->ap_Vb,   &c->er_part,  &c->st_part};
+                      &c->ap_St,     &c->ap_B,    &c->ap_C,     &c->ap_fro, &c->ap_Sb,    &c->ap_Bb,
+                      &c->er_part,   &c->st_part};
     for (TskBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);

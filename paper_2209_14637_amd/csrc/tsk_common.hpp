@@ -214,6 +214,186 @@ __device__ inline double *jacobi_eig_lds(double *H, double *Hn, double *W, int p
     return H;
 }
 
+// Slot t of round rd of the round-robin pairing of p players (player 0
+// fixed, the others rotated by rd): returns (a, b), a < b.  Pure arithmetic,
+// so no pairing table has to be read in the inner loops.
+__device__ __forceinline__ void rr_pair(int t, int rd, int p, int &a, int &b) {
+    int ia = 0;
+    if (t != 0) {
+        ia = t - 1 + rd;
+        if (ia >= p - 1) ia -= p - 1;
+        ia += 1;
+    }
+    int ib = p - 2 - t + rd;
+    if (ib >= p - 1) ib -= p - 1;
+    ib += 1;
+    a = ia < ib ? ia : ib;
+    b = ia < ib ? ib : ia;
+}
+
+// Cyclic Jacobi for a symmetric p x p FP64 matrix in LDS, one workgroup of
+// 256 threads, in place.  Each round rotates the p/2 disjoint pairs of the
+// round-robin ordering: the rotations are computed by p/2 threads into rot,
+// then every 2x2 block (P, Q), P <= Q, of J^T H J is rewritten by one thread
+// together with its mirror image (the blocks are disjoint, so no second
+// buffer is needed) and the eigenvector matrix is updated, W <- W J, stored
+// TRANSPOSED (Wt[j][i] = W[i][j]).  A thread's blocks and items are fixed
+// pair SLOTS; the indices occupying a slot advance by one (cyclically over
+// 1..p-1, index 0 fixed) from round to round, so they are updated by an
+// increment instead of being recomputed, and every load of a round is issued
+// before its arithmetic.  Stops when the off-diagonal mass is below
+// 1e-20 ||H||_F^2 (quadratic convergence makes the eigenvalues exact to
+// rounding well before).  MAXB >= ceil(p(p+2)/8 / 256),
+// MAXW >= ceil(p^2/2 / 256).  On exit H is diagonal to rounding and
+// H_in = W diag W^T.  p even <= 64; rot: p doubles.
+template <int MAXB, int MAXW>
+__device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, double *rot, int max_sweeps,
+                                     double *red4) {
+    const int tid = threadIdx.x;
+    const int half = p / 2;
+    double tot = 0.0;
+    for (int e = tid; e < p * p; e += 256) {
+        const int i = e / p, j = e % p;
+        Wt[i * ld + j] = (i == j) ? 1.0 : 0.0;
+        const double h = H[i * ld + j];
+        tot += h * h;
+    }
+    tot = block_sum_f64(tot, red4);
+    // slot -> indices at round 0 (rr_pair(t, 0)); ordered pairs (first,
+    // second) are kept as produced, the rotation convention only needs the
+    // same order in every use
+    auto slot0 = [&](int t, int &a, int &b) {
+        a = t == 0 ? 0 : t;
+        b = p - 1 - t;
+    };
+    auto adv = [&](int x) { return x == 0 ? 0 : (x == p - 1 ? 1 : x + 1); };
+    // fixed work items: blocks along the diagonals Q - P = 0, 1, ... and W
+    // items row-fastest, so neighbouring threads touch different rows AND
+    // columns (the row stride may be a multiple of the LDS bank count)
+    const int nblk = half * (half + 1) / 2;
+    bool bv[MAXB], wv_[MAXW];
+    int bA[MAXB], bB[MAXB], bX[MAXB], bY[MAXB], bP[MAXB], bQ[MAXB];
+    int wI[MAXW], wX[MAXW], wY[MAXW], wQ[MAXW];
+    {
+        int dg = 0, off = 0;
+#pragma unroll
+        for (int u = 0; u < MAXB; ++u) {
+            const int e = tid + 256 * u;
+            int P = 0, Q = 0;
+            bv[u] = e < nblk;
+            if (bv[u]) {
+                while (e - off >= half - dg) {
+                    off += half - dg;
+                    ++dg;
+                }
+                P = e - off;
+                Q = P + dg;
+            }
+            bP[u] = P;
+            bQ[u] = Q;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < MAXW; ++u) {
+        const int e = tid + 256 * u;
+        wv_[u] = e < p * half;
+        wI[u] = wv_[u] ? e % p : 0;
+        wQ[u] = wv_[u] ? e / p : 0;
+    }
+    int tA = 0, tB = 1;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        double off = 0.0;
+        for (int e = tid; e < p * p; e += 256) {
+            const int i = e / p, j = e % p;
+            const double h = H[i * ld + j];
+            if (i != j) off += h * h;
+        }
+        off = block_sum_f64(off, red4);
+        if (off <= 1e-20 * tot || tot == 0.0) break;
+        // indices of every slot at round 0 (the cycle returns there after
+        // p - 1 rounds)
+        if (tid < half) slot0(tid, tA, tB);
+#pragma unroll
+        for (int u = 0; u < MAXB; ++u) {
+            slot0(bP[u], bA[u], bB[u]);
+            slot0(bQ[u], bX[u], bY[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < MAXW; ++u) slot0(wQ[u], wX[u], wY[u]);
+#pragma nounroll
+        for (int rd = 0; rd < p - 1; ++rd) {
+            if (tid < half) {
+                double cc, ss;
+                jacobi_rot(H, ld, tA, tB, cc, ss);
+                rot[2 * tid] = cc;
+                rot[2 * tid + 1] = ss;
+            }
+            __syncthreads();
+            // blocks: gather (unused slots read block (0, 0): in bounds,
+            // never stored), then compute and write
+            double hv[MAXB][4], rv[MAXB][4];
+#pragma unroll
+            for (int u = 0; u < MAXB; ++u) {
+                const int a = bA[u], b = bB[u], x = bX[u], y = bY[u];
+                rv[u][0] = rot[2 * bP[u]]; rv[u][1] = rot[2 * bP[u] + 1];
+                rv[u][2] = rot[2 * bQ[u]]; rv[u][3] = rot[2 * bQ[u] + 1];
+                hv[u][0] = H[a * ld + x]; hv[u][1] = H[a * ld + y];
+                hv[u][2] = H[b * ld + x]; hv[u][3] = H[b * ld + y];
+            }
+#pragma unroll
+            for (int u = 0; u < MAXB; ++u) {
+                const double cp = rv[u][0], sp = rv[u][1], cq = rv[u][2], sq = rv[u][3];
+                const double hax = hv[u][0], hay = hv[u][1], hbx = hv[u][2], hby = hv[u][3];
+                const double tax = cq * hax - sq * hay, tay = sq * hax + cq * hay;
+                const double tbx = cq * hbx - sq * hby, tby = sq * hbx + cq * hby;
+                const double nax = cp * tax - sp * tbx, nay = cp * tay - sp * tby;
+                const double nbx = sp * tax + cp * tbx, nby = sp * tay + cp * tby;
+                const int a = bA[u], b = bB[u], x = bX[u], y = bY[u];
+                if (bv[u]) {
+                    H[a * ld + x] = nax;
+                    H[a * ld + y] = nay;
+                    H[b * ld + x] = nbx;
+                    H[b * ld + y] = nby;
+                    if (bP[u] != bQ[u]) {  // off-diagonal block: its mirror image too
+                        H[x * ld + a] = nax;
+                        H[y * ld + a] = nay;
+                        H[x * ld + b] = nbx;
+                        H[y * ld + b] = nby;
+                    }
+                }
+            }
+            // W items: gather, compute, write
+            double wv[MAXW][2], wr[MAXW][2];
+#pragma unroll
+            for (int u = 0; u < MAXW; ++u) {
+                wr[u][0] = rot[2 * wQ[u]]; wr[u][1] = rot[2 * wQ[u] + 1];
+                wv[u][0] = Wt[wX[u] * ld + wI[u]]; wv[u][1] = Wt[wY[u] * ld + wI[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < MAXW; ++u) {
+                const double cq = wr[u][0], sq = wr[u][1], w0 = wv[u][0], w1 = wv[u][1];
+                if (wv_[u]) {
+                    Wt[wX[u] * ld + wI[u]] = cq * w0 - sq * w1;
+                    Wt[wY[u] * ld + wI[u]] = sq * w0 + cq * w1;
+                }
+            }
+            // next round: every slot's indices advance
+            tA = adv(tA);
+            tB = adv(tB);
+#pragma unroll
+            for (int u = 0; u < MAXB; ++u) {
+                bA[u] = adv(bA[u]); bB[u] = adv(bB[u]); bX[u] = adv(bX[u]); bY[u] = adv(bY[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < MAXW; ++u) {
+                wX[u] = adv(wX[u]);
+                wY[u] = adv(wY[u]);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // Stable descending order of the diagonal of H (p entries) into perm; run by
 // thread 0 only, callers sync afterwards.
 __device__ inline void sort_diag_desc(const double *H, int p, int ld, int *perm) {
@@ -383,8 +563,8 @@ struct tsk_ctx_s {
     TskBuf gram_part, gram_G;
     TskBuf eig_Y0, eig_Y1, eig_Rinv, eig_part, eig_C, eig_X, eig_GX, eig_small, eig_U;
     TskBuf counters;
-    TskBuf ap_St, ap_B, ap_Vt, ap_C, ap_fro, ap_qflag;
-    TskBuf ap_Sb, ap_Vb;  // bf16 hi/lo copies of S and V^T (bf16 path)
+    TskBuf ap_St, ap_B, ap_C, ap_fro;
+    TskBuf ap_Sb, ap_Bb;  // bf16 hi/lo pairs of S and B (bf16 path)
     TskBuf er_part, st_part;
     // eigensolver controls
     int eig_block = 0, eig_max_iter = 300, eig_check = 4;

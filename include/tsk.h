@@ -167,11 +167,14 @@ tsk_status tsk_error(tsk_ctx ctx, const tsk_stack *A, const float *L, const floa
 
 /* Eigensolver controls (defaults in brackets): block = search-block width p
  * [k + max(12, k/2), at most 64 and at most m]; max_iter = cap on filtered
- * subspace steps [300]; tol = residual tolerance relative to theta_1 [1e-7,
- * the rounding level of an FP32-accumulated Gram, so the Ritz vectors are
- * exact eigenvectors of a matrix within that distance of G]; check =
- * filtered steps between convergence tests [4].  A value <= 0 restores the
- * default. */
+ * subspace steps [300]; tol = residual tolerance relative to theta_1 [by
+ * the precision of the Gram's products: 1e-7 for FP32 (the rounding level
+ * of FP32 accumulation, so the Ritz vectors are exact eigenvectors of a
+ * matrix within that distance of G), 1e-5 for bf16 (rounding the data to
+ * bf16 already moves G by about 1e-4 theta_1); tsk_eig_topk uses 1e-7];
+ * check = filtered steps to the first convergence test [4]; later tests are
+ * placed where the observed residual decay predicts convergence (at most
+ * 4 * check steps apart).  A value <= 0 restores the default. */
 tsk_status tsk_set_eig_params(tsk_ctx ctx, int32_t block, int32_t max_iter, double tol,
                               int32_t check);
 

@@ -370,17 +370,18 @@ __global__ __launch_bounds__(256) void eig_gx_kernel(const double *__restrict__ 
     block_gram(Xs, Zs, pp, part + (int64_t)blockIdx.x * ntri);
     if (!last_block(counter)) return;
     __shared__ double rot[EIG_MAXPP];
-    __shared__ int pairs[(EIG_MAXPP - 1) * (EIG_MAXPP / 2)];
     __shared__ int perm[EIG_MAXPP];
     __shared__ double red4[4];
     double *H = lds, *W = lds + pp * pp, *Hn = lds + 2 * pp * pp;
     reduce_tri(part, gridDim.x, pp, H);
-    H = jacobi_eig_lds(H, Hn, W, pp, pp, rot, pairs, 40, red4);
+    (void)Hn;
+    jacobi_eig_wg<(EIG_MAXPP * (EIG_MAXPP + 2) / 8 + 255) / 256, (EIG_MAXPP * EIG_MAXPP / 2 + 255) / 256>(
+        H, W, pp, pp, rot, 40, red4);  // W holds the eigenvectors transposed
     if (threadIdx.x == 0) sort_diag_desc(H, pp, pp, perm);
     __syncthreads();
     for (int t = threadIdx.x; t < pp * pp; t += blockDim.x) {
         const int i = t / pp, j = t % pp;
-        small[SM_W + t] = W[i * pp + perm[j]];
+        small[SM_W + t] = W[perm[j] * pp + i];
     }
     for (int j = threadIdx.x; j < pp; j += blockDim.x) small[SM_THETA + j] = H[perm[j] * pp + perm[j]];
     if (threadIdx.x == 0) {
@@ -494,7 +495,7 @@ __global__ void eig_emit_kernel(const double *__restrict__ X, const double *__re
 }  // namespace
 
 tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *S, double *lambda,
-                           int32_t *iters_out) {
+                           int32_t *iters_out, double tol_default) {
     const int qx = k / 2 > 12 ? k / 2 : 12;
     int p = c->eig_block > 0 ? c->eig_block : k + qx;
     if (p > EIG_MAXPP) p = EIG_MAXPP;
@@ -542,7 +543,7 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
                            "LDS attribute");
     }
     const double tol_chol = 1e-26;
-    const double tol = c->eig_tol > 0 ? c->eig_tol : 1e-7;
+    const double tol = c->eig_tol > 0 ? c->eig_tol : tol_default;
     const dim3 gmv((unsigned)nmv, (unsigned)KS);
 
     auto mv = [&](const double *in) -> tsk_status {
@@ -609,13 +610,19 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
     TSK_TRY(gx(1));
     TSK_TRY(rot());
 
+    // Convergence checks (Rayleigh-Ritz + residuals) are spaced adaptively:
+    // after two checks the per-step decay of the largest residual predicts
+    // how many filtered steps remain, and the next check is placed there
+    // (at least 1, at most 4 x `check` steps away).
     const int check = c->eig_check > 0 ? c->eig_check : 4;
     const int max_steps = c->eig_max_iter > 0 ? c->eig_max_iter : 300;
     int steps = 0;
     double hs[2] = {0.0, 0.0};
     bool converged = false;
+    int next = check;
+    double prev_res = -1.0;
     while (steps < max_steps) {
-        const int nb = (max_steps - steps < check) ? max_steps - steps : check;
+        const int nb = (max_steps - steps < next) ? max_steps - steps : next;
         for (int s = 0; s < nb; ++s) TSK_TRY(filter_step(s == nb - 1));
         TSK_TRY(rot());
         steps += nb;
@@ -627,6 +634,16 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
             converged = true;
             break;
         }
+        const double res = hs[SM_RES];
+        next = check;
+        if (prev_res > 0.0 && res > 0.0 && res < prev_res) {
+            const double rate = pow(res / prev_res, 1.0 / nb);  // per filtered step
+            const double need = log(tol / res) / log(rate);
+            if (need > 0.0 && need < 1e6) next = (int)ceil(need);
+            if (next < 1) next = 1;
+            if (next > 4 * check) next = 4 * check;
+        }
+        prev_res = res;
     }
     TSK_LAUNCH(c, TSK_KERNEL_EIG_RR,
                hipLaunchKernelGGL(eig_emit_kernel, dim3((unsigned)((m * k + 255) / 256)), dim3(256), 0, c->stream,

@@ -10,7 +10,7 @@ tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *
 tsk_status tsk_stage_enqueue(tsk_ctx c, const tsk_stack *s, int dtype, void *dst, int64_t ldd, int64_t strided,
                              float *scale, double *norm2);
 tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *S, double *lambda,
-                           int32_t *iters_out);
+                           int32_t *iters_out, double tol_default);
 tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
                              float *sigma, double *relerr, int32_t *flags);
 tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
@@ -264,7 +264,7 @@ tsk_status tsk_eig_topk(tsk_ctx c, const double *G, int64_t m, int32_t k, float 
     if (!lambda) return tsk_fail(c, TSK_E_ARG, "tsk_eig_topk: lambda is required");
     TSK_TRY(tsk_check_dev(c, G, sizeof(double) * m * m, "G"));
     TSK_TRY(tsk_check_dev(c, S, sizeof(float) * k * m, "S"));
-    tsk_status st = tsk_eig_enqueue(c, G, m, k, S, lambda, iters);
+    tsk_status st = tsk_eig_enqueue(c, G, m, k, S, lambda, iters, TSK_EIG_TOL_F32);
     return st;
 }
 
@@ -283,7 +283,7 @@ tsk_status tsk_train(tsk_ctx c, const tsk_stack *train, int32_t k, int32_t compu
     TSK_TRY(tsk_grow(c, c->gram_G, sizeof(double) * m * m));
     double *G = (double *)c->gram_G.p;
     TSK_TRY(tsk_gram_enqueue(c, train, compute, G));
-    return tsk_eig_enqueue(c, G, m, k, S, lambda, iters);
+    return tsk_eig_enqueue(c, G, m, k, S, lambda, iters, compute == TSK_BF16 ? TSK_EIG_TOL_BF16 : TSK_EIG_TOL_F32);
 }
 
 tsk_status tsk_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test, int32_t r, int32_t compute,
@@ -327,7 +327,7 @@ tsk_status tsk_set_eig_params(tsk_ctx c, int32_t block, int32_t max_iter, double
     if (!c) return TSK_E_ARG;
     c->eig_block = block > 0 ? block : 0;
     c->eig_max_iter = max_iter > 0 ? max_iter : 300;
-    c->eig_tol = tol > 0 ? tol : 1e-7;
+    c->eig_tol = tol > 0 ? tol : 0.0;  // 0: the default for the Gram's precision
     c->eig_check = check > 0 ? check : 4;
     return TSK_OK;
 }

@@ -79,18 +79,11 @@ __device__ __forceinline__ double block_sum_f64(double v, double *scratch4) {
 }
 
 // ---------------------------------------------------------------------------
-// Cyclic Jacobi eigensolver for a symmetric p x p FP64 matrix held in LDS,
-// run by one whole workgroup.  Parallel (round-robin) ordering: each round
-// rotates p/2 disjoint index pairs, p-1 rounds per sweep; the pairing of
-// every round is tabulated once in LDS.  Because the pairs are disjoint,
-// H' = J^T H J splits into independent 2x2 blocks J_P^T H_PQ J_Q.  A round
-// is: the p/2 rotations (one thread each) into LDS, barrier, every 2x2 block
-// of H' written into Hn and W <- W J, barrier, swap H and Hn.  The Frobenius
-// norm is invariant, so the stopping test needs only the off-diagonal mass.
-// On exit the returned buffer is (numerically) diagonal and W holds the
-// eigenvectors as columns (H_in = W diag W^T).  p must be even (pad with a
-// zero row/column), p <= 64; ld is the row stride of H, Hn and W.
-// LDS scratch: rot (p doubles), ptab ((p-1)*(p/2) ints).
+// Cyclic Jacobi eigensolver pieces (Golub & Van Loan, Section 8.5): parallel
+// round-robin ordering, each round rotates p/2 disjoint index pairs, p-1
+// rounds per sweep.  Because the pairs are disjoint, H' = J^T H J splits
+// into independent 2x2 blocks J_P^T H_PQ J_Q.  The Frobenius norm is
+// invariant, so the stopping test needs only the off-diagonal mass.
 // ---------------------------------------------------------------------------
 // Reciprocal and reciprocal square root from the hardware FP64 estimates
 // refined by Newton-Raphson steps (each step squares the relative error).
@@ -122,96 +115,6 @@ __device__ __forceinline__ void jacobi_rot(const double *H, int ld, int a, int b
         c = rsq_nr(1.0 + t * t);
         s = t * c;
     }
-}
-
-__device__ inline double *jacobi_eig_lds(double *H, double *Hn, double *W, int p, int ld, double *rot, int *ptab,
-                                         int max_sweeps, double *red4) {
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const int half = p / 2;
-    // pairing table: round r, slot t -> (a, b), a < b; player 0 fixed, the
-    // others rotated by r
-    for (int e = tid; e < (p - 1) * half; e += nth) {
-        const int r = e / half, t = e % half;
-        const int ia = (t == 0) ? 0 : 1 + ((t - 1 + r) % (p - 1));
-        const int ib = 1 + ((p - 2 - t + r) % (p - 1));
-        ptab[e] = ia < ib ? (ia | (ib << 8)) : (ib | (ia << 8));
-    }
-    double tot = 0.0;
-    for (int e = tid; e < p * p; e += nth) {
-        const int i = e / p, j = e % p;
-        W[i * ld + j] = (i == j) ? 1.0 : 0.0;
-        const double h = H[i * ld + j];
-        tot += h * h;
-    }
-    tot = block_sum_f64(tot, red4);  // includes a barrier: ptab and W ready
-    // this thread's 2x2 blocks (P, Q) and W items (row i, pair Q): fixed
-    constexpr int MAXB = 4;  // (64/2)^2 / 256 blocks per thread at most
-    int bP[MAXB], bQ[MAXB], wI[MAXB * 2], wQ[MAXB * 2];
-#pragma unroll
-    for (int u = 0; u < MAXB; ++u) {
-        const int e = tid + nth * u;
-        bP[u] = e < half * half ? e / half : -1;
-        bQ[u] = e < half * half ? e % half : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < 2 * MAXB; ++u) {
-        const int e = tid + nth * u;
-        wI[u] = e < p * half ? e / half : -1;
-        wQ[u] = e < p * half ? e % half : 0;
-    }
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        double off = 0.0;
-        for (int e = tid; e < p * p; e += nth) {
-            const int i = e / p, j = e % p;
-            const double h = H[i * ld + j];
-            if (i != j) off += h * h;
-        }
-        off = block_sum_f64(off, red4);
-        if (off <= 1e-30 * tot || tot == 0.0) break;
-        for (int round = 0; round < p - 1; ++round) {
-            const int *pr = ptab + round * half;
-            if (tid < half) {
-                const int ab = pr[tid];
-                double cc, ss;
-                jacobi_rot(H, ld, ab & 255, ab >> 8, cc, ss);
-                rot[2 * tid] = cc;
-                rot[2 * tid + 1] = ss;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < MAXB; ++u) {
-                if (bP[u] < 0) continue;
-                const int ab = pr[bP[u]], xy = pr[bQ[u]];
-                const int a = ab & 255, b = ab >> 8, x = xy & 255, y = xy >> 8;
-                const double cp = rot[2 * bP[u]], sp = rot[2 * bP[u] + 1];
-                const double cq = rot[2 * bQ[u]], sq = rot[2 * bQ[u] + 1];
-                const double hax = H[a * ld + x], hay = H[a * ld + y], hbx = H[b * ld + x], hby = H[b * ld + y];
-                // columns: x' = cq x - sq y, y' = sq x + cq y
-                const double tax = cq * hax - sq * hay, tay = sq * hax + cq * hay;
-                const double tbx = cq * hbx - sq * hby, tby = sq * hbx + cq * hby;
-                // rows: a' = cp a - sp b, b' = sp a + cp b
-                Hn[a * ld + x] = cp * tax - sp * tbx;
-                Hn[a * ld + y] = cp * tay - sp * tby;
-                Hn[b * ld + x] = sp * tax + cp * tbx;
-                Hn[b * ld + y] = sp * tay + cp * tby;
-            }
-#pragma unroll
-            for (int u = 0; u < 2 * MAXB; ++u) {
-                if (wI[u] < 0) continue;
-                const int xy = pr[wQ[u]], i = wI[u];
-                const int x = xy & 255, y = xy >> 8;
-                const double cq = rot[2 * wQ[u]], sq = rot[2 * wQ[u] + 1];
-                const double wx = W[i * ld + x], wy = W[i * ld + y];
-                W[i * ld + x] = cq * wx - sq * wy;
-                W[i * ld + y] = sq * wx + cq * wy;
-            }
-            __syncthreads();
-            double *t = H;
-            H = Hn;
-            Hn = t;
-        }
-    }
-    return H;
 }
 
 // Slot t of round rd of the round-robin pairing of p players (player 0
@@ -568,7 +471,7 @@ struct tsk_ctx_s {
     TskBuf er_part, st_part;
     // eigensolver controls
     int eig_block = 0, eig_max_iter = 300, eig_check = 4;
-    double eig_tol = 1e-7;
+    double eig_tol = 0.0;  // 0: TSK_EIG_TOL_F32 / TSK_EIG_TOL_BF16 by the Gram's precision
     // timing
     uint32_t timing = 0;  // bit i: bracket launches of kernel class i with events
     std::vector<TskEvent> pending;
@@ -576,6 +479,15 @@ struct tsk_ctx_s {
     int64_t launches[TSK_KERNEL_COUNT] = {};
     double ms[TSK_KERNEL_COUNT] = {};
 };
+
+// Default residual tolerances of the eigensolver, relative to theta_1, by the
+// precision of the Gram's products.  FP32: the rounding level of FP32
+// accumulation.  bf16: rounding the data to bf16 perturbs G by about
+// 1e-4 theta_1 (2 ||E|| ||A|| with ||E|| ~ 2^-9 / sqrt(3) rms(A)
+// (sqrt(m) + sqrt(nN))), so iterating below 1e-5 theta_1 cannot bring the
+// Ritz vectors closer to those of the exact Gram.
+constexpr double TSK_EIG_TOL_F32 = 1e-7;
+constexpr double TSK_EIG_TOL_BF16 = 1e-5;
 
 // host helpers (runtime.hip)
 tsk_status tsk_fail(tsk_ctx c, tsk_status st, const std::string &msg);

@@ -233,7 +233,7 @@ __device__ __forceinline__ void hstash(uint16_t *buf, const HRaw<SrcT> &raw) {
 }
 
 template <typename SrcT>
-__global__ __launch_bounds__(256) void gram_bf16_kernel(const SrcT *__restrict__ A, int64_t m, int64_t n,
+__global__ __launch_bounds__(256, 2 * (sizeof(SrcT) == 2) + (sizeof(SrcT) != 2)) void gram_bf16_kernel(const SrcT *__restrict__ A, int64_t m, int64_t n,
                                                         int64_t ld, int64_t stride, int64_t count, int T,
                                                         int nchunks, int per_xcd, float *__restrict__ part) {
     __shared__ uint16_t lds[2 * HBUF];
@@ -259,36 +259,63 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(const SrcT *__restrict__
 
     const int64_t spd = (n + HK - 1) / HK;
     const int64_t nst = (d1 - d0) * spd;
-    HRaw<SrcT> pre;
-    hfetch(A + d0 * stride, m, n, ld, rb0, cb0, 0, pre);
-    hstash(lds, pre);
-    __syncthreads();
-    for (int64_t st = 0; st < nst; ++st) {
-        const uint16_t *cur = lds + (st & 1) * HBUF;
-        const bool more = st + 1 < nst;
-        if (more) {
-            const int64_t s1 = st + 1;
-            const int64_t d = d0 + s1 / spd;
-            hfetch(A + d * stride, m, n, ld, rb0, cb0, (s1 % spd) * HK, pre);
-        }
-        v4u a[4][2], b[4][2];
+    // bf16 source: global loads run two stages ahead of the MFMAs (two
+    // register sets, used alternately): a stage's MFMA time is far shorter
+    // than the memory latency, so one stage of lookahead leaves every stage
+    // waiting.
+    auto fetch = [&](int64_t s1, HRaw<SrcT> &dst) {
+        const int64_t d = d0 + s1 / spd;
+        hfetch(A + d * stride, m, n, ld, rb0, cb0, (s1 % spd) * HK, dst);
+    };
+    auto mma_stage = [&](const uint16_t *cur) {
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            const uint16_t *ra = cur + (wr + x * 16 + ii) * HLD + 8 * q;
-            const uint16_t *rc = cur + (wc + x * 16 + ii) * HLD + 8 * q;
-            a[x][0] = *reinterpret_cast<const v4u *>(ra);
-            a[x][1] = *reinterpret_cast<const v4u *>(ra + 32);
-            b[x][0] = *reinterpret_cast<const v4u *>(rc);
-            b[x][1] = *reinterpret_cast<const v4u *>(rc + 32);
-        }
+        for (int h = 0; h < 2; ++h) {
+            v4u a[4], b[4];
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+            for (int x = 0; x < 4; ++x) {
+                a[x] = *reinterpret_cast<const v4u *>(cur + (wr + x * 16 + ii) * HLD + 8 * q + 32 * h);
+                b[x] = *reinterpret_cast<const v4u *>(cur + (wc + x * 16 + ii) * HLD + 8 * q + 32 * h);
+            }
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x32_bf16(a[x][h], b[y][h], acc[x][y]);
-        if (more) hstash(lds + ((st + 1) & 1) * HBUF, pre);
+                for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x32_bf16(a[x], b[y], acc[x][y]);
+        }
+    };
+    if constexpr (sizeof(SrcT) == 2) {
+        HRaw<SrcT> p0, p1;
+        fetch(0, p0);
+        hstash(lds, p0);
+        if (nst > 1) fetch(1, p1);
         __syncthreads();
+        // pairs of stages: stage st lives in buffer 0, st + 1 in buffer 1; p1
+        // carries stage st + 1 (issued a stage earlier), p0 receives st + 2
+        int64_t st = 0;
+        for (; st + 1 < nst; st += 2) {
+            if (st + 2 < nst) fetch(st + 2, p0);
+            mma_stage(lds);
+            hstash(lds + HBUF, p1);
+            __syncthreads();
+            if (st + 3 < nst) fetch(st + 3, p1);
+            mma_stage(lds + HBUF);
+            if (st + 2 < nst) hstash(lds, p0);
+            __syncthreads();
+        }
+        if (st < nst) mma_stage(lds);
+    } else {
+        // FP32 source: twice the registers per staged stage, so one stage of
+        // lookahead (the conversion to bf16 happens on the way into LDS)
+        HRaw<SrcT> pre;
+        fetch(0, pre);
+        hstash(lds, pre);
+        __syncthreads();
+        for (int64_t st = 0; st < nst; ++st) {
+            const bool more = st + 1 < nst;
+            if (more) fetch(st + 1, pre);
+            mma_stage(lds + (st & 1) * HBUF);
+            if (more) hstash(lds + ((st + 1) & 1) * HBUF, pre);
+            __syncthreads();
+        }
     }
     float *P = part + ((int64_t)chunk * T + t) * (GT * GT);
 #pragma unroll

@@ -13,6 +13,9 @@ Workloads (synthetic streams; the paper's datasets are not available):
       path on the same FP32 test matrices is timed beside it.
   hsi_fp32: 1024 x 768 stream (the HSI shape), 400 + 400, k = 20, r = 10,
       FP32 path, gated at 1e-5.
+  t3stream_e4m3: 1920 x 1080 stream with Student-t(3) noise at 1e-2, 4000
+      training + 1000 test matrices, k = 40, r = 20, e4m3 storage; errors of
+      the e4m3, bf16 and FP32 applies with the same sketch side by side.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                   [--no-cpu-baseline]
@@ -28,10 +31,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "e4m3": 5000.0}
 PEAK_HBM_GBS = 8000.0
-TAU = {"f32": 1e-5, "bf16": 1e-3}
-ORDER_CPU_SAMPLE = {"stream_bf16": (12, 32), "hsi_fp32": (40, 64)}
+TAU = {"f32": 1e-5, "bf16": 1e-3, "e4m3": 1e-3}
+ORDER_CPU_SAMPLE = {"stream_bf16": (12, 32), "hsi_fp32": (40, 64), "t3stream_e4m3": (12, 32)}
+WORKLOADS = {
+    "stream_bf16": ("bf16", "spec_bf16_1920", "stream_1920x1080_k40_r20"),
+    "hsi_fp32": ("f32", "spec_hsi_fp32", "hsi_1024x768_k20_r10"),
+    "t3stream_e4m3": ("e4m3", "spec_fp8_1920", "t3stream_1920x1080_k40_r20"),
+}
 
 
 def log(msg):
@@ -106,8 +114,8 @@ def run(args):
     from paper_2209_14637_amd import synth, tsk
 
     wl = args.workload
-    prec = "bf16" if wl == "stream_bf16" else "f32"
-    spec = synth.spec_bf16_1920() if wl == "stream_bf16" else synth.spec_hsi_fp32()
+    prec, spec_name, gname = WORKLOADS[wl]
+    spec = getattr(synth, spec_name)()
     m, n, k, r = spec.m, spec.n, spec.k, spec.r
     log(f"generating {spec.n_train}+{spec.n_test} slices of {m}x{n}")
     st = synth.Stream(spec)
@@ -121,23 +129,23 @@ def run(args):
     stream = torch.cuda.current_stream()
     rec_extra = {}
 
-    if prec == "bf16":
+    if prec != "f32":
         # staging (quantisation) is outside the step: timed on its own
-        ctx.stage(tr[:1], "bf16")
+        ctx.stage(tr[:1], prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        Tr = ctx.stage(tr, "bf16")
+        Tr = ctx.stage(tr, prec)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        Te = ctx.stage(te, "bf16")
+        Te = ctx.stage(te, prec)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         del tr
         torch.cuda.empty_cache()
-        stage_bytes = spec.n_test * m * n * (4 + 2)
+        stage_bytes = spec.n_test * m * n * (4 + (2 if prec == "bf16" else 1))
         rec_extra["stage_ms"] = {"train": (t1 - t0) * 1e3, "test": (t2 - t1) * 1e3,
                                  "test_gbs": stage_bytes / (t2 - t1) / 1e9}
-        train_in, test_in, compute = Tr, Te, "bf16"
+        train_in, test_in, compute = Tr, Te, prec
     else:
         train_in, test_in, compute = tr, te, "f32"
 
@@ -163,7 +171,6 @@ def run(args):
     per_kernel_ms, kt = kernel_breakdown(ctx, step, nb)
 
     # parity of the last step against the oracle's stored values
-    gname = "stream_1920x1080_k40_r20" if prec == "bf16" else "hsi_1024x768_k20_r10"
     gpath = os.path.join(ROOT, "tests", "golden", gname + ".json")
     parity = None
     if os.path.exists(gpath):
@@ -187,8 +194,8 @@ def run(args):
     gram_red_ms = kt_gram["gram_reduce"][1] / max(kt_gram["gram_reduce"][0], 1)
     gram_flops = m * (m + 1) * n * spec.n_train
     gram_tflops = gram_flops / ((gram_ms + gram_red_ms) / 1e3) / 1e12
-    gram_kernel = {"f32": "gram_f32_kernel", "bf16": "gram_bf16_kernel<uint16_t>"}[prec]
-    elt = {"f32": 4, "bf16": 2}[prec]
+    gram_kernel = {"f32": "gram_f32_kernel", "bf16": "gram_bf16_kernel<uint16_t>", "e4m3": "gram_e4m3_kernel"}[prec]
+    elt = {"f32": 4, "bf16": 2, "e4m3": 1}[prec]
     apply_bytes = spec.n_test * m * n * elt
     dom = max(per_kernel_ms, key=per_kernel_ms.get)
     if dom == "gram":
@@ -210,7 +217,18 @@ def run(args):
         if name in per_kernel_ms:
             roof_apply[f"{name}_kernel_gbs"] = apply_bytes / (per_kernel_ms[name] / 1e3) / 1e9
 
-    if prec == "bf16":
+    if prec == "e4m3" and parity is not None:
+        # the same sketch applied to bf16 and FP32 copies of the test
+        # matrices: errors side by side against the oracle
+        ne = parity["matrices"]
+        ref = np.array(json.load(open(gpath))["relerr"])
+        side = {}
+        for form, A in (("e4m3", test_in), ("bf16", ctx.stage(te[:ne], "bf16")), ("f32", te[:ne])):
+            o = ctx.apply(S, A if form != "e4m3" else tsk.Staged(A.data[:ne], n, "e4m3", A.scale[:ne]), r)
+            e_exp = ctx.error(te[:ne], o["L"][:ne], o["R"][:ne]).cpu().numpy()
+            side[form] = float(np.max(np.abs(e_exp - ref) / ref))
+        rec_extra["max_rel_dev_by_apply_form_same_sketch"] = side
+    if prec != "f32":
         # the plain FP32 path on the same FP32 test matrices and sketch
         o32 = ctx.apply(S, te, r)
         torch.cuda.synchronize()
@@ -225,7 +243,7 @@ def run(args):
             t32.append(e0.elapsed_time(e1))
         ms32 = float(np.median(t32))
         rec_extra["fp32_path_same_stream"] = {"apply_ms": ms32, "matrices_per_s": spec.n_test / (ms32 / 1e3),
-                                              "bf16_speedup": ms32 / apply_med}
+                                              f"{prec}_speedup": ms32 / apply_med}
 
     rec = {
         "metric": "sketch-apply matrices/s + Gram TFLOP/s at rel-err <=1e-3 vs FP64 oracle",
@@ -241,9 +259,12 @@ def run(args):
         "dtype": prec,
         "data": "synthetic",
         "config": {"workload": (f"{wl}: {m}x{n} stream, {spec.n_train} train / {spec.n_test} test, rank-40 law "
-                                f"i^-1.5 + {spec.eta:g} Gaussian noise, slow drift, k={k}, r={r}, "
-                                + ("bf16 storage, FP32 accumulation, FP64 small factorizations"
-                                   if prec == "bf16" else "FP32")),
+                                f"i^-1.5 + {spec.eta:g} {'Student-t(3)' if spec.noise == 't3' else 'Gaussian'} "
+                                f"noise, slow drift, k={k}, r={r}, "
+                                + {"bf16": "bf16 storage, FP32 accumulation, FP64 small factorizations",
+                                   "e4m3": "e4m3 storage (power-of-two scale per matrix), e4m3 Gram, bf16 products "
+                                           "in the apply, FP32 accumulation, FP64 small factorizations",
+                                   "f32": "FP32"}[prec]),
                    "m": m, "n": n, "n_train": spec.n_train, "n_test": spec.n_test, "k": k, "r": r},
         "gram_tflops": gram_tflops,
         "train_ms": float(np.median(train_ms)),
@@ -265,7 +286,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="stream_bf16", choices=["stream_bf16", "hsi_fp32"])
+    ap.add_argument("--workload", default="stream_bf16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

@@ -105,9 +105,11 @@ tsk_status tsk_stage(tsk_ctx ctx, const tsk_stack *src, int32_t dtype, void *dst
  *     G = A_(1) A_(1)^T = sum_{d<count} A_d A_d^T,   A_(1) = [A_1|...|A_N].
  * G: device, m x m FP64, full symmetric matrix.  Products accumulate in FP32
  * inside a chunk of slices and in FP64 across chunks.  compute:
- *   TSK_F32  : FP32 stack, FP32 products;
- *   TSK_BF16 : bf16 products, from a TSK_BF16 stack as stored or from an
- *              FP32 stack rounded to bf16 (nearest even) as it is loaded.
+ *   TSK_F32    : FP32 stack, FP32 products;
+ *   TSK_BF16   : bf16 products, from a TSK_BF16 stack as stored or from an
+ *                FP32 stack rounded to bf16 (nearest even) as it is loaded;
+ *   TSK_F8E4M3 : e4m3 products of a TSK_F8E4M3 stack, each slice's products
+ *                multiplied exactly by 1/scale[d]^2 (power of two).
  * Enqueue only. */
 tsk_status tsk_gram(tsk_ctx ctx, const tsk_stack *train, int32_t compute, double *G);
 
@@ -147,11 +149,16 @@ tsk_status tsk_train(tsk_ctx ctx, const tsk_stack *train, int32_t k, int32_t com
  * (the Pythagorean identity of the proof of Theorem 1), flags (count int32,
  * nullable, TSK_FLAG_*).  Requires 1 <= r < k <= min(m, n), k <= 64.
  * compute must match the stack's dtype:
- *   TSK_F32  : FP32 products S A_d and A_d V_d;
- *   TSK_BF16 : bf16 stack; products with bf16 A_d and S, V_d each split
- *              into a bf16 pair (hi + lo), so the only rounding beyond FP32
- *              is that of the stored A_d; ||A_d|| is that of the stored
- *              values.
+ *   TSK_F32    : FP32 products S A_d and A_d V_d;
+ *   TSK_BF16   : bf16 stack; products with bf16 A_d and S, V_d each split
+ *                into a bf16 pair (hi + lo), so the only rounding beyond
+ *                FP32 is that of the stored A_d; ||A_d|| is that of the
+ *                stored values;
+ *   TSK_F8E4M3 : e4m3 stack; the stored values divided by scale[d] are
+ *                widened exactly to bf16 and multiplied as in TSK_BF16 (the
+ *                apply is bound by memory traffic, which the 1-byte storage
+ *                halves; rounding S or V_d to e4m3 would add error and save
+ *                nothing).
  * The small factorizations (CholeskyQR2, C^T C eigenproblem) are FP64 in
  * every form.  Enqueue only. */
 tsk_status tsk_apply(tsk_ctx ctx, const float *S, int32_t k, const tsk_stack *test, int32_t r,
@@ -171,7 +178,8 @@ tsk_status tsk_error(tsk_ctx ctx, const tsk_stack *A, const float *L, const floa
  * the precision of the Gram's products: 1e-7 for FP32 (the rounding level
  * of FP32 accumulation, so the Ritz vectors are exact eigenvectors of a
  * matrix within that distance of G), 1e-5 for bf16 (rounding the data to
- * bf16 already moves G by about 1e-4 theta_1); tsk_eig_topk uses 1e-7];
+ * bf16 already moves G by about 1e-4 theta_1), 1e-4 for e4m3 (16 times
+ * coarser rounding than bf16); tsk_eig_topk uses 1e-7];
  * check = filtered steps to the first convergence test [4]; later tests are
  * placed where the observed residual decay predicts convergence (at most
  * 4 * check steps apart).  A value <= 0 restores the default. */

@@ -204,13 +204,27 @@ __global__ void prep_sketch_bf16_kernel(const float *__restrict__ S, int k, int 
     Sb[(int64_t)kp * mp + e] = (uint16_t)l;
 }
 
-__device__ __forceinline__ v4u load_bf16x8(const uint16_t *p, int64_t c, int64_t n) {
+// 8 consecutive elements (columns c .. c+7 of a row, zero from column n on)
+// as 8 bf16: bf16 storage as is; e4m3 storage widened to bf16 and multiplied
+// by inv = 1/s_d (both exact).
+__device__ __forceinline__ v4u load8(const uint16_t *p, int64_t c, int64_t n, float) {
     if (c + 7 < n) return *reinterpret_cast<const v4u *>(p);
     unsigned w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (int e = 0; e < 8; ++e)
         if (c + e < n) w[e >> 1] |= (unsigned)p[e] << (16 * (e & 1));
     return v4u{w[0], w[1], w[2], w[3]};
+}
+__device__ __forceinline__ v4u load8(const uint8_t *p, int64_t c, int64_t n, float inv) {
+    uint2 w = uint2{0u, 0u};
+    if (c + 7 < n) {
+        w = *reinterpret_cast<const uint2 *>(p);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (c + e < n) (e < 4 ? w.x : w.y) |= (unsigned)p[e] << (8 * (e & 3));
+    }
+    return e4m3x8_to_bf16(w, inv);
 }
 
 // B_d = S A_d.  The contraction runs over the rows of A_d, but an MFMA lane
@@ -220,10 +234,11 @@ __device__ __forceinline__ v4u load_bf16x8(const uint16_t *p, int64_t c, int64_t
 // of those 8 rows.  One wave covers 128 columns, 32 rows per step; the next
 // step's rows are in flight during the MFMAs.  ||A_d||^2 is accumulated from
 // the same registers (FP32 per step, FP64 across steps).
-template <int MT>
-__global__ __launch_bounds__(64) void sketch_bf16_kernel(const uint16_t *__restrict__ A, int64_t m, int64_t n,
-                                                          int64_t ld, int64_t stride, const uint16_t *__restrict__ Sb,
-                                                          int64_t mp, float *__restrict__ B, uint16_t *__restrict__ Bb,
+template <int MT, typename ET>
+__global__ __launch_bounds__(64) void sketch_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
+                                                          int64_t m, int64_t n, int64_t ld, int64_t stride,
+                                                          const uint16_t *__restrict__ Sb, int64_t mp,
+                                                          float *__restrict__ B, uint16_t *__restrict__ Bb,
                                                           int64_t ldb, double *__restrict__ fro_part, int npanel) {
     constexpr int kp = MT * 16;
     const int64_t d = blockIdx.y;
@@ -232,7 +247,8 @@ __global__ __launch_bounds__(64) void sketch_bf16_kernel(const uint16_t *__restr
     const int q = lane >> 4, ii = lane & 15;
     const int64_t c8 = (int64_t)panel * SKB_PANEL + 8 * ii;
     const bool any = c8 < n;
-    const uint16_t *Ad = A + d * stride + (any ? c8 : 0);
+    const float inv = scale ? 1.0f / scale[d] : 1.0f;
+    const ET *Ad = A + d * stride + (any ? c8 : 0);
     const uint16_t *Sh = Sb + (int64_t)ii * mp + 8 * q;
     const uint16_t *Sl = Sh + (int64_t)kp * mp;
     v4f acc[MT][8];
@@ -245,7 +261,7 @@ __global__ __launch_bounds__(64) void sketch_bf16_kernel(const uint16_t *__restr
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int64_t row = 8 * q + e;
-        x[e] = (any && row < m) ? load_bf16x8(Ad + row * ld, c8, n) : v4u{0u, 0u, 0u, 0u};
+        x[e] = (any && row < m) ? load8(Ad + row * ld, c8, n, inv) : v4u{0u, 0u, 0u, 0u};
     }
     for (int64_t r0 = 0; r0 < m; r0 += 32) {
         const bool more = r0 + 32 < m;
@@ -253,7 +269,7 @@ __global__ __launch_bounds__(64) void sketch_bf16_kernel(const uint16_t *__restr
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int64_t row = r0 + 32 + 8 * q + e;
-            nx[e] = (more && any && row < m) ? load_bf16x8(Ad + row * ld, c8, n) : v4u{0u, 0u, 0u, 0u};
+            nx[e] = (more && any && row < m) ? load8(Ad + row * ld, c8, n, inv) : v4u{0u, 0u, 0u, 0u};
         }
         v4u sh[MT], sl[MT];
 #pragma unroll
@@ -321,17 +337,19 @@ __global__ __launch_bounds__(64) void sketch_bf16_kernel(const uint16_t *__restr
 // (q, i) reads 8 consecutive columns of row i of each of 8 row tiles; the rows
 // of the bf16 pair of B_d give the other operand directly.  One wave covers
 // 128 rows.
-template <int NT>
-__global__ __launch_bounds__(64) void project_bf16_kernel(const uint16_t *__restrict__ A, int64_t m, int64_t n,
-                                                           int64_t ld, int64_t stride, const uint16_t *__restrict__ Bb,
-                                                           int64_t ldv, float *__restrict__ C) {
+template <int NT, typename ET>
+__global__ __launch_bounds__(64) void project_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
+                                                           int64_t m, int64_t n, int64_t ld, int64_t stride,
+                                                           const uint16_t *__restrict__ Bb, int64_t ldv,
+                                                           float *__restrict__ C) {
     constexpr int kp = NT * 16;
     const int64_t d = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, ii = lane & 15;
     const int64_t r0 = (int64_t)blockIdx.x * PJB_ROWS;
-    const uint16_t *Ad = A + d * stride;
-    const uint16_t *arow[8];
+    const float inv = scale ? 1.0f / scale[d] : 1.0f;
+    const ET *Ad = A + d * stride;
+    const ET *arow[8];
     bool av[8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
@@ -348,13 +366,13 @@ __global__ __launch_bounds__(64) void project_bf16_kernel(const uint16_t *__rest
         for (int b = 0; b < NT; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
     v4u xa[8];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) xa[a] = (av[a] && 8 * q < n) ? load_bf16x8(arow[a], 8 * q, n) : v4u{0u, 0u, 0u, 0u};
+    for (int a = 0; a < 8; ++a) xa[a] = (av[a] && 8 * q < n) ? load8(arow[a], 8 * q, n, inv) : v4u{0u, 0u, 0u, 0u};
     for (int64_t c0 = 0; c0 < n; c0 += 32) {
         const int64_t cn = c0 + 32 + 8 * q;  // this lane's columns in the next step
         v4u nxa[8];
 #pragma unroll
         for (int a = 0; a < 8; ++a)
-            nxa[a] = (av[a] && cn < n) ? load_bf16x8(arow[a] + c0 + 32, cn, n) : v4u{0u, 0u, 0u, 0u};
+            nxa[a] = (av[a] && cn < n) ? load8(arow[a] + c0 + 32, cn, n, inv) : v4u{0u, 0u, 0u, 0u};
         v4u vh[NT], vl[NT];
 #pragma unroll
         for (int b = 0; b < NT; ++b) {
@@ -716,8 +734,11 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
     return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags);
 }
 
-tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
-                                  float *sigma, double *relerr, int32_t *flags) {
+// bf16 form (ET = uint16_t, bf16 stack) and e4m3 form (ET = uint8_t, e4m3
+// stack with per-slice scales, widened to bf16 in registers).
+template <typename ET>
+static tsk_status apply_lowp_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
+                                     float *sigma, double *relerr, int32_t *flags) {
     const int64_t m = s->m, n = s->n, count = s->count;
     const int kp = (k + 15) / 16 * 16;
     const int64_t mp = (m + 31) / 32 * 32;
@@ -731,25 +752,32 @@ tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_st
     uint16_t *Sb = (uint16_t *)c->ap_Sb.p, *Bb = (uint16_t *)c->ap_Bb.p;
     float *B = (float *)c->ap_B.p, *Cm = (float *)c->ap_C.p;
     double *fro = (double *)c->ap_fro.p;
-    const uint16_t *A = (const uint16_t *)s->A;
+    const ET *A = (const ET *)s->A;
+    const float *sc = s->scale;
     TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
                hipLaunchKernelGGL(prep_sketch_bf16_kernel, dim3((unsigned)((kp * mp + 255) / 256)), dim3(256), 0,
                                   c->stream, S, k, kp, m, mp, Sb));
     const dim3 gs((unsigned)npanel, (unsigned)count);
-#define TSK_SKB(MTV)                                                                                              \
-    TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                              \
-               hipLaunchKernelGGL(sketch_bf16_kernel<MTV>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, \
-                                  (const uint16_t *)Sb, mp, B, Bb, ldv, fro, npanel))
+#define TSK_SKB(MTV)                                                                                     \
+    TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                     \
+               hipLaunchKernelGGL((sketch_bf16_kernel<MTV, ET>), gs, dim3(64), 0, c->stream, A, sc, m, n, \
+                                  s->ld, s->stride, (const uint16_t *)Sb, mp, B, Bb, ldv, fro, npanel))
     TSK_KP_SWITCH(kp / 16, TSK_SKB(1), TSK_SKB(2), TSK_SKB(3), TSK_SKB(4))
 #undef TSK_SKB
     const dim3 gp((unsigned)((m + PJB_ROWS - 1) / PJB_ROWS), (unsigned)count);
-#define TSK_PJB(NTV)                                                                                     \
-    TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                    \
-               hipLaunchKernelGGL(project_bf16_kernel<NTV>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, \
-                                  s->stride, (const uint16_t *)Bb, ldv, Cm))
+#define TSK_PJB(NTV)                                                                                      \
+    TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                     \
+               hipLaunchKernelGGL((project_bf16_kernel<NTV, ET>), gp, dim3(64), 0, c->stream, A, sc, m, n, \
+                                  s->ld, s->stride, (const uint16_t *)Bb, ldv, Cm))
     TSK_KP_SWITCH(kp / 16, TSK_PJB(1), TSK_PJB(2), TSK_PJB(3), TSK_PJB(4))
 #undef TSK_PJB
     return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags);
+}
+
+tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
+                                  float *sigma, double *relerr, int32_t *flags) {
+    if (s->dtype == TSK_F8E4M3) return apply_lowp_enqueue<uint8_t>(c, S, k, s, r, L, R, sigma, relerr, flags);
+    return apply_lowp_enqueue<uint16_t>(c, S, k, s, r, L, R, sigma, relerr, flags);
 }
 
 tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, const float *R, int r, double *relerr) {

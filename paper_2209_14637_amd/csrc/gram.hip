@@ -330,6 +330,132 @@ __global__ __launch_bounds__(256, 2 * (sizeof(SrcT) == 2) + (sizeof(SrcT) != 2))
             }
 }
 
+// ---------------------------------------------------------------------------
+// e4m3 products (the e4m3 form): same tiling; a stage is 128 e4m3 columns
+// (again 128 bytes of every staged row), one 16x16x128 MFMA per tile per
+// stage.  Slice d is stored as A_d s_d with s_d = 2^j_d, so each product is
+// multiplied by 2^-2j_d through the MFMA's own operand scales (E8M0, exact);
+// stages never straddle slices.
+// ---------------------------------------------------------------------------
+constexpr int QK = 128;  // e4m3 columns per stage
+
+__device__ __forceinline__ void qfetch(const uint8_t *__restrict__ Ad, int64_t m, int64_t n, int64_t ld,
+                                       int64_t rb0, int64_t cb0, int64_t c0, v4u (&v)[8]) {
+    const int t = threadIdx.x;
+    const int64_t cc = c0 + 16 * (t & 7);
+    const bool fullc = cc + 15 < n;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int64_t row = (u < 4 ? rb0 : cb0) + (t >> 3) + 32 * (u & 3);
+        v4u x = v4u{0u, 0u, 0u, 0u};
+        if (row < m && cc < n) {
+            const uint8_t *p = Ad + row * ld + cc;
+            if (fullc) {
+                x = *reinterpret_cast<const v4u *>(p);
+            } else {
+                unsigned w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    if (cc + e < n) w[e >> 2] |= (unsigned)p[e] << (8 * (e & 3));
+                x = v4u{w[0], w[1], w[2], w[3]};
+            }
+        }
+        v[u] = x;
+    }
+}
+
+__device__ __forceinline__ void qstash(uint8_t *buf, const v4u (&v)[8]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int r = (u < 4 ? 0 : GT) + (t >> 3) + 32 * (u & 3);
+        *reinterpret_cast<v4u *>(buf + r * (2 * HLD) + 16 * (t & 7)) = v[u];
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void gram_e4m3_kernel(const uint8_t *__restrict__ A,
+                                                           const float *__restrict__ scale, int64_t m, int64_t n,
+                                                           int64_t ld, int64_t stride, int64_t count, int T,
+                                                           int nchunks, int per_xcd, float *__restrict__ part) {
+    constexpr int QLD = 2 * HLD;        // padded LDS row, bytes (144)
+    constexpr int QBUF = 2 * GT * QLD;  // bytes per stage buffer
+    __shared__ uint8_t lds[2 * QBUF];
+    const int w = blockIdx.x;
+    const int xcd = w & 7, local = w >> 3;
+    const int t = local % T, sub = local / T;
+    const int chunk = xcd * per_xcd + sub;
+    const int64_t d0 = (int64_t)chunk * count / nchunks;
+    const int64_t d1 = (int64_t)(chunk + 1) * count / nchunks;
+    if (d0 >= d1) return;
+    int bi, bj;
+    tile_coords(t, bi, bj);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = lane >> 4, ii = lane & 15;
+    const int64_t rb0 = (int64_t)bi * GT, cb0 = (int64_t)bj * GT;
+    const int wr = (wv >> 1) * 64, wc = GT + (wv & 1) * 64;
+    v4f acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int64_t spd = (n + QK - 1) / QK;
+    const int64_t nst = (d1 - d0) * spd;
+    auto fetch = [&](int64_t s1, v4u (&dst)[8]) {
+        const int64_t d = d0 + s1 / spd;
+        qfetch(A + d * stride, m, n, ld, rb0, cb0, (s1 % spd) * QK, dst);
+    };
+    // E8M0 operand scale 2^-j of the stage's slice (scale[d] = 2^j)
+    auto escale = [&](int64_t s1) {
+        int j;
+        frexpf(scale[d0 + s1 / spd], &j);
+        return 127 - (j - 1);
+    };
+    auto mma_stage = [&](const uint8_t *cur, int es) {
+        v8i a[4], b[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const uint8_t *ra = cur + (wr + x * 16 + ii) * QLD + 32 * q;
+            const uint8_t *rc = cur + (wc + x * 16 + ii) * QLD + 32 * q;
+            const v4u a0 = *reinterpret_cast<const v4u *>(ra), a1 = *reinterpret_cast<const v4u *>(ra + 16);
+            const v4u b0 = *reinterpret_cast<const v4u *>(rc), b1 = *reinterpret_cast<const v4u *>(rc + 16);
+            a[x] = v8i{(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+            b[x] = v8i{(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x128_e4m3(a[x], b[y], acc[x][y], es, es);
+    };
+    v4u p0[8], p1[8];
+    fetch(0, p0);
+    qstash(lds, p0);
+    if (nst > 1) fetch(1, p1);
+    __syncthreads();
+    int64_t st = 0;
+    for (; st + 1 < nst; st += 2) {
+        if (st + 2 < nst) fetch(st + 2, p0);
+        mma_stage(lds, escale(st));
+        qstash(lds + QBUF, p1);
+        __syncthreads();
+        if (st + 3 < nst) fetch(st + 3, p1);
+        mma_stage(lds + QBUF, escale(st + 1));
+        if (st + 2 < nst) qstash(lds, p0);
+        __syncthreads();
+    }
+    if (st < nst) mma_stage(lds, escale(st));
+    float *P = part + ((int64_t)chunk * T + t) * (GT * GT);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int lr = (wv >> 1) * 64 + x * 16 + 4 * q + r;
+                const int lc = (wv & 1) * 64 + y * 16 + ii;
+                P[lr * GT + lc] = acc[x][y][r];
+            }
+}
+
 // G[i][j] = sum over non-empty chunks (in chunk order) of the partial tiles,
 // in FP64; diagonal tiles use their lower entry for both (i,j) and (j,i).
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const float *__restrict__ part, int64_t m,
@@ -357,7 +483,8 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const float *__restric
 
 // Enqueue the Gram of a validated stack into device G (m x m FP64).
 // compute TSK_F32: FP32 stack, FP32 products.  compute TSK_BF16: FP32 stack
-// rounded to bf16 on load, or a bf16 stack as stored.
+// rounded to bf16 on load, or a bf16 stack as stored.  compute TSK_F8E4M3:
+// an e4m3 stack with its per-slice scales.
 tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *G) {
     const int64_t m = s->m, count = s->count;
     const int nb = (int)((m + GT - 1) / GT);
@@ -375,6 +502,11 @@ tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *
         TSK_LAUNCH(c, TSK_KERNEL_GRAM,
                    hipLaunchKernelGGL(gram_f32_kernel, dim3(grid), dim3(256), 0, c->stream,
                                       (const float *)s->A, m, s->n, s->ld, s->stride, count, T, nchunks,
+                                      per_xcd, part));
+    } else if (compute == TSK_F8E4M3) {
+        TSK_LAUNCH(c, TSK_KERNEL_GRAM,
+                   hipLaunchKernelGGL(gram_e4m3_kernel, dim3(grid), dim3(256), 0, c->stream,
+                                      (const uint8_t *)s->A, s->scale, m, s->n, s->ld, s->stride, count, T, nchunks,
                                       per_xcd, part));
     } else if (s->dtype == TSK_F32) {
         TSK_LAUNCH(c, TSK_KERNEL_GRAM,

@@ -122,7 +122,11 @@ static tsk_status check_gram_compute(tsk_ctx c, const tsk_stack *s, int32_t comp
             return tsk_fail(c, TSK_E_ARG, w + ": compute TSK_BF16 needs an FP32 or bf16 stack");
         return TSK_OK;
     }
-    return tsk_fail(c, TSK_E_ARG, w + ": compute must be TSK_F32 or TSK_BF16");
+    if (compute == TSK_F8E4M3) {
+        if (s->dtype != TSK_F8E4M3) return tsk_fail(c, TSK_E_ARG, w + ": compute TSK_F8E4M3 needs an e4m3 stack");
+        return TSK_OK;
+    }
+    return tsk_fail(c, TSK_E_ARG, w + ": compute must be TSK_F32, TSK_BF16 or TSK_F8E4M3");
 }
 
 void tsk_ev_begin(tsk_ctx c, int cls, hipEvent_t *a) {
@@ -283,7 +287,8 @@ tsk_status tsk_train(tsk_ctx c, const tsk_stack *train, int32_t k, int32_t compu
     TSK_TRY(tsk_grow(c, c->gram_G, sizeof(double) * m * m));
     double *G = (double *)c->gram_G.p;
     TSK_TRY(tsk_gram_enqueue(c, train, compute, G));
-    return tsk_eig_enqueue(c, G, m, k, S, lambda, iters, compute == TSK_BF16 ? TSK_EIG_TOL_BF16 : TSK_EIG_TOL_F32);
+    const double tol = compute == TSK_F8E4M3 ? TSK_EIG_TOL_F8 : compute == TSK_BF16 ? TSK_EIG_TOL_BF16 : TSK_EIG_TOL_F32;
+    return tsk_eig_enqueue(c, G, m, k, S, lambda, iters, tol);
 }
 
 tsk_status tsk_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test, int32_t r, int32_t compute,
@@ -292,8 +297,8 @@ tsk_status tsk_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test
     c->err.clear();
     DeviceGuard g(c->device);
     TSK_TRY(tsk_check_stack(c, test, "test"));
-    if (compute != TSK_F32 && compute != TSK_BF16)
-        return tsk_fail(c, TSK_E_ARG, "tsk_apply: compute must be TSK_F32 or TSK_BF16");
+    if (compute != TSK_F32 && compute != TSK_BF16 && compute != TSK_F8E4M3)
+        return tsk_fail(c, TSK_E_ARG, "tsk_apply: compute must be TSK_F32, TSK_BF16 or TSK_F8E4M3");
     if (test->dtype != compute) return tsk_fail(c, TSK_E_ARG, "tsk_apply: compute must match the stack's dtype");
     const int64_t m = test->m, n = test->n, cnt = test->count;
     if (r < 1 || r >= k) return tsk_fail(c, TSK_E_ARG, "tsk_apply: need 1 <= r < k");
@@ -305,7 +310,7 @@ tsk_status tsk_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test
     TSK_TRY(tsk_check_dev(c, sigma, sizeof(float) * cnt * r, "sigma"));
     if (relerr) TSK_TRY(tsk_check_dev(c, relerr, sizeof(double) * cnt, "relerr"));
     if (flags) TSK_TRY(tsk_check_dev(c, flags, sizeof(int32_t) * cnt, "flags"));
-    if (compute == TSK_BF16) return tsk_apply_bf16_enqueue(c, S, k, test, r, L, R, sigma, relerr, flags);
+    if (compute != TSK_F32) return tsk_apply_bf16_enqueue(c, S, k, test, r, L, R, sigma, relerr, flags);
     return tsk_apply_enqueue(c, S, k, test, r, L, R, sigma, relerr, flags);
 }
 

@@ -39,6 +39,30 @@ __device__ __forceinline__ v4f mfma16x16x32_bf16(v4u a, v4u b, v4f c) {
                                                    0, 0);
 }
 
+// 16x16x128 e4m3 x e4m3 with block scales (FP32 accumulate), measured on
+// gfx950: lane 16*q + i supplies 32 bytes of row i of A and of column i of
+// B; byte e of lane (q, i) of A pairs with byte e of lane (q, i') of B (the
+// contraction order is the same on both operands); D as for the f32 shape.
+// sa, sb: E8M0 exponents (127 = 1.0) multiplying the A and B operands.
+typedef int v8i __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ v4f mfma16x16x128_e4m3(v8i a, v8i b, v4f c, int sa, int sb) {
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, sa, 0, sb);
+}
+// Two e4m3 bytes of w (bytes 0,1, or 2,3 when hi) to two bf16 packed in a
+// dword, multiplied by the power of two sc (exact: e4m3 values are bf16
+// values).
+__device__ __forceinline__ unsigned e4m3x2_to_bf16(unsigned w, float sc, bool hi) {
+    typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+    const v2bf b = hi ? __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w, sc, true)
+                      : __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w, sc, false);
+    return __builtin_bit_cast(unsigned, b);
+}
+// 8 e4m3 bytes (two dwords) -> 8 bf16 (four dwords), times sc.
+__device__ __forceinline__ v4u e4m3x8_to_bf16(uint2 w, float sc) {
+    return v4u{e4m3x2_to_bf16(w.x, sc, false), e4m3x2_to_bf16(w.x, sc, true), e4m3x2_to_bf16(w.y, sc, false),
+               e4m3x2_to_bf16(w.y, sc, true)};
+}
+
 // bf16 bits <-> float (bf16 is the upper half of a binary32).
 __device__ __forceinline__ float bf16_lo(unsigned w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
@@ -488,6 +512,10 @@ struct tsk_ctx_s {
 // Ritz vectors closer to those of the exact Gram.
 constexpr double TSK_EIG_TOL_F32 = 1e-7;
 constexpr double TSK_EIG_TOL_BF16 = 1e-5;
+// e4m3 keeps 4 significant bits (relative rounding 2^-4 against bf16's
+// 2^-8): the Gram moves about 2^4 times further, so the tolerance is 2^4
+// times looser (rounded).
+constexpr double TSK_EIG_TOL_F8 = 1e-4;
 
 // host helpers (runtime.hip)
 tsk_status tsk_fail(tsk_ctx c, tsk_status st, const std::string &msg);

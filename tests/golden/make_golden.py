@@ -57,6 +57,9 @@ WORKLOADS = {
     # are gated against it at 1e-3)
     "stream_1920x1080_k40_r20": lambda: golden_stream(synth.spec_bf16_1920(), "stream_1920x1080_k40_r20",
                                                       n_err=32, n_opt=0),
+    # the e4m3 form's stream: 4000 training slices, Student-t(3) noise at 1e-2
+    "t3stream_1920x1080_k40_r20": lambda: golden_stream(synth.spec_fp8_1920(), "t3stream_1920x1080_k40_r20",
+                                                        n_err=32, n_opt=0),
 }
 
 if __name__ == "__main__":

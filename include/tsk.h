@@ -165,6 +165,29 @@ tsk_status tsk_apply(tsk_ctx ctx, const float *S, int32_t k, const tsk_stack *te
                      int32_t compute, float *L, float *R, float *sigma, double *relerr,
                      int32_t *flags);
 
+/* One problem of a batch: the test matrices of one stream (any shape), its
+ * sketch and outputs, exactly as the arguments of tsk_apply. */
+typedef struct {
+    tsk_stack A;          /* test matrices (device) */
+    const float *S;       /* k x A.m sketch, device FP32, rows orthonormal */
+    int32_t k, r;         /* 1 <= r < k <= min(A.m, A.n), k <= 64 */
+    float *L, *R, *sigma; /* device outputs, layouts as tsk_apply */
+    double *relerr;       /* device, nullable */
+    int32_t *flags;       /* device, nullable */
+} tsk_problem;
+
+/* The batching form of SCW (Algorithm 1): tsk_apply on every problem of
+ * `probs` -- matrices of different shapes and sketch sizes, e.g. from
+ * several streams -- in a fixed number of launches for the whole batch
+ * (one sketch-preparation launch, then one sketch, one project and one
+ * finish launch per sketch-size class ceil(k/16)), work items of all
+ * problems sharing each launch.  Results are identical to tsk_apply on each
+ * problem.  compute: as tsk_apply, and every stack's dtype must equal it.
+ * nprobs >= 1.  The problems' outputs must not overlap.  Enqueue only (the
+ * batch tables are copied from context-owned pinned memory; a later call
+ * waits for that copy before reusing it). */
+tsk_status tsk_apply_multi(tsk_ctx ctx, const tsk_problem *probs, int32_t nprobs, int32_t compute);
+
 /* Explicit relative error ||A_d - L_d R_d^T||_F / ||A_d||_F for every slice
  * (the quantity whose rank-r minimum is problem 1.1).  A: an FP32 stack.
  * L, R: device FP32 with the layout tsk_apply writes.  relerr: device FP64,

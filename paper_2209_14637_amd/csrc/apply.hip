@@ -19,6 +19,10 @@
 // in bf16, B_d split into a bf16 pair hi + lo; every later use of B_d takes
 // B_d = hi + lo, so all factors refer to the same row space).  kp = k rounded
 // up to 16; rows k..kp-1 of S, B are zero, so no masking is needed on them.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
 #include "tsk_common.hpp"
 
 namespace {
@@ -31,9 +35,8 @@ constexpr int PJ_ROWS = 64;    // rows of A_d per project workgroup (one wave)
 constexpr int MAXK = 64;
 
 // St (m x kp) = S^T with zero columns k..kp-1
-__global__ void transpose_sketch_kernel(const float *__restrict__ S, int k, int kp, int64_t m,
-                                        float *__restrict__ St) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void transpose_sketch_body(const float *__restrict__ S, int k, int kp, int64_t m,
+                                        float *__restrict__ St, int64_t e) {
     if (e >= m * kp) return;
     const int64_t i = e / kp;
     const int s = (int)(e % kp);
@@ -41,13 +44,11 @@ __global__ void transpose_sketch_kernel(const float *__restrict__ S, int k, int 
 }
 
 template <int MT>
-__global__ __launch_bounds__(64) void sketch_f32_kernel(const float *__restrict__ A, int64_t m, int64_t n,
+__device__ __forceinline__ void sketch_f32_body(const float *__restrict__ A, int64_t m, int64_t n,
                                                          int64_t ld, int64_t stride, const float *__restrict__ St,
                                                          float *__restrict__ B, int64_t ldb,
-                                                         double *__restrict__ fro_part, int npanel) {
+                                                         double *__restrict__ fro_part, int npanel, int64_t d, int panel) {
     constexpr int kp = MT * 16;
-    const int64_t d = blockIdx.y;
-    const int panel = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, jj = lane & 15;
     const int64_t col4 = (int64_t)panel * SK_PANEL + 4 * jj;  // this lane's 4 columns
@@ -116,14 +117,13 @@ __global__ __launch_bounds__(64) void sketch_f32_kernel(const float *__restrict_
 // C_d = A_d B_d^T (FP32)
 // ---------------------------------------------------------------------------
 template <int NT>
-__global__ __launch_bounds__(64) void project_f32_kernel(const float *__restrict__ A, int64_t m, int64_t n,
+__device__ __forceinline__ void project_f32_body(const float *__restrict__ A, int64_t m, int64_t n,
                                                           int64_t ld, int64_t stride, const float *__restrict__ Bm,
-                                                          int64_t ldv, float *__restrict__ C) {
+                                                          int64_t ldv, float *__restrict__ C, int64_t d, int band) {
     constexpr int kp = NT * 16;
-    const int64_t d = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, ii = lane & 15;
-    const int64_t r0 = (int64_t)blockIdx.x * PJ_ROWS;
+    const int64_t r0 = (int64_t)band * PJ_ROWS;
     const float *Ad = A + d * stride;
     const float *Vd = Bm + d * kp * ldv;
     const float *arow[4];
@@ -191,9 +191,8 @@ constexpr int PJB_ROWS = 128;   // rows per project wave (8 row tiles)
 
 // Sb = [S_hi; S_lo], each kp x mp bf16 with zero padding (rows >= k,
 // columns >= m).
-__global__ void prep_sketch_bf16_kernel(const float *__restrict__ S, int k, int kp, int64_t m, int64_t mp,
-                                        uint16_t *__restrict__ Sb) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void prep_sketch_bf16_body(const float *__restrict__ S, int k, int kp, int64_t m, int64_t mp,
+                                        uint16_t *__restrict__ Sb, int64_t e) {
     if (e >= (int64_t)kp * mp) return;
     const int s = (int)(e / mp);
     const int64_t i = e % mp;
@@ -235,14 +234,12 @@ __device__ __forceinline__ v4u load8(const uint8_t *p, int64_t c, int64_t n, flo
 // step's rows are in flight during the MFMAs.  ||A_d||^2 is accumulated from
 // the same registers (FP32 per step, FP64 across steps).
 template <int MT, typename ET>
-__global__ __launch_bounds__(64) void sketch_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
+__device__ __forceinline__ void sketch_bf16_body(const ET *__restrict__ A, const float *__restrict__ scale,
                                                           int64_t m, int64_t n, int64_t ld, int64_t stride,
                                                           const uint16_t *__restrict__ Sb, int64_t mp,
                                                           float *__restrict__ B, uint16_t *__restrict__ Bb,
-                                                          int64_t ldb, double *__restrict__ fro_part, int npanel) {
+                                                          int64_t ldb, double *__restrict__ fro_part, int npanel, int64_t d, int panel) {
     constexpr int kp = MT * 16;
-    const int64_t d = blockIdx.y;
-    const int panel = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, ii = lane & 15;
     const int64_t c8 = (int64_t)panel * SKB_PANEL + 8 * ii;
@@ -338,15 +335,14 @@ __global__ __launch_bounds__(64) void sketch_bf16_kernel(const ET *__restrict__ 
 // of the bf16 pair of B_d give the other operand directly.  One wave covers
 // 128 rows.
 template <int NT, typename ET>
-__global__ __launch_bounds__(64) void project_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
+__device__ __forceinline__ void project_bf16_body(const ET *__restrict__ A, const float *__restrict__ scale,
                                                            int64_t m, int64_t n, int64_t ld, int64_t stride,
                                                            const uint16_t *__restrict__ Bb, int64_t ldv,
-                                                           float *__restrict__ C) {
+                                                           float *__restrict__ C, int64_t d, int band) {
     constexpr int kp = NT * 16;
-    const int64_t d = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, ii = lane & 15;
-    const int64_t r0 = (int64_t)blockIdx.x * PJB_ROWS;
+    const int64_t r0 = (int64_t)band * PJB_ROWS;
     const float inv = scale ? 1.0f / scale[d] : 1.0f;
     const ET *Ad = A + d * stride;
     const ET *arow[8];
@@ -513,12 +509,12 @@ __device__ inline void small_mm(const double *X, const double *M, double *Y) {
 }
 
 template <int KP>
-__global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ B, int64_t ldb, int64_t n,
+__device__ __forceinline__ void finish_body(const float *__restrict__ B, int64_t ldb, int64_t n,
                                                      const float *__restrict__ C, int64_t m, int k, int r,
                                                      const double *__restrict__ fro_part, int npanel,
                                                      float *__restrict__ L, float *__restrict__ R,
                                                      float *__restrict__ sigma, double *__restrict__ relerr,
-                                                     int *__restrict__ flags) {
+                                                     int *__restrict__ flags, int64_t d) {
     constexpr int SZ = KP * KP;
     __shared__ double buf[3 * SZ];
     __shared__ float Zs[KP * KP];          // Z = R^-1 Y_r (k x r, row stride KP)
@@ -527,7 +523,6 @@ __global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ B
     __shared__ int dead[KP];
     __shared__ int perm[KP];
     __shared__ double s_lam[KP];
-    const int64_t d = blockIdx.x;
     const int tid = threadIdx.x;
     const float *Bd = B + d * KP * ldb;
     const float *Cd = C + d * m * KP;
@@ -615,6 +610,121 @@ __global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ B
             Rd[j * r + t] = finite ? s : qnan;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Launch forms.  One problem (tsk_apply): grid = (tile, matrix).  A batch of
+// problems of different shapes (tsk_apply_multi): a flat grid over work
+// items (problem, matrix, tile) listed by the host, each problem's shapes
+// and buffers read from its descriptor; one launch per phase covers every
+// problem of a sketch-size class.
+// ---------------------------------------------------------------------------
+struct ApDesc {
+    const void *A;
+    const float *scale;     // e4m3 scales or null
+    const float *S;         // k x m sketch
+    int64_t m, n, ld, stride, count;
+    int k, r, kp, npanel;
+    int64_t ldv, mp;
+    float *St;              // FP32 form: m x kp transposed sketch
+    uint16_t *Sb;           // bf16 / e4m3 forms: bf16 pair of S
+    float *B;
+    uint16_t *Bb;
+    float *C;
+    double *fro;
+    float *L, *R, *sigma;
+    double *relerr;
+    int32_t *flags;
+};
+
+__global__ void transpose_sketch_kernel(const float *__restrict__ S, int k, int kp, int64_t m,
+                                        float *__restrict__ St) {
+    transpose_sketch_body(S, k, kp, m, St, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void prep_sketch_bf16_kernel(const float *__restrict__ S, int k, int kp, int64_t m, int64_t mp,
+                                        uint16_t *__restrict__ Sb) {
+    prep_sketch_bf16_body(S, k, kp, m, mp, Sb, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+template <int MT>
+__global__ __launch_bounds__(64) void sketch_f32_kernel(const float *__restrict__ A, int64_t m, int64_t n,
+                                                         int64_t ld, int64_t stride, const float *__restrict__ St,
+                                                         float *__restrict__ B, int64_t ldb,
+                                                         double *__restrict__ fro_part, int npanel) {
+    sketch_f32_body<MT>(A, m, n, ld, stride, St, B, ldb, fro_part, npanel, blockIdx.y, blockIdx.x);
+}
+template <int NT>
+__global__ __launch_bounds__(64) void project_f32_kernel(const float *__restrict__ A, int64_t m, int64_t n,
+                                                          int64_t ld, int64_t stride, const float *__restrict__ Bm,
+                                                          int64_t ldv, float *__restrict__ C) {
+    project_f32_body<NT>(A, m, n, ld, stride, Bm, ldv, C, blockIdx.y, blockIdx.x);
+}
+template <int MT, typename ET>
+__global__ __launch_bounds__(64) void sketch_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
+                                                          int64_t m, int64_t n, int64_t ld, int64_t stride,
+                                                          const uint16_t *__restrict__ Sb, int64_t mp,
+                                                          float *__restrict__ B, uint16_t *__restrict__ Bb,
+                                                          int64_t ldb, double *__restrict__ fro_part, int npanel) {
+    sketch_bf16_body<MT, ET>(A, scale, m, n, ld, stride, Sb, mp, B, Bb, ldb, fro_part, npanel, blockIdx.y,
+                             blockIdx.x);
+}
+template <int NT, typename ET>
+__global__ __launch_bounds__(64) void project_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
+                                                           int64_t m, int64_t n, int64_t ld, int64_t stride,
+                                                           const uint16_t *__restrict__ Bb, int64_t ldv,
+                                                           float *__restrict__ C) {
+    project_bf16_body<NT, ET>(A, scale, m, n, ld, stride, Bb, ldv, C, blockIdx.y, blockIdx.x);
+}
+template <int KP>
+__global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ B, int64_t ldb, int64_t n,
+                                                     const float *__restrict__ C, int64_t m, int k, int r,
+                                                     const double *__restrict__ fro_part, int npanel,
+                                                     float *__restrict__ L, float *__restrict__ R,
+                                                     float *__restrict__ sigma, double *__restrict__ relerr,
+                                                     int *__restrict__ flags) {
+    finish_body<KP>(B, ldb, n, C, m, k, r, fro_part, npanel, L, R, sigma, relerr, flags, blockIdx.x);
+}
+
+// batched forms: item = (problem, matrix, tile)
+__global__ void prep_multi_kernel(const ApDesc *__restrict__ P, const int4 *__restrict__ items, int lowp) {
+    const int4 it = items[blockIdx.x];
+    const ApDesc &D = P[it.x];
+    const int64_t e = (int64_t)it.y * blockDim.x + threadIdx.x;
+    if (lowp)
+        prep_sketch_bf16_body(D.S, D.k, D.kp, D.m, D.mp, D.Sb, e);
+    else
+        transpose_sketch_body(D.S, D.k, D.kp, D.m, D.St, e);
+}
+template <int MT>
+__global__ __launch_bounds__(64) void sketch_f32_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const ApDesc &D = P[it.x];
+    sketch_f32_body<MT>((const float *)D.A, D.m, D.n, D.ld, D.stride, D.St, D.B, D.ldv, D.fro, D.npanel, it.y, it.z);
+}
+template <int NT>
+__global__ __launch_bounds__(64) void project_f32_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const ApDesc &D = P[it.x];
+    project_f32_body<NT>((const float *)D.A, D.m, D.n, D.ld, D.stride, D.B, D.ldv, D.C, it.y, it.z);
+}
+template <int MT, typename ET>
+__global__ __launch_bounds__(64) void sketch_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const ApDesc &D = P[it.x];
+    sketch_bf16_body<MT, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Sb, D.mp, D.B, D.Bb, D.ldv,
+                             D.fro, D.npanel, it.y, it.z);
+}
+template <int NT, typename ET>
+__global__ __launch_bounds__(64) void project_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const ApDesc &D = P[it.x];
+    project_bf16_body<NT, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Bb, D.ldv, D.C, it.y, it.z);
+}
+template <int KP>
+__global__ __launch_bounds__(256) void finish_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const ApDesc &D = P[it.x];
+    finish_body<KP>(D.B, D.ldv, D.n, D.C, D.m, D.k, D.r, D.fro, D.npanel, D.L, D.R, D.sigma, D.relerr, D.flags,
+                    it.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -778,6 +888,159 @@ tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_st
                                   float *sigma, double *relerr, int32_t *flags) {
     if (s->dtype == TSK_F8E4M3) return apply_lowp_enqueue<uint8_t>(c, S, k, s, r, L, R, sigma, relerr, flags);
     return apply_lowp_enqueue<uint16_t>(c, S, k, s, r, L, R, sigma, relerr, flags);
+}
+
+// Batched SCW over problems of different shapes (tsk_apply_multi).  The host
+// lays out every problem's workspace in one buffer, writes the descriptors
+// and work-item lists into pinned memory, copies them in one transfer, then
+// launches: one sketch-preparation launch for all problems, and per
+// sketch-size class (kp / 16) one sketch, one project and one finish launch.
+// Items are ordered largest problem first, so the long items start early.
+tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute) {
+    const bool lowp = compute != TSK_F32;
+    const int panel = lowp ? SKB_PANEL : SK_PANEL;
+    const int band = lowp ? PJB_ROWS : PJ_ROWS;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    std::vector<ApDesc> desc(np);
+    std::vector<size_t> off(np * 5);
+    size_t ws = 0;
+    for (int i = 0; i < np; ++i) {
+        const tsk_stack &A = pr[i].A;
+        ApDesc &D = desc[i];
+        D.A = A.A;
+        D.scale = A.scale;
+        D.S = pr[i].S;
+        D.m = A.m;
+        D.n = A.n;
+        D.ld = A.ld;
+        D.stride = A.stride;
+        D.count = A.count;
+        D.k = pr[i].k;
+        D.r = pr[i].r;
+        D.kp = (D.k + 15) / 16 * 16;
+        D.npanel = (int)((A.n + panel - 1) / panel);
+        D.ldv = (int64_t)D.npanel * panel;
+        D.mp = (A.m + 31) / 32 * 32;
+        D.L = pr[i].L;
+        D.R = pr[i].R;
+        D.sigma = pr[i].sigma;
+        D.relerr = pr[i].relerr;
+        D.flags = pr[i].flags;
+        const size_t sz[5] = {lowp ? sizeof(uint16_t) * 2 * D.kp * D.mp : sizeof(float) * D.m * D.kp,
+                              sizeof(float) * D.count * D.kp * D.ldv,
+                              lowp ? sizeof(uint16_t) * D.count * 2 * D.kp * D.ldv : 0,
+                              sizeof(float) * D.count * D.m * D.kp, sizeof(double) * D.count * D.npanel};
+        for (int j = 0; j < 5; ++j) {
+            off[i * 5 + j] = ws;
+            ws += al(sz[j]);
+        }
+    }
+    TSK_TRY(tsk_grow(c, c->mp_ws, ws));
+    char *base = (char *)c->mp_ws.p;
+    for (int i = 0; i < np; ++i) {
+        ApDesc &D = desc[i];
+        D.St = lowp ? nullptr : (float *)(base + off[i * 5]);
+        D.Sb = lowp ? (uint16_t *)(base + off[i * 5]) : nullptr;
+        D.B = (float *)(base + off[i * 5 + 1]);
+        D.Bb = lowp ? (uint16_t *)(base + off[i * 5 + 2]) : nullptr;
+        D.C = (float *)(base + off[i * 5 + 3]);
+        D.fro = (double *)(base + off[i * 5 + 4]);
+    }
+    // work items: problems largest first within each list
+    std::vector<int> order(np);
+    for (int i = 0; i < np; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return desc[a].m * desc[a].n > desc[b].m * desc[b].n;
+    });
+    std::vector<int4> items;
+    for (int i : order) {  // preparation of each sketch
+        const int64_t tot = lowp ? (int64_t)desc[i].kp * desc[i].mp : desc[i].m * desc[i].kp;
+        for (int64_t b = 0; b < (tot + 255) / 256; ++b) items.push_back(int4{i, (int)b, 0, 0});
+    }
+    size_t n_prep = items.size();
+    size_t start[3][5] = {}, cnt[3][5] = {};  // [phase][class]
+    for (int ph = 0; ph < 3; ++ph)
+        for (int cl = 1; cl <= 4; ++cl) {
+            start[ph][cl] = items.size();
+            for (int i : order) {
+                const ApDesc &D = desc[i];
+                if (D.kp / 16 != cl) continue;
+                const int nt = ph == 0 ? D.npanel : ph == 1 ? (int)((D.m + band - 1) / band) : 1;
+                for (int64_t d = 0; d < D.count; ++d)
+                    for (int t = 0; t < nt; ++t) items.push_back(int4{i, (int)d, t, 0});
+            }
+            cnt[ph][cl] = items.size() - start[ph][cl];
+        }
+    // one transfer: descriptors then items
+    const size_t dbytes = al(sizeof(ApDesc) * np), ibytes = sizeof(int4) * items.size();
+    if (c->mp_ev) {
+        hipError_t e = hipEventSynchronize(c->mp_ev);  // the previous transfer has read the pinned buffer
+        if (e != hipSuccess) return tsk_hip(c, e, "batch table event");
+    }
+    if (c->mp_pin_bytes < dbytes + ibytes) {
+        if (c->mp_pin) (void)hipHostFree(c->mp_pin);
+        c->mp_pin = nullptr;
+        c->mp_pin_bytes = 0;
+        const size_t nb = (dbytes + ibytes + (1 << 16) - 1) & ~(size_t)((1 << 16) - 1);
+        if (hipHostMalloc(&c->mp_pin, nb, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->mp_pin = nullptr;
+            return tsk_fail(c, TSK_E_NOMEM, "pinned batch table allocation failed");
+        }
+        c->mp_pin_bytes = nb;
+    }
+    memcpy(c->mp_pin, desc.data(), sizeof(ApDesc) * np);
+    memcpy((char *)c->mp_pin + dbytes, items.data(), ibytes);
+    TSK_TRY(tsk_grow(c, c->mp_tab, dbytes + ibytes));
+    hipError_t e = hipMemcpyAsync(c->mp_tab.p, c->mp_pin, dbytes + ibytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return tsk_hip(c, e, "batch table copy");
+    if (!c->mp_ev && hipEventCreateWithFlags(&c->mp_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        c->mp_ev = nullptr;
+    }
+    if (c->mp_ev) (void)hipEventRecord(c->mp_ev, c->stream);
+    const ApDesc *P = (const ApDesc *)c->mp_tab.p;
+    const int4 *I = (const int4 *)((const char *)c->mp_tab.p + dbytes);
+    TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(prep_multi_kernel, dim3((unsigned)n_prep), dim3(256), 0,
+                                                        c->stream, P, I, lowp ? 1 : 0));
+    const bool e4 = compute == TSK_F8E4M3;
+#define TSK_MSK(CL)                                                                                                \
+    if (cnt[0][CL]) {                                                                                              \
+        const dim3 g((unsigned)cnt[0][CL]);                                                                        \
+        const int4 *It = I + start[0][CL];                                                                         \
+        if (!lowp)                                                                                                 \
+            TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_multi<CL>, g, dim3(64), 0, c->stream, P, It)); \
+        else if (e4)                                                                                               \
+            TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                       \
+                       hipLaunchKernelGGL((sketch_bf16_multi<CL, uint8_t>), g, dim3(64), 0, c->stream, P, It));     \
+        else                                                                                                       \
+            TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                       \
+                       hipLaunchKernelGGL((sketch_bf16_multi<CL, uint16_t>), g, dim3(64), 0, c->stream, P, It));    \
+    }
+#define TSK_MPJ(CL)                                                                                                \
+    if (cnt[1][CL]) {                                                                                              \
+        const dim3 g((unsigned)cnt[1][CL]);                                                                        \
+        const int4 *It = I + start[1][CL];                                                                         \
+        if (!lowp)                                                                                                 \
+            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_multi<CL>, g, dim3(64), 0, c->stream, P, It)); \
+        else if (e4)                                                                                               \
+            TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                      \
+                       hipLaunchKernelGGL((project_bf16_multi<CL, uint8_t>), g, dim3(64), 0, c->stream, P, It));    \
+        else                                                                                                       \
+            TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                      \
+                       hipLaunchKernelGGL((project_bf16_multi<CL, uint16_t>), g, dim3(64), 0, c->stream, P, It));   \
+    }
+#define TSK_MFN(CL)                                                                                           \
+    if (cnt[2][CL])                                                                                           \
+        TSK_LAUNCH(c, TSK_KERNEL_FINISH, hipLaunchKernelGGL(finish_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),    \
+                                                            dim3(256), 0, c->stream, P, I + start[2][CL]));
+    TSK_MSK(1) TSK_MSK(2) TSK_MSK(3) TSK_MSK(4)
+    TSK_MPJ(1) TSK_MPJ(2) TSK_MPJ(3) TSK_MPJ(4)
+    TSK_MFN(1) TSK_MFN(2) TSK_MFN(3) TSK_MFN(4)
+#undef TSK_MSK
+#undef TSK_MPJ
+#undef TSK_MFN
+    return TSK_OK;
 }
 
 tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, const float *R, int r, double *relerr) {

@@ -17,6 +17,7 @@ tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_st
                                   float *sigma, double *relerr, int32_t *flags);
 tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, const float *R, int r,
                              double *relerr);
+tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute);
 
 tsk_status tsk_fail(tsk_ctx c, tsk_status st, const std::string &msg) {
     if (c) c->err = msg;
@@ -210,9 +211,11 @@ void tsk_destroy(tsk_ctx c) {
     TskBuf *bufs[] = {&c->gram_part, &c->gram_G,  &c->eig_Y0,   &c->eig_Y1, &c->eig_Rinv, &c->eig_part,
                       &c->eig_C,     &c->eig_X,   &c->eig_GX,   &c->eig_small, &c->eig_U, &c->counters,
                       &c->ap_St,     &c->ap_B,    &c->ap_C,     &c->ap_fro, &c->ap_Sb,    &c->ap_Bb,
-                      &c->er_part,   &c->st_part};
+                      &c->er_part,   &c->st_part, &c->mp_ws,    &c->mp_tab};
     for (TskBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
+    if (c->mp_pin) (void)hipHostFree(c->mp_pin);
+    if (c->mp_ev) (void)hipEventDestroy(c->mp_ev);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     delete c;
 }
@@ -291,11 +294,9 @@ tsk_status tsk_train(tsk_ctx c, const tsk_stack *train, int32_t k, int32_t compu
     return tsk_eig_enqueue(c, G, m, k, S, lambda, iters, tol);
 }
 
-tsk_status tsk_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test, int32_t r, int32_t compute,
-                     float *L, float *R, float *sigma, double *relerr, int32_t *flags) {
-    if (!c) return TSK_E_ARG;
-    c->err.clear();
-    DeviceGuard g(c->device);
+// Arguments of one SCW problem (tsk_apply, or one problem of tsk_apply_multi).
+static tsk_status check_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test, int32_t r,
+                              int32_t compute, float *L, float *R, float *sigma, double *relerr, int32_t *flags) {
     TSK_TRY(tsk_check_stack(c, test, "test"));
     if (compute != TSK_F32 && compute != TSK_BF16 && compute != TSK_F8E4M3)
         return tsk_fail(c, TSK_E_ARG, "tsk_apply: compute must be TSK_F32, TSK_BF16 or TSK_F8E4M3");
@@ -310,6 +311,35 @@ tsk_status tsk_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test
     TSK_TRY(tsk_check_dev(c, sigma, sizeof(float) * cnt * r, "sigma"));
     if (relerr) TSK_TRY(tsk_check_dev(c, relerr, sizeof(double) * cnt, "relerr"));
     if (flags) TSK_TRY(tsk_check_dev(c, flags, sizeof(int32_t) * cnt, "flags"));
+    return TSK_OK;
+}
+
+tsk_status tsk_apply_multi(tsk_ctx c, const tsk_problem *probs, int32_t nprobs, int32_t compute) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    if (!probs || nprobs < 1 || nprobs > (1 << 20))
+        return tsk_fail(c, TSK_E_ARG, "tsk_apply_multi: need 1 <= nprobs <= 2^20 problems");
+    int64_t items = 0;
+    for (int i = 0; i < nprobs; ++i) {
+        const tsk_problem &p = probs[i];
+        tsk_status st = check_apply(c, p.S, p.k, &p.A, p.r, compute, p.L, p.R, p.sigma, p.relerr, p.flags);
+        if (st != TSK_OK) {
+            c->err = "problem " + std::to_string(i) + ": " + c->err;
+            return st;
+        }
+        items += p.A.count * (p.A.n / 64 + p.A.m / 64 + 3);
+    }
+    if (items > ((int64_t)1 << 31) - 1) return tsk_fail(c, TSK_E_SHAPE, "tsk_apply_multi: batch too large");
+    return tsk_apply_multi_enqueue(c, probs, nprobs, compute);
+}
+
+tsk_status tsk_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test, int32_t r, int32_t compute,
+                     float *L, float *R, float *sigma, double *relerr, int32_t *flags) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    TSK_TRY(check_apply(c, S, k, test, r, compute, L, R, sigma, relerr, flags));
     if (compute != TSK_F32) return tsk_apply_bf16_enqueue(c, S, k, test, r, L, R, sigma, relerr, flags);
     return tsk_apply_enqueue(c, S, k, test, r, L, R, sigma, relerr, flags);
 }

@@ -493,6 +493,10 @@ struct tsk_ctx_s {
     TskBuf ap_St, ap_B, ap_C, ap_fro;
     TskBuf ap_Sb, ap_Bb;  // bf16 hi/lo pairs of S and B (bf16 path)
     TskBuf er_part, st_part;
+    TskBuf mp_ws, mp_tab;            // batched apply: workspace, descriptors + items
+    void *mp_pin = nullptr;          // pinned host copy of the batch tables
+    size_t mp_pin_bytes = 0;
+    hipEvent_t mp_ev = nullptr;      // recorded after the last batch table copy
     // eigensolver controls
     int eig_block = 0, eig_max_iter = 300, eig_check = 4;
     double eig_tol = 0.0;  // 0: TSK_EIG_TOL_F32 / TSK_EIG_TOL_BF16 by the Gram's precision

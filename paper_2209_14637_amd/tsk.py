@@ -23,8 +23,8 @@ _STATUS = {0: "TSK_OK", 1: "TSK_E_ARG", 2: "TSK_E_SHAPE", 3: "TSK_E_NOMEM", 4: "
            5: "TSK_E_NOCONV"}
 
 EXPORTS = ["tsk_create", "tsk_destroy", "tsk_set_stream", "tsk_last_error", "tsk_stage", "tsk_gram",
-           "tsk_eig_topk", "tsk_train", "tsk_apply", "tsk_error", "tsk_set_eig_params", "tsk_timing_enable",
-           "tsk_timing_read"]
+           "tsk_eig_topk", "tsk_train", "tsk_apply", "tsk_apply_multi", "tsk_error", "tsk_set_eig_params",
+           "tsk_timing_enable", "tsk_timing_read"]
 
 _DTYPES = {"f32": TSK_F32, "bf16": TSK_BF16, "e4m3": TSK_F8E4M3}
 
@@ -39,6 +39,12 @@ class Stack(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("scale", ctypes.c_void_p),
                 ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("count", ctypes.c_int64),
                 ("ld", ctypes.c_int64), ("stride", ctypes.c_int64)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("A", Stack), ("S", ctypes.c_void_p), ("k", ctypes.c_int32), ("r", ctypes.c_int32),
+                ("L", ctypes.c_void_p), ("R", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+                ("relerr", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
 
 
 _lib = None
@@ -65,6 +71,7 @@ def load(path: str | None = None):
         "tsk_eig_topk": ([P, P, I64, I32, P, P, P], I32),
         "tsk_train": ([P, sp, I32, I32, P, P, P], I32),
         "tsk_apply": ([P, P, I32, sp, I32, I32, P, P, P, P, P], I32),
+        "tsk_apply_multi": ([P, ctypes.POINTER(Problem), I32, I32], I32),
         "tsk_error": ([P, sp, P, P, I32, P], I32),
         "tsk_set_eig_params": ([P, I32, I32, D, I32], I32),
         "tsk_timing_enable": ([P, I32], I32),
@@ -224,6 +231,38 @@ class Context:
         self._check(self.lib.tsk_apply(self.h, _ptr(S), k, ctypes.byref(s), r, s.dtype, _ptr(o["L"]), _ptr(o["R"]),
                                        _ptr(o["sigma"]), _ptr(o.get("relerr")), _ptr(o.get("flags"))))
         return o
+
+    @staticmethod
+    def _outputs(s, r, dev, relerr=True, flags=True):
+        return {"L": torch.empty((s.count, s.m, r), dtype=torch.float32, device=dev),
+                "R": torch.empty((s.count, s.n, r), dtype=torch.float32, device=dev),
+                "sigma": torch.empty((s.count, r), dtype=torch.float32, device=dev),
+                "relerr": torch.empty(s.count, dtype=torch.float64, device=dev) if relerr else None,
+                "flags": torch.empty(s.count, dtype=torch.int32, device=dev) if flags else None}
+
+    def apply_multi(self, problems, outs: list | None = None) -> list:
+        """SCW on a batch of problems [(S, A, r), ...] of different shapes
+        (tsk_apply_multi); every A must have the same format.  Returns one
+        output dict per problem (reusing `outs` when given)."""
+        self._sync_stream()
+        n = len(problems)
+        arr = (Problem * n)()
+        res, keep, dts = [], [], set()
+        for i, (S, A, r) in enumerate(problems):
+            s = _stack(A)
+            dts.add(s.dtype)
+            if S.dtype != torch.float32 or not S.is_contiguous() or S.shape[1] != s.m:
+                raise ValueError("S must be a contiguous (k, m) float32 CUDA tensor")
+            o = outs[i] if outs is not None else self._outputs(s, r, S.device)
+            opt = [o[key].data_ptr() if o.get(key) is not None else None for key in ("relerr", "flags")]
+            arr[i] = Problem(s, S.data_ptr(), S.shape[0], r, o["L"].data_ptr(), o["R"].data_ptr(),
+                             o["sigma"].data_ptr(), opt[0], opt[1])
+            res.append(o)
+            keep.append((S, A))
+        if len(dts) != 1:
+            raise ValueError("all problems of a batch must have the same format")
+        self._check(self.lib.tsk_apply_multi(self.h, arr, n, dts.pop()))
+        return res
 
     def error(self, A: torch.Tensor, L: torch.Tensor, R: torch.Tensor, relerr: torch.Tensor | None = None):
         self._sync_stream()

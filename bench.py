@@ -16,6 +16,8 @@ Workloads (synthetic streams; the paper's datasets are not available):
   t3stream_e4m3: 1920 x 1080 stream with Student-t(3) noise at 1e-2, 4000
       training + 1000 test matrices, k = 40, r = 20, e4m3 storage; errors of
       the e4m3, bf16 and FP32 applies with the same sketch side by side.
+  batch_bf16: the batching form, 8 streams of uneven shapes, 2000 test
+      matrices interleaved at random, batches of 256 (tsk_apply_multi).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                   [--no-cpu-baseline]
@@ -38,7 +40,7 @@ ORDER_CPU_SAMPLE = {"stream_bf16": (12, 32), "hsi_fp32": (40, 64), "t3stream_e4m
 WORKLOADS = {
     "stream_bf16": ("bf16", "spec_bf16_1920", "stream_1920x1080_k40_r20"),
     "hsi_fp32": ("f32", "spec_hsi_fp32", "hsi_1024x768_k20_r10"),
-    "t3stream_e4m3": ("e4m3", "spec_fp8_1920", "t3stream_1920x1080_k40_r20"),
+    "t3stream_e4m3": ("bf16", "spec_fp8_1920", "t3stream_1920x1080_k40_r20"),
 }
 
 
@@ -140,9 +142,12 @@ def run(args):
         Te = ctx.stage(te, prec)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        if wl == "t3stream_e4m3":
+            # the e4m3 form beside the gated bf16 one
+            rec_extra["_q8"] = ctx.stage(tr, "e4m3")
         del tr
         torch.cuda.empty_cache()
-        stage_bytes = spec.n_test * m * n * (4 + (2 if prec == "bf16" else 1))
+        stage_bytes = spec.n_test * m * n * (4 + 2)
         rec_extra["stage_ms"] = {"train": (t1 - t0) * 1e3, "test": (t2 - t1) * 1e3,
                                  "test_gbs": stage_bytes / (t2 - t1) / 1e9}
         train_in, test_in, compute = Tr, Te, prec
@@ -195,7 +200,7 @@ def run(args):
     gram_flops = m * (m + 1) * n * spec.n_train
     gram_tflops = gram_flops / ((gram_ms + gram_red_ms) / 1e3) / 1e12
     gram_kernel = {"f32": "gram_f32_kernel", "bf16": "gram_bf16_kernel<uint16_t>", "e4m3": "gram_e4m3_kernel"}[prec]
-    elt = {"f32": 4, "bf16": 2, "e4m3": 1}[prec]
+    elt = {"f32": 4, "bf16": 2, "e4m3": 2}[prec]  # test matrices as the gated apply reads them
     apply_bytes = spec.n_test * m * n * elt
     dom = max(per_kernel_ms, key=per_kernel_ms.get)
     if dom == "gram":
@@ -217,17 +222,42 @@ def run(args):
         if name in per_kernel_ms:
             roof_apply[f"{name}_kernel_gbs"] = apply_bytes / (per_kernel_ms[name] / 1e3) / 1e9
 
-    if prec == "e4m3" and parity is not None:
-        # the same sketch applied to bf16 and FP32 copies of the test
-        # matrices: errors side by side against the oracle
+    Tq = rec_extra.pop("_q8", None)
+    if Tq is not None and parity is not None:
+        # the e4m3 form: e4m3 Gram (timed), its sketch applied to e4m3 and
+        # bf16 test matrices; errors against the oracle side by side with the
+        # gated bf16 form
         ne = parity["matrices"]
         ref = np.array(json.load(open(gpath))["relerr"])
-        side = {}
-        for form, A in (("e4m3", test_in), ("bf16", ctx.stage(te[:ne], "bf16")), ("f32", te[:ne])):
-            o = ctx.apply(S, A if form != "e4m3" else tsk.Staged(A.data[:ne], n, "e4m3", A.scale[:ne]), r)
+        ctx.timing(["gram"])
+        ctx.timing_read(reset=True)
+        S8, lam8, it8, _ = ctx.train(Tq, k, compute="e4m3")
+        S8, lam8, it8, _ = ctx.train(Tq, k, compute="e4m3")
+        kt8 = ctx.timing_read(reset=True)
+        ctx.timing(False)
+        g8 = kt8["gram"][1] / max(kt8["gram"][0], 1)
+        q8t = ctx.stage(te, "e4m3")
+        side = {"gram_e4m3_ms": g8, "gram_e4m3_tflops": gram_flops / (g8 / 1e3) / 1e12,
+                "gram_e4m3_frac_of_5000": gram_flops / (g8 / 1e3) / 1e12 / PEAK_TFLOPS["e4m3"],
+                "eig_iterations": it8}
+        for tag, Sx, A in (("e4m3_sketch_e4m3_apply", S8, q8t), ("e4m3_sketch_bf16_apply", S8, test_in),
+                           ("bf16_sketch_bf16_apply", S, test_in)):
+            o = ctx.apply(Sx, A, r)
             e_exp = ctx.error(te[:ne], o["L"][:ne], o["R"][:ne]).cpu().numpy()
-            side[form] = float(np.max(np.abs(e_exp - ref) / ref))
-        rec_extra["max_rel_dev_by_apply_form_same_sketch"] = side
+            tt = []
+            for _ in range(3):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                ctx.apply(Sx, A, r, out=o)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                tt.append(e0.elapsed_time(e1))
+            side[tag] = {"max_rel_dev_explicit_error": float(np.max(np.abs(e_exp - ref) / ref)),
+                         "pass_1e-3": bool(np.max(np.abs(e_exp - ref) / ref) <= 1e-3),
+                         "apply_ms": float(np.median(tt)), "matrices_per_s": spec.n_test / (np.median(tt) / 1e3)}
+        del q8t, Tq
+        rec_extra["e4m3_form"] = side
     if prec != "f32":
         # the plain FP32 path on the same FP32 test matrices and sketch
         o32 = ctx.apply(S, te, r)
@@ -262,8 +292,9 @@ def run(args):
                                 f"i^-1.5 + {spec.eta:g} {'Student-t(3)' if spec.noise == 't3' else 'Gaussian'} "
                                 f"noise, slow drift, k={k}, r={r}, "
                                 + {"bf16": "bf16 storage, FP32 accumulation, FP64 small factorizations",
-                                   "e4m3": "e4m3 storage (power-of-two scale per matrix), e4m3 Gram, bf16 products "
-                                           "in the apply, FP32 accumulation, FP64 small factorizations",
+                                   "e4m3": "training matrices in e4m3 (power-of-two scale per matrix), e4m3 Gram; "
+                                           "test matrices in bf16 (the gated form; the all-e4m3 apply is "
+                                           "reported beside), FP32 accumulation, FP64 small factorizations",
                                    "f32": "FP32"}[prec]),
                    "m": m, "n": n, "n_train": spec.n_train, "n_test": spec.n_test, "k": k, "r": r},
         "gram_tflops": gram_tflops,
@@ -281,22 +312,153 @@ def run(args):
     return rec, spec
 
 
+def run_batch(args):
+    """The batching form: 8 streams of uneven shapes, 2000 test matrices
+    interleaved at random, batches of 256, bf16; each batch is one
+    tsk_apply_multi call.  The plain FP32 path (tsk_apply per stream and
+    batch) on the same matrices is timed beside it."""
+    import torch
+
+    from paper_2209_14637_amd import synth, tsk
+
+    ns = len(synth.BATCH_SHAPES)
+    n_test, bsz = 2000, 256
+    order = synth.batch_order(n_test)
+    need = [int((order == s).sum()) for s in range(ns)]
+    ctx = tsk.Context(0)
+    specs = [synth.spec_batch_stream(s) for s in range(ns)]
+    S, te32, te16 = [], [], []
+    log(f"generating 8 streams: 100 training slices each, {n_test} test matrices in all")
+    t_train = 0.0
+    for s, spec in enumerate(specs):
+        st = synth.Stream(spec)
+        tr = torch.from_numpy(st.train()).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Sd, _, _, _ = ctx.train(ctx.stage(tr, "bf16"), spec.k, compute="bf16")
+        torch.cuda.synchronize()
+        t_train += time.perf_counter() - t0
+        del tr
+        S.append(Sd)
+        t = torch.from_numpy(st.test(need[s])).cuda()
+        te32.append(t)
+        te16.append(ctx.stage(t, "bf16"))
+    # batches: per stream, the next consecutive test matrices of that stream
+    batches, nxt = [], [0] * ns
+    for b0 in range(0, n_test, bsz):
+        ids = order[b0:b0 + bsz]
+        probs = []
+        for s in range(ns):
+            c = int((ids == s).sum())
+            if c:
+                probs.append((s, nxt[s], c))
+                nxt[s] += c
+        batches.append(probs)
+
+    def problems(fmt):
+        out = []
+        for probs in batches:
+            lst = []
+            for s, d0, c in probs:
+                A = (tsk.Staged(te16[s].data[d0:d0 + c], specs[s].n, "bf16") if fmt == "bf16"
+                     else te32[s][d0:d0 + c])
+                lst.append((S[s], A, specs[s].r))
+            out.append(lst)
+        return out
+
+    pb = problems("bf16")
+    outs = [ctx.apply_multi(p) for p in pb]  # warm-up and output buffers
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(max(args.steps, 3)):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for p, o in zip(pb, outs):
+            ctx.apply_multi(p, outs=o)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    # the plain FP32 path: one tsk_apply per (batch, stream)
+    p32 = problems("f32")
+    o32 = [[ctx.apply(Sx, A, r) for Sx, A, r in p] for p in p32]
+    torch.cuda.synchronize()
+    t32 = []
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for p, oo in zip(p32, o32):
+            for (Sx, A, r), o in zip(p, oo):
+                ctx.apply(Sx, A, r, out=o)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t32.append(e0.elapsed_time(e1))
+    ms32 = float(np.median(t32))
+    # parity: the first test matrices of every stream against the oracle
+    parity = None
+    gpath = os.path.join(ROOT, "tests", "golden", "batch_8streams_k10-40.json")
+    if os.path.exists(gpath):
+        g = json.load(open(gpath))
+        worst = 0.0
+        for s, gs in enumerate(g["streams"]):
+            ref = np.array(gs["relerr"])
+            ne = min(ref.size, need[s])
+            o = ctx.apply(S[s], tsk.Staged(te16[s].data[:ne], specs[s].n, "bf16"), specs[s].r)
+            e = ctx.error(te32[s][:ne], o["L"], o["R"]).cpu().numpy()
+            worst = max(worst, float(np.max(np.abs(e - ref[:ne]) / ref[:ne])))
+        parity = {"max_rel_dev_explicit_error": worst, "tau": TAU["bf16"], "matrices": 4 * ns,
+                  "pass": bool(worst <= TAU["bf16"]),
+                  "note": "sketch trained on the GPU in bf16, oracle sketch from the oracle's FP64 training"}
+    apply_bytes = sum(specs[s].m * specs[s].n * 2 * need[s] for s in range(ns))
+    rec = {
+        "metric": "sketch-apply matrices/s + Gram TFLOP/s at rel-err <=1e-3 vs FP64 oracle",
+        "value": n_test / (ms / 1e3), "unit": "matrices/s", "n_gpus": 1, "steps": len(times), "warmup": 1,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "batch_bf16: 8 streams of shapes (256,192)..(2048,1536), k in {10,20,40}, r=k/2, "
+                               "2000 test matrices interleaved at random, batches of 256, one tsk_apply_multi per "
+                               "batch; each stream trained on 100 slices (bf16)", "streams": [list(x) for x in
+                                                                                         synth.BATCH_SHAPES],
+                   "batch": bsz, "n_test": n_test},
+        "train_ms_all_streams": t_train * 1e3,
+        "roofline_apply": {"bound": "hbm", "achieved": apply_bytes / (ms / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
+                           "unit": "GB/s", "frac": apply_bytes / (ms / 1e3) / 1e9 / PEAK_HBM_GBS,
+                           "algorithmic_bytes": apply_bytes},
+        "fp32_per_stream_path": {"ms": ms32, "matrices_per_s": n_test / (ms32 / 1e3), "bf16_batched_speedup":
+                                 ms32 / ms},
+        "parity": parity,
+    }
+    ctx.close()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="stream_bf16", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="stream_bf16", choices=sorted(WORKLOADS) + ["batch_bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU path "
               "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
         sys.exit(2)
-    rec, spec = run(args)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle on a bounded sample)")
-        rec["cpu_baseline"] = cpu_baseline(spec, *ORDER_CPU_SAMPLE[args.workload])
+    if args.workload == "batch_bf16":
+        rec = run_batch(args)
+        if not args.no_cpu_baseline:
+            from paper_2209_14637_amd import synth
+            log("cpu baseline (oracle on a bounded sample)")
+            rec["cpu_baseline"] = cpu_baseline(synth.spec_batch_stream(6), 12, 32)
+            rec["cpu_baseline"]["sample"] += " (the 1920x1080 stream of the batch)"
+    else:
+        rec, spec = run(args)
+        if not args.no_cpu_baseline:
+            log("cpu baseline (oracle on a bounded sample)")
+            rec["cpu_baseline"] = cpu_baseline(spec, *ORDER_CPU_SAMPLE[args.workload])
     print(json.dumps(rec), flush=True)
 
 

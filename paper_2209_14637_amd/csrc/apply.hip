@@ -508,58 +508,75 @@ __device__ inline void small_mm(const double *X, const double *M, double *Y) {
     __syncthreads();
 }
 
+// factor: B B^T = R^T R (Cholesky, dead pivots dropped), X = R^-1 and
+// H = X^T (C^T C) X, written to HX[d] = [H | X] (KP x KP each, FP64); the
+// number of dead pivots among the first k to q[d].
 template <int KP>
-__device__ __forceinline__ void finish_body(const float *__restrict__ B, int64_t ldb, int64_t n,
-                                                     const float *__restrict__ C, int64_t m, int k, int r,
-                                                     const double *__restrict__ fro_part, int npanel,
-                                                     float *__restrict__ L, float *__restrict__ R,
-                                                     float *__restrict__ sigma, double *__restrict__ relerr,
-                                                     int *__restrict__ flags, int64_t d) {
+__device__ __forceinline__ void factor_body(const float *__restrict__ B, int64_t ldb, int64_t n,
+                                            const float *__restrict__ C, int64_t m, int k, double *__restrict__ HX,
+                                            int *__restrict__ q, int64_t d) {
     constexpr int SZ = KP * KP;
     __shared__ double buf[3 * SZ];
-    __shared__ float Zs[KP * KP];          // Z = R^-1 Y_r (k x r, row stride KP)
-    __shared__ double rot[KP];
-    __shared__ double red4[4];
     __shared__ int dead[KP];
-    __shared__ int perm[KP];
-    __shared__ double s_lam[KP];
     const int tid = threadIdx.x;
     const float *Bd = B + d * KP * ldb;
     const float *Cd = C + d * m * KP;
     double *b0 = buf, *b1 = buf + SZ, *b2 = buf + 2 * SZ;
-    // 1. B B^T = R^T R; X = R^-1 in b2 (b0 scratch, b1 = R)
     for (int e = tid; e < SZ; e += 256) b0[e] = 0.0;
     __syncthreads();
     gram_mfma_acc<KP / 16, true>(Bd, ldb, n, b0, KP);
-    const int nd = chol_factor_inverse(b0, KP, KP, 1e-12, b1, b2, dead, k);
-    // 2. H = X^T (C^T C) X in b0
+    const int nd = chol_factor_inverse(b0, KP, KP, 1e-12, b1, b2, dead, k);  // X = R^-1 in b2
     for (int e = tid; e < SZ; e += 256) b0[e] = 0.0;
     __syncthreads();
     gram_mfma_acc<KP / 16, false>(Cd, KP, m, b0, KP);
     small_mm<KP, false>(b0, b2, b1);  // b1 = (C^T C) X
     small_mm<KP, true>(b2, b1, b0);   // b0 = X^T b1
-    // 3. H = Y diag Y^T (Y^T in b1)
+    double *o = HX + d * 2 * SZ;
+    for (int e = tid; e < SZ; e += 256) {
+        o[e] = b0[e];
+        o[SZ + e] = b2[e];
+    }
+    if (tid == 0) q[d] = nd;
+}
+
+// eig: H = Y diag Y^T (Jacobi), descending order, sigma, relerr, flags, and
+// Z = X Y_r (FP32, KP x KP, row stride KP) to Z[d].
+template <int KP>
+__device__ __forceinline__ void eig_body(const double *__restrict__ HX, const int *__restrict__ q, int k, int r,
+                                         const double *__restrict__ fro_part, int npanel, float *__restrict__ Z,
+                                         float *__restrict__ sigma, double *__restrict__ relerr,
+                                         int *__restrict__ flags, int64_t d) {
+    constexpr int SZ = KP * KP;
+    __shared__ double H[SZ], Wt[SZ];
+    __shared__ double rot[KP];
+    __shared__ double red4[4];
+    __shared__ int perm[KP];
+    __shared__ double s_lam[KP];
+    const int tid = threadIdx.x;
+    const double *Hg = HX + d * 2 * SZ, *Xg = Hg + SZ;
+    for (int e = tid; e < SZ; e += 256) H[e] = Hg[e];
+    __syncthreads();
     const int kk = k + (k & 1);  // even size for the parallel ordering
-    jacobi_eig_wg<(KP * (KP + 2) / 8 + 255) / 256, (KP * KP / 2 + 255) / 256>(b0, b1, kk, KP, rot, 40, red4);
+    jacobi_eig_wg<(KP * (KP + 2) / 8 + 255) / 256, (KP * KP / 2 + 255) / 256>(H, Wt, kk, KP, rot, 40, red4);
     // descending order: rank of each diagonal entry (ties by index)
     for (int i = tid; i < kk; i += 256) {
-        const double hi = b0[i * KP + i];
+        const double hi = H[i * KP + i];
         int rank = 0;
         for (int j = 0; j < kk; ++j) {
-            const double hj = b0[j * KP + j];
+            const double hj = H[j * KP + j];
             rank += (hj > hi) || (hj == hi && j < i);
         }
         perm[rank] = i;
     }
     __syncthreads();
-    for (int t = tid; t < kk; t += 256) s_lam[t] = b0[perm[t] * KP + perm[t]];
-    // 4. Z = X Y_r (FP32 for the output products)
+    for (int t = tid; t < kk; t += 256) s_lam[t] = H[perm[t] * KP + perm[t]];
+    float *Zd = Z + d * SZ;
     for (int e = tid; e < SZ; e += 256) {
         const int i = e / KP, t = e % KP;
         double z = 0.0;
         if (i < k && t < r)
-            for (int u = 0; u < k; ++u) z += b2[i * KP + u] * b1[perm[t] * KP + u];
-        Zs[e] = (float)z;
+            for (int u = 0; u < k; ++u) z += Xg[i * KP + u] * Wt[perm[t] * KP + u];
+        Zd[e] = (float)z;
     }
     __syncthreads();
     double fro2 = 0.0;
@@ -570,7 +587,7 @@ __device__ __forceinline__ void finish_body(const float *__restrict__ B, int64_t
     if (tid == 0) {
         double cap = 0.0;
         for (int t = 0; t < r; ++t) cap += fmax(s_lam[t], 0.0);
-        int fl = nd > 0 ? TSK_FLAG_RANKDEF : 0;
+        int fl = q[d] > 0 ? TSK_FLAG_RANKDEF : 0;
         if (!finite) fl |= TSK_FLAG_NONFIN;
         const double sr = sqrt(fmax(s_lam[r - 1], 0.0)), sr1 = sqrt(fmax(s_lam[r], 0.0));
         const double s1 = sqrt(fmax(s_lam[0], 0.0));
@@ -578,7 +595,26 @@ __device__ __forceinline__ void finish_body(const float *__restrict__ B, int64_t
         if (flags) flags[d] = fl;
         if (relerr) relerr[d] = !finite ? (double)qnan : (fro2 > 0.0 ? sqrt(fmax(fro2 - cap, 0.0) / fro2) : 0.0);
     }
-    // 5. L = C Z: one row of C per thread
+}
+
+// outputs: L = C Z (m x r) and R = B^T Z (n x r); NaN for a non-finite A_d.
+template <int KP>
+__device__ __forceinline__ void outputs_body(const float *__restrict__ B, int64_t ldb, int64_t n,
+                                             const float *__restrict__ C, int64_t m, int k, int r,
+                                             const double *__restrict__ fro_part, int npanel,
+                                             const float *__restrict__ Z, float *__restrict__ L,
+                                             float *__restrict__ R, int64_t d) {
+    __shared__ float Zs[KP * KP];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < KP * KP; e += 256) Zs[e] = Z[d * KP * KP + e];
+    double fro2 = 0.0;
+    for (int p = 0; p < npanel; ++p) fro2 += fro_part[d * npanel + p];
+    const bool finite = isfinite(fro2);
+    const float qnan = __builtin_nanf("");
+    __syncthreads();
+    const float *Bd = B + d * KP * ldb;
+    const float *Cd = C + d * m * KP;
+    // L = C Z: one row of C per thread
     float *Ld = L + d * m * r;
     for (int64_t i = tid; i < m; i += 256) {
         float cv[KP];
@@ -597,7 +633,7 @@ __device__ __forceinline__ void finish_body(const float *__restrict__ B, int64_t
             Ld[i * r + t] = finite ? s : qnan;
         }
     }
-    // 6. R = B^T Z: one column of B per thread
+    // R = B^T Z: one column of B per thread
     float *Rd = R + d * n * r;
     for (int64_t j = tid; j < n; j += 256) {
         float vv[KP];
@@ -632,6 +668,9 @@ struct ApDesc {
     uint16_t *Bb;
     float *C;
     double *fro;
+    double *HX;             // per matrix [H | X], KP x KP FP64 each
+    float *Z;               // per matrix KP x KP
+    int *q;                 // per matrix dead-pivot count
     float *L, *R, *sigma;
     double *relerr;
     int32_t *flags;
@@ -675,13 +714,25 @@ __global__ __launch_bounds__(64) void project_bf16_kernel(const ET *__restrict__
     project_bf16_body<NT, ET>(A, scale, m, n, ld, stride, Bb, ldv, C, blockIdx.y, blockIdx.x);
 }
 template <int KP>
-__global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ B, int64_t ldb, int64_t n,
-                                                     const float *__restrict__ C, int64_t m, int k, int r,
-                                                     const double *__restrict__ fro_part, int npanel,
-                                                     float *__restrict__ L, float *__restrict__ R,
-                                                     float *__restrict__ sigma, double *__restrict__ relerr,
-                                                     int *__restrict__ flags) {
-    finish_body<KP>(B, ldb, n, C, m, k, r, fro_part, npanel, L, R, sigma, relerr, flags, blockIdx.x);
+__global__ __launch_bounds__(256) void factor_kernel(const float *__restrict__ B, int64_t ldb, int64_t n,
+                                                     const float *__restrict__ C, int64_t m, int k,
+                                                     double *__restrict__ HX, int *__restrict__ q) {
+    factor_body<KP>(B, ldb, n, C, m, k, HX, q, blockIdx.x);
+}
+template <int KP>
+__global__ __launch_bounds__(256) void eig_kernel(const double *__restrict__ HX, const int *__restrict__ q, int k,
+                                                  int r, const double *__restrict__ fro_part, int npanel,
+                                                  float *__restrict__ Z, float *__restrict__ sigma,
+                                                  double *__restrict__ relerr, int *__restrict__ flags) {
+    eig_body<KP>(HX, q, k, r, fro_part, npanel, Z, sigma, relerr, flags, blockIdx.x);
+}
+template <int KP>
+__global__ __launch_bounds__(256) void outputs_kernel(const float *__restrict__ B, int64_t ldb, int64_t n,
+                                                      const float *__restrict__ C, int64_t m, int k, int r,
+                                                      const double *__restrict__ fro_part, int npanel,
+                                                      const float *__restrict__ Z, float *__restrict__ L,
+                                                      float *__restrict__ R) {
+    outputs_body<KP>(B, ldb, n, C, m, k, r, fro_part, npanel, Z, L, R, blockIdx.x);
 }
 
 // batched forms: item = (problem, matrix, tile)
@@ -720,11 +771,22 @@ __global__ __launch_bounds__(64) void project_bf16_multi(const ApDesc *__restric
     project_bf16_body<NT, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Bb, D.ldv, D.C, it.y, it.z);
 }
 template <int KP>
-__global__ __launch_bounds__(256) void finish_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+__global__ __launch_bounds__(256) void factor_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
-    finish_body<KP>(D.B, D.ldv, D.n, D.C, D.m, D.k, D.r, D.fro, D.npanel, D.L, D.R, D.sigma, D.relerr, D.flags,
-                    it.y);
+    factor_body<KP>(D.B, D.ldv, D.n, D.C, D.m, D.k, D.HX, D.q, it.y);
+}
+template <int KP>
+__global__ __launch_bounds__(256) void eig_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const ApDesc &D = P[it.x];
+    eig_body<KP>(D.HX, D.q, D.k, D.r, D.fro, D.npanel, D.Z, D.sigma, D.relerr, D.flags, it.y);
+}
+template <int KP>
+__global__ __launch_bounds__(256) void outputs_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const ApDesc &D = P[it.x];
+    outputs_body<KP>(D.B, D.ldv, D.n, D.C, D.m, D.k, D.r, D.fro, D.npanel, D.Z, D.L, D.R, it.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -798,14 +860,27 @@ __global__ void error_final_kernel(const double *__restrict__ part, int nblk, in
         default: return tsk_fail(c, TSK_E_ARG, "k > 64"); \
     }
 
+// factor, eig and outputs launches of one problem (workspace grown here)
 static tsk_status finish_enqueue(tsk_ctx c, int kp, const float *B, int64_t ldv, int64_t n, const float *Cm,
                                  int64_t m, int k, int r, const double *fro, int npanel, int64_t count, float *L,
                                  float *R, float *sigma, double *relerr, int32_t *flags) {
+    TSK_TRY(tsk_grow(c, c->ap_HX, sizeof(double) * count * 2 * kp * kp));
+    TSK_TRY(tsk_grow(c, c->ap_Z, sizeof(float) * count * kp * kp + sizeof(int) * count));
+    double *HX = (double *)c->ap_HX.p;
+    float *Z = (float *)c->ap_Z.p;
+    int *q = (int *)(Z + count * kp * kp);
     const dim3 g((unsigned)count);
-#define TSK_FIN(KPV)                                                                                        \
-    TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                        \
-               hipLaunchKernelGGL(finish_kernel<KPV>, g, dim3(256), 0, c->stream, B, ldv, n, Cm, m, k, r, fro, \
-                                  npanel, L, R, sigma, relerr, flags))
+#define TSK_FIN(KPV)                                                                                              \
+    do {                                                                                                          \
+        TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(factor_kernel<KPV>, g, dim3(256), 0, c->stream, B, ldv, n, \
+                                                        Cm, m, k, HX, q));                                        \
+        TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                          \
+                   hipLaunchKernelGGL(eig_kernel<KPV>, g, dim3(256), 0, c->stream, (const double *)HX,            \
+                                      (const int *)q, k, r, fro, npanel, Z, sigma, relerr, flags));              \
+        TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                          \
+                   hipLaunchKernelGGL(outputs_kernel<KPV>, g, dim3(256), 0, c->stream, B, ldv, n, Cm, m, k, r,    \
+                                      fro, npanel, (const float *)Z, L, R));                                      \
+    } while (0)
     TSK_KP_SWITCH(kp / 16, TSK_FIN(16), TSK_FIN(32), TSK_FIN(48), TSK_FIN(64))
 #undef TSK_FIN
     return TSK_OK;
@@ -894,15 +969,17 @@ tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_st
 // lays out every problem's workspace in one buffer, writes the descriptors
 // and work-item lists into pinned memory, copies them in one transfer, then
 // launches: one sketch-preparation launch for all problems, and per
-// sketch-size class (kp / 16) one sketch, one project and one finish launch.
+// sketch-size class (kp / 16) one launch of each later phase (sketch,
+// project, factor, eig, outputs).
 // Items are ordered largest problem first, so the long items start early.
 tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute) {
     const bool lowp = compute != TSK_F32;
     const int panel = lowp ? SKB_PANEL : SK_PANEL;
     const int band = lowp ? PJB_ROWS : PJ_ROWS;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    constexpr int NREG = 8;  // workspace regions per problem
     std::vector<ApDesc> desc(np);
-    std::vector<size_t> off(np * 5);
+    std::vector<size_t> off(np * NREG);
     size_t ws = 0;
     for (int i = 0; i < np; ++i) {
         const tsk_stack &A = pr[i].A;
@@ -926,12 +1003,16 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
         D.sigma = pr[i].sigma;
         D.relerr = pr[i].relerr;
         D.flags = pr[i].flags;
-        const size_t sz[5] = {lowp ? sizeof(uint16_t) * 2 * D.kp * D.mp : sizeof(float) * D.m * D.kp,
-                              sizeof(float) * D.count * D.kp * D.ldv,
-                              lowp ? sizeof(uint16_t) * D.count * 2 * D.kp * D.ldv : 0,
-                              sizeof(float) * D.count * D.m * D.kp, sizeof(double) * D.count * D.npanel};
-        for (int j = 0; j < 5; ++j) {
-            off[i * 5 + j] = ws;
+        const size_t sz[NREG] = {lowp ? sizeof(uint16_t) * 2 * D.kp * D.mp : sizeof(float) * D.m * D.kp,
+                                 sizeof(float) * D.count * D.kp * D.ldv,
+                                 lowp ? sizeof(uint16_t) * D.count * 2 * D.kp * D.ldv : 0,
+                                 sizeof(float) * D.count * D.m * D.kp,
+                                 sizeof(double) * D.count * D.npanel,
+                                 sizeof(double) * D.count * 2 * D.kp * D.kp,
+                                 sizeof(float) * D.count * D.kp * D.kp,
+                                 sizeof(int) * D.count};
+        for (int j = 0; j < NREG; ++j) {
+            off[i * NREG + j] = ws;
             ws += al(sz[j]);
         }
     }
@@ -939,12 +1020,16 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
     char *base = (char *)c->mp_ws.p;
     for (int i = 0; i < np; ++i) {
         ApDesc &D = desc[i];
-        D.St = lowp ? nullptr : (float *)(base + off[i * 5]);
-        D.Sb = lowp ? (uint16_t *)(base + off[i * 5]) : nullptr;
-        D.B = (float *)(base + off[i * 5 + 1]);
-        D.Bb = lowp ? (uint16_t *)(base + off[i * 5 + 2]) : nullptr;
-        D.C = (float *)(base + off[i * 5 + 3]);
-        D.fro = (double *)(base + off[i * 5 + 4]);
+        const size_t *o = &off[i * NREG];
+        D.St = lowp ? nullptr : (float *)(base + o[0]);
+        D.Sb = lowp ? (uint16_t *)(base + o[0]) : nullptr;
+        D.B = (float *)(base + o[1]);
+        D.Bb = lowp ? (uint16_t *)(base + o[2]) : nullptr;
+        D.C = (float *)(base + o[3]);
+        D.fro = (double *)(base + o[4]);
+        D.HX = (double *)(base + o[5]);
+        D.Z = (float *)(base + o[6]);
+        D.q = (int *)(base + o[7]);
     }
     // work items: problems largest first within each list
     std::vector<int> order(np);
@@ -1030,16 +1115,28 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
             TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                      \
                        hipLaunchKernelGGL((project_bf16_multi<CL, uint16_t>), g, dim3(64), 0, c->stream, P, It));   \
     }
-#define TSK_MFN(CL)                                                                                           \
-    if (cnt[2][CL])                                                                                           \
-        TSK_LAUNCH(c, TSK_KERNEL_FINISH, hipLaunchKernelGGL(finish_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),    \
+#define TSK_MFA(CL)                                                                                          \
+    if (cnt[2][CL])                                                                                          \
+        TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(factor_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),       \
+                                                        dim3(256), 0, c->stream, P, I + start[2][CL]));
+#define TSK_MEG(CL)                                                                                          \
+    if (cnt[2][CL])                                                                                          \
+        TSK_LAUNCH(c, TSK_KERNEL_FINISH, hipLaunchKernelGGL(eig_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),      \
+                                                            dim3(256), 0, c->stream, P, I + start[2][CL]));
+#define TSK_MOU(CL)                                                                                          \
+    if (cnt[2][CL])                                                                                          \
+        TSK_LAUNCH(c, TSK_KERNEL_FINISH, hipLaunchKernelGGL(outputs_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),  \
                                                             dim3(256), 0, c->stream, P, I + start[2][CL]));
     TSK_MSK(1) TSK_MSK(2) TSK_MSK(3) TSK_MSK(4)
     TSK_MPJ(1) TSK_MPJ(2) TSK_MPJ(3) TSK_MPJ(4)
-    TSK_MFN(1) TSK_MFN(2) TSK_MFN(3) TSK_MFN(4)
+    TSK_MFA(1) TSK_MFA(2) TSK_MFA(3) TSK_MFA(4)
+    TSK_MEG(1) TSK_MEG(2) TSK_MEG(3) TSK_MEG(4)
+    TSK_MOU(1) TSK_MOU(2) TSK_MOU(3) TSK_MOU(4)
 #undef TSK_MSK
 #undef TSK_MPJ
-#undef TSK_MFN
+#undef TSK_MFA
+#undef TSK_MEG
+#undef TSK_MOU
     return TSK_OK;
 }
 

@@ -211,7 +211,7 @@ void tsk_destroy(tsk_ctx c) {
     TskBuf *bufs[] = {&c->gram_part, &c->gram_G,  &c->eig_Y0,   &c->eig_Y1, &c->eig_Rinv, &c->eig_part,
                       &c->eig_C,     &c->eig_X,   &c->eig_GX,   &c->eig_small, &c->eig_U, &c->counters,
                       &c->ap_St,     &c->ap_B,    &c->ap_C,     &c->ap_fro, &c->ap_Sb,    &c->ap_Bb,
-                      &c->er_part,   &c->st_part, &c->mp_ws,    &c->mp_tab};
+                      &c->ap_HX,     &c->ap_Z,    &c->er_part,  &c->st_part, &c->mp_ws,  &c->mp_tab};
     for (TskBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->mp_pin) (void)hipHostFree(c->mp_pin);

@@ -132,10 +132,13 @@ __device__ __forceinline__ void jacobi_rot(const double *H, int ld, int a, int b
     c = 1.0;
     s = 0.0;
     if (hab != 0.0 && fabs(hab) > 1e-18 * sqrt(fabs(haa * hbb))) {
-        const double tau = (hbb - haa) * rcp_nr(2.0 * hab);
+        // t from the hardware estimates (an angle that is slightly off still
+        // shrinks H[a][b] by the estimates' relative error, so the sweeps
+        // converge); c refined so that c^2 + s^2 = 1 to rounding
+        const double tau = (hbb - haa) * __builtin_amdgcn_rcp(2.0 * hab);
         const double q = 1.0 + tau * tau;
-        const double root = q * rsq_nr(q);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + root);
+        const double root = q * __builtin_amdgcn_rsq(q);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) * __builtin_amdgcn_rcp(fabs(tau) + root);
         c = rsq_nr(1.0 + t * t);
         s = t * c;
     }
@@ -169,8 +172,9 @@ __device__ __forceinline__ void rr_pair(int t, int rd, int p, int &a, int &b) {
 // 1..p-1, index 0 fixed) from round to round, so they are updated by an
 // increment instead of being recomputed, and every load of a round is issued
 // before its arithmetic.  Stops when the off-diagonal mass is below
-// 1e-20 ||H||_F^2 (quadratic convergence makes the eigenvalues exact to
-// rounding well before).  MAXB >= ceil(p(p+2)/8 / 256),
+// 1e-18 ||H||_F^2: eigenvalues are then exact to rounding (their error is
+// second order in the off-diagonal part) and eigenvectors to 1e-9 of the
+// relative gap.  MAXB >= ceil(p(p+2)/8 / 256),
 // MAXW >= ceil(p^2/2 / 256).  On exit H is diagonal to rounding and
 // H_in = W diag W^T.  p even <= 64; rot: p doubles.
 template <int MAXB, int MAXW>
@@ -236,7 +240,7 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
             if (i != j) off += h * h;
         }
         off = block_sum_f64(off, red4);
-        if (off <= 1e-20 * tot || tot == 0.0) break;
+        if (off <= 1e-18 * tot || tot == 0.0) break;
         // indices of every slot at round 0 (the cycle returns there after
         // p - 1 rounds)
         if (tid < half) slot0(tid, tA, tB);
@@ -492,6 +496,7 @@ struct tsk_ctx_s {
     TskBuf counters;
     TskBuf ap_St, ap_B, ap_C, ap_fro;
     TskBuf ap_Sb, ap_Bb;  // bf16 hi/lo pairs of S and B (bf16 path)
+    TskBuf ap_HX, ap_Z;   // per-matrix small factors
     TskBuf er_part, st_part;
     TskBuf mp_ws, mp_tab;            // batched apply: workspace, descriptors + items
     void *mp_pin = nullptr;          // pinned host copy of the batch tables

@@ -50,7 +50,27 @@ def golden_stream(spec, name, n_err=64, n_opt=16):
     print(name, "lambda_1..3", lam[:3], "e[:3]", e[:3], f"train {t_train:.1f}s")
 
 
+def golden_batch(name, n_train=100, n_err=4):
+    """The uneven-shape batch workload: per stream, the oracle's sketch from
+    its training slices and the errors of its first n_err test matrices."""
+    out = {"workload": name, "source": "oracle/tsko.c via tests/golden/make_golden.py", "streams": []}
+    t0 = time.time()
+    for s in range(len(synth.BATCH_SHAPES)):
+        spec = synth.spec_batch_stream(s, n_train=n_train)
+        st = synth.Stream(spec)
+        S, lam = oracle.train(st.train(), spec.k)
+        res = oracle.apply(st.test(n_err), S, spec.r)
+        out["streams"].append({"spec": {k: v for k, v in spec.__dict__.items()}, "lambda": lam.tolist(),
+                               "relerr": res["relerr"].tolist(), "flags": res["flags"].tolist()})
+        print(name, "stream", s, spec.m, spec.n, "e[:2]", res["relerr"][:2], flush=True)
+    out["oracle_seconds"] = time.time() - t0
+    out["threads"] = oracle.threads()
+    with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 WORKLOADS = {
+    "batch_8streams_k10-40": lambda: golden_batch("batch_8streams_k10-40"),
     "hsi_1024x768_k20_r10": lambda: golden_stream(synth.spec_hsi_fp32(), "hsi_1024x768_k20_r10"),
     # the precision form's stream: 1000 training slices of 1920 x 1080; the
     # oracle's reference is on the FP32 values (the reduced-precision paths

@@ -226,19 +226,71 @@ __device__ __forceinline__ v4u load8(const uint8_t *p, int64_t c, int64_t n, flo
     return e4m3x8_to_bf16(w, inv);
 }
 
+// The same 8 elements when all of them are in range, in two halves: raw8
+// issues the load (its result may stay in flight while earlier data is in
+// use) and widen8 turns the stored bytes into bf16.
+__device__ __forceinline__ v4u raw8(const uint16_t *p) { return *reinterpret_cast<const v4u *>(p); }
+__device__ __forceinline__ uint2 raw8(const uint8_t *p) { return *reinterpret_cast<const uint2 *>(p); }
+__device__ __forceinline__ v4u widen8(v4u w, float) { return w; }
+__device__ __forceinline__ v4u widen8(uint2 w, float inv) { return e4m3x8_to_bf16(w, inv); }
+template <typename ET>
+struct Raw8;
+template <>
+struct Raw8<uint16_t> {
+    using type = v4u;
+};
+template <>
+struct Raw8<uint8_t> {
+    using type = uint2;
+};
+template <typename ET>
+using raw8_t = typename Raw8<ET>::type;
+
+// One 32-row step of B_d = S A_d.  x[e] holds the lane's 8 columns of row
+// 8q + e of the step; sh / sl the S pair's 8 contraction indices for each
+// of the MT row tiles.  The 8 x 8 bf16 block is transposed in registers so
+// that MFMA u takes column u of the 8 rows; ||A_d||^2 is summed from the same
+// registers (FP32 per step, FP64 across steps).
+template <int MT>
+__device__ __forceinline__ void sketch_step(const v4u (&x)[8], const v4u (&sh)[MT], const v4u (&sl)[MT],
+                                            v4f (&acc)[MT][8], double &fro) {
+    float f = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f += sumsq_bf16x8(x[e]);
+    fro += (double)f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int j = u >> 1;
+        v4u bt;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const unsigned lo = x[2 * t][j], hi = x[2 * t + 1][j];
+            bt[t] = (u & 1) ? ((lo >> 16) | (hi & 0xffff0000u)) : ((lo & 0xffffu) | (hi << 16));
+        }
+#pragma unroll
+        for (int a = 0; a < MT; ++a) {
+            acc[a][u] = mfma16x16x32_bf16(sh[a], bt, acc[a][u]);
+            acc[a][u] = mfma16x16x32_bf16(sl[a], bt, acc[a][u]);
+        }
+    }
+}
+
 // B_d = S A_d.  The contraction runs over the rows of A_d, but an MFMA lane
 // needs 8 consecutive contraction indices: lane (q, i) loads 16 bytes (8
-// columns) from each of the 8 rows r0 + 8q + e and transposes the 8 x 8
-// block in registers, so that MFMA u (u = 0..7) takes column c0 + 8i + u
-// of those 8 rows.  One wave covers 128 columns, 32 rows per step; the next
-// step's rows are in flight during the MFMAs.  ||A_d||^2 is accumulated from
-// the same registers (FP32 per step, FP64 across steps).
+// columns) from each of the 8 rows r0 + 8q + e and transposes the block in
+// registers (sketch_step).  One wave covers 128 columns, 32 rows per step.
+// Whole steps of a panel whose lanes each hold 8 columns wholly inside or
+// wholly outside [0, n) use unconditional loads, with the next step's rows
+// and S pair in flight during this step's MFMAs; the last partial step, and
+// every step of a panel that splits a lane's 8 columns at n, load element by
+// element.
 template <int MT, typename ET>
 __device__ __forceinline__ void sketch_bf16_body(const ET *__restrict__ A, const float *__restrict__ scale,
-                                                          int64_t m, int64_t n, int64_t ld, int64_t stride,
-                                                          const uint16_t *__restrict__ Sb, int64_t mp,
-                                                          float *__restrict__ B, uint16_t *__restrict__ Bb,
-                                                          int64_t ldb, double *__restrict__ fro_part, int npanel, int64_t d, int panel) {
+                                                 int64_t m, int64_t n, int64_t ld, int64_t stride,
+                                                 const uint16_t *__restrict__ Sb, int64_t mp,
+                                                 float *__restrict__ B, uint16_t *__restrict__ Bb,
+                                                 int64_t ldb, double *__restrict__ fro_part, int npanel, int64_t d,
+                                                 int panel) {
     constexpr int kp = MT * 16;
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, ii = lane & 15;
@@ -254,47 +306,61 @@ __device__ __forceinline__ void sketch_bf16_body(const ET *__restrict__ A, const
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc[a][u] = v4f{0.f, 0.f, 0.f, 0.f};
     double fro = 0.0;
-    v4u x[8];
+    int64_t r0 = 0;
+    const int64_t mfull = m & ~(int64_t)31;
+    if (__all(!any || c8 + 8 <= n) && mfull > 0) {
+        raw8_t<ET> x[8];
+        v4u sh[MT], sl[MT];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int64_t row = 8 * q + e;
-        x[e] = (any && row < m) ? load8(Ad + row * ld, c8, n, inv) : v4u{0u, 0u, 0u, 0u};
+        for (int e = 0; e < 8; ++e) x[e] = raw8(Ad + (int64_t)(8 * q + e) * ld);
+#pragma unroll
+        for (int a = 0; a < MT; ++a) {
+            sh[a] = *reinterpret_cast<const v4u *>(Sh + (int64_t)a * 16 * mp);
+            sl[a] = *reinterpret_cast<const v4u *>(Sl + (int64_t)a * 16 * mp);
+        }
+        for (; r0 < mfull; r0 += 32) {
+            // the last whole step loads its own rows again (in range, unused)
+            const int64_t rn = r0 + 32 < mfull ? r0 + 32 : r0;
+            raw8_t<ET> nx[8];
+            v4u nsh[MT], nsl[MT];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) nx[e] = raw8(Ad + (rn + 8 * q + e) * ld);
+#pragma unroll
+            for (int a = 0; a < MT; ++a) {
+                nsh[a] = *reinterpret_cast<const v4u *>(Sh + (int64_t)a * 16 * mp + rn);
+                nsl[a] = *reinterpret_cast<const v4u *>(Sl + (int64_t)a * 16 * mp + rn);
+            }
+            // the loads above are issued here, before this step's MFMAs (the
+            // compiler would otherwise move them after the MFMAs or re-issue
+            // them next to their use)
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+            v4u xb[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) xb[e] = any ? widen8(x[e], inv) : v4u{0u, 0u, 0u, 0u};
+            sketch_step<MT>(xb, sh, sl, acc, fro);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = nx[e];
+#pragma unroll
+            for (int a = 0; a < MT; ++a) {
+                sh[a] = nsh[a];
+                sl[a] = nsl[a];
+            }
+        }
     }
-    for (int64_t r0 = 0; r0 < m; r0 += 32) {
-        const bool more = r0 + 32 < m;
-        v4u nx[8];
+    for (; r0 < m; r0 += 32) {
+        v4u x[8], sh[MT], sl[MT];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const int64_t row = r0 + 32 + 8 * q + e;
-            nx[e] = (more && any && row < m) ? load8(Ad + row * ld, c8, n, inv) : v4u{0u, 0u, 0u, 0u};
+            const int64_t row = r0 + 8 * q + e;
+            x[e] = (any && row < m) ? load8(Ad + row * ld, c8, n, inv) : v4u{0u, 0u, 0u, 0u};
         }
-        v4u sh[MT], sl[MT];
 #pragma unroll
         for (int a = 0; a < MT; ++a) {
             sh[a] = *reinterpret_cast<const v4u *>(Sh + (int64_t)a * 16 * mp + r0);
             sl[a] = *reinterpret_cast<const v4u *>(Sl + (int64_t)a * 16 * mp + r0);
         }
-        float f = 0.f;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) f += sumsq_bf16x8(x[e]);
-        fro += (double)f;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = u >> 1;
-            v4u bt;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const unsigned lo = x[2 * t][j], hi = x[2 * t + 1][j];
-                bt[t] = (u & 1) ? ((lo >> 16) | (hi & 0xffff0000u)) : ((lo & 0xffffu) | (hi << 16));
-            }
-#pragma unroll
-            for (int a = 0; a < MT; ++a) {
-                acc[a][u] = mfma16x16x32_bf16(sh[a], bt, acc[a][u]);
-                acc[a][u] = mfma16x16x32_bf16(sl[a], bt, acc[a][u]);
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = nx[e];
+        sketch_step<MT>(x, sh, sl, acc, fro);
     }
     // lane holds B[a*16 + 4q + r][c8 + u] in acc[a][u][r].  Each value is
     // split into hi = RNE(b), lo = RNE(b - hi); B' = hi + lo (exact in FP32)
@@ -330,15 +396,32 @@ __device__ __forceinline__ void sketch_bf16_body(const ET *__restrict__ A, const
     if (threadIdx.x == 0) fro_part[d * npanel + panel] = tot;
 }
 
+// One 32-column step of C_d = A_d B_d^T: xa[a] holds 8 columns of row a*16 + i
+// of the band, vh / vl the same 8 columns of row b*16 + i of the B pair.
+template <int NT>
+__device__ __forceinline__ void project_step(const v4u (&xa)[8], const v4u (&vh)[NT], const v4u (&vl)[NT],
+                                             v4f (&acc)[8][NT]) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) acc[a][b] = mfma16x16x32_bf16(xa[a], vh[b], acc[a][b]);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) acc[a][b] = mfma16x16x32_bf16(xa[a], vl[b], acc[a][b]);
+}
+
 // C_d = A_d B_d^T: contraction over the columns of A_d (contiguous), so lane
 // (q, i) reads 8 consecutive columns of row i of each of 8 row tiles; the rows
 // of the bf16 pair of B_d give the other operand directly.  One wave covers
-// 128 rows.
+// 128 rows (rows past m read row m - 1 and are not stored).  Whole 32-column
+// steps keep the next step's A and B in flight during this step's MFMAs; the
+// last partial step loads element by element.
 template <int NT, typename ET>
 __device__ __forceinline__ void project_bf16_body(const ET *__restrict__ A, const float *__restrict__ scale,
-                                                           int64_t m, int64_t n, int64_t ld, int64_t stride,
-                                                           const uint16_t *__restrict__ Bb, int64_t ldv,
-                                                           float *__restrict__ C, int64_t d, int band) {
+                                                  int64_t m, int64_t n, int64_t ld, int64_t stride,
+                                                  const uint16_t *__restrict__ Bb, int64_t ldv,
+                                                  float *__restrict__ C, int64_t d, int band) {
     constexpr int kp = NT * 16;
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, ii = lane & 15;
@@ -346,12 +429,10 @@ __device__ __forceinline__ void project_bf16_body(const ET *__restrict__ A, cons
     const float inv = scale ? 1.0f / scale[d] : 1.0f;
     const ET *Ad = A + d * stride;
     const ET *arow[8];
-    bool av[8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
         const int64_t row = r0 + a * 16 + ii;
-        av[a] = row < m;
-        arow[a] = Ad + (av[a] ? row : 0) * ld + 8 * q;
+        arow[a] = Ad + (row < m ? row : m - 1) * ld + 8 * q;
     }
     const uint16_t *Bh = Bb + d * 2 * kp * ldv + (int64_t)ii * ldv + 8 * q;
     const uint16_t *Bl = Bh + (int64_t)kp * ldv;
@@ -360,30 +441,58 @@ __device__ __forceinline__ void project_bf16_body(const ET *__restrict__ A, cons
     for (int a = 0; a < 8; ++a)
 #pragma unroll
         for (int b = 0; b < NT; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-    v4u xa[8];
+    // whole 32-column steps in two register sets: the loads of one step are
+    // issued before the MFMAs of the other
+    const int64_t nst = n / 32;
+    auto fetch = [&](int64_t c, raw8_t<ET>(&xa)[8], v4u(&vh)[NT], v4u(&vl)[NT]) {
 #pragma unroll
-    for (int a = 0; a < 8; ++a) xa[a] = (av[a] && 8 * q < n) ? load8(arow[a], 8 * q, n, inv) : v4u{0u, 0u, 0u, 0u};
-    for (int64_t c0 = 0; c0 < n; c0 += 32) {
-        const int64_t cn = c0 + 32 + 8 * q;  // this lane's columns in the next step
-        v4u nxa[8];
+        for (int a = 0; a < 8; ++a) xa[a] = raw8(arow[a] + c);
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
-            nxa[a] = (av[a] && cn < n) ? load8(arow[a] + c0 + 32, cn, n, inv) : v4u{0u, 0u, 0u, 0u};
-        v4u vh[NT], vl[NT];
+        for (int b = 0; b < NT; ++b) {
+            vh[b] = *reinterpret_cast<const v4u *>(Bh + (int64_t)b * 16 * ldv + c);
+            vl[b] = *reinterpret_cast<const v4u *>(Bl + (int64_t)b * 16 * ldv + c);
+        }
+        // the loads are issued here, ahead of the MFMAs that follow (the
+        // compiler would otherwise move them after those MFMAs or re-issue
+        // them next to their use)
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto step = [&](const raw8_t<ET>(&xa)[8], const v4u(&vh)[NT], const v4u(&vl)[NT]) {
+        v4u xb[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) xb[a] = widen8(xa[a], inv);
+        project_step<NT>(xb, vh, vl, acc);
+    };
+    int64_t s = 0;
+    if (nst > 0) {
+        raw8_t<ET> x0[8], x1[8];
+        v4u h0[NT], l0[NT], h1[NT], l1[NT];
+        fetch(0, x0, h0, l0);
+        for (; s + 2 <= nst; s += 2) {
+            fetch((s + 1) * 32, x1, h1, l1);
+            step(x0, h0, l0);
+            // the step after the pair (the last step again when there is none)
+            fetch((s + 2 < nst ? s + 2 : nst - 1) * 32, x0, h0, l0);
+            step(x1, h1, l1);
+        }
+        if (s < nst) {  // odd count: set 0 holds the last whole step
+            step(x0, h0, l0);
+            ++s;
+        }
+    }
+    const int64_t c0 = s * 32;
+    if (c0 < n) {
+        const int64_t cl = c0 + 8 * q;  // this lane's columns of the last step
+        v4u xa[8], vh[NT], vl[NT];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) xa[a] = cl < n ? load8(arow[a] + c0, cl, n, inv) : v4u{0u, 0u, 0u, 0u};
 #pragma unroll
         for (int b = 0; b < NT; ++b) {
             vh[b] = *reinterpret_cast<const v4u *>(Bh + (int64_t)b * 16 * ldv + c0);
             vl[b] = *reinterpret_cast<const v4u *>(Bl + (int64_t)b * 16 * ldv + c0);
         }
-#pragma unroll
-        for (int a = 0; a < 8; ++a)
-#pragma unroll
-            for (int b = 0; b < NT; ++b) {
-                acc[a][b] = mfma16x16x32_bf16(xa[a], vh[b], acc[a][b]);
-                acc[a][b] = mfma16x16x32_bf16(xa[a], vl[b], acc[a][b]);
-            }
-#pragma unroll
-        for (int a = 0; a < 8; ++a) xa[a] = nxa[a];
+        project_step<NT>(xa, vh, vl, acc);
     }
     float *Cd = C + d * m * kp;
 #pragma unroll

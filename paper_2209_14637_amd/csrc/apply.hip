@@ -800,11 +800,35 @@ __global__ __launch_bounds__(64) void sketch_f32_kernel(const float *__restrict_
                                                          double *__restrict__ fro_part, int npanel) {
     sketch_f32_body<MT>(A, m, n, ld, stride, St, B, ldb, fro_part, npanel, blockIdx.y, blockIdx.x);
 }
+// Matrix and band of workgroup p of a projection launch (count matrices of
+// nb bands each, one-dimensional grid) such that all bands of a matrix run on
+// one XCD at about the same time and share that XCD's L2 copy of B_d (read by
+// every band).  Workgroups go to the 8 XCDs in turn (workgroup p to XCD
+// p mod 8), so slot j of XCD x takes band j mod nb of matrix x + 8 (j / nb);
+// the matrices after the last whole group of 8 are taken in plain order.
+__device__ __forceinline__ void xcd_band(int64_t p, int64_t count, int nb, int64_t &d, int &band) {
+    const int64_t g8 = count / 8 * 8;
+    const int64_t whole = g8 * nb;
+    if (p < whole) {
+        const int64_t j = p / 8;
+        d = p % 8 + 8 * (j / nb);
+        band = (int)(j % nb);
+    } else {
+        const int64_t t = p - whole;
+        d = g8 + t / nb;
+        band = (int)(t % nb);
+    }
+}
+
 template <int NT>
 __global__ __launch_bounds__(64) void project_f32_kernel(const float *__restrict__ A, int64_t m, int64_t n,
                                                           int64_t ld, int64_t stride, const float *__restrict__ Bm,
-                                                          int64_t ldv, float *__restrict__ C) {
-    project_f32_body<NT>(A, m, n, ld, stride, Bm, ldv, C, blockIdx.y, blockIdx.x);
+                                                          int64_t ldv, float *__restrict__ C, int64_t count,
+                                                          int nb) {
+    int64_t d;
+    int band;
+    xcd_band(blockIdx.x, count, nb, d, band);
+    project_f32_body<NT>(A, m, n, ld, stride, Bm, ldv, C, d, band);
 }
 template <int MT, typename ET>
 __global__ __launch_bounds__(64) void sketch_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
@@ -819,8 +843,11 @@ template <int NT, typename ET>
 __global__ __launch_bounds__(64) void project_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
                                                            int64_t m, int64_t n, int64_t ld, int64_t stride,
                                                            const uint16_t *__restrict__ Bb, int64_t ldv,
-                                                           float *__restrict__ C) {
-    project_bf16_body<NT, ET>(A, scale, m, n, ld, stride, Bb, ldv, C, blockIdx.y, blockIdx.x);
+                                                           float *__restrict__ C, int64_t count, int nb) {
+    int64_t d;
+    int band;
+    xcd_band(blockIdx.x, count, nb, d, band);
+    project_bf16_body<NT, ET>(A, scale, m, n, ld, stride, Bb, ldv, C, d, band);
 }
 template <int KP>
 __global__ __launch_bounds__(256) void factor_kernel(const float *__restrict__ B, int64_t ldb, int64_t n,
@@ -863,6 +890,7 @@ __global__ __launch_bounds__(64) void sketch_f32_multi(const ApDesc *__restrict_
 template <int NT>
 __global__ __launch_bounds__(64) void project_f32_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
+    if (it.x < 0) return;  // padding of the XCD-interleaved item list
     const ApDesc &D = P[it.x];
     project_f32_body<NT>((const float *)D.A, D.m, D.n, D.ld, D.stride, D.B, D.ldv, D.C, it.y, it.z);
 }
@@ -876,6 +904,7 @@ __global__ __launch_bounds__(64) void sketch_bf16_multi(const ApDesc *__restrict
 template <int NT, typename ET>
 __global__ __launch_bounds__(64) void project_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
+    if (it.x < 0) return;  // padding of the XCD-interleaved item list
     const ApDesc &D = P[it.x];
     project_bf16_body<NT, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Bb, D.ldv, D.C, it.y, it.z);
 }
@@ -1018,11 +1047,12 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
                                   (const float *)St, B, ldv, fro, npanel))
     TSK_KP_SWITCH(kp / 16, TSK_SK(1), TSK_SK(2), TSK_SK(3), TSK_SK(4))
 #undef TSK_SK
-    const dim3 gp((unsigned)((m + PJ_ROWS - 1) / PJ_ROWS), (unsigned)count);
+    const int nb = (int)((m + PJ_ROWS - 1) / PJ_ROWS);
+    const dim3 gp((unsigned)(nb * count));
 #define TSK_PJ(NTV)                                                                                           \
     TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                         \
                hipLaunchKernelGGL(project_f32_kernel<NTV>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, \
-                                  (const float *)B, ldv, Cm))
+                                  (const float *)B, ldv, Cm, count, nb))
     TSK_KP_SWITCH(kp / 16, TSK_PJ(1), TSK_PJ(2), TSK_PJ(3), TSK_PJ(4))
 #undef TSK_PJ
     return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags);
@@ -1058,11 +1088,12 @@ static tsk_status apply_lowp_enqueue(tsk_ctx c, const float *S, int k, const tsk
                                   s->ld, s->stride, (const uint16_t *)Sb, mp, B, Bb, ldv, fro, npanel))
     TSK_KP_SWITCH(kp / 16, TSK_SKB(1), TSK_SKB(2), TSK_SKB(3), TSK_SKB(4))
 #undef TSK_SKB
-    const dim3 gp((unsigned)((m + PJB_ROWS - 1) / PJB_ROWS), (unsigned)count);
+    const int nb = (int)((m + PJB_ROWS - 1) / PJB_ROWS);
+    const dim3 gp((unsigned)(nb * count));
 #define TSK_PJB(NTV)                                                                                      \
     TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                     \
                hipLaunchKernelGGL((project_bf16_kernel<NTV, ET>), gp, dim3(64), 0, c->stream, A, sc, m, n, \
-                                  s->ld, s->stride, (const uint16_t *)Bb, ldv, Cm))
+                                  s->ld, s->stride, (const uint16_t *)Bb, ldv, Cm, count, nb))
     TSK_KP_SWITCH(kp / 16, TSK_PJB(1), TSK_PJB(2), TSK_PJB(3), TSK_PJB(4))
 #undef TSK_PJB
     return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags);
@@ -1162,6 +1193,25 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
                 const int nt = ph == 0 ? D.npanel : ph == 1 ? (int)((D.m + band - 1) / band) : 1;
                 for (int64_t d = 0; d < D.count; ++d)
                     for (int t = 0; t < nt; ++t) items.push_back(int4{i, (int)d, t, 0});
+            }
+            if (ph == 1) {
+                // projection: all bands of a matrix on one XCD (items go to
+                // the 8 XCDs in turn), so they share its L2 copy of B_d;
+                // matrices are dealt to the XCDs in turn, the lists
+                // interleaved and padded with items that do nothing
+                std::vector<int4> xl[8];
+                int64_t mi = 0;
+                for (size_t a = start[ph][cl]; a < items.size(); ++mi) {
+                    size_t b = a;
+                    while (b < items.size() && items[b].x == items[a].x && items[b].y == items[a].y) ++b;
+                    xl[mi % 8].insert(xl[mi % 8].end(), items.begin() + a, items.begin() + b);
+                    a = b;
+                }
+                size_t len = 0;
+                for (auto &v : xl) len = std::max(len, v.size());
+                items.resize(start[ph][cl]);
+                for (size_t j = 0; j < len; ++j)
+                    for (auto &v : xl) items.push_back(j < v.size() ? v[j] : int4{-1, 0, 0, 0});
             }
             cnt[ph][cl] = items.size() - start[ph][cl];
         }

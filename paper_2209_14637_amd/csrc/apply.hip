@@ -21,6 +21,8 @@
 // up to 16; rows k..kp-1 of S, B are zero, so no masking is needed on them.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "tsk_common.hpp"
@@ -187,7 +189,6 @@ __device__ __forceinline__ void project_f32_body(const float *__restrict__ A, in
 // significant bits of S and B and the only extra rounding is that of A_d.
 // ---------------------------------------------------------------------------
 constexpr int SKB_PANEL = 128;  // columns per sketch wave (16 lanes x 8)
-constexpr int PJB_ROWS = 128;   // rows per project wave (8 row tiles)
 
 // Sb = [S_hi; S_lo], each kp x mp bf16 with zero padding (rows >= k,
 // columns >= m).
@@ -396,113 +397,168 @@ __device__ __forceinline__ void sketch_bf16_body(const ET *__restrict__ A, const
     if (threadIdx.x == 0) fro_part[d * npanel + panel] = tot;
 }
 
-// One 32-column step of C_d = A_d B_d^T: xa[a] holds 8 columns of row a*16 + i
-// of the band, vh / vl the same 8 columns of row b*16 + i of the B pair.
-template <int NT>
-__device__ __forceinline__ void project_step(const v4u (&xa)[8], const v4u (&vh)[NT], const v4u (&vl)[NT],
-                                             v4f (&acc)[8][NT]) {
+// 16 bytes of a row starting at element c, zero from element n on (the
+// storage bytes as they are, no widening).
+template <typename ET>
+__device__ __forceinline__ v4u load16_tail(const ET *p, int64_t c, int64_t n) {
+    constexpr int NE = 16 / (int)sizeof(ET);
+    unsigned w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int b = 0; b < NT; ++b) acc[a][b] = mfma16x16x32_bf16(xa[a], vh[b], acc[a][b]);
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int b = 0; b < NT; ++b) acc[a][b] = mfma16x16x32_bf16(xa[a], vl[b], acc[a][b]);
+    for (int e = 0; e < NE; ++e)
+        if (c + e < n) {
+            const int byte = e * (int)sizeof(ET);
+            w[byte >> 2] |= (unsigned)p[e] << (8 * (byte & 3));
+        }
+    return v4u{w[0], w[1], w[2], w[3]};
 }
 
-// C_d = A_d B_d^T: contraction over the columns of A_d (contiguous), so lane
-// (q, i) reads 8 consecutive columns of row i of each of 8 row tiles; the rows
-// of the bf16 pair of B_d give the other operand directly.  One wave covers
-// 128 rows (rows past m read row m - 1 and are not stored).  Whole 32-column
-// steps keep the next step's A and B in flight during this step's MFMAs; the
-// last partial step loads element by element.
-template <int NT, typename ET>
-__device__ __forceinline__ void project_bf16_body(const ET *__restrict__ A, const float *__restrict__ scale,
-                                                  int64_t m, int64_t n, int64_t ld, int64_t stride,
-                                                  const uint16_t *__restrict__ Bb, int64_t ldv,
-                                                  float *__restrict__ C, int64_t d, int band) {
+// C_d = A_d B_d^T through LDS.  A workgroup (4 waves) takes 128 rows of one
+// matrix; wave w computes rows 32w .. 32w+31 (two row tiles) against all kp
+// columns.  Each step covers K columns: the workgroup reads the 128 row
+// segments of A and the 2kp row segments of the B pair with coalesced
+// 16-byte loads, keeps them in registers while the previous step's MFMAs
+// run, and stores them into LDS; the waves read their MFMA operands from
+// there (lane (q, i): 8 consecutive columns of row i of a tile).  Rows past
+// m and columns past n enter as zeros; B is read only up to its padded
+// width ldv (its columns n .. ldv-1 are zero).
+constexpr int PJL_ROWS = 128;
+constexpr int PJL_THREADS = 256;
+__host__ __device__ constexpr int pjl_lds_bytes(int K, int eb, int kp) {
+    return PJL_ROWS * (K * eb + 16) + 2 * kp * (2 * K + 16);
+}
+
+template <int NT, int K, typename ET>
+__device__ __forceinline__ void project_lds_body(const ET *A, const float *__restrict__ scale, int64_t m,
+                                                 int64_t n, int64_t ld, int64_t stride,
+                                                 const uint16_t *Bb, int64_t ldv, float *__restrict__ C,
+                                                 int64_t d, int band, unsigned char *lds) {
     constexpr int kp = NT * 16;
-    const int lane = threadIdx.x & 63;
+    constexpr int EB = (int)sizeof(ET);
+    constexpr int CE = 16 / EB;
+    constexpr int RA = K * EB + 16;        // LDS row stride of A
+    constexpr int RB = 2 * K + 16;         // LDS row stride of the B pair
+    constexpr int CPA = K * EB / 16;       // chunks per A row segment
+    constexpr int CPB = K / 8;             // chunks per B row segment
+    constexpr int AJ = PJL_ROWS * CPA / PJL_THREADS;
+    constexpr int BJ = 2 * kp * CPB / PJL_THREADS;
+    static_assert(PJL_THREADS % CPA == 0 && PJL_THREADS % CPB == 0, "chunk mapping");
+    static_assert(PJL_ROWS * CPA % PJL_THREADS == 0 && 2 * kp * CPB % PJL_THREADS == 0, "chunk count");
+    const int tid = (int)threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int q = lane >> 4, ii = lane & 15;
-    const int64_t r0 = (int64_t)band * PJB_ROWS;
+    const int64_t r0 = (int64_t)band * PJL_ROWS;
     const float inv = scale ? 1.0f / scale[d] : 1.0f;
     const ET *Ad = A + d * stride;
-    const ET *arow[8];
+    const uint16_t *Bd = Bb + d * 2 * kp * ldv;
+    unsigned char *la = lds, *lb = lds + PJL_ROWS * RA;
+    // this thread's chunks: A column chunk ca of rows ra0 + j * (256 / CPA),
+    // B column chunk cb of pair rows rb0 + j * (256 / CPB)
+    const int ca = tid % CPA, ra0 = tid / CPA;
+    const int cb = tid % CPB, rb0 = tid / CPB;
+    const int64_t nst = (n + K - 1) / K;
+    v4f acc[2][NT];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        const int64_t row = r0 + a * 16 + ii;
-        arow[a] = Ad + (row < m ? row : m - 1) * ld + 8 * q;
-    }
-    const uint16_t *Bh = Bb + d * 2 * kp * ldv + (int64_t)ii * ldv + 8 * q;
-    const uint16_t *Bl = Bh + (int64_t)kp * ldv;
-    v4f acc[8][NT];
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < NT; ++b) acc[t][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    // WHOLE: every chunk lies wholly inside or wholly past column n
+    auto run = [&](auto whole_tag) {
+        constexpr bool WHOLE = decltype(whole_tag)::value;
+        // fetch issues the loads of a step; stash zeroes what lies past m, n or
+        // ldv (only once the data is needed, so the loads stay in flight) and
+        // stores the step into LDS.  Rows past m read row 0, chunks past n or ldv
+        // read column 0 (in range).
+        auto fetch = [&](int64_t c0, v4u(&sa)[AJ], v4u(&sb)[BJ]) {
+            const int64_t gc = c0 + (int64_t)ca * CE;
+            const bool full = gc + CE <= n, none = gc >= n;
 #pragma unroll
-        for (int b = 0; b < NT; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-    // whole 32-column steps in two register sets: the loads of one step are
-    // issued before the MFMAs of the other
-    const int64_t nst = n / 32;
-    auto fetch = [&](int64_t c, raw8_t<ET>(&xa)[8], v4u(&vh)[NT], v4u(&vl)[NT]) {
+            for (int j = 0; j < AJ; ++j) {
+                const int64_t row = r0 + ra0 + j * (PJL_THREADS / CPA);
+                const bool rok = row < m;
+                if constexpr (WHOLE)
+                    sa[j] = *reinterpret_cast<const v4u *>(Ad + (rok ? row : 0) * ld + (full ? gc : 0));
+                else
+                    sa[j] = (rok && !none) ? load16_tail(Ad + row * ld + gc, gc, n) : v4u{0u, 0u, 0u, 0u};
+            }
+            const int64_t bc = c0 + (int64_t)cb * 8;
+            const bool bok = bc < ldv;  // ldv is a multiple of 128 >= n, so a chunk is in or out whole
 #pragma unroll
-        for (int a = 0; a < 8; ++a) xa[a] = raw8(arow[a] + c);
+            for (int j = 0; j < BJ; ++j) {
+                const int brow = rb0 + j * (PJL_THREADS / CPB);
+                sb[j] = *reinterpret_cast<const v4u *>(Bd + (int64_t)brow * ldv + (bok ? bc : 0));
+            }
+            // the loads above are issued here, ahead of the MFMAs that follow
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        auto stash = [&](int64_t c0, const v4u(&sa)[AJ], const v4u(&sb)[BJ]) {
+            const bool full = c0 + (int64_t)ca * CE + CE <= n;
 #pragma unroll
-        for (int b = 0; b < NT; ++b) {
-            vh[b] = *reinterpret_cast<const v4u *>(Bh + (int64_t)b * 16 * ldv + c);
-            vl[b] = *reinterpret_cast<const v4u *>(Bl + (int64_t)b * 16 * ldv + c);
+            for (int j = 0; j < AJ; ++j) {
+                const bool keep = !WHOLE || (full && r0 + ra0 + j * (PJL_THREADS / CPA) < m);
+                *reinterpret_cast<v4u *>(la + (ra0 + j * (PJL_THREADS / CPA)) * RA + ca * 16) =
+                    keep ? sa[j] : v4u{0u, 0u, 0u, 0u};
+            }
+            const bool bok = c0 + (int64_t)cb * 8 < ldv;
+#pragma unroll
+            for (int j = 0; j < BJ; ++j)
+                *reinterpret_cast<v4u *>(lb + (rb0 + j * (PJL_THREADS / CPB)) * RB + cb * 16) =
+                    bok ? sb[j] : v4u{0u, 0u, 0u, 0u};
+        };
+        v4u sa[AJ], sb[BJ];
+        fetch(0, sa, sb);
+        stash(0, sa, sb);
+        __syncthreads();
+        for (int64_t s = 0; s < nst; ++s) {
+            const int64_t c0 = s * K;
+            const bool more = s + 1 < nst;
+            // the next step (the last step loads its own again: in range, unused;
+            // no branch around the loads, so the compiler's wait counts stay exact)
+            fetch(more ? c0 + K : c0, sa, sb);
+#pragma unroll
+            for (int kb = 0; kb < K / 32; ++kb) {  // (columns past n are zeros)
+                v4u xa[2], vh[NT], vl[NT];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const unsigned char *p = la + (32 * w + 16 * t + ii) * RA + (kb * 32 + 8 * q) * EB;
+                    if constexpr (EB == 2)
+                        xa[t] = *reinterpret_cast<const v4u *>(p);
+                    else
+                        xa[t] = widen8(*reinterpret_cast<const uint2 *>(p), inv);
+                }
+#pragma unroll
+                for (int b = 0; b < NT; ++b) {
+                    vh[b] = *reinterpret_cast<const v4u *>(lb + (16 * b + ii) * RB + (kb * 32 + 8 * q) * 2);
+                    vl[b] = *reinterpret_cast<const v4u *>(lb + (kp + 16 * b + ii) * RB + (kb * 32 + 8 * q) * 2);
+                }
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int b = 0; b < NT; ++b) acc[t][b] = mfma16x16x32_bf16(xa[t], vh[b], acc[t][b]);
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int b = 0; b < NT; ++b) acc[t][b] = mfma16x16x32_bf16(xa[t], vl[b], acc[t][b]);
+            }
+            __syncthreads();
+            if (more) {
+                stash(c0 + K, sa, sb);
+                __syncthreads();
+            }
         }
-        // the loads are issued here, ahead of the MFMAs that follow (the
-        // compiler would otherwise move them after those MFMAs or re-issue
-        // them next to their use)
-        asm volatile("" ::: "memory");
-        __builtin_amdgcn_sched_barrier(0);
     };
-    auto step = [&](const raw8_t<ET>(&xa)[8], const v4u(&vh)[NT], const v4u(&vl)[NT]) {
-        v4u xb[8];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) xb[a] = widen8(xa[a], inv);
-        project_step<NT>(xb, vh, vl, acc);
-    };
-    int64_t s = 0;
-    if (nst > 0) {
-        raw8_t<ET> x0[8], x1[8];
-        v4u h0[NT], l0[NT], h1[NT], l1[NT];
-        fetch(0, x0, h0, l0);
-        for (; s + 2 <= nst; s += 2) {
-            fetch((s + 1) * 32, x1, h1, l1);
-            step(x0, h0, l0);
-            // the step after the pair (the last step again when there is none)
-            fetch((s + 2 < nst ? s + 2 : nst - 1) * 32, x0, h0, l0);
-            step(x1, h1, l1);
-        }
-        if (s < nst) {  // odd count: set 0 holds the last whole step
-            step(x0, h0, l0);
-            ++s;
-        }
-    }
-    const int64_t c0 = s * 32;
-    if (c0 < n) {
-        const int64_t cl = c0 + 8 * q;  // this lane's columns of the last step
-        v4u xa[8], vh[NT], vl[NT];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) xa[a] = cl < n ? load8(arow[a] + c0, cl, n, inv) : v4u{0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int b = 0; b < NT; ++b) {
-            vh[b] = *reinterpret_cast<const v4u *>(Bh + (int64_t)b * 16 * ldv + c0);
-            vl[b] = *reinterpret_cast<const v4u *>(Bl + (int64_t)b * 16 * ldv + c0);
-        }
-        project_step<NT>(xa, vh, vl, acc);
-    }
+    if (n % CE == 0)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
     float *Cd = C + d * m * kp;
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int64_t row = r0 + a * 16 + 4 * q + r;
+            const int64_t row = r0 + 32 * w + 16 * t + 4 * q + r;
             if (row < m) {
 #pragma unroll
-                for (int b = 0; b < NT; ++b) Cd[row * kp + b * 16 + ii] = acc[a][b][r];
+                for (int b = 0; b < NT; ++b) Cd[row * kp + b * 16 + ii] = acc[t][b][r];
             }
         }
 }
@@ -839,15 +895,21 @@ __global__ __launch_bounds__(64) void sketch_bf16_kernel(const ET *__restrict__ 
     sketch_bf16_body<MT, ET>(A, scale, m, n, ld, stride, Sb, mp, B, Bb, ldb, fro_part, npanel, blockIdx.y,
                              blockIdx.x);
 }
+// Columns per projection step: 128 (256-byte bf16 rows; LDS 60 KB at kp = 48,
+// two workgroups per CU, which measured faster than 256 columns at one).
+template <typename ET>
+constexpr int pjl_k() { return 128; }
+
 template <int NT, typename ET>
-__global__ __launch_bounds__(64) void project_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
-                                                           int64_t m, int64_t n, int64_t ld, int64_t stride,
-                                                           const uint16_t *__restrict__ Bb, int64_t ldv,
-                                                           float *__restrict__ C, int64_t count, int nb) {
+__global__ __launch_bounds__(256) void project_bf16_kernel(const ET *A, const float *__restrict__ scale, int64_t m,
+                                                           int64_t n, int64_t ld, int64_t stride, const uint16_t *Bb,
+                                                           int64_t ldv, float *__restrict__ C, int64_t count,
+                                                           int nb) {
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
     int64_t d;
     int band;
     xcd_band(blockIdx.x, count, nb, d, band);
-    project_bf16_body<NT, ET>(A, scale, m, n, ld, stride, Bb, ldv, C, d, band);
+    project_lds_body<NT, pjl_k<ET>(), ET>(A, scale, m, n, ld, stride, Bb, ldv, C, d, band, lds_dyn);
 }
 template <int KP>
 __global__ __launch_bounds__(256) void factor_kernel(const float *__restrict__ B, int64_t ldb, int64_t n,
@@ -902,11 +964,13 @@ __global__ __launch_bounds__(64) void sketch_bf16_multi(const ApDesc *__restrict
                              D.fro, D.npanel, it.y, it.z);
 }
 template <int NT, typename ET>
-__global__ __launch_bounds__(64) void project_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+__global__ __launch_bounds__(256) void project_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int4 it = items[blockIdx.x];
     if (it.x < 0) return;  // padding of the XCD-interleaved item list
     const ApDesc &D = P[it.x];
-    project_bf16_body<NT, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Bb, D.ldv, D.C, it.y, it.z);
+    project_lds_body<NT, pjl_k<ET>(), ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Bb, D.ldv, D.C,
+                                          it.y, it.z, lds_dyn);
 }
 template <int KP>
 __global__ __launch_bounds__(256) void factor_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
@@ -998,6 +1062,12 @@ __global__ void error_final_kernel(const double *__restrict__ part, int nblk, in
         default: return tsk_fail(c, TSK_E_ARG, "k > 64"); \
     }
 
+// Dynamic LDS above the default limit has to be allowed per kernel.
+static tsk_status allow_lds(tsk_ctx c, const void *f, size_t bytes) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return e == hipSuccess ? TSK_OK : tsk_hip(c, e, "LDS attribute");
+}
+
 // factor, eig and outputs launches of one problem (workspace grown here)
 static tsk_status finish_enqueue(tsk_ctx c, int kp, const float *B, int64_t ldv, int64_t n, const float *Cm,
                                  int64_t m, int k, int r, const double *fro, int npanel, int64_t count, float *L,
@@ -1088,12 +1158,16 @@ static tsk_status apply_lowp_enqueue(tsk_ctx c, const float *S, int k, const tsk
                                   s->ld, s->stride, (const uint16_t *)Sb, mp, B, Bb, ldv, fro, npanel))
     TSK_KP_SWITCH(kp / 16, TSK_SKB(1), TSK_SKB(2), TSK_SKB(3), TSK_SKB(4))
 #undef TSK_SKB
-    const int nb = (int)((m + PJB_ROWS - 1) / PJB_ROWS);
+    const int nb = (int)((m + PJL_ROWS - 1) / PJL_ROWS);
     const dim3 gp((unsigned)(nb * count));
-#define TSK_PJB(NTV)                                                                                      \
-    TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                     \
-               hipLaunchKernelGGL((project_bf16_kernel<NTV, ET>), gp, dim3(64), 0, c->stream, A, sc, m, n, \
-                                  s->ld, s->stride, (const uint16_t *)Bb, ldv, Cm, count, nb))
+    const size_t pjl = (size_t)pjl_lds_bytes(pjl_k<ET>(), (int)sizeof(ET), kp);
+#define TSK_PJB(NTV)                                                                                          \
+    {                                                                                                         \
+        TSK_TRY(allow_lds(c, (const void *)project_bf16_kernel<NTV, ET>, pjl));                               \
+        TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                     \
+                   hipLaunchKernelGGL((project_bf16_kernel<NTV, ET>), gp, dim3(PJL_THREADS), pjl, c->stream,    \
+                                      A, sc, m, n, s->ld, s->stride, (const uint16_t *)Bb, ldv, Cm, count, nb)); \
+    }
     TSK_KP_SWITCH(kp / 16, TSK_PJB(1), TSK_PJB(2), TSK_PJB(3), TSK_PJB(4))
 #undef TSK_PJB
     return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags);
@@ -1115,7 +1189,7 @@ tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_st
 tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute) {
     const bool lowp = compute != TSK_F32;
     const int panel = lowp ? SKB_PANEL : SK_PANEL;
-    const int band = lowp ? PJB_ROWS : PJ_ROWS;
+    const int band = lowp ? PJL_ROWS : PJ_ROWS;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     constexpr int NREG = 8;  // workspace regions per problem
     std::vector<ApDesc> desc(np);
@@ -1265,14 +1339,19 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
     if (cnt[1][CL]) {                                                                                              \
         const dim3 g((unsigned)cnt[1][CL]);                                                                        \
         const int4 *It = I + start[1][CL];                                                                         \
-        if (!lowp)                                                                                                 \
+        if (!lowp) {                                                                                               \
             TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_multi<CL>, g, dim3(64), 0, c->stream, P, It)); \
-        else if (e4)                                                                                               \
-            TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                      \
-                       hipLaunchKernelGGL((project_bf16_multi<CL, uint8_t>), g, dim3(64), 0, c->stream, P, It));    \
-        else                                                                                                       \
-            TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                      \
-                       hipLaunchKernelGGL((project_bf16_multi<CL, uint16_t>), g, dim3(64), 0, c->stream, P, It));   \
+        } else if (e4) {                                                                                           \
+            const size_t pjl = (size_t)pjl_lds_bytes(pjl_k<uint8_t>(), 1, 16 * CL);                                \
+            TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<CL, uint8_t>, pjl));                             \
+            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL((project_bf16_multi<CL, uint8_t>), g,             \
+                                                                 dim3(PJL_THREADS), pjl, c->stream, P, It));       \
+        } else {                                                                                                   \
+            const size_t pjl = (size_t)pjl_lds_bytes(pjl_k<uint16_t>(), 2, 16 * CL);                               \
+            TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<CL, uint16_t>, pjl));                            \
+            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL((project_bf16_multi<CL, uint16_t>), g,            \
+                                                                 dim3(PJL_THREADS), pjl, c->stream, P, It));       \
+        }                                                                                                          \
     }
 #define TSK_MFA(CL)                                                                                          \
     if (cnt[2][CL])                                                                                          \

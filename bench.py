@@ -35,8 +35,43 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "e4m3": 5000.0}
 PEAK_HBM_GBS = 8000.0
+COPY_BYTES = 256 << 20  # calibration copy of the counter pass
+# HBM traffic of the Gram kernel per launch, from two rocprofv3 --pmc runs of
+# `bench.py --counter-pass` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch,
+# mean of the two Gram launches), each scaled by what the same counter reads
+# for the calibration copy of COPY_BYTES (copy_fetch_kib, copy_write_kib).
+# Valid only for the kernel sources they were taken on (sha256 of the files
+# below); otherwise traffic is reported as null.
+TRAFFIC_SOURCES = ("paper_2209_14637_amd/csrc/gram.hip", "paper_2209_14637_amd/csrc/tsk_common.hpp")
+MEASURED_TRAFFIC = {
+    "stream_bf16": {"kernel": "gram_bf16_kernel<uint16_t>", "fetch_kib": 15030532.0, "write_kib": 184449.5,
+                    "copy_fetch_kib": 131086.5, "copy_write_kib": 262144.0,
+                    "sha256": "0223dca1f528c4c165ac637980addf23d0be331aa6205d51d9aceafd9a6dded6"},
+    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1392953.0, "write_kib": 147462.0,
+                 "copy_fetch_kib": 131090.5, "copy_write_kib": 262144.0,
+                 "sha256": "0223dca1f528c4c165ac637980addf23d0be331aa6205d51d9aceafd9a6dded6"},
+}
+
+
+def traffic_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per Gram launch (calibrated FETCH + WRITE), or None when the
+    counters were taken on other kernel sources."""
+    t = MEASURED_TRAFFIC.get(workload)
+    if t is None or t["sha256"] != traffic_sha():
+        return None
+    return (t["fetch_kib"] * COPY_BYTES / (t["copy_fetch_kib"] * 1024) +
+            t["write_kib"] * COPY_BYTES / (t["copy_write_kib"] * 1024)) * 1024
 TAU = {"f32": 1e-5, "bf16": 1e-3, "e4m3": 1e-3}
-ORDER_CPU_SAMPLE = {"stream_bf16": (12, 32), "hsi_fp32": (40, 64), "t3stream_e4m3": (12, 32)}
+ORDER_CPU_SAMPLE = {"stream_bf16": (40, 128), "hsi_fp32": (100, 200), "t3stream_e4m3": (40, 128)}
 WORKLOADS = {
     "stream_bf16": ("bf16", "spec_bf16_1920", "stream_1920x1080_k40_r20"),
     "hsi_fp32": ("f32", "spec_hsi_fp32", "hsi_1024x768_k20_r10"),
@@ -154,6 +189,21 @@ def run(args):
     else:
         train_in, test_in, compute = tr, te, "f32"
 
+    if args.counter_pass:
+        # hardware-counter pass (run under rocprofv3 --pmc): two launches of
+        # the training Gram, then a plain 256 MiB device copy twice, which
+        # calibrates what the counters read per byte actually moved
+        for _ in range(2):
+            ctx.gram(train_in, compute=compute)
+        torch.cuda.synchronize()
+        x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(2):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        ctx.close()
+        return {"counter_pass": wl, "gram_launches": 2, "copy_bytes": COPY_BYTES, "copies": 2}, spec
+
     outbuf = {}
 
     def step():
@@ -206,9 +256,14 @@ def run(args):
     if dom == "gram":
         achieved = gram_flops / (gram_ms / 1e3) / 1e12
         peak = PEAK_TFLOPS[prec]
+        traffic = measured_traffic(wl) if MEASURED_TRAFFIC.get(wl, {}).get("kernel") == gram_kernel else None
         roof = {"kernel": gram_kernel, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "avg_launch_ms": gram_ms, "launches": kt_gram["gram"][0],
-                "algorithmic_work": f"m(m+1)nN = {gram_flops:.4e} flop per launch"}
+                "frac": achieved / peak, "traffic": traffic, "avg_launch_ms": gram_ms, "launches": kt_gram["gram"][0],
+                "algorithmic_work": f"m(m+1)nN = {gram_flops:.4e} flop per launch",
+                "algorithmic_bytes": spec.n_train * m * n * elt,
+                "traffic_note": "HBM bytes per launch: FETCH_SIZE + WRITE_SIZE (rocprofv3 --pmc, bench.py "
+                                "--counter-pass), each scaled by the counter's reading for a plain 256 MiB copy; "
+                                "null when taken on other kernel sources"}
     else:
         avg = kt[dom][1] / max(kt[dom][0], 1)
         roof = {"kernel": dom, "bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
@@ -442,6 +497,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="stream_bf16", choices=sorted(WORKLOADS) + ["batch_bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="only the Gram launches and a calibration copy, for rocprofv3 --pmc runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU path "
@@ -456,7 +513,7 @@ def main():
             rec["cpu_baseline"]["sample"] += " (the 1920x1080 stream of the batch)"
     else:
         rec, spec = run(args)
-        if not args.no_cpu_baseline:
+        if not args.no_cpu_baseline and not args.counter_pass:
             log("cpu baseline (oracle on a bounded sample)")
             rec["cpu_baseline"] = cpu_baseline(spec, *ORDER_CPU_SAMPLE[args.workload])
     print(json.dumps(rec), flush=True)

@@ -203,7 +203,7 @@ tsk_status tsk_error(tsk_ctx ctx, const tsk_stack *A, const float *L, const floa
  * matrix within that distance of G), 1e-5 for bf16 (rounding the data to
  * bf16 already moves G by about 1e-4 theta_1), 1e-4 for e4m3 (16 times
  * coarser rounding than bf16); tsk_eig_topk uses 1e-7];
- * check = filtered steps to the first convergence test [4]; later tests are
+ * check = filtered steps to the first convergence test [6]; later tests are
  * placed where the observed residual decay predicts convergence (at most
  * 4 * check steps apart).  A value <= 0 restores the default. */
 tsk_status tsk_set_eig_params(tsk_ctx ctx, int32_t block, int32_t max_iter, double tol,

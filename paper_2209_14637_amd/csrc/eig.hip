@@ -496,7 +496,7 @@ __global__ void eig_emit_kernel(const double *__restrict__ X, const double *__re
 
 tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *S, double *lambda,
                            int32_t *iters_out, double tol_default) {
-    const int qx = k / 2 > 12 ? k / 2 : 12;
+    const int qx = k / 2 > 12 ? k / 2 : 12;  // guard columns beyond k
     int p = c->eig_block > 0 ? c->eig_block : k + qx;
     if (p > EIG_MAXPP) p = EIG_MAXPP;
     if (p > m) p = (int)m;
@@ -614,7 +614,7 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
     // after two checks the per-step decay of the largest residual predicts
     // how many filtered steps remain, and the next check is placed there
     // (at least 1, at most 4 x `check` steps away).
-    const int check = c->eig_check > 0 ? c->eig_check : 4;
+    const int check = c->eig_check > 0 ? c->eig_check : 6;
     const int max_steps = c->eig_max_iter > 0 ? c->eig_max_iter : 300;
     int steps = 0;
     double hs[2] = {0.0, 0.0};

@@ -363,7 +363,7 @@ tsk_status tsk_set_eig_params(tsk_ctx c, int32_t block, int32_t max_iter, double
     c->eig_block = block > 0 ? block : 0;
     c->eig_max_iter = max_iter > 0 ? max_iter : 300;
     c->eig_tol = tol > 0 ? tol : 0.0;  // 0: the default for the Gram's precision
-    c->eig_check = check > 0 ? check : 4;
+    c->eig_check = check > 0 ? check : 6;
     return TSK_OK;
 }
 

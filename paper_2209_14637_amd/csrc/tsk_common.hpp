@@ -503,7 +503,7 @@ struct tsk_ctx_s {
     size_t mp_pin_bytes = 0;
     hipEvent_t mp_ev = nullptr;      // recorded after the last batch table copy
     // eigensolver controls
-    int eig_block = 0, eig_max_iter = 300, eig_check = 4;
+    int eig_block = 0, eig_max_iter = 300, eig_check = 6;
     double eig_tol = 0.0;  // 0: TSK_EIG_TOL_F32 / TSK_EIG_TOL_BF16 by the Gram's precision
     // timing
     uint32_t timing = 0;  // bit i: bracket launches of kernel class i with events

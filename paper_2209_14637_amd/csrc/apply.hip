@@ -585,33 +585,45 @@ __device__ inline void gram_mfma_acc(const float *__restrict__ X, int64_t ldx, i
     if (ROWS) {
         // K-steps of 16 columns: lane (q, i) holds columns c + 4q .. +3 of row
         // t*16 + i; component u feeds MFMA u (same order on both operands)
+        // (UR K-steps per iteration, all their loads issued first; steps
+        // past s1 read column 0 again, in range, and are not used)
         const int64_t nst = (len + 15) / 16;
         const int64_t s0 = nst * wv / 4, s1 = nst * (wv + 1) / 4;
-        for (int64_t st = s0; st < s1; ++st) {
-            const int64_t c = st * 16 + 4 * q;
-            float4 x[NT];
+        constexpr int UR = 4;
+        for (int64_t st = s0; st < s1; st += UR) {
+            float4 x[UR][NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) x[t] = *reinterpret_cast<const float4 *>(X + (int64_t)(t * 16 + ii) * ldx + c);
+            for (int h = 0; h < UR; ++h) {
+                const int64_t c = (st + h < s1 ? st + h : s0) * 16 + 4 * q;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                double xv[NT];
+                for (int t = 0; t < NT; ++t)
+                    x[h][t] = *reinterpret_cast<const float4 *>(X + (int64_t)(t * 16 + ii) * ldx + c);
+            }
 #pragma unroll
-                for (int t = 0; t < NT; ++t) xv[t] = (double)(u == 0 ? x[t].x : u == 1 ? x[t].y : u == 2 ? x[t].z : x[t].w);
-                int pr = 0;
+            for (int h = 0; h < UR; ++h) {
+                if (st + h >= s1) break;
 #pragma unroll
-                for (int ta = 0; ta < NT; ++ta)
+                for (int u = 0; u < 4; ++u) {
+                    double xv[NT];
 #pragma unroll
-                    for (int tb = ta; tb < NT; ++tb) {
-                        acc[pr] = mfma16x16x4_f64(xv[ta], xv[tb], acc[pr]);
-                        ++pr;
-                    }
+                    for (int t = 0; t < NT; ++t)
+                        xv[t] = (double)(u == 0 ? x[h][t].x : u == 1 ? x[h][t].y : u == 2 ? x[h][t].z : x[h][t].w);
+                    int pr = 0;
+#pragma unroll
+                    for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+                        for (int tb = ta; tb < NT; ++tb) {
+                            acc[pr] = mfma16x16x4_f64(xv[ta], xv[tb], acc[pr]);
+                            ++pr;
+                        }
+                }
             }
         }
     } else {
         // K-steps of 4 rows: lane (q, i) holds row r + q, columns t*16 + i
         const int64_t nst = (len + 3) / 4;
         const int64_t s0 = nst * wv / 4, s1 = nst * (wv + 1) / 4;
-        constexpr int UH = 8;  // K-steps per iteration (all their loads issued first)
+        constexpr int UH = 16;  // K-steps per iteration (all their loads issued first)
         for (int64_t st = s0; st < s1; st += UH) {
             float xf[UH][NT];
 #pragma unroll

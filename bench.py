@@ -44,12 +44,12 @@ COPY_BYTES = 256 << 20  # calibration copy of the counter pass
 # below); otherwise traffic is reported as null.
 TRAFFIC_SOURCES = ("paper_2209_14637_amd/csrc/gram.hip", "paper_2209_14637_amd/csrc/tsk_common.hpp")
 MEASURED_TRAFFIC = {
-    "stream_bf16": {"kernel": "gram_bf16_kernel<uint16_t>", "fetch_kib": 15415676.0, "write_kib": 184457.0,
-                    "copy_fetch_kib": 131086.5, "copy_write_kib": 262144.0,
-                    "sha256": "88d6dbc4b534a337e9d4261729ef0ba245731849cb49300a4a5418c7eef15a5d"},
-    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1389390.5, "write_kib": 147461.0,
-                 "copy_fetch_kib": 131091.0, "copy_write_kib": 262144.0,
-                 "sha256": "88d6dbc4b534a337e9d4261729ef0ba245731849cb49300a4a5418c7eef15a5d"},
+    "stream_bf16": {"kernel": "gram_bf16_kernel<uint16_t>", "fetch_kib": 11337987.0, "write_kib": 491646.7,
+                    "copy_fetch_kib": 131086.2, "copy_write_kib": 262144.0,
+                    "sha256": "f5c40ccd260918ea22845931132e463352c50362ef4f6ad432254d14486e12d2"},
+    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1117489.7, "write_kib": 294919.5,
+                 "copy_fetch_kib": 131086.1, "copy_write_kib": 262144.0,
+                 "sha256": "f5c40ccd260918ea22845931132e463352c50362ef4f6ad432254d14486e12d2"},
 }
 
 

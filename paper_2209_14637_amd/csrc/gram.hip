@@ -489,7 +489,20 @@ tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *
     const int64_t m = s->m, count = s->count;
     const int nb = (int)((m + GT - 1) / GT);
     const int T = nb * (nb + 1) / 2;
-    int per_xcd = (2048 + 8 * T - 1) / (8 * T);
+    // chunks per XCD: at least 2048 workgroups in all, and among up to four
+    // times that minimum the count whose workgroups fill whole rounds of the
+    // 64 resident on an XCD (2 per CU), so no round runs part-empty
+    const int pmin = (2048 + 8 * T - 1) / (8 * T);
+    int per_xcd = pmin;
+    double best = 1.0;
+    for (int pc = pmin; pc <= 4 * pmin; ++pc) {
+        const int64_t wg = (int64_t)pc * T;
+        const double waste = (double)((wg + 63) / 64 * 64 - wg) / (double)((wg + 63) / 64 * 64);
+        if (waste < best - 1e-12) {
+            best = waste;
+            per_xcd = pc;
+        }
+    }
     const int64_t cap = count / 8;
     if (per_xcd > cap) per_xcd = (int)(cap > 1 ? cap : 1);
     if (per_xcd < 1) per_xcd = 1;

@@ -71,7 +71,7 @@ def measured_traffic(workload):
     return (t["fetch_kib"] * COPY_BYTES / (t["copy_fetch_kib"] * 1024) +
             t["write_kib"] * COPY_BYTES / (t["copy_write_kib"] * 1024)) * 1024
 TAU = {"f32": 1e-5, "bf16": 1e-3, "e4m3": 1e-3}
-ORDER_CPU_SAMPLE = {"stream_bf16": (40, 128), "hsi_fp32": (100, 200), "t3stream_e4m3": (40, 128)}
+ORDER_CPU_SAMPLE = {"stream_bf16": (100, 512), "hsi_fp32": (200, 400), "t3stream_e4m3": (100, 512)}
 WORKLOADS = {
     "stream_bf16": ("bf16", "spec_bf16_1920", "stream_1920x1080_k40_r20"),
     "hsi_fp32": ("f32", "spec_hsi_fp32", "hsi_1024x768_k20_r10"),

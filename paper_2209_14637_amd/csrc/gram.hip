@@ -331,6 +331,172 @@ __global__ __launch_bounds__(256, 2 * (sizeof(SrcT) == 2) + (sizeof(SrcT) != 2))
 }
 
 // ---------------------------------------------------------------------------
+// Wide-tile bf16 Gram for a bf16 stack: 256x256 tiles of G's lower triangle,
+// 8 waves, each owning a 128x64 block (8x4 MFMA 16x16x32 tiles).  A tile
+// reads half the operand bytes per flop of a 128x128 tile, which is what the
+// per-CU path from L2 allows at full MFMA rate.  The tile's 128x128 quarters
+// are written as the same per-chunk partials as the 128x128 kernels (quarter
+// (2I+a, 2J+b) of tile (I, J)), so one reduction serves both.  Waves whose
+// quarter lies above the diagonal or past the last row skip their MFMAs; a
+// diagonal tile stages its 256 rows once and reads both operands from them.
+// ---------------------------------------------------------------------------
+constexpr int WT = 256;                 // tile edge
+constexpr int WLD = HK;                 // LDS row: 64 bf16 (128 bytes), unpadded
+constexpr int WBUF = 2 * WT * WLD;      // bf16 elements per stage buffer
+constexpr int W_THREADS = 512;
+constexpr size_t W_LDS = 2 * WBUF * sizeof(uint16_t);
+
+// LDS bank layout (measured on gfx950: 16-byte accesses are served 32 lanes
+// at a time over 128 four-byte banks).  The 16-byte chunk c of LDS row r is
+// stored at chunk c ^ wswz(r): the 32 lanes of an MFMA operand read (16
+// rows of one 16-row block, two adjacent chunks) then fall on 32 distinct
+// 16-byte bank groups, and so do the 32 lanes of a store (4 whole rows).
+__device__ __forceinline__ int wswz(int r) { return 2 * ((r >> 2) & 3); }
+
+// Rows of one stage: wave v stages rows 64v..64v+63 of the 512 (row block,
+// then column block), 8 rows per load: lane l takes 16-byte chunk l & 7 of
+// row 8u + (l >> 3) of its 64 (128 contiguous bytes per row).
+__device__ __forceinline__ int wrow(int u, int l) { return 8 * u + (l >> 3); }
+
+// 8 16-byte loads of one stage, unconditional: rows past the last are read
+// from row m - 1 and columns past n from column 0 (both in bounds, since ld
+// is a multiple of 8 elements) and are zeroed by the masks at the LDS store.
+// roff: byte offsets of this thread's 8 rows in a slice (a slice is under
+// 4 GiB); co: byte offset of its column.
+__device__ __forceinline__ void wfetch(const uint16_t *Ad, const uint32_t (&roff)[8], uint32_t co, v4u (&v)[8]) {
+    const char *base = reinterpret_cast<const char *>(Ad);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const v4u *>(base + (roff[u] + co));
+}
+
+// Mask of the valid bf16 elements among the 8 of a 16-byte chunk (nv valid).
+__device__ __forceinline__ v4u colmask(int nv) {
+    v4u k;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) k[j] = nv >= 2 * j + 2 ? 0xffffffffu : (nv == 2 * j + 1 ? 0xffffu : 0u);
+    return k;
+}
+
+// rowbits bit u: row u of this thread's 8 is a row of the matrix.
+__device__ __forceinline__ void wstash(uint16_t *buf, int rl0, const v4u (&v)[8], unsigned rowbits, v4u cm) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const v4u k = ((rowbits >> u) & 1u) ? cm : v4u{0u, 0u, 0u, 0u};
+        const int r = rl0 + wrow(u, l);
+        *reinterpret_cast<v4u *>(buf + r * WLD + 8 * ((l & 7) ^ wswz(r))) = v[u] & k;
+    }
+}
+
+__global__ __launch_bounds__(W_THREADS) void gram_bf16_wide_kernel(const uint16_t *__restrict__ A, int64_t m,
+                                                                   int64_t n, int64_t ld, int64_t stride,
+                                                                   int64_t count, int TW, int T, int nchunks,
+                                                                   int per_xcd, float *__restrict__ part) {
+    extern __shared__ __align__(16) uint16_t wlds[];
+    const int w = blockIdx.x;
+    const int xcd = w & 7, local = w >> 3;
+    const int t = local % TW, sub = local / TW;
+    const int chunk = xcd * per_xcd + sub;
+    const int64_t d0 = (int64_t)chunk * count / nchunks;
+    const int64_t d1 = (int64_t)(chunk + 1) * count / nchunks;
+    if (d0 >= d1) return;
+    int bi, bj;
+    tile_coords(t, bi, bj);
+    const bool diag = bi == bj;
+    const int nb = (int)((m + GT - 1) / GT);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = lane >> 4, ii = lane & 15;
+    const int wr = wv >> 2, wc = wv & 3;
+    // this wave's 128x128 quarter of G, in 128-block coordinates
+    const int qa = 2 * bi + wr, qb = 2 * bj + (wc >> 1);
+    const bool active = qa < nb && qb <= qa;
+    const int ra = wr * 128, rb = (diag ? 0 : WT) + wc * 64;
+    // staged rows: waves 0-3 the row block, waves 4-7 the column block (not
+    // staged for a diagonal tile, whose operands share the row block)
+    const bool stager = !diag || wv < 4;
+    const int64_t rbase = (wv < 4 ? (int64_t)bi * WT : (int64_t)bj * WT - WT) + 64 * wv;
+    const int rl0 = 64 * wv;
+
+    v4f acc[8][4];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    const int64_t spd = (n + HK - 1) / HK;
+    const int64_t nst = (d1 - d0) * spd;
+    unsigned rowbits = 0;
+    uint32_t roff[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int64_t row = rbase + wrow(u, lane);
+        rowbits |= (row < m ? 1u : 0u) << u;
+        roff[u] = (uint32_t)((row < m ? row : m - 1) * ld * 2);
+    }
+    // the next stage to fetch: slice fd, first column fc
+    int64_t fd = d0, fc = 0;
+    auto fetch = [&](v4u (&dst)[8], v4u &cm) {
+        const int64_t cc = fc + 8 * (lane & 7);
+        cm = colmask((int)min(max(n - cc, (int64_t)0), (int64_t)8));
+        // past the chunk's last stage the loads repeat a stage of the chunk
+        // (never stored), so every wave issues the same loads each stage
+        wfetch(A + (fd < d1 ? fd : d1 - 1) * stride, roff, (uint32_t)(cc < n ? 2 * cc : 0), dst);
+        fc += HK;
+        if (fc >= n) {
+            fc = 0;
+            ++fd;
+        }
+    };
+    auto mma_stage = [&](const uint16_t *cur) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // rows ra + 16x + ii and rb + 16y + ii all have swizzle wswz(ii)
+            const int co = 8 * ((q + 4 * h) ^ wswz(ii));
+            v4u a[8], b[4];
+#pragma unroll
+            for (int x = 0; x < 8; ++x) a[x] = *reinterpret_cast<const v4u *>(cur + (ra + x * 16 + ii) * WLD + co);
+#pragma unroll
+            for (int y = 0; y < 4; ++y) b[y] = *reinterpret_cast<const v4u *>(cur + (rb + y * 16 + ii) * WLD + co);
+#pragma unroll
+            for (int x = 0; x < 8; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x32_bf16(a[x], b[y], acc[x][y]);
+        }
+    };
+    // every wave issues every fetch (unconditional loads keep the wait
+    // counts exact: a stage's store waits only for that stage's loads)
+    v4u p0[8], p1[8], c0m, c1m;
+    fetch(p0, c0m);
+    if (stager) wstash(wlds, rl0, p0, rowbits, c0m);
+    fetch(p1, c1m);
+    __syncthreads();
+    // pairs of stages: stage st in buffer 0, st + 1 in buffer 1; p1 carries
+    // stage st + 1 (issued a stage earlier), p0 receives st + 2
+    int64_t st = 0;
+    for (; st + 1 < nst; st += 2) {
+        fetch(p0, c0m);
+        if (active) mma_stage(wlds);
+        if (stager) wstash(wlds + WBUF, rl0, p1, rowbits, c1m);
+        __syncthreads();
+        fetch(p1, c1m);
+        if (active) mma_stage(wlds + WBUF);
+        if (stager && st + 2 < nst) wstash(wlds, rl0, p0, rowbits, c0m);
+        __syncthreads();
+    }
+    if (st < nst && active) mma_stage(wlds);
+    if (!active) return;
+    const int tq = qa * (qa + 1) / 2 + qb;
+    float *P = part + ((int64_t)chunk * T + tq) * (GT * GT);
+    const int lc0 = (wc & 1) * 64;
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) P[(x * 16 + 4 * q + r) * GT + lc0 + y * 16 + ii] = acc[x][y][r];
+}
+
+// ---------------------------------------------------------------------------
 // e4m3 products (the e4m3 form): same tiling; a stage is 128 e4m3 columns
 // (again 128 bytes of every staged row), one 16x16x128 MFMA per tile per
 // stage.  Slice d is stored as A_d s_d with s_d = 2^j_d, so each product is
@@ -481,6 +647,28 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const float *__restric
 
 }  // namespace
 
+// Chunks per XCD for tiles tiles, res workgroups resident per XCD: at least
+// 2048 workgroups in all, and among up to four times that minimum the count
+// whose workgroups fill whole rounds of the resident ones, so no round runs
+// part-empty; at most count / 8 (every chunk holds a slice).
+static int pick_per_xcd(int tiles, int res, int64_t count) {
+    const int pmin = (2048 + 8 * tiles - 1) / (8 * tiles);
+    int per_xcd = pmin;
+    double best = 1.0;
+    for (int pc = pmin; pc <= 4 * pmin; ++pc) {
+        const int64_t wg = (int64_t)pc * tiles;
+        const int64_t full = (wg + res - 1) / res * res;
+        const double waste = (double)(full - wg) / (double)full;
+        if (waste < best - 1e-12) {
+            best = waste;
+            per_xcd = pc;
+        }
+    }
+    const int64_t cap = count / 8;
+    if (per_xcd > cap) per_xcd = (int)(cap > 1 ? cap : 1);
+    return per_xcd < 1 ? 1 : per_xcd;
+}
+
 // Enqueue the Gram of a validated stack into device G (m x m FP64).
 // compute TSK_F32: FP32 stack, FP32 products.  compute TSK_BF16: FP32 stack
 // rounded to bf16 on load, or a bf16 stack as stored.  compute TSK_F8E4M3:
@@ -489,29 +677,27 @@ tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *
     const int64_t m = s->m, count = s->count;
     const int nb = (int)((m + GT - 1) / GT);
     const int T = nb * (nb + 1) / 2;
-    // chunks per XCD: at least 2048 workgroups in all, and among up to four
-    // times that minimum the count whose workgroups fill whole rounds of the
-    // 64 resident on an XCD (2 per CU), so no round runs part-empty
-    const int pmin = (2048 + 8 * T - 1) / (8 * T);
-    int per_xcd = pmin;
-    double best = 1.0;
-    for (int pc = pmin; pc <= 4 * pmin; ++pc) {
-        const int64_t wg = (int64_t)pc * T;
-        const double waste = (double)((wg + 63) / 64 * 64 - wg) / (double)((wg + 63) / 64 * 64);
-        if (waste < best - 1e-12) {
-            best = waste;
-            per_xcd = pc;
-        }
-    }
-    const int64_t cap = count / 8;
-    if (per_xcd > cap) per_xcd = (int)(cap > 1 ? cap : 1);
-    if (per_xcd < 1) per_xcd = 1;
+    const bool wide = compute == TSK_BF16 && s->dtype == TSK_BF16 && m * s->ld * 2 < ((int64_t)1 << 32);
+    const int nbw = (int)((m + WT - 1) / WT);
+    const int TW = nbw * (nbw + 1) / 2;
+    // wide tiles: one workgroup per CU, 32 resident per XCD; 128x128 tiles:
+    // two per CU, 64 resident
+    const int per_xcd = wide ? pick_per_xcd(TW, 32, count) : pick_per_xcd(T, 64, count);
     const int nchunks = 8 * per_xcd;
     const size_t part_bytes = (size_t)nchunks * T * GT * GT * sizeof(float);
     TSK_TRY(tsk_grow(c, c->gram_part, part_bytes));
     float *part = (float *)c->gram_part.p;
     const unsigned grid = (unsigned)(8 * per_xcd * T);
-    if (compute == TSK_F32) {
+    if (wide) {
+        const hipError_t e =
+            hipFuncSetAttribute((const void *)gram_bf16_wide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)W_LDS);
+        if (e != hipSuccess) return tsk_hip(c, e, "Gram LDS attribute");
+        TSK_LAUNCH(c, TSK_KERNEL_GRAM,
+                   hipLaunchKernelGGL(gram_bf16_wide_kernel, dim3((unsigned)(8 * per_xcd * TW)), dim3(W_THREADS),
+                                      W_LDS, c->stream, (const uint16_t *)s->A, m, s->n, s->ld, s->stride, count,
+                                      TW, T, nchunks, per_xcd, part));
+    } else if (compute == TSK_F32) {
         TSK_LAUNCH(c, TSK_KERNEL_GRAM,
                    hipLaunchKernelGGL(gram_f32_kernel, dim3(grid), dim3(256), 0, c->stream,
                                       (const float *)s->A, m, s->n, s->ld, s->stride, count, T, nchunks,

@@ -119,7 +119,12 @@ def test_stage_e4m3_bitexact(ctx, orc, shape):
 # Gram in bf16
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("shape", [(3, 64, 48), (5, 200, 37), (40, 300, 100), (9, 130, 257), (1, 5, 3)])
+# bf16 stacks take the 256x256-tile kernel: the shapes cover a lone diagonal
+# tile (m <= 256), tile rows whose second 128-row half is partly or wholly
+# past m (300, 384, 520), n ragged against the 64-column stage and the
+# 8-column chunk, and more and fewer slices than slice chunks
+@pytest.mark.parametrize("shape", [(3, 64, 48), (5, 200, 37), (40, 300, 100), (9, 130, 257), (1, 5, 3),
+                                   (70, 384, 136), (4, 520, 64), (2, 256, 8)])
 @pytest.mark.parametrize("src", ["f32", "bf16"])
 def test_gram_bf16_integer_exact(ctx, orc, shape, src):
     cnt, m, n = shape

@@ -427,11 +427,22 @@ __host__ __device__ constexpr int pjl_lds_bytes(int K, int eb, int kp) {
     return PJL_ROWS * (K * eb + 16) + 2 * kp * (2 * K + 16);
 }
 
+// With ctc, the band's C^T C (FP64; the upper-triangle 16x16 tile pairs of
+// the kp x kp product, pair p = (ta, tb), ta <= tb, in row-major order,
+// each tile row-major) goes to ctc[(d nb + band) NPAIR 256 ...], nb the
+// bands of a matrix: for row tile t and accumulator register r, lane (q, i)
+// holds C[row0 + 4q + r][16b + i], the operand layout of a 16x16x4 FP64
+// MFMA whose K index runs over 4 rows, so the products (FP32 values, exact
+// in FP64) come straight from the accumulators.  The four waves' sums are
+// added in wave order.  LDS: pjl_ctc_bytes(kp) of it is reused for that.
+__host__ __device__ constexpr int pjl_ctc_bytes(int kp) { return 3 * (kp / 16) * (kp / 16 + 1) / 2 * 256 * 8; }
+
 template <int NT, int K, typename ET>
 __device__ __forceinline__ void project_lds_body(const ET *A, const float *__restrict__ scale, int64_t m,
                                                  int64_t n, int64_t ld, int64_t stride,
                                                  const uint16_t *Bb, int64_t ldv, float *__restrict__ C,
-                                                 int64_t d, int band, unsigned char *lds) {
+                                                 int64_t d, int band, unsigned char *lds,
+                                                 double *__restrict__ ctc) {
     constexpr int kp = NT * 16;
     constexpr int EB = (int)sizeof(ET);
     constexpr int CE = 16 / EB;
@@ -561,6 +572,51 @@ __device__ __forceinline__ void project_lds_body(const ET *A, const float *__res
                 for (int b = 0; b < NT; ++b) Cd[row * kp + b * 16 + ii] = acc[t][b][r];
             }
         }
+    if (ctc) {
+        constexpr int NPAIR = NT * (NT + 1) / 2;
+        v4d g[NPAIR];
+#pragma unroll
+        for (int p = 0; p < NPAIR; ++p) g[p] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double xv[NT];
+#pragma unroll
+                for (int b = 0; b < NT; ++b) xv[b] = (double)acc[t][b][r];
+                int p = 0;
+#pragma unroll
+                for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+                    for (int tb = ta; tb < NT; ++tb) {
+                        g[p] = mfma16x16x4_f64(xv[ta], xv[tb], g[p]);
+                        ++p;
+                    }
+            }
+        // waves 1-3 park their sums in LDS (free: every wave is past the
+        // main loop's last barrier); wave 0 adds them in order and writes
+        // f64 result layout: lane holds D[q + 4r][i]
+        double *gs = reinterpret_cast<double *>(lds);
+        if (w > 0) {
+#pragma unroll
+            for (int p = 0; p < NPAIR; ++p)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) gs[((w - 1) * NPAIR + p) * 256 + (q + 4 * r) * 16 + ii] = g[p][r];
+        }
+        __syncthreads();
+        if (w == 0) {
+            const int nb = (int)((m + PJL_ROWS - 1) / PJL_ROWS);
+            double *o = ctc + ((int64_t)d * nb + band) * (NPAIR * 256);
+#pragma unroll
+            for (int p = 0; p < NPAIR; ++p)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = (q + 4 * r) * 16 + ii;
+                    o[p * 256 + e] = ((g[p][r] + gs[p * 256 + e]) + gs[(NPAIR + p) * 256 + e]) +
+                                     gs[(2 * NPAIR + p) * 256 + e];
+                }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -691,7 +747,7 @@ __device__ inline void small_mm(const double *X, const double *M, double *Y) {
 template <int KP>
 __device__ __forceinline__ void factor_body(const float *__restrict__ B, int64_t ldb, int64_t n,
                                             const float *__restrict__ C, int64_t m, int k, double *__restrict__ HX,
-                                            int *__restrict__ q, int64_t d) {
+                                            int *__restrict__ q, int64_t d, const double *__restrict__ ctc) {
     constexpr int SZ = KP * KP;
     __shared__ double buf[3 * SZ];
     __shared__ int dead[KP];
@@ -705,7 +761,27 @@ __device__ __forceinline__ void factor_body(const float *__restrict__ B, int64_t
     const int nd = chol_factor_inverse(b0, KP, KP, 1e-12, b1, b2, dead, k);  // X = R^-1 in b2
     for (int e = tid; e < SZ; e += 256) b0[e] = 0.0;
     __syncthreads();
-    gram_mfma_acc<KP / 16, false>(Cd, KP, m, b0, KP);
+    if (ctc) {
+        // C^T C from the projection's per-band sums, added in band order
+        constexpr int NT = KP / 16, NPAIR = NT * (NT + 1) / 2;
+        const int nb = (int)((m + PJL_ROWS - 1) / PJL_ROWS);
+        const double *src = ctc + d * nb * (NPAIR * 256);
+        for (int e = tid; e < NPAIR * 256; e += 256) {
+            double s = 0.0;
+            for (int b = 0; b < nb; ++b) s += src[(int64_t)b * (NPAIR * 256) + e];
+            int p = e >> 8, ta = 0;
+            while (p >= NT - ta) {
+                p -= NT - ta;
+                ++ta;
+            }
+            const int tb = ta + p, a = (e >> 4) & 15, c = e & 15;
+            b0[(16 * ta + a) * KP + 16 * tb + c] = s;
+            if (ta != tb) b0[(16 * tb + c) * KP + 16 * ta + a] = s;
+        }
+        __syncthreads();
+    } else {
+        gram_mfma_acc<KP / 16, false>(Cd, KP, m, b0, KP);
+    }
     small_mm<KP, false>(b0, b2, b1);  // b1 = (C^T C) X
     small_mm<KP, true>(b2, b1, b0);   // b0 = X^T b1
     double *o = HX + d * 2 * SZ;
@@ -775,19 +851,52 @@ __device__ __forceinline__ void eig_body(const double *__restrict__ HX, const in
 }
 
 // outputs: L = C Z (m x r) and R = B^T Z (n x r); NaN for a non-finite A_d.
+// out[t] = sum_u v[u] Z[u][t] for t < r (Z in LDS, row stride KP), four
+// columns per pass (one broadcast 16-byte LDS read per four FMAs; each sum
+// runs over u in order); NaN everywhere when the matrix was not finite.
+template <int KP>
+__device__ __forceinline__ void outputs_row(const float (&v)[KP], const float *Zs, int r, bool finite,
+                                            float *out) {
+    const float qnan = __builtin_nanf("");
+    // Z stays in LDS: without this the compiler keeps it in registers across
+    // rows (four times the registers, a quarter of the resident workgroups)
+    asm volatile("" ::: "memory");
+    for (int t0 = 0; t0 < r; t0 += 4) {
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        // groups of 8 rows of Z; the empty asm takes the sums as operands
+        // and orders memory, so a group's FMAs finish before the next
+        // group's reads and at most 8 reads are live
+#pragma unroll
+        for (int u0 = 0; u0 < KP; u0 += 8) {
+#pragma unroll
+            for (int u = u0; u < u0 + 8; ++u) {
+                const float4 z = *reinterpret_cast<const float4 *>(Zs + u * KP + t0);
+                s0 += v[u] * z.x;
+                s1 += v[u] * z.y;
+                s2 += v[u] * z.z;
+                s3 += v[u] * z.w;
+            }
+            asm volatile("" : "+v"(s0), "+v"(s1), "+v"(s2), "+v"(s3) : : "memory");
+        }
+        const float sv[4] = {s0, s1, s2, s3};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (t0 + e < r) out[t0 + e] = finite ? sv[e] : qnan;
+    }
+}
+
 template <int KP>
 __device__ __forceinline__ void outputs_body(const float *__restrict__ B, int64_t ldb, int64_t n,
                                              const float *__restrict__ C, int64_t m, int k, int r,
                                              const double *__restrict__ fro_part, int npanel,
                                              const float *__restrict__ Z, float *__restrict__ L,
                                              float *__restrict__ R, int64_t d) {
-    __shared__ float Zs[KP * KP];
+    __shared__ __align__(16) float Zs[KP * KP];
     const int tid = threadIdx.x;
     for (int e = tid; e < KP * KP; e += 256) Zs[e] = Z[d * KP * KP + e];
     double fro2 = 0.0;
     for (int p = 0; p < npanel; ++p) fro2 += fro_part[d * npanel + p];
     const bool finite = isfinite(fro2);
-    const float qnan = __builtin_nanf("");
     __syncthreads();
     const float *Bd = B + d * KP * ldb;
     const float *Cd = C + d * m * KP;
@@ -803,12 +912,7 @@ __device__ __forceinline__ void outputs_body(const float *__restrict__ B, int64_
             cv[u + 2] = f.z;
             cv[u + 3] = f.w;
         }
-        for (int t = 0; t < r; ++t) {
-            float s = 0.f;
-#pragma unroll
-            for (int u = 0; u < KP; ++u) s += cv[u] * Zs[u * KP + t];
-            Ld[i * r + t] = finite ? s : qnan;
-        }
+        outputs_row<KP>(cv, Zs, r, finite, Ld + i * r);
     }
     // R = B^T Z: one column of B per thread
     float *Rd = R + d * n * r;
@@ -816,12 +920,7 @@ __device__ __forceinline__ void outputs_body(const float *__restrict__ B, int64_
         float vv[KP];
 #pragma unroll
         for (int u = 0; u < KP; ++u) vv[u] = u < k ? Bd[u * ldb + j] : 0.f;
-        for (int t = 0; t < r; ++t) {
-            float s = 0.f;
-#pragma unroll
-            for (int u = 0; u < KP; ++u) s += vv[u] * Zs[u * KP + t];
-            Rd[j * r + t] = finite ? s : qnan;
-        }
+        outputs_row<KP>(vv, Zs, r, finite, Rd + j * r);
     }
 }
 
@@ -846,6 +945,7 @@ struct ApDesc {
     float *C;
     double *fro;
     double *HX;             // per matrix [H | X], KP x KP FP64 each
+    double *ctc;            // bf16 / e4m3 forms: per-band C^T C sums; FP32 form: null
     float *Z;               // per matrix KP x KP
     int *q;                 // per matrix dead-pivot count
     float *L, *R, *sigma;
@@ -912,22 +1012,25 @@ __global__ __launch_bounds__(64) void sketch_bf16_kernel(const ET *__restrict__ 
 template <typename ET>
 constexpr int pjl_k() { return 128; }
 
+// two workgroups per CU (at most 256 VGPRs, which the C^T C epilogue would
+// otherwise exceed at kp = 64)
 template <int NT, typename ET>
-__global__ __launch_bounds__(256) void project_bf16_kernel(const ET *A, const float *__restrict__ scale, int64_t m,
+__global__ __launch_bounds__(256, 2) void project_bf16_kernel(const ET *A, const float *__restrict__ scale, int64_t m,
                                                            int64_t n, int64_t ld, int64_t stride, const uint16_t *Bb,
                                                            int64_t ldv, float *__restrict__ C, int64_t count,
-                                                           int nb) {
+                                                           int nb, double *__restrict__ ctc) {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     int64_t d;
     int band;
     xcd_band(blockIdx.x, count, nb, d, band);
-    project_lds_body<NT, pjl_k<ET>(), ET>(A, scale, m, n, ld, stride, Bb, ldv, C, d, band, lds_dyn);
+    project_lds_body<NT, pjl_k<ET>(), ET>(A, scale, m, n, ld, stride, Bb, ldv, C, d, band, lds_dyn, ctc);
 }
 template <int KP>
 __global__ __launch_bounds__(256) void factor_kernel(const float *__restrict__ B, int64_t ldb, int64_t n,
                                                      const float *__restrict__ C, int64_t m, int k,
-                                                     double *__restrict__ HX, int *__restrict__ q) {
-    factor_body<KP>(B, ldb, n, C, m, k, HX, q, blockIdx.x);
+                                                     double *__restrict__ HX, int *__restrict__ q,
+                                                     const double *__restrict__ ctc) {
+    factor_body<KP>(B, ldb, n, C, m, k, HX, q, blockIdx.x, ctc);
 }
 template <int KP>
 __global__ __launch_bounds__(256) void eig_kernel(const double *__restrict__ HX, const int *__restrict__ q, int k,
@@ -976,19 +1079,19 @@ __global__ __launch_bounds__(64) void sketch_bf16_multi(const ApDesc *__restrict
                              D.fro, D.npanel, it.y, it.z);
 }
 template <int NT, typename ET>
-__global__ __launch_bounds__(256) void project_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+__global__ __launch_bounds__(256, 2) void project_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int4 it = items[blockIdx.x];
     if (it.x < 0) return;  // padding of the XCD-interleaved item list
     const ApDesc &D = P[it.x];
     project_lds_body<NT, pjl_k<ET>(), ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Bb, D.ldv, D.C,
-                                          it.y, it.z, lds_dyn);
+                                          it.y, it.z, lds_dyn, D.ctc);
 }
 template <int KP>
 __global__ __launch_bounds__(256) void factor_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
-    factor_body<KP>(D.B, D.ldv, D.n, D.C, D.m, D.k, D.HX, D.q, it.y);
+    factor_body<KP>(D.B, D.ldv, D.n, D.C, D.m, D.k, D.HX, D.q, it.y, D.ctc);
 }
 template <int KP>
 __global__ __launch_bounds__(256) void eig_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
@@ -1080,10 +1183,11 @@ static tsk_status allow_lds(tsk_ctx c, const void *f, size_t bytes) {
     return e == hipSuccess ? TSK_OK : tsk_hip(c, e, "LDS attribute");
 }
 
-// factor, eig and outputs launches of one problem (workspace grown here)
+// factor, eig and outputs launches of one problem (workspace grown here);
+// ctc: the projection's per-band C^T C sums, or null (computed from C)
 static tsk_status finish_enqueue(tsk_ctx c, int kp, const float *B, int64_t ldv, int64_t n, const float *Cm,
                                  int64_t m, int k, int r, const double *fro, int npanel, int64_t count, float *L,
-                                 float *R, float *sigma, double *relerr, int32_t *flags) {
+                                 float *R, float *sigma, double *relerr, int32_t *flags, const double *ctc) {
     TSK_TRY(tsk_grow(c, c->ap_HX, sizeof(double) * count * 2 * kp * kp));
     TSK_TRY(tsk_grow(c, c->ap_Z, sizeof(float) * count * kp * kp + sizeof(int) * count));
     double *HX = (double *)c->ap_HX.p;
@@ -1093,7 +1197,7 @@ static tsk_status finish_enqueue(tsk_ctx c, int kp, const float *B, int64_t ldv,
 #define TSK_FIN(KPV)                                                                                              \
     do {                                                                                                          \
         TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(factor_kernel<KPV>, g, dim3(256), 0, c->stream, B, ldv, n, \
-                                                        Cm, m, k, HX, q));                                        \
+                                                        Cm, m, k, HX, q, ctc));                                   \
         TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                          \
                    hipLaunchKernelGGL(eig_kernel<KPV>, g, dim3(256), 0, c->stream, (const double *)HX,            \
                                       (const int *)q, k, r, fro, npanel, Z, sigma, relerr, flags));              \
@@ -1137,7 +1241,8 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
                                   (const float *)B, ldv, Cm, count, nb))
     TSK_KP_SWITCH(kp / 16, TSK_PJ(1), TSK_PJ(2), TSK_PJ(3), TSK_PJ(4))
 #undef TSK_PJ
-    return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags);
+    return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags,
+                          nullptr);
 }
 
 // bf16 form (ET = uint16_t, bf16 stack) and e4m3 form (ET = uint8_t, e4m3
@@ -1172,17 +1277,22 @@ static tsk_status apply_lowp_enqueue(tsk_ctx c, const float *S, int k, const tsk
 #undef TSK_SKB
     const int nb = (int)((m + PJL_ROWS - 1) / PJL_ROWS);
     const dim3 gp((unsigned)(nb * count));
-    const size_t pjl = (size_t)pjl_lds_bytes(pjl_k<ET>(), (int)sizeof(ET), kp);
+    const size_t pjl = (size_t)std::max(pjl_lds_bytes(pjl_k<ET>(), (int)sizeof(ET), kp), pjl_ctc_bytes(kp));
+    // the per-band C^T C sums follow the per-matrix [H | X] in one buffer
+    const int npair = (kp / 16) * (kp / 16 + 1) / 2;
+    TSK_TRY(tsk_grow(c, c->ap_HX, sizeof(double) * count * (2 * kp * kp + (int64_t)nb * npair * 256)));
+    double *ctc = (double *)c->ap_HX.p + count * 2 * kp * kp;
 #define TSK_PJB(NTV)                                                                                          \
     {                                                                                                         \
         TSK_TRY(allow_lds(c, (const void *)project_bf16_kernel<NTV, ET>, pjl));                               \
         TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                     \
                    hipLaunchKernelGGL((project_bf16_kernel<NTV, ET>), gp, dim3(PJL_THREADS), pjl, c->stream,    \
-                                      A, sc, m, n, s->ld, s->stride, (const uint16_t *)Bb, ldv, Cm, count, nb)); \
+                                      A, sc, m, n, s->ld, s->stride, (const uint16_t *)Bb, ldv, Cm, count, nb, \
+                                      ctc));                                                                  \
     }
     TSK_KP_SWITCH(kp / 16, TSK_PJB(1), TSK_PJB(2), TSK_PJB(3), TSK_PJB(4))
 #undef TSK_PJB
-    return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags);
+    return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags, ctc);
 }
 
 tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
@@ -1203,7 +1313,7 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
     const int panel = lowp ? SKB_PANEL : SK_PANEL;
     const int band = lowp ? PJL_ROWS : PJ_ROWS;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    constexpr int NREG = 8;  // workspace regions per problem
+    constexpr int NREG = 9;  // workspace regions per problem
     std::vector<ApDesc> desc(np);
     std::vector<size_t> off(np * NREG);
     size_t ws = 0;
@@ -1236,7 +1346,10 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
                                  sizeof(double) * D.count * D.npanel,
                                  sizeof(double) * D.count * 2 * D.kp * D.kp,
                                  sizeof(float) * D.count * D.kp * D.kp,
-                                 sizeof(int) * D.count};
+                                 sizeof(int) * D.count,
+                                 lowp ? sizeof(double) * D.count * ((A.m + band - 1) / band) *
+                                            ((D.kp / 16) * (D.kp / 16 + 1) / 2 * 256)
+                                      : 0};
         for (int j = 0; j < NREG; ++j) {
             off[i * NREG + j] = ws;
             ws += al(sz[j]);
@@ -1256,6 +1369,7 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
         D.HX = (double *)(base + o[5]);
         D.Z = (float *)(base + o[6]);
         D.q = (int *)(base + o[7]);
+        D.ctc = lowp ? (double *)(base + o[8]) : nullptr;
     }
     // work items: problems largest first within each list
     std::vector<int> order(np);
@@ -1354,12 +1468,12 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
         if (!lowp) {                                                                                               \
             TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_multi<CL>, g, dim3(64), 0, c->stream, P, It)); \
         } else if (e4) {                                                                                           \
-            const size_t pjl = (size_t)pjl_lds_bytes(pjl_k<uint8_t>(), 1, 16 * CL);                                \
+            const size_t pjl = (size_t)std::max(pjl_lds_bytes(pjl_k<uint8_t>(), 1, 16 * CL), pjl_ctc_bytes(16 * CL)); \
             TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<CL, uint8_t>, pjl));                             \
             TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL((project_bf16_multi<CL, uint8_t>), g,             \
                                                                  dim3(PJL_THREADS), pjl, c->stream, P, It));       \
         } else {                                                                                                   \
-            const size_t pjl = (size_t)pjl_lds_bytes(pjl_k<uint16_t>(), 2, 16 * CL);                               \
+            const size_t pjl = (size_t)std::max(pjl_lds_bytes(pjl_k<uint16_t>(), 2, 16 * CL), pjl_ctc_bytes(16 * CL)); \
             TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<CL, uint16_t>, pjl));                            \
             TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL((project_bf16_multi<CL, uint16_t>), g,            \
                                                                  dim3(PJL_THREADS), pjl, c->stream, P, It));       \

@@ -854,8 +854,10 @@ __device__ __forceinline__ void eig_body(const double *__restrict__ HX, const in
 // out[t] = sum_u v[u] Z[u][t] for t < r (Z in LDS, row stride KP), four
 // columns per pass (one broadcast 16-byte LDS read per four FMAs; each sum
 // runs over u in order); NaN everywhere when the matrix was not finite.
+// vec: out is 16-byte aligned and r a multiple of 4, so each pass is one
+// 16-byte store (scattered 4-byte stores ran at under 1 TB/s).
 template <int KP>
-__device__ __forceinline__ void outputs_row(const float (&v)[KP], const float *Zs, int r, bool finite,
+__device__ __forceinline__ void outputs_row(const float (&v)[KP], const float *Zs, int r, bool finite, bool vec,
                                             float *out) {
     const float qnan = __builtin_nanf("");
     // Z stays in LDS: without this the compiler keeps it in registers across
@@ -878,10 +880,15 @@ __device__ __forceinline__ void outputs_row(const float (&v)[KP], const float *Z
             }
             asm volatile("" : "+v"(s0), "+v"(s1), "+v"(s2), "+v"(s3) : : "memory");
         }
-        const float sv[4] = {s0, s1, s2, s3};
+        if (!finite) s0 = s1 = s2 = s3 = qnan;
+        if (vec) {
+            *reinterpret_cast<float4 *>(out + t0) = float4{s0, s1, s2, s3};
+        } else {
+            const float sv[4] = {s0, s1, s2, s3};
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (t0 + e < r) out[t0 + e] = finite ? sv[e] : qnan;
+            for (int e = 0; e < 4; ++e)
+                if (t0 + e < r) out[t0 + e] = sv[e];
+        }
     }
 }
 
@@ -897,6 +904,7 @@ __device__ __forceinline__ void outputs_body(const float *__restrict__ B, int64_
     double fro2 = 0.0;
     for (int p = 0; p < npanel; ++p) fro2 += fro_part[d * npanel + p];
     const bool finite = isfinite(fro2);
+    const bool vec = r % 4 == 0 && ((reinterpret_cast<uintptr_t>(L) | reinterpret_cast<uintptr_t>(R)) & 15) == 0;
     __syncthreads();
     const float *Bd = B + d * KP * ldb;
     const float *Cd = C + d * m * KP;
@@ -912,7 +920,7 @@ __device__ __forceinline__ void outputs_body(const float *__restrict__ B, int64_
             cv[u + 2] = f.z;
             cv[u + 3] = f.w;
         }
-        outputs_row<KP>(cv, Zs, r, finite, Ld + i * r);
+        outputs_row<KP>(cv, Zs, r, finite, vec, Ld + i * r);
     }
     // R = B^T Z: one column of B per thread
     float *Rd = R + d * n * r;
@@ -920,7 +928,7 @@ __device__ __forceinline__ void outputs_body(const float *__restrict__ B, int64_
         float vv[KP];
 #pragma unroll
         for (int u = 0; u < KP; ++u) vv[u] = u < k ? Bd[u * ldb + j] : 0.f;
-        outputs_row<KP>(vv, Zs, r, finite, Rd + j * r);
+        outputs_row<KP>(vv, Zs, r, finite, vec, Rd + j * r);
     }
 }
 

@@ -331,27 +331,36 @@ __global__ __launch_bounds__(256, 2 * (sizeof(SrcT) == 2) + (sizeof(SrcT) != 2))
 }
 
 // ---------------------------------------------------------------------------
-// Wide-tile bf16 Gram for a bf16 stack: 256x256 tiles of G's lower triangle,
-// 8 waves, each owning a 128x64 block (8x4 MFMA 16x16x32 tiles).  A tile
-// reads half the operand bytes per flop of a 128x128 tile, which is what the
-// per-CU path from L2 allows at full MFMA rate.  The tile's 128x128 quarters
-// are written as the same per-chunk partials as the 128x128 kernels (quarter
-// (2I+a, 2J+b) of tile (I, J)), so one reduction serves both.  Waves whose
-// quarter lies above the diagonal or past the last row skip their MFMAs; a
-// diagonal tile stages its 256 rows once and reads both operands from them.
+// Wide-tile Gram for a bf16 stack (16x16x32 bf16 MFMA) or an e4m3 stack
+// (16x16x128 e4m3 MFMA whose E8M0 operand scales fold the slice's scale in
+// exactly): 256x256 tiles of G's lower triangle, 8 waves, each owning a
+// 128x64 block (8x4 MFMA 16x16 tiles).  A tile reads half the operand bytes
+// per flop of a 128x128 tile, which is what the per-CU path from L2 allows at
+// full MFMA rate.  The tile's 128x128 quarters are written as the same
+// per-chunk partials as the 128x128 kernels (quarter (2I+a, 2J+b) of tile
+// (I, J)), so one reduction serves both.  Waves whose quarter lies above the
+// diagonal or past the last row skip their MFMAs; a diagonal tile stages its
+// 256 rows once and reads both operands from them.  A stage is 128 bytes of
+// every operand row: 64 bf16 or 128 e4m3 columns (an e4m3 stage never
+// straddles slices, so one scale serves it).
 // ---------------------------------------------------------------------------
 constexpr int WT = 256;                 // tile edge
-constexpr int WLD = HK;                 // LDS row: 64 bf16 (128 bytes), unpadded
-constexpr int WBUF = 2 * WT * WLD;      // bf16 elements per stage buffer
+constexpr int WROW = 128;               // LDS row: 128 bytes, unpadded
+constexpr int WBUF = 2 * WT * WROW;     // bytes per stage buffer
 constexpr int W_THREADS = 512;
-constexpr size_t W_LDS = 2 * WBUF * sizeof(uint16_t);
+constexpr size_t W_LDS = 2 * WBUF;
 
 // LDS bank layout (measured on gfx950: 16-byte accesses are served 32 lanes
 // at a time over 128 four-byte banks).  The 16-byte chunk c of LDS row r is
 // stored at chunk c ^ wswz(r): the 32 lanes of an MFMA operand read (16
-// rows of one 16-row block, two adjacent chunks) then fall on 32 distinct
-// 16-byte bank groups, and so do the 32 lanes of a store (4 whole rows).
-__device__ __forceinline__ int wswz(int r) { return 2 * ((r >> 2) & 3); }
+// rows of one 16-row block; chunks q and q + 4h of bf16 operands, chunks 2q
+// or 2q + 1 of e4m3 operands, q < 2) then fall on 32 distinct 16-byte bank
+// groups, and so do the 32 lanes of a store (4 whole rows).
+template <typename ET>
+__device__ __forceinline__ int wswz(int r) {
+    const int a = (r >> 2) & 3;
+    return sizeof(ET) == 2 ? 2 * a : (a & 1) + 4 * (a >> 1);
+}
 
 // Rows of one stage: wave v stages rows 64v..64v+63 of the 512 (row block,
 // then column block), 8 rows per load: lane l takes 16-byte chunk l & 7 of
@@ -360,39 +369,52 @@ __device__ __forceinline__ int wrow(int u, int l) { return 8 * u + (l >> 3); }
 
 // 8 16-byte loads of one stage, unconditional: rows past the last are read
 // from row m - 1 and columns past n from column 0 (both in bounds, since ld
-// is a multiple of 8 elements) and are zeroed by the masks at the LDS store.
-// roff: byte offsets of this thread's 8 rows in a slice (a slice is under
-// 4 GiB); co: byte offset of its column.
-__device__ __forceinline__ void wfetch(const uint16_t *Ad, const uint32_t (&roff)[8], uint32_t co, v4u (&v)[8]) {
+// is a multiple of 16 bytes) and are zeroed by the masks at the LDS store.
+// Byte offsets within a slice are 32-bit (a slice is under 4 GiB); row0:
+// this thread's first row (its others follow 8 apart), ldb: row stride in
+// bytes, co: byte offset of its column.
+__device__ __forceinline__ void wfetch(const void *Ad, int row0, int mlast, uint32_t ldb, uint32_t co, v4u (&v)[8]) {
     const char *base = reinterpret_cast<const char *>(Ad);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const v4u *>(base + (roff[u] + co));
+    for (int u = 0; u < 8; ++u) {
+        const uint32_t off = (uint32_t)min(row0 + 8 * u, mlast) * ldb + co;
+        v[u] = *reinterpret_cast<const v4u *>(base + off);
+    }
 }
 
-// Mask of the valid bf16 elements among the 8 of a 16-byte chunk (nv valid).
-__device__ __forceinline__ v4u colmask(int nv) {
+// Mask of the valid bytes of a 16-byte chunk whose first nb bytes are valid.
+__device__ __forceinline__ v4u colmask(int nb) {
     v4u k;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) k[j] = nv >= 2 * j + 2 ? 0xffffffffu : (nv == 2 * j + 1 ? 0xffffu : 0u);
+    for (int j = 0; j < 4; ++j) {
+        const int v = nb - 4 * j;
+        k[j] = v >= 4 ? 0xffffffffu : (v <= 0 ? 0u : (1u << (8 * v)) - 1u);
+    }
     return k;
 }
 
-// rowbits bit u: row u of this thread's 8 is a row of the matrix.
-__device__ __forceinline__ void wstash(uint16_t *buf, int rl0, const v4u (&v)[8], unsigned rowbits, v4u cm) {
+// rowbits bit u: row u of this thread's 8 is a row of the matrix; nvb: the
+// valid bytes of this thread's 16-byte column chunk.
+template <typename ET>
+__device__ __forceinline__ void wstash(uint8_t *buf, int rl0, const v4u (&v)[8], unsigned rowbits, int nvb) {
     const int l = threadIdx.x & 63;
+    const v4u cm = colmask(nvb);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const v4u k = ((rowbits >> u) & 1u) ? cm : v4u{0u, 0u, 0u, 0u};
         const int r = rl0 + wrow(u, l);
-        *reinterpret_cast<v4u *>(buf + r * WLD + 8 * ((l & 7) ^ wswz(r))) = v[u] & k;
+        *reinterpret_cast<v4u *>(buf + r * WROW + 16 * ((l & 7) ^ wswz<ET>(r))) = v[u] & k;
     }
 }
 
-__global__ __launch_bounds__(W_THREADS) void gram_bf16_wide_kernel(const uint16_t *__restrict__ A, int64_t m,
-                                                                   int64_t n, int64_t ld, int64_t stride,
-                                                                   int64_t count, int TW, int T, int nchunks,
-                                                                   int per_xcd, float *__restrict__ part) {
-    extern __shared__ __align__(16) uint16_t wlds[];
+template <typename ET>
+__global__ __launch_bounds__(W_THREADS) void gram_wide_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
+                                                              int64_t m, int64_t n, int64_t ld, int64_t stride,
+                                                              int64_t count, int TW, int T, int nchunks, int per_xcd,
+                                                              float *__restrict__ part) {
+    constexpr int EB = (int)sizeof(ET);
+    constexpr int SC = WROW / EB;  // columns per stage
+    extern __shared__ __align__(16) uint8_t wlds[];
     const int w = blockIdx.x;
     const int xcd = w & 7, local = w >> 3;
     const int t = local % TW, sub = local / TW;
@@ -423,67 +445,105 @@ __global__ __launch_bounds__(W_THREADS) void gram_bf16_wide_kernel(const uint16_
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    const int64_t spd = (n + HK - 1) / HK;
+    const int64_t spd = (n + SC - 1) / SC;
     const int64_t nst = (d1 - d0) * spd;
     unsigned rowbits = 0;
-    uint32_t roff[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int64_t row = rbase + wrow(u, lane);
-        rowbits |= (row < m ? 1u : 0u) << u;
-        roff[u] = (uint32_t)((row < m ? row : m - 1) * ld * 2);
-    }
-    // the next stage to fetch: slice fd, first column fc
+    for (int u = 0; u < 8; ++u) rowbits |= (rbase + wrow(u, lane) < m ? 1u : 0u) << u;
+    const int row0 = (int)(rbase + wrow(0, lane));
+    const uint32_t ldb = (uint32_t)(ld * EB);
+    // valid bytes of this thread's chunk in the stage starting at column c
+    auto nvb = [&](int64_t c) {
+        return (int)min(max(n - (c + (int64_t)(16 / EB) * (lane & 7)), (int64_t)0), (int64_t)(16 / EB)) * EB;
+    };
+    // the next stage to fetch: slice fd, first column fc (returned in fcs);
+    // es: the E8M0 operand scale 2^-j of its slice (scale[d] = 2^j), e4m3
     int64_t fd = d0, fc = 0;
-    auto fetch = [&](v4u (&dst)[8], v4u &cm) {
-        const int64_t cc = fc + 8 * (lane & 7);
-        cm = colmask((int)min(max(n - cc, (int64_t)0), (int64_t)8));
+    auto fetch = [&](v4u (&dst)[8], int64_t &fcs, int &es) {
+        const int64_t cc = fc + (int64_t)(16 / EB) * (lane & 7);
+        fcs = fc;
         // past the chunk's last stage the loads repeat a stage of the chunk
         // (never stored), so every wave issues the same loads each stage
-        wfetch(A + (fd < d1 ? fd : d1 - 1) * stride, roff, (uint32_t)(cc < n ? 2 * cc : 0), dst);
-        fc += HK;
+        const int64_t dd = fd < d1 ? fd : d1 - 1;
+        wfetch(A + dd * stride, row0, (int)(m - 1), ldb, (uint32_t)(cc < n ? cc * EB : 0), dst);
+        es = 127;
+        if constexpr (EB == 1) {
+            int j;
+            frexpf(scale[dd], &j);
+            es = 127 - (j - 1);
+        }
+        fc += SC;
         if (fc >= n) {
             fc = 0;
             ++fd;
         }
     };
-    auto mma_stage = [&](const uint16_t *cur) {
+    auto mma_stage = [&](const uint8_t *cur, int es) {
+        if constexpr (EB == 2) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            // rows ra + 16x + ii and rb + 16y + ii all have swizzle wswz(ii)
-            const int co = 8 * ((q + 4 * h) ^ wswz(ii));
-            v4u a[8], b[4];
+            for (int h = 0; h < 2; ++h) {
+                // rows ra + 16x + ii and rb + 16y + ii all have swizzle wswz(ii)
+                const int co = 16 * ((q + 4 * h) ^ wswz<ET>(ii));
+                v4u a[8], b[4];
 #pragma unroll
-            for (int x = 0; x < 8; ++x) a[x] = *reinterpret_cast<const v4u *>(cur + (ra + x * 16 + ii) * WLD + co);
+                for (int x = 0; x < 8; ++x) a[x] = *reinterpret_cast<const v4u *>(cur + (ra + x * 16 + ii) * WROW + co);
 #pragma unroll
-            for (int y = 0; y < 4; ++y) b[y] = *reinterpret_cast<const v4u *>(cur + (rb + y * 16 + ii) * WLD + co);
+                for (int y = 0; y < 4; ++y) b[y] = *reinterpret_cast<const v4u *>(cur + (rb + y * 16 + ii) * WROW + co);
 #pragma unroll
-            for (int x = 0; x < 8; ++x)
+                for (int x = 0; x < 8; ++x)
 #pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x32_bf16(a[x], b[y], acc[x][y]);
+                    for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x32_bf16(a[x], b[y], acc[x][y]);
+            }
+        } else {
+            // lane (q, i): bytes 32q .. 32q + 31 of its row (chunks 2q, 2q + 1)
+            const int c0 = 16 * ((2 * q) ^ wswz<ET>(ii)), c1 = 16 * ((2 * q + 1) ^ wswz<ET>(ii));
+            auto frag = [&](int row) {
+                const v4u lo = *reinterpret_cast<const v4u *>(cur + row * WROW + c0);
+                const v4u hi = *reinterpret_cast<const v4u *>(cur + row * WROW + c1);
+                return v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+            };
+            // two halves of the B tiles (16 fewer registers than all four;
+            // the A operands are read twice, LDS has the bandwidth), one A
+            // operand at a time: the empty asm keeps each tile row's LDS
+            // reads below the previous row's (issued all at once they need
+            // 64 more VGPRs, and spill reloads wait for every load in flight)
+#pragma unroll
+            for (int yh = 0; yh < 2; ++yh) {
+                const v8i b0 = frag(rb + (2 * yh) * 16 + ii), b1 = frag(rb + (2 * yh + 1) * 16 + ii);
+#pragma unroll
+                for (int x = 0; x < 8; ++x) {
+                    const v8i a = frag(ra + x * 16 + ii);
+                    acc[x][2 * yh] = mfma16x16x128_e4m3(a, b0, acc[x][2 * yh], es, es);
+                    acc[x][2 * yh + 1] = mfma16x16x128_e4m3(a, b1, acc[x][2 * yh + 1], es, es);
+                    asm volatile("" ::: "memory");
+                }
+            }
         }
     };
     // every wave issues every fetch (unconditional loads keep the wait
     // counts exact: a stage's store waits only for that stage's loads)
-    v4u p0[8], p1[8], c0m, c1m;
-    fetch(p0, c0m);
-    if (stager) wstash(wlds, rl0, p0, rowbits, c0m);
-    fetch(p1, c1m);
+    v4u p0[8], p1[8];
+    int64_t f0, f1;
+    int e0, e1;
+    fetch(p0, f0, e0);
+    if (stager) wstash<ET>(wlds, rl0, p0, rowbits, nvb(f0));
+    fetch(p1, f1, e1);
     __syncthreads();
     // pairs of stages: stage st in buffer 0, st + 1 in buffer 1; p1 carries
     // stage st + 1 (issued a stage earlier), p0 receives st + 2
     int64_t st = 0;
     for (; st + 1 < nst; st += 2) {
-        fetch(p0, c0m);
-        if (active) mma_stage(wlds);
-        if (stager) wstash(wlds + WBUF, rl0, p1, rowbits, c1m);
+        const int es_a = e0, es_b = e1;
+        fetch(p0, f0, e0);
+        if (active) mma_stage(wlds, es_a);
+        if (stager) wstash<ET>(wlds + WBUF, rl0, p1, rowbits, nvb(f1));
         __syncthreads();
-        fetch(p1, c1m);
-        if (active) mma_stage(wlds + WBUF);
-        if (stager && st + 2 < nst) wstash(wlds, rl0, p0, rowbits, c0m);
+        fetch(p1, f1, e1);
+        if (active) mma_stage(wlds + WBUF, es_b);
+        if (stager && st + 2 < nst) wstash<ET>(wlds, rl0, p0, rowbits, nvb(f0));
         __syncthreads();
     }
-    if (st < nst && active) mma_stage(wlds);
+    if (st < nst && active) mma_stage(wlds, e0);
     if (!active) return;
     const int tq = qa * (qa + 1) / 2 + qb;
     float *P = part + ((int64_t)chunk * T + tq) * (GT * GT);
@@ -677,7 +737,10 @@ tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *
     const int64_t m = s->m, count = s->count;
     const int nb = (int)((m + GT - 1) / GT);
     const int T = nb * (nb + 1) / 2;
-    const bool wide = compute == TSK_BF16 && s->dtype == TSK_BF16 && m * s->ld * 2 < ((int64_t)1 << 32);
+    // bf16 and e4m3 stacks (slices under 4 GiB) take the 256x256 tiles
+    const int eb = s->dtype == TSK_BF16 ? 2 : 1;
+    const bool wide = ((compute == TSK_BF16 && s->dtype == TSK_BF16) || compute == TSK_F8E4M3) &&
+                      m * s->ld * eb < ((int64_t)1 << 32);
     const int nbw = (int)((m + WT - 1) / WT);
     const int TW = nbw * (nbw + 1) / 2;
     // wide tiles: one workgroup per CU, 32 resident per XCD; 128x128 tiles:
@@ -689,14 +752,20 @@ tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *
     float *part = (float *)c->gram_part.p;
     const unsigned grid = (unsigned)(8 * per_xcd * T);
     if (wide) {
-        const hipError_t e =
-            hipFuncSetAttribute((const void *)gram_bf16_wide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)W_LDS);
+        const void *fn = eb == 2 ? (const void *)gram_wide_kernel<uint16_t> : (const void *)gram_wide_kernel<uint8_t>;
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)W_LDS);
         if (e != hipSuccess) return tsk_hip(c, e, "Gram LDS attribute");
-        TSK_LAUNCH(c, TSK_KERNEL_GRAM,
-                   hipLaunchKernelGGL(gram_bf16_wide_kernel, dim3((unsigned)(8 * per_xcd * TW)), dim3(W_THREADS),
-                                      W_LDS, c->stream, (const uint16_t *)s->A, m, s->n, s->ld, s->stride, count,
-                                      TW, T, nchunks, per_xcd, part));
+        const dim3 gw((unsigned)(8 * per_xcd * TW));
+        if (eb == 2)
+            TSK_LAUNCH(c, TSK_KERNEL_GRAM,
+                       hipLaunchKernelGGL(gram_wide_kernel<uint16_t>, gw, dim3(W_THREADS), W_LDS, c->stream,
+                                          (const uint16_t *)s->A, nullptr, m, s->n, s->ld, s->stride, count, TW, T,
+                                          nchunks, per_xcd, part));
+        else
+            TSK_LAUNCH(c, TSK_KERNEL_GRAM,
+                       hipLaunchKernelGGL(gram_wide_kernel<uint8_t>, gw, dim3(W_THREADS), W_LDS, c->stream,
+                                          (const uint8_t *)s->A, s->scale, m, s->n, s->ld, s->stride, count, TW, T,
+                                          nchunks, per_xcd, part));
     } else if (compute == TSK_F32) {
         TSK_LAUNCH(c, TSK_KERNEL_GRAM,
                    hipLaunchKernelGGL(gram_f32_kernel, dim3(grid), dim3(256), 0, c->stream,

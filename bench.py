@@ -44,12 +44,12 @@ COPY_BYTES = 256 << 20  # calibration copy of the counter pass
 # below); otherwise traffic is reported as null.
 TRAFFIC_SOURCES = ("paper_2209_14637_amd/csrc/gram.hip", "paper_2209_14637_amd/csrc/tsk_common.hpp")
 MEASURED_TRAFFIC = {
-    "stream_bf16": {"kernel": "gram_bf16_wide_kernel", "fetch_kib": 7266164.8, "write_kib": 491522.9,
-                    "copy_fetch_kib": 131086.1, "copy_write_kib": 262144.0,
-                    "sha256": "c7b3bd72d7fcfc89cacd98574edeb3f49371262f3b786bb687a0a3a01163e60c"},
-    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1118658.3, "write_kib": 294920.7,
-                 "copy_fetch_kib": 131086.3, "copy_write_kib": 262144.0,
-                 "sha256": "c7b3bd72d7fcfc89cacd98574edeb3f49371262f3b786bb687a0a3a01163e60c"},
+    "stream_bf16": {"kernel": "gram_wide_kernel<uint16_t>", "fetch_kib": 8123515.3, "write_kib": 491524.5,
+                    "copy_fetch_kib": 131086.2, "copy_write_kib": 262144.0,
+                    "sha256": "f10d32293fb6a8a71a7c6a081f11b2e20c3cdd4f6559c9e412d24f30820eb3da"},
+    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1117920.5, "write_kib": 294919.7,
+                 "copy_fetch_kib": 131086.2, "copy_write_kib": 262144.0,
+                 "sha256": "f10d32293fb6a8a71a7c6a081f11b2e20c3cdd4f6559c9e412d24f30820eb3da"},
 }
 
 
@@ -249,7 +249,8 @@ def run(args):
     gram_red_ms = kt_gram["gram_reduce"][1] / max(kt_gram["gram_reduce"][0], 1)
     gram_flops = m * (m + 1) * n * spec.n_train
     gram_tflops = gram_flops / ((gram_ms + gram_red_ms) / 1e3) / 1e12
-    gram_kernel = {"f32": "gram_f32_kernel", "bf16": "gram_bf16_wide_kernel", "e4m3": "gram_e4m3_kernel"}[prec]
+    gram_kernel = {"f32": "gram_f32_kernel", "bf16": "gram_wide_kernel<uint16_t>",
+                   "e4m3": "gram_wide_kernel<uint8_t>"}[prec]
     elt = {"f32": 4, "bf16": 2, "e4m3": 2}[prec]  # test matrices as the gated apply reads them
     apply_bytes = spec.n_test * m * n * elt
     dom = max(per_kernel_ms, key=per_kernel_ms.get)

@@ -362,26 +362,6 @@ __device__ __forceinline__ int wswz(int r) {
     return sizeof(ET) == 2 ? 2 * a : (a & 1) + 4 * (a >> 1);
 }
 
-// Rows of one stage: wave v stages rows 64v..64v+63 of the 512 (row block,
-// then column block), 8 rows per load: lane l takes 16-byte chunk l & 7 of
-// row 8u + (l >> 3) of its 64 (128 contiguous bytes per row).
-__device__ __forceinline__ int wrow(int u, int l) { return 8 * u + (l >> 3); }
-
-// 8 16-byte loads of one stage, unconditional: rows past the last are read
-// from row m - 1 and columns past n from column 0 (both in bounds, since ld
-// is a multiple of 16 bytes) and are zeroed by the masks at the LDS store.
-// Byte offsets within a slice are 32-bit (a slice is under 4 GiB); row0:
-// this thread's first row (its others follow 8 apart), ldb: row stride in
-// bytes, co: byte offset of its column.
-__device__ __forceinline__ void wfetch(const void *Ad, int row0, int mlast, uint32_t ldb, uint32_t co, v4u (&v)[8]) {
-    const char *base = reinterpret_cast<const char *>(Ad);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const uint32_t off = (uint32_t)min(row0 + 8 * u, mlast) * ldb + co;
-        v[u] = *reinterpret_cast<const v4u *>(base + off);
-    }
-}
-
 // Mask of the valid bytes of a 16-byte chunk whose first nb bytes are valid.
 __device__ __forceinline__ v4u colmask(int nb) {
     v4u k;
@@ -393,27 +373,27 @@ __device__ __forceinline__ v4u colmask(int nb) {
     return k;
 }
 
-// rowbits bit u: row u of this thread's 8 is a row of the matrix; nvb: the
-// valid bytes of this thread's 16-byte column chunk.
-template <typename ET>
-__device__ __forceinline__ void wstash(uint8_t *buf, int rl0, const v4u (&v)[8], unsigned rowbits, int nvb) {
-    const int l = threadIdx.x & 63;
-    const v4u cm = colmask(nvb);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const v4u k = ((rowbits >> u) & 1u) ? cm : v4u{0u, 0u, 0u, 0u};
-        const int r = rl0 + wrow(u, l);
-        *reinterpret_cast<v4u *>(buf + r * WROW + 16 * ((l & 7) ^ wswz<ET>(r))) = v[u] & k;
-    }
-}
-
+// ---------------------------------------------------------------------------
+// The kernel loads the operand rows straight into LDS (global_load_lds, 16
+// bytes per lane): no register staging and no LDS store instructions (a
+// register-staged version with loads two stages ahead was 5-10% slower).  The compiler waits for every such load in flight
+// before any later LDS read, so a stage reads all its MFMA operands into
+// registers first, then issues the next stage's loads into the other buffer,
+// then runs its MFMAs; the loads are waited for at the end of the stage.
+// Lane l of a load writes LDS row 8u + (l >> 3) of its wave's 64, physical
+// chunk l & 7, so it loads the logical chunk (l & 7) ^ wswz(row).  Rows
+// past m load row m - 1 (they only feed entries the reduction discards);
+// chunks reaching past column n load in-bounds columns and are rewritten
+// masked by the wave that loaded them once its loads have landed.
+// ---------------------------------------------------------------------------
 template <typename ET>
 __global__ __launch_bounds__(W_THREADS) void gram_wide_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
-                                                              int64_t m, int64_t n, int64_t ld, int64_t stride,
-                                                              int64_t count, int TW, int T, int nchunks, int per_xcd,
-                                                              float *__restrict__ part) {
+                                                             int64_t m, int64_t n, int64_t ld, int64_t stride,
+                                                             int64_t count, int TW, int T, int nchunks, int per_xcd,
+                                                             float *__restrict__ part) {
     constexpr int EB = (int)sizeof(ET);
     constexpr int SC = WROW / EB;  // columns per stage
+    constexpr int CE = 16 / EB;    // columns per 16-byte chunk
     extern __shared__ __align__(16) uint8_t wlds[];
     const int w = blockIdx.x;
     const int xcd = w & 7, local = w >> 3;
@@ -429,15 +409,19 @@ __global__ __launch_bounds__(W_THREADS) void gram_wide_kernel(const ET *__restri
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int q = lane >> 4, ii = lane & 15;
     const int wr = wv >> 2, wc = wv & 3;
-    // this wave's 128x128 quarter of G, in 128-block coordinates
     const int qa = 2 * bi + wr, qb = 2 * bj + (wc >> 1);
     const bool active = qa < nb && qb <= qa;
     const int ra = wr * 128, rb = (diag ? 0 : WT) + wc * 64;
-    // staged rows: waves 0-3 the row block, waves 4-7 the column block (not
-    // staged for a diagonal tile, whose operands share the row block)
     const bool stager = !diag || wv < 4;
     const int64_t rbase = (wv < 4 ? (int64_t)bi * WT : (int64_t)bj * WT - WT) + 64 * wv;
     const int rl0 = 64 * wv;
+    const uint32_t ldb = (uint32_t)(ld * EB);
+    // load u of this thread: logical chunk lcu(u) of LDS row rl0 + 8u +
+    // (lane >> 3), matrix row row0 + 8u, recomputed at every use from values
+    // passed through an empty asm (hoisted out of the loop they hold 16
+    // VGPRs and the kernel spills)
+    const int row0 = (int)(rbase + (lane >> 3));
+    auto lcu = [&](int u, int ln) { return (ln & 7) ^ wswz<ET>(rl0 + 8 * u + (ln >> 3)); };
 
     v4f acc[8][4];
 #pragma unroll
@@ -447,103 +431,120 @@ __global__ __launch_bounds__(W_THREADS) void gram_wide_kernel(const ET *__restri
 
     const int64_t spd = (n + SC - 1) / SC;
     const int64_t nst = (d1 - d0) * spd;
-    unsigned rowbits = 0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) rowbits |= (rbase + wrow(u, lane) < m ? 1u : 0u) << u;
-    const int row0 = (int)(rbase + wrow(0, lane));
-    const uint32_t ldb = (uint32_t)(ld * EB);
-    // valid bytes of this thread's chunk in the stage starting at column c
-    auto nvb = [&](int64_t c) {
-        return (int)min(max(n - (c + (int64_t)(16 / EB) * (lane & 7)), (int64_t)0), (int64_t)(16 / EB)) * EB;
+    const bool ragged = n % SC != 0;
+    // the stage after the current one: slice nd, first column nc
+    int64_t nd = d0, nc = 0;
+    auto advance = [&]() {
+        nc += SC;
+        if (nc >= n) {
+            nc = 0;
+            ++nd;
+        }
     };
-    // the next stage to fetch: slice fd, first column fc (returned in fcs);
-    // es: the E8M0 operand scale 2^-j of its slice (scale[d] = 2^j), e4m3
-    int64_t fd = d0, fc = 0;
-    auto fetch = [&](v4u (&dst)[8], int64_t &fcs, int &es) {
-        const int64_t cc = fc + (int64_t)(16 / EB) * (lane & 7);
-        fcs = fc;
-        // past the chunk's last stage the loads repeat a stage of the chunk
-        // (never stored), so every wave issues the same loads each stage
-        const int64_t dd = fd < d1 ? fd : d1 - 1;
-        wfetch(A + dd * stride, row0, (int)(m - 1), ldb, (uint32_t)(cc < n ? cc * EB : 0), dst);
-        es = 127;
+    auto issue = [&](uint8_t *buf) {
+        const char *base = reinterpret_cast<const char *>(A + nd * stride);
+        int ln = lane, r0 = row0;
+        asm volatile("" : "+v"(ln), "+v"(r0));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t col = nc + (int64_t)CE * lcu(u, ln);
+            const uint32_t roff = (uint32_t)min(r0 + 8 * u, (int)(m - 1)) * ldb;
+            const char *src = base + (roff + (uint32_t)(col < n ? col * EB : 0));
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src),
+                                             (__attribute__((address_space(3))) void *)(buf + (rl0 + 8 * u) * WROW),
+                                             16, 0, 0);
+        }
+    };
+    // once this wave's loads of the stage at column c have landed: its chunks
+    // reaching past n keep their valid bytes only
+    auto fix = [&](uint8_t *buf, int64_t c) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t col = c + (int64_t)CE * lcu(u, lane);
+            if (col + CE > n) {
+                v4u *pch = reinterpret_cast<v4u *>(buf + (rl0 + 8 * u + (lane >> 3)) * WROW + 16 * (lane & 7));
+                const int nvb = (int)min(max(n - col, (int64_t)0), (int64_t)CE) * EB;
+                *pch = *pch & colmask(nvb);
+            }
+        }
+    };
+    auto escale = [&](int64_t d) {
+        int es = 127;
         if constexpr (EB == 1) {
             int j;
-            frexpf(scale[dd], &j);
+            frexpf(scale[d], &j);
             es = 127 - (j - 1);
         }
-        fc += SC;
-        if (fc >= n) {
-            fc = 0;
-            ++fd;
-        }
+        return es;
     };
-    auto mma_stage = [&](const uint8_t *cur, int es) {
+    // stage 0
+    if (stager) issue(wlds);
+    int64_t cd = nd, cc = nc;  // the current stage
+    advance();
+    __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): this wave's loads have landed
+    if (stager && ragged && cc + SC > n) fix(wlds, cc);
+    __syncthreads();
+    for (int64_t st = 0; st < nst; ++st) {
+        const uint8_t *cur = wlds + (st & 1) * WBUF;
+        uint8_t *nxt = wlds + ((st + 1) & 1) * WBUF;
+        const bool more = st + 1 < nst;
+        const int es = escale(cd);
         if constexpr (EB == 2) {
+            // every operand of the stage into registers, then the next
+            // stage's loads, then the MFMAs
+            v4u a[2][8], b[2][4];
+            if (active) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                // rows ra + 16x + ii and rb + 16y + ii all have swizzle wswz(ii)
-                const int co = 16 * ((q + 4 * h) ^ wswz<ET>(ii));
-                v4u a[8], b[4];
+                for (int h = 0; h < 2; ++h) {
+                    const int co = 16 * ((q + 4 * h) ^ wswz<ET>(ii));
 #pragma unroll
-                for (int x = 0; x < 8; ++x) a[x] = *reinterpret_cast<const v4u *>(cur + (ra + x * 16 + ii) * WROW + co);
+                    for (int x = 0; x < 8; ++x)
+                        a[h][x] = *reinterpret_cast<const v4u *>(cur + (ra + x * 16 + ii) * WROW + co);
 #pragma unroll
-                for (int y = 0; y < 4; ++y) b[y] = *reinterpret_cast<const v4u *>(cur + (rb + y * 16 + ii) * WROW + co);
+                    for (int y = 0; y < 4; ++y)
+                        b[h][y] = *reinterpret_cast<const v4u *>(cur + (rb + y * 16 + ii) * WROW + co);
+                }
+            }
+            if (stager && more) issue(nxt);
+            if (active) {
 #pragma unroll
-                for (int x = 0; x < 8; ++x)
+                for (int h = 0; h < 2; ++h)
 #pragma unroll
-                    for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x32_bf16(a[x], b[y], acc[x][y]);
+                    for (int x = 0; x < 8; ++x)
+#pragma unroll
+                        for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x32_bf16(a[h][x], b[h][y], acc[x][y]);
             }
         } else {
-            // lane (q, i): bytes 32q .. 32q + 31 of its row (chunks 2q, 2q + 1)
             const int c0 = 16 * ((2 * q) ^ wswz<ET>(ii)), c1 = 16 * ((2 * q + 1) ^ wswz<ET>(ii));
             auto frag = [&](int row) {
                 const v4u lo = *reinterpret_cast<const v4u *>(cur + row * WROW + c0);
                 const v4u hi = *reinterpret_cast<const v4u *>(cur + row * WROW + c1);
                 return v8i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
             };
-            // two halves of the B tiles (16 fewer registers than all four;
-            // the A operands are read twice, LDS has the bandwidth), one A
-            // operand at a time: the empty asm keeps each tile row's LDS
-            // reads below the previous row's (issued all at once they need
-            // 64 more VGPRs, and spill reloads wait for every load in flight)
+            v8i a[8], b[4];
+            if (active) {
 #pragma unroll
-            for (int yh = 0; yh < 2; ++yh) {
-                const v8i b0 = frag(rb + (2 * yh) * 16 + ii), b1 = frag(rb + (2 * yh + 1) * 16 + ii);
+                for (int y = 0; y < 4; ++y) b[y] = frag(rb + y * 16 + ii);
 #pragma unroll
-                for (int x = 0; x < 8; ++x) {
-                    const v8i a = frag(ra + x * 16 + ii);
-                    acc[x][2 * yh] = mfma16x16x128_e4m3(a, b0, acc[x][2 * yh], es, es);
-                    acc[x][2 * yh + 1] = mfma16x16x128_e4m3(a, b1, acc[x][2 * yh + 1], es, es);
-                    asm volatile("" ::: "memory");
-                }
+                for (int x = 0; x < 8; ++x) a[x] = frag(ra + x * 16 + ii);
+            }
+            if (stager && more) issue(nxt);
+            if (active) {
+#pragma unroll
+                for (int x = 0; x < 8; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x128_e4m3(a[x], b[y], acc[x][y], es, es);
             }
         }
-    };
-    // every wave issues every fetch (unconditional loads keep the wait
-    // counts exact: a stage's store waits only for that stage's loads)
-    v4u p0[8], p1[8];
-    int64_t f0, f1;
-    int e0, e1;
-    fetch(p0, f0, e0);
-    if (stager) wstash<ET>(wlds, rl0, p0, rowbits, nvb(f0));
-    fetch(p1, f1, e1);
-    __syncthreads();
-    // pairs of stages: stage st in buffer 0, st + 1 in buffer 1; p1 carries
-    // stage st + 1 (issued a stage earlier), p0 receives st + 2
-    int64_t st = 0;
-    for (; st + 1 < nst; st += 2) {
-        const int es_a = e0, es_b = e1;
-        fetch(p0, f0, e0);
-        if (active) mma_stage(wlds, es_a);
-        if (stager) wstash<ET>(wlds + WBUF, rl0, p1, rowbits, nvb(f1));
-        __syncthreads();
-        fetch(p1, f1, e1);
-        if (active) mma_stage(wlds + WBUF, es_b);
-        if (stager && st + 2 < nst) wstash<ET>(wlds, rl0, p0, rowbits, nvb(f0));
+        // the MFMAs stay ahead of the wait, which covers the loads' latency
+        __builtin_amdgcn_sched_barrier(0);
+        cd = nd;
+        cc = nc;
+        advance();
+        __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
+        if (stager && more && ragged && cc + SC > n) fix(nxt, cc);
         __syncthreads();
     }
-    if (st < nst && active) mma_stage(wlds, e0);
     if (!active) return;
     const int tq = qa * (qa + 1) / 2 + qb;
     float *P = part + ((int64_t)chunk * T + tq) * (GT * GT);

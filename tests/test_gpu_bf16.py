@@ -138,6 +138,22 @@ def test_gram_bf16_integer_exact(ctx, orc, shape, src):
     assert np.array_equal(G.cpu().numpy(), orc.gram(a))
 
 
+@pytest.mark.parametrize("shape", [(5, 300, 37), (70, 384, 136), (3, 260, 1000)])
+def test_gram_bf16_padding_masked(ctx, orc, shape):
+    """A bf16 stack whose padding columns n .. ld-1 hold NaN: the Gram reads
+    only columns below n (the 256x256-tile kernel loads whole 16-byte chunks
+    and masks what lies past n, also in a stage's partial last chunk)."""
+    cnt, m, n = shape
+    _say(f"gram bf16 NaN padding {shape}")
+    a = synth.integer_stack(cnt, m, n, seed=sum(shape) + 11)
+    ld = (n + 7) // 8 * 8 + 8
+    buf = torch.full((cnt, m, ld), float("nan"), dtype=torch.bfloat16)
+    buf[:, :, :n] = torch.from_numpy(a).to(torch.bfloat16)
+    G = ctx.gram(buf.cuda()[:, :, :n], compute="bf16")
+    torch.cuda.synchronize()
+    assert np.array_equal(G.cpu().numpy(), orc.gram(a))
+
+
 def test_gram_bf16_float(ctx, orc):
     cnt, m, n = 12, 200, 150
     _say("gram bf16 float")

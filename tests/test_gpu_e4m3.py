@@ -76,6 +76,23 @@ def test_gram_e4m3_integer_exact(ctx, orc, shape):
     assert np.array_equal(G.cpu().numpy(), orc.gram(a))
 
 
+@pytest.mark.parametrize("shape", [(5, 300, 37), (70, 384, 136), (3, 260, 1000)])
+def test_gram_e4m3_padding_masked(ctx, orc, shape):
+    """An e4m3 stack whose padding bytes n .. ld-1 are NaN codes (0x7f): the
+    Gram reads only columns below n (whole 16-byte chunks are loaded and
+    what lies past n is masked, also in a stage's partial last chunk)."""
+    cnt, m, n = shape
+    _say(f"gram e4m3 NaN padding {shape}")
+    a = synth.integer_stack(cnt, m, n, seed=sum(shape) + 13)
+    st = ctx.stage(dev32(a, fill=0.0), "e4m3")
+    torch.cuda.synchronize()
+    assert st.data.shape[2] > n
+    st.data[:, :, n:] = 0x7F
+    G = ctx.gram(st, compute="e4m3")
+    torch.cuda.synchronize()
+    assert np.array_equal(G.cpu().numpy(), orc.gram(a))
+
+
 def test_gram_e4m3_float_scales_differ(ctx, orc):
     """Slices whose magnitudes span 4^11, so their scales differ: the Gram of
     every single slice (the scale folding, at every magnitude) and of the

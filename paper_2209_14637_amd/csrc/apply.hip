@@ -800,8 +800,8 @@ __device__ __forceinline__ void eig_body(const double *__restrict__ HX, const in
                                          float *__restrict__ sigma, double *__restrict__ relerr,
                                          int *__restrict__ flags, int64_t d) {
     constexpr int SZ = KP * KP;
-    __shared__ double H[SZ], Wt[SZ];
-    __shared__ double rot[KP];
+    __shared__ __align__(16) double H[SZ], Wt[SZ];
+    __shared__ __align__(16) double rot[KP];
     __shared__ double red4[4];
     __shared__ int perm[KP];
     __shared__ double s_lam[KP];
@@ -810,7 +810,7 @@ __device__ __forceinline__ void eig_body(const double *__restrict__ HX, const in
     for (int e = tid; e < SZ; e += 256) H[e] = Hg[e];
     __syncthreads();
     const int kk = k + (k & 1);  // even size for the parallel ordering
-    jacobi_eig_wg<(KP * (KP + 2) / 8 + 255) / 256, (KP * KP / 2 + 255) / 256>(H, Wt, kk, KP, rot, 40, red4);
+    jacobi_eig_wg<(KP * (KP + 2) / 8 + 255) / 256, (KP * KP / 4 + 255) / 256>(H, Wt, kk, KP, rot, 40, red4);
     // descending order: rank of each diagonal entry (ties by index)
     for (int i = tid; i < kk; i += 256) {
         const double hi = H[i * KP + i];

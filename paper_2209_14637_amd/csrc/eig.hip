@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void eig_filter_kernel(const double *__restric
                                                          double *__restrict__ Y2, double *__restrict__ part,
                                                          unsigned *counter, double *__restrict__ small,
                                                          double tol_chol) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     double *Zs = lds;  // RW_RB x pp
     const int64_t r0 = (int64_t)blockIdx.x * RW_RB;
     load_mv_rows(P, KS, m, pp, r0, Zs);
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void eig_apply_kernel(const double *__restrict
                                                         double *__restrict__ Out, int want_gram,
                                                         double *__restrict__ part, unsigned *counter,
                                                         double *__restrict__ small, double tol_chol) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     double *Rs = lds;              // pp x pp
     double *Is = Rs + pp * pp;     // RW_RB x pp
     double *Os = Is + RW_RB * pp;  // RW_RB x pp
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void eig_gxr_kernel(const double *__restrict__
                                                       const double *__restrict__ Y2, double *__restrict__ X,
                                                       double *__restrict__ GX, double *__restrict__ Y1,
                                                       const double *__restrict__ small) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     double *Rs = lds, *Zs = Rs + pp * pp, *Ys = Zs + RW_RB * pp;
     const int64_t r0 = (int64_t)blockIdx.x * RW_RB;
     for (int t = threadIdx.x; t < pp * pp; t += blockDim.x) Rs[t] = small[SM_RINV + t];
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void eig_gx_kernel(const double *__restrict__ 
                                                      const double *__restrict__ X, double *__restrict__ GX,
                                                      double *__restrict__ Y1, int rr, double *__restrict__ part,
                                                      unsigned *counter, double *__restrict__ small) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     double *Zs = lds, *Xs = lds + RW_RB * pp;
     const int64_t r0 = (int64_t)blockIdx.x * RW_RB;
     load_mv_rows(P, KS, m, pp, r0, Zs);
@@ -369,13 +369,13 @@ __global__ __launch_bounds__(256) void eig_gx_kernel(const double *__restrict__ 
     const int ntri = pp * (pp + 1) / 2;
     block_gram(Xs, Zs, pp, part + (int64_t)blockIdx.x * ntri);
     if (!last_block(counter)) return;
-    __shared__ double rot[EIG_MAXPP];
+    __shared__ __align__(16) double rot[EIG_MAXPP];
     __shared__ int perm[EIG_MAXPP];
     __shared__ double red4[4];
     double *H = lds, *W = lds + pp * pp, *Hn = lds + 2 * pp * pp;
     reduce_tri(part, gridDim.x, pp, H);
     (void)Hn;
-    jacobi_eig_wg<(EIG_MAXPP * (EIG_MAXPP + 2) / 8 + 255) / 256, (EIG_MAXPP * EIG_MAXPP / 2 + 255) / 256>(
+    jacobi_eig_wg<(EIG_MAXPP * (EIG_MAXPP + 2) / 8 + 255) / 256, (EIG_MAXPP * EIG_MAXPP / 4 + 255) / 256>(
         H, W, pp, pp, rot, 40, red4);  // W holds the eigenvectors transposed
     if (threadIdx.x == 0) sort_diag_desc(H, pp, pp, perm);
     __syncthreads();
@@ -402,7 +402,7 @@ __global__ __launch_bounds__(256) void eig_rot_kernel(int64_t m, int pp, int k, 
                                                       double *__restrict__ GX, double *__restrict__ Y1,
                                                       double *__restrict__ part, unsigned *counter,
                                                       double *__restrict__ small, double tol) {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     double *Ws = lds, *Xs = Ws + pp * pp, *Gs = Xs + RW_RB * pp, *Rs = Gs + RW_RB * pp;
     const int64_t r0 = (int64_t)blockIdx.x * RW_RB;
     for (int t = threadIdx.x; t < pp * pp; t += blockDim.x) Ws[t] = small[SM_W + t];

@@ -174,9 +174,12 @@ __device__ __forceinline__ void rr_pair(int t, int rd, int p, int &a, int &b) {
 // before its arithmetic.  Stops when the off-diagonal mass is below
 // 1e-18 ||H||_F^2: eigenvalues are then exact to rounding (their error is
 // second order in the off-diagonal part) and eigenvectors to 1e-9 of the
-// relative gap.  MAXB >= ceil(p(p+2)/8 / 256),
-// MAXW >= ceil(p^2/2 / 256).  On exit H is diagonal to rounding and
-// H_in = W diag W^T.  p even <= 64; rot: p doubles.
+// relative gap.  The round is bound by LDS instruction issue, so a rotation
+// is stored as one (c, s) pair and a W item covers two adjacent entries
+// (16-byte accesses).  MAXB >= ceil(p(p+2)/8 / 256),
+// MAXW >= ceil(p^2/4 / 256).  On exit H is diagonal to rounding and
+// H_in = W diag W^T.  p even <= 64, ld even; rot: p doubles; Wt and rot
+// 16-byte aligned.
 template <int MAXB, int MAXW>
 __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, double *rot, int max_sweeps,
                                      double *red4) {
@@ -224,12 +227,13 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
             bQ[u] = Q;
         }
     }
+    // W items: entry pairs (column 2c, 2c + 1) of the two rows of a slot
 #pragma unroll
     for (int u = 0; u < MAXW; ++u) {
         const int e = tid + 256 * u;
-        wv_[u] = e < p * half;
-        wI[u] = wv_[u] ? e % p : 0;
-        wQ[u] = wv_[u] ? e / p : 0;
+        wv_[u] = e < half * half;
+        wI[u] = wv_[u] ? 2 * (e % half) : 0;
+        wQ[u] = wv_[u] ? e / half : 0;
     }
     int tA = 0, tB = 1;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
@@ -256,8 +260,7 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
             if (tid < half) {
                 double cc, ss;
                 jacobi_rot(H, ld, tA, tB, cc, ss);
-                rot[2 * tid] = cc;
-                rot[2 * tid + 1] = ss;
+                *reinterpret_cast<double2 *>(rot + 2 * tid) = double2{cc, ss};
             }
             __syncthreads();
             // blocks: gather (unused slots read block (0, 0): in bounds,
@@ -266,8 +269,10 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
 #pragma unroll
             for (int u = 0; u < MAXB; ++u) {
                 const int a = bA[u], b = bB[u], x = bX[u], y = bY[u];
-                rv[u][0] = rot[2 * bP[u]]; rv[u][1] = rot[2 * bP[u] + 1];
-                rv[u][2] = rot[2 * bQ[u]]; rv[u][3] = rot[2 * bQ[u] + 1];
+                const double2 rp = *reinterpret_cast<const double2 *>(rot + 2 * bP[u]);
+                const double2 rq = *reinterpret_cast<const double2 *>(rot + 2 * bQ[u]);
+                rv[u][0] = rp.x; rv[u][1] = rp.y;
+                rv[u][2] = rq.x; rv[u][3] = rq.y;
                 hv[u][0] = H[a * ld + x]; hv[u][1] = H[a * ld + y];
                 hv[u][2] = H[b * ld + x]; hv[u][3] = H[b * ld + y];
             }
@@ -293,19 +298,22 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
                     }
                 }
             }
-            // W items: gather, compute, write
-            double wv[MAXW][2], wr[MAXW][2];
+            // W items: gather, compute, write (two adjacent entries of each row)
+            double2 w0v[MAXW], w1v[MAXW], wr[MAXW];
 #pragma unroll
             for (int u = 0; u < MAXW; ++u) {
-                wr[u][0] = rot[2 * wQ[u]]; wr[u][1] = rot[2 * wQ[u] + 1];
-                wv[u][0] = Wt[wX[u] * ld + wI[u]]; wv[u][1] = Wt[wY[u] * ld + wI[u]];
+                wr[u] = *reinterpret_cast<const double2 *>(rot + 2 * wQ[u]);
+                w0v[u] = *reinterpret_cast<const double2 *>(Wt + wX[u] * ld + wI[u]);
+                w1v[u] = *reinterpret_cast<const double2 *>(Wt + wY[u] * ld + wI[u]);
             }
 #pragma unroll
             for (int u = 0; u < MAXW; ++u) {
-                const double cq = wr[u][0], sq = wr[u][1], w0 = wv[u][0], w1 = wv[u][1];
+                const double cq = wr[u].x, sq = wr[u].y;
                 if (wv_[u]) {
-                    Wt[wX[u] * ld + wI[u]] = cq * w0 - sq * w1;
-                    Wt[wY[u] * ld + wI[u]] = sq * w0 + cq * w1;
+                    *reinterpret_cast<double2 *>(Wt + wX[u] * ld + wI[u]) =
+                        double2{cq * w0v[u].x - sq * w1v[u].x, cq * w0v[u].y - sq * w1v[u].y};
+                    *reinterpret_cast<double2 *>(Wt + wY[u] * ld + wI[u]) =
+                        double2{sq * w0v[u].x + cq * w1v[u].x, sq * w0v[u].y + cq * w1v[u].y};
                 }
             }
             // next round: every slot's indices advance

@@ -205,6 +205,9 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
     // items row-fastest, so neighbouring threads touch different rows AND
     // columns (the row stride may be a multiple of the LDS bank count)
     const int nblk = half * (half + 1) / 2;
+    // item slots that hold work for some thread (MAXB, MAXW cover the largest
+    // p; the loops below skip the rest, a uniform test)
+    const int nbu = (nblk + 255) / 256, nwu = (half * half + 255) / 256;
     bool bv[MAXB], wv_[MAXW];
     int bA[MAXB], bB[MAXB], bX[MAXB], bY[MAXB], bP[MAXB], bQ[MAXB];
     int wI[MAXW], wX[MAXW], wY[MAXW], wQ[MAXW];
@@ -268,6 +271,7 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
             double hv[MAXB][4], rv[MAXB][4];
 #pragma unroll
             for (int u = 0; u < MAXB; ++u) {
+                if (u >= nbu) break;
                 const int a = bA[u], b = bB[u], x = bX[u], y = bY[u];
                 const double2 rp = *reinterpret_cast<const double2 *>(rot + 2 * bP[u]);
                 const double2 rq = *reinterpret_cast<const double2 *>(rot + 2 * bQ[u]);
@@ -278,6 +282,7 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
             }
 #pragma unroll
             for (int u = 0; u < MAXB; ++u) {
+                if (u >= nbu) break;
                 const double cp = rv[u][0], sp = rv[u][1], cq = rv[u][2], sq = rv[u][3];
                 const double hax = hv[u][0], hay = hv[u][1], hbx = hv[u][2], hby = hv[u][3];
                 const double tax = cq * hax - sq * hay, tay = sq * hax + cq * hay;
@@ -302,12 +307,14 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
             double2 w0v[MAXW], w1v[MAXW], wr[MAXW];
 #pragma unroll
             for (int u = 0; u < MAXW; ++u) {
+                if (u >= nwu) break;
                 wr[u] = *reinterpret_cast<const double2 *>(rot + 2 * wQ[u]);
                 w0v[u] = *reinterpret_cast<const double2 *>(Wt + wX[u] * ld + wI[u]);
                 w1v[u] = *reinterpret_cast<const double2 *>(Wt + wY[u] * ld + wI[u]);
             }
 #pragma unroll
             for (int u = 0; u < MAXW; ++u) {
+                if (u >= nwu) break;
                 const double cq = wr[u].x, sq = wr[u].y;
                 if (wv_[u]) {
                     *reinterpret_cast<double2 *>(Wt + wX[u] * ld + wI[u]) =

@@ -994,8 +994,11 @@ __global__ __launch_bounds__(64) void project_f32_kernel(const float *__restrict
     xcd_band(blockIdx.x, count, nb, d, band);
     project_f32_body<NT>(A, m, n, ld, stride, Bm, ldv, C, d, band);
 }
+// two waves per SIMD (at most 256 VGPRs; left to itself the compiler took 260
+// for the e4m3 form and 288 for kp = 32, one wave per SIMD); kp = 64 would
+// spill under that bound and keeps one wave
 template <int MT, typename ET>
-__global__ __launch_bounds__(64) void sketch_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
+__global__ __launch_bounds__(64, MT < 4 ? 2 : 1) void sketch_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
                                                           int64_t m, int64_t n, int64_t ld, int64_t stride,
                                                           const uint16_t *__restrict__ Sb, int64_t mp,
                                                           float *__restrict__ B, uint16_t *__restrict__ Bb,
@@ -1068,7 +1071,7 @@ __global__ __launch_bounds__(64) void project_f32_multi(const ApDesc *__restrict
     project_f32_body<NT>((const float *)D.A, D.m, D.n, D.ld, D.stride, D.B, D.ldv, D.C, it.y, it.z);
 }
 template <int MT, typename ET>
-__global__ __launch_bounds__(64) void sketch_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+__global__ __launch_bounds__(64, MT < 4 ? 2 : 1) void sketch_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
     sketch_bf16_body<MT, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Sb, D.mp, D.B, D.Bb, D.ldv,

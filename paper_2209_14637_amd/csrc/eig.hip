@@ -27,6 +27,8 @@
 //  eig_emit   : S (k x m, FP32) from the converged Ritz vectors.
 // Reductions across workgroups go through per-workgroup partials summed in a
 // fixed order, so results are bitwise reproducible.
+#include <type_traits>
+
 #include "tsk_common.hpp"
 
 namespace {
@@ -103,13 +105,16 @@ __global__ void eig_init_kernel(double *Y, int64_t m, int pp, int p, double *sma
 }
 
 // P[ks][r0:r0+16][:] = G[r0:r0+16, K_ks] * In[K_ks, :]
-__global__ __launch_bounds__(256) void eig_mv_kernel(const double *__restrict__ G, int64_t m, int pp,
-                                                     const double *__restrict__ In, double *__restrict__ P,
-                                                     int64_t kchunk) {
+// (G and In without __restrict__: with it the compiler treats their loads as
+// invariant and sinks the next step's loads to their use, which leaves no
+// load in flight during the MFMAs)
+template <int NT>
+__global__ __launch_bounds__(256) void eig_mv_kernel(const double *G, int64_t m, int pp, const double *In,
+                                                     double *__restrict__ P, int64_t kchunk) {
     __shared__ double wpart[4 * MV_RB * EIG_MAXPP];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int q = lane >> 4, ii = lane & 15;
-    const int nt = pp >> 4;
+    const int nt = NT;
     const int64_t r0 = (int64_t)blockIdx.x * MV_RB;
     const int ks = blockIdx.y;
     const int64_t row = r0 + ii;
@@ -119,46 +124,68 @@ __global__ __launch_bounds__(256) void eig_mv_kernel(const double *__restrict__ 
     const int64_t kb = (int64_t)ks * kchunk + wv * kw;
     int64_t ke = kb + kw;
     if (ke > m) ke = m;
-    v4d acc[NT_MAX];
+    v4d acc[NT];
 #pragma unroll
-    for (int x = 0; x < NT_MAX; ++x) acc[x] = v4d{0.0, 0.0, 0.0, 0.0};
-    double a[4], b[4][NT_MAX];
-    auto load = [&](int64_t k0, double (&aa)[4], double (&bb)[4][NT_MAX]) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t kk = k0 + 4 * q + u;
-            const bool kv = kk < ke;
-            aa[u] = (rv && kv) ? grow[kk] : 0.0;
-            const double *yr = In + (kv ? kk : 0) * pp + ii;
-#pragma unroll
-            for (int x = 0; x < NT_MAX; ++x) bb[u][x] = (kv && x < nt) ? yr[x * 16] : 0.0;
-        }
-    };
-    if (kb < ke) load(kb, a, b);
-    for (int64_t k0 = kb; k0 < ke; k0 += 16) {
-        double an[4], bn[4][NT_MAX];
-        const bool more = k0 + 16 < ke;
-        if (more) load(k0 + 16, an, bn);
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int x = 0; x < NT_MAX; ++x)
-                if (x < nt) acc[x] = mfma16x16x4_f64(a[u], b[u][x], acc[x]);
-        if (more) {
+    for (int x = 0; x < NT; ++x) acc[x] = v4d{0.0, 0.0, 0.0, 0.0};
+    // whole steps of 16 and a row block inside m (uniform per wave): a loop
+    // whose loads carry no conditions, so the next step's stay in flight
+    // during this step's MFMAs; otherwise every load is guarded
+    const bool whole = r0 + MV_RB <= m && (ke - kb) % 16 == 0;
+    auto run = [&](auto whole_tag) {
+        constexpr bool WHOLE = decltype(whole_tag)::value;
+        auto load = [&](int64_t k0, double (&aa)[4], double (&bb)[4][NT]) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                a[u] = an[u];
+                const int64_t kk = k0 + 4 * q + u;
+                if constexpr (WHOLE) {
+                    aa[u] = grow[kk];
+                    const double *yr = In + kk * pp + ii;
 #pragma unroll
-                for (int x = 0; x < NT_MAX; ++x) b[u][x] = bn[u][x];
+                    for (int x = 0; x < NT; ++x) bb[u][x] = yr[x * 16];
+                } else {
+                    const bool kv = kk < ke;
+                    aa[u] = (rv && kv) ? grow[kk] : 0.0;
+                    const double *yr = In + (kv ? kk : 0) * pp + ii;
+#pragma unroll
+                    for (int x = 0; x < NT; ++x) bb[u][x] = kv ? yr[x * 16] : 0.0;
+                }
             }
+        };
+        auto mma = [&](const double (&aa)[4], const double (&bb)[4][NT]) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int x = 0; x < NT; ++x) acc[x] = mfma16x16x4_f64(aa[u], bb[u][x], acc[x]);
+        };
+        // two register sets used in turn (copying the next step's values
+        // into the current set would wait for its loads at once): steps in
+        // pairs, a0 holding the first of a pair, a1 the second
+        double a0[4], b0[4][NT], a1[4], b1[4][NT];
+        int64_t k0 = kb;
+        if (kb < ke) load(kb, a0, b0);
+        for (; k0 + 16 < ke; k0 += 32) {
+            load(k0 + 16, a1, b1);
+            // the loads above are issued here, ahead of the MFMAs
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+            mma(a0, b0);
+            // past the last step the loads repeat step k0 + 16 (in range, unused)
+            load(k0 + 32 < ke ? k0 + 32 : k0 + 16, a0, b0);
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+            mma(a1, b1);
         }
-    }
+        if (k0 < ke) mma(a0, b0);
+    };
+    if (whole)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
     // f64 result layout: lane holds D[q + 4r][ii]
 #pragma unroll
-    for (int x = 0; x < NT_MAX; ++x)
-        if (x < nt)
+    for (int x = 0; x < NT; ++x)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) wpart[(wv * 16 + q + 4 * r) * pp + x * 16 + ii] = acc[x][r];
+        for (int r = 0; r < 4; ++r) wpart[(wv * 16 + q + 4 * r) * pp + x * 16 + ii] = acc[x][r];
     __syncthreads();
     double *out = P + ((int64_t)ks * m + r0) * pp;
     for (int e = threadIdx.x; e < MV_RB * pp; e += blockDim.x) {
@@ -547,8 +574,16 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
     const dim3 gmv((unsigned)nmv, (unsigned)KS);
 
     auto mv = [&](const double *in) -> tsk_status {
-        TSK_LAUNCH(c, TSK_KERNEL_EIG_ITER,
-                   hipLaunchKernelGGL(eig_mv_kernel, gmv, dim3(256), 0, c->stream, G, m, pp, in, P, kchunk));
+#define TSK_MV(NTV)                                                                                     \
+    TSK_LAUNCH(c, TSK_KERNEL_EIG_ITER,                                                                  \
+               hipLaunchKernelGGL(eig_mv_kernel<NTV>, gmv, dim3(256), 0, c->stream, G, m, pp, in, P, kchunk))
+        switch (pp / 16) {  // pp is a multiple of 16, at most EIG_MAXPP
+            case 1: TSK_MV(1); break;
+            case 2: TSK_MV(2); break;
+            case 3: TSK_MV(3); break;
+            default: TSK_MV(4); break;
+        }
+#undef TSK_MV
         return TSK_OK;
     };
     auto apply = [&](const double *in, double *out, int gram) -> tsk_status {

@@ -395,15 +395,27 @@ __global__ __launch_bounds__(256) void eig_gx_kernel(const double *__restrict__ 
     if (!rr) return;
     const int ntri = pp * (pp + 1) / 2;
     block_gram(Xs, Zs, pp, part + (int64_t)blockIdx.x * ntri);
-    if (!last_block(counter)) return;
+}
+
+// Rayleigh-Ritz on the block: one workgroup of RR_THREADS threads sums the
+// nparts partial Grams (in order), diagonalizes the pp x pp projection by
+// cyclic Jacobi, and writes the Ritz vectors (descending) and values and the
+// damped interval of the next filter to small.  A kernel of its own, so the
+// Jacobi, which one workgroup runs while the rest of the GPU waits, has four
+// times the threads of a row workgroup.  lds: 2 pp^2 doubles.
+constexpr int RR_THREADS = 1024;
+__global__ __launch_bounds__(RR_THREADS) void eig_rr_kernel(const double *__restrict__ part, int nparts, int pp,
+                                                            int live, double *__restrict__ small) {
+    extern __shared__ __align__(16) double lds[];
     __shared__ __align__(16) double rot[EIG_MAXPP];
     __shared__ int perm[EIG_MAXPP];
-    __shared__ double red4[4];
-    double *H = lds, *W = lds + pp * pp, *Hn = lds + 2 * pp * pp;
-    reduce_tri(part, gridDim.x, pp, H);
-    (void)Hn;
-    jacobi_eig_wg<(EIG_MAXPP * (EIG_MAXPP + 2) / 8 + 255) / 256, (EIG_MAXPP * EIG_MAXPP / 4 + 255) / 256>(
-        H, W, pp, pp, rot, 40, red4);  // W holds the eigenvectors transposed
+    __shared__ double red[RR_THREADS / 64];
+    double *H = lds, *W = lds + pp * pp;
+    reduce_tri(part, nparts, pp, H);
+    jacobi_eig_wg<(EIG_MAXPP * (EIG_MAXPP + 2) / 8 + RR_THREADS - 1) / RR_THREADS,
+                  (EIG_MAXPP * EIG_MAXPP / 4 + RR_THREADS - 1) / RR_THREADS, RR_THREADS>(H, W, pp, pp, rot, 40,
+                                                                                        red);
+    // W holds the eigenvectors transposed
     if (threadIdx.x == 0) sort_diag_desc(H, pp, pp, perm);
     __syncthreads();
     for (int t = threadIdx.x; t < pp * pp; t += blockDim.x) {
@@ -554,7 +566,8 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
     const size_t lds_filter = sizeof(double) * (RW_RB * pp > 3 * pp * pp ? RW_RB * pp : 3 * pp * pp);
     const size_t lds_apply =
         sizeof(double) * (pp * pp + 2 * RW_RB * pp > 3 * pp * pp ? pp * pp + 2 * RW_RB * pp : 3 * pp * pp);
-    const size_t lds_gx = sizeof(double) * (2 * RW_RB * pp > 3 * pp * pp ? 2 * RW_RB * pp : 3 * pp * pp);
+    const size_t lds_gx = sizeof(double) * 2 * RW_RB * pp;
+    const size_t lds_rr = sizeof(double) * 2 * pp * pp;
     const size_t lds_rot = sizeof(double) * (pp * pp + 3 * RW_RB * pp);
     {
         hipError_t a1 = hipFuncSetAttribute((const void *)eig_filter_kernel,
@@ -565,6 +578,9 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_gx);
         hipError_t a4 = hipFuncSetAttribute((const void *)eig_rot_kernel,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_rot);
+        if (a4 == hipSuccess)
+            a4 = hipFuncSetAttribute((const void *)eig_rr_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_rr);
         if (a1 != hipSuccess || a2 != hipSuccess || a3 != hipSuccess || a4 != hipSuccess)
             return tsk_hip(c, a1 != hipSuccess ? a1 : a2 != hipSuccess ? a2 : a3 != hipSuccess ? a3 : a4,
                            "LDS attribute");
@@ -596,6 +612,10 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
         TSK_LAUNCH(c, rr ? TSK_KERNEL_EIG_RR : TSK_KERNEL_EIG_ITER,
                    hipLaunchKernelGGL(eig_gx_kernel, dim3(nrw), dim3(256), lds_gx, c->stream, (const double *)P, KS,
                                       m, pp, p, (const double *)X, GX, Y1, rr, part, counter, small));
+        if (rr)
+            TSK_LAUNCH(c, TSK_KERNEL_EIG_RR,
+                       hipLaunchKernelGGL(eig_rr_kernel, dim3(1), dim3(RR_THREADS), lds_rr, c->stream,
+                                          (const double *)part, nrw, pp, p, small));
         return TSK_OK;
     };
     auto rot = [&]() -> tsk_status {

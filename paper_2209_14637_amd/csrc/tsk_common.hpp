@@ -91,6 +91,21 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
+// Block-wide FP64 sum over NW waves (blockDim.x == 64 NW), the wave sums
+// added in wave order; result valid in every thread.  scratch: NW doubles.
+template <int NW>
+__device__ __forceinline__ double block_sum_nw(double v, double *scratch) {
+    v = wave_sum_f64(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) scratch[w] = v;
+    __syncthreads();
+    double t = scratch[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) t += scratch[i];
+    __syncthreads();
+    return t;
+}
+
 // Block-wide FP64 sum for blockDim.x == 256; result valid in every thread.
 __device__ __forceinline__ double block_sum_f64(double v, double *scratch4) {
     v = wave_sum_f64(v);
@@ -162,8 +177,9 @@ __device__ __forceinline__ void rr_pair(int t, int rd, int p, int &a, int &b) {
 }
 
 // Cyclic Jacobi for a symmetric p x p FP64 matrix in LDS, one workgroup of
-// 256 threads, in place.  Each round rotates the p/2 disjoint pairs of the
-// round-robin ordering: the rotations are computed by p/2 threads into rot,
+// NTH threads (256 or 1024), in place.  Each round rotates the p/2 disjoint
+// pairs of the round-robin ordering: the rotations are computed by p/2
+// threads into rot,
 // then every 2x2 block (P, Q), P <= Q, of J^T H J is rewritten by one thread
 // together with its mirror image (the blocks are disjoint, so no second
 // buffer is needed) and the eigenvector matrix is updated, W <- W J, stored
@@ -174,25 +190,24 @@ __device__ __forceinline__ void rr_pair(int t, int rd, int p, int &a, int &b) {
 // before its arithmetic.  Stops when the off-diagonal mass is below
 // 1e-18 ||H||_F^2: eigenvalues are then exact to rounding (their error is
 // second order in the off-diagonal part) and eigenvectors to 1e-9 of the
-// relative gap.  The round is bound by LDS instruction issue, so a rotation
-// is stored as one (c, s) pair and a W item covers two adjacent entries
-// (16-byte accesses).  MAXB >= ceil(p(p+2)/8 / 256),
-// MAXW >= ceil(p^2/4 / 256).  On exit H is diagonal to rounding and
+// relative gap.  A rotation is stored as one (c, s) pair and a W item
+// covers two adjacent entries (16-byte accesses).  MAXB >= ceil(p(p+2)/8 /
+// NTH), MAXW >= ceil(p^2/4 / NTH).  On exit H is diagonal to rounding and
 // H_in = W diag W^T.  p even <= 64, ld even; rot: p doubles; Wt and rot
-// 16-byte aligned.
-template <int MAXB, int MAXW>
+// 16-byte aligned; red: NTH/64 doubles.
+template <int MAXB, int MAXW, int NTH = 256>
 __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, double *rot, int max_sweeps,
                                      double *red4) {
     const int tid = threadIdx.x;
     const int half = p / 2;
     double tot = 0.0;
-    for (int e = tid; e < p * p; e += 256) {
+    for (int e = tid; e < p * p; e += NTH) {
         const int i = e / p, j = e % p;
         Wt[i * ld + j] = (i == j) ? 1.0 : 0.0;
         const double h = H[i * ld + j];
         tot += h * h;
     }
-    tot = block_sum_f64(tot, red4);
+    tot = block_sum_nw<NTH / 64>(tot, red4);
     // slot -> indices at round 0 (rr_pair(t, 0)); ordered pairs (first,
     // second) are kept as produced, the rotation convention only needs the
     // same order in every use
@@ -207,7 +222,7 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
     const int nblk = half * (half + 1) / 2;
     // item slots that hold work for some thread (MAXB, MAXW cover the largest
     // p; the loops below skip the rest, a uniform test)
-    const int nbu = (nblk + 255) / 256, nwu = (half * half + 255) / 256;
+    const int nbu = (nblk + NTH - 1) / NTH, nwu = (half * half + NTH - 1) / NTH;
     bool bv[MAXB], wv_[MAXW];
     int bA[MAXB], bB[MAXB], bX[MAXB], bY[MAXB], bP[MAXB], bQ[MAXB];
     int wI[MAXW], wX[MAXW], wY[MAXW], wQ[MAXW];
@@ -215,7 +230,7 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
         int dg = 0, off = 0;
 #pragma unroll
         for (int u = 0; u < MAXB; ++u) {
-            const int e = tid + 256 * u;
+            const int e = tid + NTH * u;
             int P = 0, Q = 0;
             bv[u] = e < nblk;
             if (bv[u]) {
@@ -233,7 +248,7 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
     // W items: entry pairs (column 2c, 2c + 1) of the two rows of a slot
 #pragma unroll
     for (int u = 0; u < MAXW; ++u) {
-        const int e = tid + 256 * u;
+        const int e = tid + NTH * u;
         wv_[u] = e < half * half;
         wI[u] = wv_[u] ? 2 * (e % half) : 0;
         wQ[u] = wv_[u] ? e / half : 0;
@@ -241,12 +256,12 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
     int tA = 0, tB = 1;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         double off = 0.0;
-        for (int e = tid; e < p * p; e += 256) {
+        for (int e = tid; e < p * p; e += NTH) {
             const int i = e / p, j = e % p;
             const double h = H[i * ld + j];
             if (i != j) off += h * h;
         }
-        off = block_sum_f64(off, red4);
+        off = block_sum_nw<NTH / 64>(off, red4);
         if (off <= 1e-18 * tot || tot == 0.0) break;
         // indices of every slot at round 0 (the cycle returns there after
         // p - 1 rounds)

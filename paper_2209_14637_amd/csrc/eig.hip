@@ -225,16 +225,30 @@ __device__ inline void load_mv_rows(const double *__restrict__ P, int KS, int64_
 }
 
 // Upper triangle of A^T B over the block's rows (A, B: RW_RB x pp in LDS)
-// into part (ntri doubles).
+// into part (ntri doubles, row-major upper triangle).  FP64 MFMA 16x16x4:
+// the 16x16 tile pairs (ta <= tb) are dealt to the four waves, K runs over
+// the rows in steps of 4 (lane (q, i) supplies A[k0 + q][16 ta + i] and
+// B[k0 + q][16 tb + i]; the result lane holds D[q + 4r][i]).
 __device__ inline void block_gram(const double *As, const double *Bs, int pp, double *part) {
-    const int ntri = pp * (pp + 1) / 2;
-    for (int e = threadIdx.x; e < ntri; e += blockDim.x) {
-        int a, b;
-        tri_index(e, pp, a, b);
-        double s = 0.0;
-#pragma unroll 8
-        for (int i = 0; i < RW_RB; ++i) s += As[i * pp + a] * Bs[i * pp + b];
-        part[e] = s;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = lane >> 4, ii = lane & 15;
+    const int nt = pp >> 4, npair = nt * (nt + 1) / 2;
+    for (int pr = wv; pr < npair; pr += (int)(blockDim.x >> 6)) {
+        int ta = 0, rem = pr;
+        while (rem >= nt - ta) {
+            rem -= nt - ta;
+            ++ta;
+        }
+        const int tb = ta + rem;
+        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k0 = 0; k0 < RW_RB; k0 += 4)
+            acc = mfma16x16x4_f64(As[(k0 + q) * pp + 16 * ta + ii], Bs[(k0 + q) * pp + 16 * tb + ii], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ga = 16 * ta + q + 4 * r, gb = 16 * tb + ii;
+            if (ga <= gb) part[ga * pp - ga * (ga - 1) / 2 + (gb - ga)] = acc[r];
+        }
     }
 }
 

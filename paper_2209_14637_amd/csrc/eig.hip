@@ -17,11 +17,14 @@
 //  eig_mv     : P = G In, FP64 MFMA 16x16x4, grid = 16-row blocks x K-splits,
 //               operands prefetched one step ahead.
 //  eig_filter : sums the K-split partials, Y2 = 2/e (G Y1 - c Y1) - X,
-//               partial Gram of Y2; the last workgroup (ticket counter)
-//               reduces the partials and runs Cholesky + triangular inverse.
-//  eig_apply  : Out = In Rinv (+ partial Gram and last-workgroup Cholesky).
+//               partial Gram of Y2.
+//  eig_apply  : Out = In Rinv (+ partial Gram).
+//  eig_chol   : one 1024-thread workgroup: sums the partial Grams in order,
+//               Cholesky + triangular inverse -> Rinv.
 //  eig_gx     : GX = G X, Y1 = (GX - c X)/e, or the Rayleigh-Ritz variant:
-//               partial X^T G X, last workgroup runs the Jacobi eigensolver.
+//               partial X^T G X.
+//  eig_rr     : one 1024-thread workgroup: sums the partials of X^T G X and
+//               runs the Jacobi eigensolver.
 //  eig_rot    : X <- X W, GX <- GX W (Ritz vectors), Y1, residuals and the
 //               sign convention; last workgroup sets the convergence flag.
 //  eig_emit   : S (k x m, FP32) from the converged Ritz vectors.
@@ -35,6 +38,7 @@ namespace {
 
 constexpr int MV_RB = 16;      // rows per matvec workgroup (one MFMA tile)
 constexpr int RW_RB = 64;      // rows per row-kernel workgroup
+constexpr int RR_THREADS = 1024;  // threads of the one-workgroup small-matrix kernels
 constexpr int EIG_MAXPP = 64;  // largest padded block
 constexpr int NT_MAX = EIG_MAXPP / 16;
 
@@ -285,12 +289,12 @@ __device__ inline void chol_inverse(double *C, int pp, double tol_rel, double *l
 // Row kernels (RW_RB rows per workgroup, 256 threads)
 // ---------------------------------------------------------------------------
 
-// Y2 = 2/e (G Y1 - c Y1) - X; Gram(Y2) -> Cholesky -> Rinv
+// Y2 = 2/e (G Y1 - c Y1) - X; partial Gram(Y2) (the Cholesky follows in
+// eig_chol_kernel)
 __global__ __launch_bounds__(256) void eig_filter_kernel(const double *__restrict__ P, int KS, int64_t m, int pp,
                                                          const double *__restrict__ Y1, const double *__restrict__ X,
                                                          double *__restrict__ Y2, double *__restrict__ part,
-                                                         unsigned *counter, double *__restrict__ small,
-                                                         double tol_chol) {
+                                                         const double *__restrict__ small) {
     extern __shared__ __align__(16) double lds[];
     double *Zs = lds;  // RW_RB x pp
     const int64_t r0 = (int64_t)blockIdx.x * RW_RB;
@@ -311,17 +315,12 @@ __global__ __launch_bounds__(256) void eig_filter_kernel(const double *__restric
     __syncthreads();
     const int ntri = pp * (pp + 1) / 2;
     block_gram(Zs, Zs, pp, part + (int64_t)blockIdx.x * ntri);
-    if (!last_block(counter)) return;
-    double *C = lds;
-    reduce_tri(part, gridDim.x, pp, C);
-    chol_inverse(C, pp, tol_chol, lds + pp * pp, small + SM_RINV);
 }
 
-// Out = In Rinv; optionally Gram(Out) -> Cholesky -> Rinv (new)
+// Out = In Rinv; optionally Gram(Out) (the Cholesky follows in eig_chol_kernel)
 __global__ __launch_bounds__(256) void eig_apply_kernel(const double *__restrict__ In, int64_t m, int pp,
                                                         double *__restrict__ Out, int want_gram,
-                                                        double *__restrict__ part, unsigned *counter,
-                                                        double *__restrict__ small, double tol_chol) {
+                                                        double *__restrict__ part, const double *__restrict__ small) {
     extern __shared__ __align__(16) double lds[];
     double *Rs = lds;              // pp x pp
     double *Is = Rs + pp * pp;     // RW_RB x pp
@@ -344,9 +343,17 @@ __global__ __launch_bounds__(256) void eig_apply_kernel(const double *__restrict
     __syncthreads();
     const int ntri = pp * (pp + 1) / 2;
     block_gram(Os, Os, pp, part + (int64_t)blockIdx.x * ntri);
-    if (!last_block(counter)) return;
+}
+
+// Sum of the nparts partial Grams (in order) -> Cholesky -> Rinv, by one
+// workgroup of RR_THREADS threads in a kernel of its own (it ran as the last
+// row workgroup, 256 threads, while the rest of the GPU waited).  lds: 3 pp^2
+// doubles.
+__global__ __launch_bounds__(RR_THREADS) void eig_chol_kernel(const double *__restrict__ part, int nparts, int pp,
+                                                              double *__restrict__ small, double tol_chol) {
+    extern __shared__ __align__(16) double lds[];
     double *C = lds;
-    reduce_tri(part, gridDim.x, pp, C);
+    reduce_tri(part, nparts, pp, C);
     chol_inverse(C, pp, tol_chol, lds + pp * pp, small + SM_RINV);
 }
 
@@ -384,13 +391,12 @@ __global__ __launch_bounds__(256) void eig_gxr_kernel(const double *__restrict__
     }
 }
 
-// GX = G X.  rr = 0: Y1 = (GX - c X)/e.  rr = 1: partial X^T GX, and the last
-// workgroup diagonalises H = X^T G X -> W (columns in descending order), theta,
-// and the next filter interval.
+// GX = G X.  rr = 0: Y1 = (GX - c X)/e.  rr = 1: partial X^T GX per
+// workgroup (eig_rr_kernel sums them and diagonalises).
 __global__ __launch_bounds__(256) void eig_gx_kernel(const double *__restrict__ P, int KS, int64_t m, int pp, int live,
                                                      const double *__restrict__ X, double *__restrict__ GX,
                                                      double *__restrict__ Y1, int rr, double *__restrict__ part,
-                                                     unsigned *counter, double *__restrict__ small) {
+                                                     const double *__restrict__ small) {
     extern __shared__ __align__(16) double lds[];
     double *Zs = lds, *Xs = lds + RW_RB * pp;
     const int64_t r0 = (int64_t)blockIdx.x * RW_RB;
@@ -417,7 +423,6 @@ __global__ __launch_bounds__(256) void eig_gx_kernel(const double *__restrict__ 
 // damped interval of the next filter to small.  A kernel of its own, so the
 // Jacobi, which one workgroup runs while the rest of the GPU waits, has four
 // times the threads of a row workgroup.  lds: 2 pp^2 doubles.
-constexpr int RR_THREADS = 1024;
 __global__ __launch_bounds__(RR_THREADS) void eig_rr_kernel(const double *__restrict__ part, int nparts, int pp,
                                                             int live, double *__restrict__ small) {
     extern __shared__ __align__(16) double lds[];
@@ -577,11 +582,11 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
     hipError_t e = hipMemsetAsync(c->counters.p, 0, 256, c->stream);
     if (e != hipSuccess) return tsk_hip(c, e, "memset");
 
-    const size_t lds_filter = sizeof(double) * (RW_RB * pp > 3 * pp * pp ? RW_RB * pp : 3 * pp * pp);
-    const size_t lds_apply =
-        sizeof(double) * (pp * pp + 2 * RW_RB * pp > 3 * pp * pp ? pp * pp + 2 * RW_RB * pp : 3 * pp * pp);
+    const size_t lds_filter = sizeof(double) * RW_RB * pp;
+    const size_t lds_apply = sizeof(double) * (pp * pp + 2 * RW_RB * pp);
     const size_t lds_gx = sizeof(double) * 2 * RW_RB * pp;
     const size_t lds_rr = sizeof(double) * 2 * pp * pp;
+    const size_t lds_chol = sizeof(double) * 3 * pp * pp;
     const size_t lds_rot = sizeof(double) * (pp * pp + 3 * RW_RB * pp);
     {
         hipError_t a1 = hipFuncSetAttribute((const void *)eig_filter_kernel,
@@ -595,6 +600,9 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
         if (a4 == hipSuccess)
             a4 = hipFuncSetAttribute((const void *)eig_rr_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds_rr);
+        if (a4 == hipSuccess)
+            a4 = hipFuncSetAttribute((const void *)eig_chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_chol);
         if (a1 != hipSuccess || a2 != hipSuccess || a3 != hipSuccess || a4 != hipSuccess)
             return tsk_hip(c, a1 != hipSuccess ? a1 : a2 != hipSuccess ? a2 : a3 != hipSuccess ? a3 : a4,
                            "LDS attribute");
@@ -616,16 +624,23 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
 #undef TSK_MV
         return TSK_OK;
     };
+    auto chol = [&]() -> tsk_status {
+        TSK_LAUNCH(c, TSK_KERNEL_EIG_ITER,
+                   hipLaunchKernelGGL(eig_chol_kernel, dim3(1), dim3(RR_THREADS), lds_chol, c->stream,
+                                      (const double *)part, nrw, pp, small, tol_chol));
+        return TSK_OK;
+    };
     auto apply = [&](const double *in, double *out, int gram) -> tsk_status {
         TSK_LAUNCH(c, TSK_KERNEL_EIG_ITER,
                    hipLaunchKernelGGL(eig_apply_kernel, dim3(nrw), dim3(256), lds_apply, c->stream, in, m, pp, out,
-                                      gram, part, counter, small, tol_chol));
-        return TSK_OK;
+                                      gram, part, (const double *)small));
+        return gram ? chol() : TSK_OK;
     };
     auto gx = [&](int rr) -> tsk_status {
         TSK_LAUNCH(c, rr ? TSK_KERNEL_EIG_RR : TSK_KERNEL_EIG_ITER,
                    hipLaunchKernelGGL(eig_gx_kernel, dim3(nrw), dim3(256), lds_gx, c->stream, (const double *)P, KS,
-                                      m, pp, p, (const double *)X, GX, Y1, rr, part, counter, small));
+                                      m, pp, p, (const double *)X, GX, Y1, rr, part,
+                                      (const double *)small));
         if (rr)
             TSK_LAUNCH(c, TSK_KERNEL_EIG_RR,
                        hipLaunchKernelGGL(eig_rr_kernel, dim3(1), dim3(RR_THREADS), lds_rr, c->stream,
@@ -652,7 +667,8 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
         TSK_LAUNCH(c, TSK_KERNEL_EIG_ITER,
                    hipLaunchKernelGGL(eig_filter_kernel, dim3(nrw), dim3(256), lds_filter, c->stream,
                                       (const double *)P, KS, m, pp, (const double *)Y1, (const double *)X, Y2, part,
-                                      counter, small, tol_chol));
+                                      (const double *)small));
+        TSK_TRY(chol());
         if (!rr) {
             TSK_TRY(mv(Y2));
             TSK_LAUNCH(c, TSK_KERNEL_EIG_ITER,

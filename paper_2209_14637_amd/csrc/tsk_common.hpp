@@ -463,8 +463,8 @@ __device__ inline int chol_factor_inverse(double *C, int ld, int pp, double tol_
     }
     __syncthreads();
     const double thr = tol_rel * s_maxd;
-    // each thread owns the upper-triangle entries e = tid + 256 u of the
-    // pp x pp matrix (u < 16 covers pp <= 64)
+    // each thread owns the upper-triangle entries e = tid + blockDim.x u of
+    // the pp x pp matrix (u < 16 covers pp <= 64 from 256 threads up)
     int ea[16], eb[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {

@@ -166,8 +166,11 @@ class Context:
         s = _stack(A)
         if s.dtype != TSK_F32:
             raise TypeError("stage() takes an FP32 stack")
-        per16 = 8 if dtype == "bf16" else 16
-        ld = (s.n + per16 - 1) // per16 * per16
+        # rows start on 128-byte cache lines: with a stride that is only a
+        # multiple of 16 bytes, a 256-byte row segment spans three lines and
+        # the streaming kernels lose about a quarter of their read rate
+        per128 = 64 if dtype == "bf16" else 128
+        ld = (s.n + per128 - 1) // per128 * per128
         tdt = torch.bfloat16 if dtype == "bf16" else torch.uint8
         dev = A.device
         out = torch.empty((s.count, s.m, ld), dtype=tdt, device=dev)

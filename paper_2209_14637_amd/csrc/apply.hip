@@ -276,13 +276,26 @@ __device__ __forceinline__ void sketch_step(const v4u (&x)[8], const v4u (&sh)[M
     }
 }
 
+// Steps kept in flight by a sketch wave.  A step issues 8 row loads and
+// 2 MT loads of the S pair (a wave has at most 63 vector memory instructions
+// outstanding) and holds 8 x 16 (bf16) or 8 x 8 (e4m3) bytes of rows plus
+// MT x 32 bytes of S per lane; the ring stays within about 200 of the 256
+// VGPRs (the accumulators live in AGPRs), beyond which the compiler moves
+// slots through copies that wait on the loads in flight.
+template <int MT, typename ET>
+constexpr int sk_ring() {
+    return sizeof(ET) == 2 ? (MT == 1 ? 5 : MT == 2 ? 4 : 3) : (MT == 1 ? 6 : MT == 2 ? 5 : MT == 3 ? 4 : 3);
+}
+
 // B_d = S A_d.  The contraction runs over the rows of A_d, but an MFMA lane
 // needs 8 consecutive contraction indices: lane (q, i) loads 16 bytes (8
 // columns) from each of the 8 rows r0 + 8q + e and transposes the block in
 // registers (sketch_step).  One wave covers 128 columns, 32 rows per step.
 // Whole steps of a panel whose lanes each hold 8 columns wholly inside or
-// wholly outside [0, n) use unconditional loads, with the next step's rows
-// and S pair in flight during this step's MFMAs; the last partial step, and
+// wholly outside [0, n) use unconditional loads, with the rows and S pair of
+// the next sk_ring<MT, ET>() - 1 steps in flight during this step's MFMAs (one
+// wave per SIMD: the ring takes most of the 512 registers a lone wave
+// has); the last partial step, and
 // every step of a panel that splits a lane's 8 columns at n, load element by
 // element.
 template <int MT, typename ET>
@@ -310,44 +323,68 @@ __device__ __forceinline__ void sketch_bf16_body(const ET *__restrict__ A, const
     int64_t r0 = 0;
     const int64_t mfull = m & ~(int64_t)31;
     if (__all(!any || c8 + 8 <= n) && mfull > 0) {
-        raw8_t<ET> x[8];
-        v4u sh[MT], sl[MT];
+        // ring of D steps in flight: step s sits in slot s % D and is reloaded
+        // D steps ahead right after its MFMAs; reloads past the last whole
+        // step repeat it (in range, unused)
+        constexpr int D = sk_ring<MT, ET>();
+        const int64_t nst = mfull >> 5;
+        raw8_t<ET> x[D][8];
+        v4u sh[D][MT], sl[D][MT];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = raw8(Ad + (int64_t)(8 * q + e) * ld);
+        for (int j = 0; j < D; ++j) {
+            const int64_t rs = (j < nst ? (int64_t)j : nst - 1) * 32;
 #pragma unroll
-        for (int a = 0; a < MT; ++a) {
-            sh[a] = *reinterpret_cast<const v4u *>(Sh + (int64_t)a * 16 * mp);
-            sl[a] = *reinterpret_cast<const v4u *>(Sl + (int64_t)a * 16 * mp);
-        }
-        for (; r0 < mfull; r0 += 32) {
-            // the last whole step loads its own rows again (in range, unused)
-            const int64_t rn = r0 + 32 < mfull ? r0 + 32 : r0;
-            raw8_t<ET> nx[8];
-            v4u nsh[MT], nsl[MT];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) nx[e] = raw8(Ad + (rn + 8 * q + e) * ld);
+            for (int e = 0; e < 8; ++e) x[j][e] = raw8(Ad + (rs + 8 * q + e) * ld);
 #pragma unroll
             for (int a = 0; a < MT; ++a) {
-                nsh[a] = *reinterpret_cast<const v4u *>(Sh + (int64_t)a * 16 * mp + rn);
-                nsl[a] = *reinterpret_cast<const v4u *>(Sl + (int64_t)a * 16 * mp + rn);
-            }
-            // the loads above are issued here, before this step's MFMAs (the
-            // compiler would otherwise move them after the MFMAs or re-issue
-            // them next to their use)
-            asm volatile("" ::: "memory");
-            __builtin_amdgcn_sched_barrier(0);
-            v4u xb[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) xb[e] = any ? widen8(x[e], inv) : v4u{0u, 0u, 0u, 0u};
-            sketch_step<MT>(xb, sh, sl, acc, fro);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) x[e] = nx[e];
-#pragma unroll
-            for (int a = 0; a < MT; ++a) {
-                sh[a] = nsh[a];
-                sl[a] = nsl[a];
+                sh[j][a] = *reinterpret_cast<const v4u *>(Sh + (int64_t)a * 16 * mp + rs);
+                sl[j][a] = *reinterpret_cast<const v4u *>(Sl + (int64_t)a * 16 * mp + rs);
             }
         }
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        int64_t s0 = 0;
+        for (; s0 + D <= nst; s0 += D) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                v4u xb[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) xb[e] = any ? widen8(x[j][e], inv) : v4u{0u, 0u, 0u, 0u};
+                sketch_step<MT>(xb, sh[j], sl[j], acc, fro);
+                // the reloads may not move above the slot's last MFMAs (its
+                // S pair would need a second register set and copies): the
+                // accumulators are taken as operands of an empty asm first
+#pragma unroll
+                for (int a = 0; a < MT; ++a)
+                    asm volatile("" ::"a"(acc[a][0]), "a"(acc[a][1]), "a"(acc[a][2]), "a"(acc[a][3]),
+                                 "a"(acc[a][4]), "a"(acc[a][5]), "a"(acc[a][6]), "a"(acc[a][7])
+                                 : "memory");
+                __builtin_amdgcn_sched_barrier(0);
+                const int64_t sn = s0 + j + D, rs = (sn < nst ? sn : nst - 1) * 32;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[j][e] = raw8(Ad + (rs + 8 * q + e) * ld);
+#pragma unroll
+                for (int a = 0; a < MT; ++a) {
+                    sh[j][a] = *reinterpret_cast<const v4u *>(Sh + (int64_t)a * 16 * mp + rs);
+                    sl[j][a] = *reinterpret_cast<const v4u *>(Sl + (int64_t)a * 16 * mp + rs);
+                }
+                // the reloads are issued here (the compiler would otherwise
+                // sink them to their use one ring turn later)
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // the last nst - s0 (< D) steps are in slots 0 .. nst - s0 - 1
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (s0 + j < nst) {
+                v4u xb[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) xb[e] = any ? widen8(x[j][e], inv) : v4u{0u, 0u, 0u, 0u};
+                sketch_step<MT>(xb, sh[j], sl[j], acc, fro);
+            }
+        }
+        r0 = mfull;
     }
     for (; r0 < m; r0 += 32) {
         v4u x[8], sh[MT], sl[MT];
@@ -994,11 +1031,10 @@ __global__ __launch_bounds__(64) void project_f32_kernel(const float *__restrict
     xcd_band(blockIdx.x, count, nb, d, band);
     project_f32_body<NT>(A, m, n, ld, stride, Bm, ldv, C, d, band);
 }
-// two waves per SIMD (at most 256 VGPRs; left to itself the compiler took 260
-// for the e4m3 form and 288 for kp = 32, one wave per SIMD); kp = 64 would
-// spill under that bound and keeps one wave
+// one wave per SIMD: its register ring keeps several steps of rows in
+// flight (HBM latency under load is several microseconds)
 template <int MT, typename ET>
-__global__ __launch_bounds__(64, MT < 4 ? 2 : 1) void sketch_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
+__global__ __launch_bounds__(64, 1) void sketch_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
                                                           int64_t m, int64_t n, int64_t ld, int64_t stride,
                                                           const uint16_t *__restrict__ Sb, int64_t mp,
                                                           float *__restrict__ B, uint16_t *__restrict__ Bb,
@@ -1071,7 +1107,7 @@ __global__ __launch_bounds__(64) void project_f32_multi(const ApDesc *__restrict
     project_f32_body<NT>((const float *)D.A, D.m, D.n, D.ld, D.stride, D.B, D.ldv, D.C, it.y, it.z);
 }
 template <int MT, typename ET>
-__global__ __launch_bounds__(64, MT < 4 ? 2 : 1) void sketch_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+__global__ __launch_bounds__(64, 1) void sketch_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
     sketch_bf16_body<MT, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Sb, D.mp, D.B, D.Bb, D.ldv,

@@ -1042,10 +1042,12 @@ __global__ __launch_bounds__(64, 1) void sketch_bf16_kernel(const ET *__restrict
     sketch_bf16_body<MT, ET>(A, scale, m, n, ld, stride, Sb, mp, B, Bb, ldb, fro_part, npanel, blockIdx.y,
                              blockIdx.x);
 }
-// Columns per projection step: 128 (256-byte bf16 rows; LDS 60 KB at kp = 48,
-// two workgroups per CU, which measured faster than 256 columns at one).
+// Columns per projection step: 64 for bf16 (LDS 37 KB and 112 VGPRs at
+// kp = 48: four workgroups per CU, 5% faster than 128 columns at two, which
+// measured faster than 256 at one; keeping two steps of loads in flight
+// instead of one gained nothing), 128 for e4m3 (also 128-byte segments).
 template <typename ET>
-constexpr int pjl_k() { return 128; }
+constexpr int pjl_k() { return sizeof(ET) == 2 ? 64 : 128; }
 
 // two workgroups per CU (at most 256 VGPRs, which the C^T C epilogue would
 // otherwise exceed at kp = 64)

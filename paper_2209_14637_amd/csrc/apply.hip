@@ -783,7 +783,7 @@ __device__ __forceinline__ void factor_body(const float *__restrict__ B, int64_t
     for (int e = tid; e < SZ; e += 256) b0[e] = 0.0;
     __syncthreads();
     gram_mfma_acc<KP / 16, true>(Bd, ldb, n, b0, KP);
-    const int nd = chol_factor_inverse(b0, KP, KP, 1e-12, b1, b2, dead, k);  // X = R^-1 in b2
+    const int nd = chol_factor_inverse<(KP * KP + 255) / 256>(b0, KP, KP, 1e-12, b1, b2, dead, k);  // X = R^-1 in b2
     for (int e = tid; e < SZ; e += 256) b0[e] = 0.0;
     __syncthreads();
     if (ctc) {

@@ -281,7 +281,7 @@ __device__ inline void reduce_tri(const double *__restrict__ part, int nparts, i
 __device__ inline void chol_inverse(double *C, int pp, double tol_rel, double *lds, double *Rinv) {
     __shared__ int dead[EIG_MAXPP];
     double *R = lds, *X = lds + pp * pp;
-    chol_factor_inverse(C, pp, pp, tol_rel, R, X, dead);
+    chol_factor_inverse<(EIG_MAXPP * EIG_MAXPP + RR_THREADS - 1) / RR_THREADS>(C, pp, pp, tol_rel, R, X, dead);
     for (int e = threadIdx.x; e < pp * pp; e += blockDim.x) Rinv[e] = X[e];
 }
 

@@ -444,58 +444,75 @@ __device__ inline void upper_tri_inverse(const double *R, double *X, int pp, dou
 
 // ---------------------------------------------------------------------------
 // Cholesky C = R^T R of a symmetric positive semi-definite pp x pp matrix in
-// LDS (row stride ld; only the upper triangle is read, C is destroyed), one
-// barrier per column, then X = R^-1 (LDS, stride pp).  A pivot <=
-// tol_rel * max(diag) marks the index dead: its row of R and its row and
-// column of X are zero.  R, X: LDS pp*pp each; dead: LDS pp ints.  Returns (in
-// every thread) the number of dead indices below `live`.
+// LDS (row stride ld; only the upper triangle is read, C is destroyed), then
+// X = R^-1 (LDS, stride pp).  A pivot <= tol_rel * max(diag) marks the index
+// dead: its row of R and its row and column of X are zero.  R, X: LDS pp*pp
+// each; dead: LDS pp ints.  Returns (in every thread) the number of dead
+// indices below `live`.  MAXU: entries per thread, at least
+// ceil(pp^2 / blockDim.x) (a compile-time bound keeps them in registers).
+// Right-looking, one barrier per column: each thread keeps the upper-triangle
+// entries it owns in registers for the whole factorisation; at step j the
+// owners of row j (final by then) publish it into one of two LDS row buffers
+// (the first 2 pp doubles of X) and write row j of R, and every owner of an
+// entry (a, b), a > j, subtracts C[j][a] C[j][b] / C[j][j] from it.  (Updating
+// the entries in LDS made each thread's three accesses per entry wait on one
+// another: 1.1 us per column at pp = 64.)
 // ---------------------------------------------------------------------------
+template <int MAXU>
 __device__ inline int chol_factor_inverse(double *C, int ld, int pp, double tol_rel, double *R, double *X, int *dead,
                                           int live = 1 << 30) {
     __shared__ double s_maxd;
     __shared__ int s_nd;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        double mx = 0.0;
-        for (int j = 0; j < pp; ++j) mx = fmax(mx, C[j * ld + j]);
-        s_maxd = mx;
-        s_nd = 0;
-    }
-    __syncthreads();
-    const double thr = tol_rel * s_maxd;
-    // each thread owns the upper-triangle entries e = tid + blockDim.x u of
-    // the pp x pp matrix (u < 16 covers pp <= 64 from 256 threads up)
-    int ea[16], eb[16];
+    const int nth = (int)blockDim.x;
+    if (tid < 64) {  // largest diagonal entry (wave 0)
+        double v = tid < pp ? C[tid * ld + tid] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int e = tid + (int)blockDim.x * u;
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+        if (tid == 0) {
+            s_maxd = v;
+            s_nd = 0;
+        }
+    }
+    // each thread owns the upper-triangle entries e = tid + nth u, u < MAXU,
+    // of the pp x pp matrix
+    int ea[MAXU], eb[MAXU];
+    double cv[MAXU];
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u) {
+        const int e = tid + nth * u;
         const int a = e / pp, b = e % pp;
         const bool own = e < pp * pp && a <= b;
         ea[u] = own ? a : -1;
         eb[u] = own ? b : 0;
+        cv[u] = own ? C[a * ld + b] : 0.0;
     }
+    for (int e = tid; e < pp * pp; e += nth)
+        if (e % pp < e / pp) R[e] = 0.0;
+    __syncthreads();
+    const double thr = tol_rel * s_maxd;
     for (int j = 0; j < pp; ++j) {
-        const double piv = C[j * ld + j];
+        double *rb = X + (j & 1) * pp;
+#pragma unroll
+        for (int u = 0; u < MAXU; ++u)
+            if (ea[u] == j) rb[eb[u]] = cv[u];
+        __syncthreads();
+        const double piv = rb[j];
         const bool dj = !(piv > thr) || !(piv > 0.0);
         if (tid == 0) {
             dead[j] = dj;
             if (dj && j < live) ++s_nd;
         }
+        const double sq = dj ? 1.0 : sqrt(piv);
+#pragma unroll
+        for (int u = 0; u < MAXU; ++u)
+            if (ea[u] == j) R[j * pp + eb[u]] = dj ? 0.0 : cv[u] / sq;
         if (!dj) {
             const double inv = 1.0 / piv;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                if (ea[u] > j) {
-                    const int a = ea[u], b = eb[u];
-                    C[a * ld + b] -= C[j * ld + a] * C[j * ld + b] * inv;
-                }
-            }
+            for (int u = 0; u < MAXU; ++u)
+                if (ea[u] > j) cv[u] -= rb[ea[u]] * rb[eb[u]] * inv;
         }
-        __syncthreads();
-    }
-    for (int e = tid; e < pp * pp; e += blockDim.x) {
-        const int a = e / pp, b = e % pp;
-        R[e] = (b >= a && !dead[a]) ? C[a * ld + b] / sqrt(C[a * ld + a]) : 0.0;
     }
     __syncthreads();
     // C is free now: scratch of the inverse (needs ld >= pp)

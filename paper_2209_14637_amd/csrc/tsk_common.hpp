@@ -453,9 +453,11 @@ __device__ inline void upper_tri_inverse(const double *R, double *X, int pp, dou
 // Right-looking, one barrier per column: each thread keeps the upper-triangle
 // entries it owns in registers for the whole factorisation; at step j the
 // owners of row j (final by then) publish it into one of two LDS row buffers
-// (the first 2 pp doubles of X) and write row j of R, and every owner of an
-// entry (a, b), a > j, subtracts C[j][a] C[j][b] / C[j][j] from it.  (Updating
-// the entries in LDS made each thread's three accesses per entry wait on one
+// (the first 2 pp doubles of X), and every owner of an entry (a, b), a > j,
+// subtracts C[j][a] C[j][b] / C[j][j] from it, all its reads of the row
+// issued before the first use.  R = rows / sqrt(pivots) is formed after the
+// loop (the pivots are kept in X), off the per-column path.  (Updating the
+// entries in LDS made each thread's three accesses per entry wait on one
 // another: 1.1 us per column at pp = 64.)
 // ---------------------------------------------------------------------------
 template <int MAXU>
@@ -491,29 +493,46 @@ __device__ inline int chol_factor_inverse(double *C, int ld, int pp, double tol_
         if (e % pp < e / pp) R[e] = 0.0;
     __syncthreads();
     const double thr = tol_rel * s_maxd;
+    double *pv = X + 2 * pp;  // the pivots, for R once the loop is done
+    double ra[MAXU], rc[MAXU];
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u) ra[u] = rc[u] = 0.0;
     for (int j = 0; j < pp; ++j) {
         double *rb = X + (j & 1) * pp;
 #pragma unroll
         for (int u = 0; u < MAXU; ++u)
             if (ea[u] == j) rb[eb[u]] = cv[u];
         __syncthreads();
+        // the column's reads are all issued before any of them is used
         const double piv = rb[j];
+#pragma unroll
+        for (int u = 0; u < MAXU; ++u)
+            if (ea[u] > j) {
+                ra[u] = rb[ea[u]];
+                rc[u] = rb[eb[u]];
+            }
+        asm volatile("" ::: "memory");
         const bool dj = !(piv > thr) || !(piv > 0.0);
         if (tid == 0) {
             dead[j] = dj;
+            pv[j] = piv;
             if (dj && j < live) ++s_nd;
         }
-        const double sq = dj ? 1.0 : sqrt(piv);
-#pragma unroll
-        for (int u = 0; u < MAXU; ++u)
-            if (ea[u] == j) R[j * pp + eb[u]] = dj ? 0.0 : cv[u] / sq;
         if (!dj) {
             const double inv = 1.0 / piv;
 #pragma unroll
             for (int u = 0; u < MAXU; ++u)
-                if (ea[u] > j) cv[u] -= rb[ea[u]] * rb[eb[u]] * inv;
+                if (ea[u] > j) cv[u] -= ra[u] * rc[u] * inv;
         }
     }
+    __syncthreads();
+    // row a of R: the final row a of the update divided by sqrt(pivot a)
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u)
+        if (ea[u] >= 0) {
+            const int a = ea[u];
+            R[a * pp + eb[u]] = dead[a] ? 0.0 : cv[u] / sqrt(pv[a]);
+        }
     __syncthreads();
     // C is free now: scratch of the inverse (needs ld >= pp)
     upper_tri_inverse(R, X, pp, C);

@@ -212,6 +212,32 @@ def test_apply_bf16_with_oracle_sketch(ctx, orc, spec_kw):
     assert (out["flags"].cpu().numpy() & 1).sum() == 0
 
 
+@pytest.mark.parametrize("shape", [(6, 300, 203, 20, 10), (4, 96, 1080, 16, 8), (5, 520, 130, 40, 20)])
+def test_apply_bf16_padding_masked(ctx, shape):
+    """A staged bf16 stack has a 128-byte row stride, and what its padding
+    columns n .. ld-1 hold does not reach the apply's outputs: NaN padding
+    gives the same bits as zero padding (the sketch's and the projection's
+    partial last steps mask what lies past n)."""
+    cnt, m, n, k, r = shape
+    _say(f"apply bf16 NaN padding {shape}")
+    rng = np.random.default_rng(m + n + k)
+    a = rng.standard_normal((cnt, m, n)).astype(np.float32)
+    S = np.ascontiguousarray(np.linalg.qr(rng.standard_normal((m, k)))[0].T, dtype=np.float32)
+    st = ctx.stage(dev32(a, fill=0.0), "bf16")
+    torch.cuda.synchronize()
+    ld = st.data.shape[2]
+    assert ld >= n and (ld * 2) % 128 == 0
+    st.data[:, :, n:] = 0.0
+    zero = {key: v.clone() for key, v in ctx.apply(dev(S), st, r).items() if v is not None}
+    torch.cuda.synchronize()
+    st.data[:, :, n:] = float("nan")
+    nan = ctx.apply(dev(S), st, r)
+    torch.cuda.synchronize()
+    for key in ("L", "R", "sigma", "relerr"):
+        assert torch.equal(zero[key], nan[key]), key
+    assert torch.isfinite(zero["relerr"]).all()
+
+
 def test_train_apply_bf16_end_to_end(ctx, orc):
     spec = synth.spec_hsi_fp32().replace(m=384, n=280, n_train=60, n_test=16, k=20, r=10)
     _say("train+apply bf16 end to end")

@@ -93,6 +93,32 @@ def test_gram_e4m3_padding_masked(ctx, orc, shape):
     assert np.array_equal(G.cpu().numpy(), orc.gram(a))
 
 
+@pytest.mark.parametrize("shape", [(6, 300, 203, 20, 10), (4, 96, 1080, 16, 8)])
+def test_apply_e4m3_padding_masked(ctx, shape):
+    """A staged e4m3 stack has a 128-byte row stride, and NaN codes (0x7f) in
+    its padding bytes n .. ld-1 give the same apply outputs, bit for bit, as
+    zero padding."""
+    cnt, m, n, k, r = shape
+    _say(f"apply e4m3 NaN padding {shape}")
+    rng = np.random.default_rng(m + n + k + 1)
+    a = rng.standard_normal((cnt, m, n)).astype(np.float32)
+    S = np.ascontiguousarray(np.linalg.qr(rng.standard_normal((m, k)))[0].T, dtype=np.float32)
+    Sd = torch.from_numpy(S).cuda()
+    st = ctx.stage(dev32(a, fill=0.0), "e4m3")
+    torch.cuda.synchronize()
+    ld = st.data.shape[2]
+    assert ld >= n and ld % 128 == 0
+    st.data[:, :, n:] = 0
+    zero = {key: v.clone() for key, v in ctx.apply(Sd, st, r).items() if v is not None}
+    torch.cuda.synchronize()
+    st.data[:, :, n:] = 0x7F
+    nan = ctx.apply(Sd, st, r)
+    torch.cuda.synchronize()
+    for key in ("L", "R", "sigma", "relerr"):
+        assert torch.equal(zero[key], nan[key]), key
+    assert torch.isfinite(zero["relerr"]).all()
+
+
 def test_gram_e4m3_float_scales_differ(ctx, orc):
     """Slices whose magnitudes span 4^11, so their scales differ: the Gram of
     every single slice (the scale folding, at every magnitude) and of the

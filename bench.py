@@ -502,8 +502,8 @@ def main():
                     help="only the Gram launches and a calibration copy, for rocprofv3 --pmc runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU path "
-              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print("bench.py runs on one GPU only: it measures the single-GPU path "
+              "(sharding the stream over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch_bf16":
         rec = run_batch(args)

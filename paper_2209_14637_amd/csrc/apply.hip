@@ -190,8 +190,12 @@ __device__ __forceinline__ void project_f32_body(const float *__restrict__ A, in
 // ---------------------------------------------------------------------------
 constexpr int SKB_PANEL = 128;  // columns per sketch wave (16 lanes x 8)
 
-// Sb = [S_hi; S_lo], each kp x mp bf16 with zero padding (rows >= k,
-// columns >= m).
+// The bf16 pair (hi, lo) of S, kp x mp with zero padding (rows >= k,
+// columns >= m), in the order the sketch's MFMA lanes read it: for 32-column
+// step st, 16-row tile a and half h (0: hi, 1: lo), lane 16q + i holds the
+// 8 entries S[16a + i][32 st + 8q .. 32 st + 8q + 7], so one load
+// instruction reads 1 KB in one piece (((st kp/16 + a) 2 + h) 64 + lane) 8.
+// (Row-major halves made each load touch 16 half cache lines.)
 __device__ __forceinline__ void prep_sketch_bf16_body(const float *__restrict__ S, int k, int kp, int64_t m, int64_t mp,
                                         uint16_t *__restrict__ Sb, int64_t e) {
     if (e >= (int64_t)kp * mp) return;
@@ -200,8 +204,11 @@ __device__ __forceinline__ void prep_sketch_bf16_body(const float *__restrict__ 
     const float x = (s < k && i < m) ? S[(int64_t)s * m + i] : 0.f;
     const unsigned h = pack_bf16(x, 0.f) & 0xffffu;
     const unsigned l = pack_bf16(x - bf16_lo(h), 0.f) & 0xffffu;
-    Sb[e] = (uint16_t)h;
-    Sb[(int64_t)kp * mp + e] = (uint16_t)l;
+    const int64_t st = i >> 5;
+    const int c = (int)(i & 31), lane = 16 * (c >> 3) + (s & 15);
+    const int64_t o = ((st * (kp / 16) + (s >> 4)) * 2 * 64 + lane) * 8 + (c & 7);
+    Sb[o] = (uint16_t)h;
+    Sb[o + 512] = (uint16_t)l;
 }
 
 // 8 consecutive elements (columns c .. c+7 of a row, zero from column n on)
@@ -312,8 +319,8 @@ __device__ __forceinline__ void sketch_bf16_body(const ET *__restrict__ A, const
     const bool any = c8 < n;
     const float inv = scale ? 1.0f / scale[d] : 1.0f;
     const ET *Ad = A + d * stride + (any ? c8 : 0);
-    const uint16_t *Sh = Sb + (int64_t)ii * mp + 8 * q;
-    const uint16_t *Sl = Sh + (int64_t)kp * mp;
+    // S pair of step st, tile a: Sp + (st MT + a) 1024 (hi), + 512 (lo)
+    const uint16_t *Sp = Sb + 8 * lane;
     v4f acc[MT][8];
 #pragma unroll
     for (int a = 0; a < MT; ++a)
@@ -337,8 +344,8 @@ __device__ __forceinline__ void sketch_bf16_body(const ET *__restrict__ A, const
             for (int e = 0; e < 8; ++e) x[j][e] = raw8(Ad + (rs + 8 * q + e) * ld);
 #pragma unroll
             for (int a = 0; a < MT; ++a) {
-                sh[j][a] = *reinterpret_cast<const v4u *>(Sh + (int64_t)a * 16 * mp + rs);
-                sl[j][a] = *reinterpret_cast<const v4u *>(Sl + (int64_t)a * 16 * mp + rs);
+                sh[j][a] = *reinterpret_cast<const v4u *>(Sp + ((rs >> 5) * MT + a) * 1024);
+                sl[j][a] = *reinterpret_cast<const v4u *>(Sp + ((rs >> 5) * MT + a) * 1024 + 512);
             }
         }
         asm volatile("" ::: "memory");
@@ -365,8 +372,8 @@ __device__ __forceinline__ void sketch_bf16_body(const ET *__restrict__ A, const
                 for (int e = 0; e < 8; ++e) x[j][e] = raw8(Ad + (rs + 8 * q + e) * ld);
 #pragma unroll
                 for (int a = 0; a < MT; ++a) {
-                    sh[j][a] = *reinterpret_cast<const v4u *>(Sh + (int64_t)a * 16 * mp + rs);
-                    sl[j][a] = *reinterpret_cast<const v4u *>(Sl + (int64_t)a * 16 * mp + rs);
+                    sh[j][a] = *reinterpret_cast<const v4u *>(Sp + ((rs >> 5) * MT + a) * 1024);
+                    sl[j][a] = *reinterpret_cast<const v4u *>(Sp + ((rs >> 5) * MT + a) * 1024 + 512);
                 }
                 // the reloads are issued here (the compiler would otherwise
                 // sink them to their use one ring turn later)
@@ -395,8 +402,8 @@ __device__ __forceinline__ void sketch_bf16_body(const ET *__restrict__ A, const
         }
 #pragma unroll
         for (int a = 0; a < MT; ++a) {
-            sh[a] = *reinterpret_cast<const v4u *>(Sh + (int64_t)a * 16 * mp + r0);
-            sl[a] = *reinterpret_cast<const v4u *>(Sl + (int64_t)a * 16 * mp + r0);
+            sh[a] = *reinterpret_cast<const v4u *>(Sp + ((r0 >> 5) * MT + a) * 1024);
+            sl[a] = *reinterpret_cast<const v4u *>(Sp + ((r0 >> 5) * MT + a) * 1024 + 512);
         }
         sketch_step<MT>(x, sh, sl, acc, fro);
     }

@@ -129,7 +129,7 @@ tsk_status tsk_gram(tsk_ctx ctx, const tsk_stack *train, int32_t compute, double
 tsk_status tsk_eig_topk(tsk_ctx ctx, const double *G, int64_t m, int32_t k,
                         float *S, double *lambda, int32_t *iters);
 
-/* Training, Algorithm 2 lines 1-2: tsk_gram (same stack/compute rules)
+/* Training (the first half of Algorithm 2): tsk_gram (same stack/compute rules)
  * followed by tsk_eig_topk on the context's workspace.  S: device FP32
  * k x m.  lambda: host k+1.  iters: host, nullable.  Requires 1 <= k < m,
  * k <= 52.  Synchronises the stream. */
@@ -139,7 +139,7 @@ tsk_status tsk_train(tsk_ctx ctx, const tsk_stack *train, int32_t k, int32_t com
 /* SCW, Algorithm 1, on every slice of `test` with the sketch S (k x m,
  * device FP32, rows orthonormal):
  *   1. B_d = S A_d (k x n);  V_d = orthonormal basis of the row space of B_d
- *      (n x k), by CholeskyQR2 -- the QR replacement for the SVD of line 1
+ *      (n x k), by CholeskyQR2 -- the QR replacement for Algorithm 1's SVD
  *      that Section 3.2 allows;
  *   2. C_d = A_d V_d (m x k) and its rank-r truncation via the eigen-
  *      decomposition C_d^T C_d = Y diag(sigma^2) Y^T;

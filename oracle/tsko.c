@@ -458,8 +458,8 @@ int tsko_qr(const double *A, int64_t m, int64_t n, double *Q, double *R) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Training: Algorithm 2 lines 1-2.  S* = first k columns of U^(1) (eq. 3.3  */
-/* and the sentence after it), i.e. the top-k eigenvectors of the Gram.      */
+/* Training: first half of Algorithm 2.  S* = first k columns of U^(1) (eq. */
+/* 3.3 and the sentence after it), i.e. the top-k eigenvectors of the Gram. */
 /* ------------------------------------------------------------------------ */
 int tsko_train_from_gram(const double *G, int64_t m, int64_t k, double *S, double *lambda) {
     if (!G || !S || k < 1 || k > m) return -1;

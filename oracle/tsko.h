@@ -61,7 +61,7 @@ int tsko_svd(const double *A, int64_t m, int64_t n, double *U, double *s, double
  * Q: m x n with orthonormal columns, R: n x n upper triangular. */
 int tsko_qr(const double *A, int64_t m, int64_t n, double *Q, double *R);
 
-/* Training (Algorithm 2, lines 1-2; Section 3.1): S = top-k eigenvectors of
+/* Training (first half of Algorithm 2; Section 3.1): S = top-k eigenvectors of
  * the mode-1 Gram as rows (S S^T = I_k), in descending eigenvalue order,
  * sign-canonical.  lambda: k+1 leading eigenvalues (lambda_{k+1} is 0 when
  * k == m).  Also returns ||A||_F^2 in *fro2 (nullable). */

@@ -4,7 +4,7 @@
 //            slice, MFMA; also ||A_d||_F^2 in FP64.
 //  project : C_d = A_d B_d^T (m x k), MFMA (second pass over A_d).
 //  finish  : one workgroup per matrix.  Section 3.2 notes that only the
-//            orthogonalisation of line 1 matters (QR may replace the SVD), so
+//            orthogonalisation in Algorithm 1 matters (QR may replace the SVD), so
 //            V_d is kept implicit: with B_d B_d^T = R^T R (Cholesky, FP64),
 //            V_d = B_d^T R^-1 is an orthonormal basis of the row space of
 //            S A_d, A_d V_d = C_d R^-1, and

@@ -78,7 +78,7 @@ def test_eigh_jacobi_crosscheck(orc):
 
 
 # ---------------------------------------------------------------------------
-# SVD and QR (Algorithm 1 lines 1-2; QR variant of Section 3.2)
+# SVD and QR (Algorithm 1; QR variant of Section 3.2)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("shape", [(1, 1), (1, 5), (5, 1), (6, 4), (4, 6), (40, 13), (13, 40)])

@@ -54,6 +54,7 @@ def lib():
             "tsko_train_f32": [_P, _I, _I, _I, _I, _P, _P, _P],
             "tsko_train_from_gram": [_P, _I, _I, _P, _P],
             "tsko_scw": [_P, _I, _I, _P, _I, _I, ctypes.c_int, _P, _P, _P, _P, _P, _P],
+            "tsko_scw_basis": [_P, _I, _I, _P, _I, ctypes.c_int, _P, _P],
             "tsko_apply_f32": [_P, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P, _P],
             "tsko_error_f32": [_P, _I, _I, _I, _P, _P, _I, _P],
             "tsko_opt_f32": [_P, _I, _I, _I, _I, _P, _P],
@@ -180,6 +181,19 @@ def scw(A: np.ndarray, S: np.ndarray, r: int, vmode: int = 0, want_ahat: bool = 
     if want_ahat:
         out["Ahat"] = Ah
     return out
+
+
+def scw_basis(A: np.ndarray, S: np.ndarray, vmode: int = 0):
+    """Step 1 of Algorithm 1: V (n x k, orthonormal columns) spanning the row
+    space of S A, and the flags (RANKDEF) of that step."""
+    A = _f64(A)
+    S = _f64(S)
+    m, n = A.shape
+    k = S.shape[0]
+    V = np.empty((n, k))
+    fl = np.zeros(1, dtype=np.int32)
+    _check(lib().tsko_scw_basis(_p(A), m, n, _p(S), k, vmode, _p(V), _p(fl)), "scw_basis")
+    return V, int(fl[0])
 
 
 def apply(A: np.ndarray, S: np.ndarray, r: int, factors: bool = True):

@@ -491,30 +491,19 @@ int tsko_train_f32(const float *A, int64_t count, int64_t m, int64_t n, int64_t 
 /* ------------------------------------------------------------------------ */
 /* SCW, Algorithm 1.                                                         */
 /* ------------------------------------------------------------------------ */
-int tsko_scw(const double *A, int64_t m, int64_t n, const double *S, int64_t k, int64_t r,
-             int vmode, double *L, double *R, double *sigma, double *Ahat,
-             double *relerr, int32_t *flags) {
-    if (!A || !S || m <= 0 || n <= 0 || r < 1 || k <= r || k > m || k > n) return -1;
+/* Step 1 of Algorithm 1: B = S A and an orthonormal basis V (n x k) of its
+ * row space (thin SVD of B, or Householder QR of B^T with vmode = 1). */
+int tsko_scw_basis(const double *A, int64_t m, int64_t n, const double *S, int64_t k, int vmode,
+                   double *V, int32_t *flags) {
+    if (!A || !S || !V || m <= 0 || n <= 0 || k < 1 || k > m || k > n) return -1;
     int32_t fl = 0;
-    double fro2 = 0.0;
-    for (int64_t i = 0; i < m * n; i++) {
-        if (!isfinite(A[i])) fl |= TSKO_FLAG_NONFIN;
-        fro2 += A[i] * A[i];
-    }
-    if (fl & TSKO_FLAG_NONFIN) {
-        if (relerr) *relerr = NAN;
-        if (flags) *flags = fl;
-        return 0;
-    }
-    /* step 1: B = S A (k x n) */
     double *B = dalloc((size_t)(k * n));
     for (int64_t s = 0; s < k; s++)
         for (int64_t i = 0; i < m; i++) {
             double sv = MUT(11) ? S[i * k + s] : S[s * m + i];
             for (int64_t j = 0; j < n; j++) B[s * n + j] += sv * A[i * n + j];
         }
-    /* orthonormal basis V (n x k) of the row space of B */
-    double *V = dalloc((size_t)(n * k));
+    memset(V, 0, sizeof(double) * (size_t)(n * k));
     if (vmode == 1) {
         double *Bt = dalloc((size_t)(n * k));
         for (int64_t s = 0; s < k; s++)
@@ -536,6 +525,31 @@ int tsko_scw(const double *A, int64_t m, int64_t n, const double *S, int64_t k, 
         }
         free(sb); free(Vtb);
     }
+    free(B);
+    if (flags) *flags = fl;
+    return 0;
+}
+
+int tsko_scw(const double *A, int64_t m, int64_t n, const double *S, int64_t k, int64_t r,
+             int vmode, double *L, double *R, double *sigma, double *Ahat,
+             double *relerr, int32_t *flags) {
+    if (!A || !S || m <= 0 || n <= 0 || r < 1 || k <= r || k > m || k > n) return -1;
+    int32_t fl = 0;
+    double fro2 = 0.0;
+    for (int64_t i = 0; i < m * n; i++) {
+        if (!isfinite(A[i])) fl |= TSKO_FLAG_NONFIN;
+        fro2 += A[i] * A[i];
+    }
+    if (fl & TSKO_FLAG_NONFIN) {
+        if (relerr) *relerr = NAN;
+        if (flags) *flags = fl;
+        return 0;
+    }
+    /* step 1: B = S A (k x n) and V (n x k), an orthonormal basis of row(B) */
+    double *V = dalloc((size_t)(n * k));
+    int32_t fb = 0;
+    tsko_scw_basis(A, m, n, S, k, vmode, V, &fb);
+    fl |= fb;
     /* step 2: C = A V (m x k), thin SVD C = U Sig Y^T */
     double *C = dalloc((size_t)(m * k));
     for (int64_t i = 0; i < m; i++)
@@ -571,7 +585,7 @@ int tsko_scw(const double *A, int64_t m, int64_t n, const double *S, int64_t k, 
     if (sigma) memcpy(sigma, sc, sizeof(double) * (size_t)r);
     if (relerr) *relerr = fro2 > 0.0 ? sqrt(res2 / fro2) : 0.0;
     if (flags) *flags = fl;
-    free(B); free(V); free(C); free(Uc); free(sc); free(Yt); free(Lm); free(Rm);
+    free(V); free(C); free(Uc); free(sc); free(Yt); free(Lm); free(Rm);
     return 0;
 }
 

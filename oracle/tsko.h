@@ -69,6 +69,13 @@ int tsko_train_f32(const float *A, int64_t count, int64_t m, int64_t n, int64_t 
                    double *S, double *lambda, double *fro2);
 int tsko_train_from_gram(const double *G, int64_t m, int64_t k, double *S, double *lambda);
 
+/* Step 1 of Algorithm 1 alone: V (n x k, column-orthonormal) spans the row
+ * space of S A (thin SVD of S A; vmode = 1: Householder QR of (S A)^T).
+ * Directions with sigma_i(S A) <= 1e-13 sigma_1 are zero columns and set
+ * flag RANKDEF in *flags (nullable).  This is the V that tsko_scw uses. */
+int tsko_scw_basis(const double *A, int64_t m, int64_t n, const double *S, int64_t k, int vmode,
+                   double *V, int32_t *flags);
+
 /* SCW (Algorithm 1) on one matrix A (m x n) with sketch S (k x m), r < k:
  *   1. B = S A;  V = right singular vectors of B (thin SVD, n x k) -- or, with
  *      vmode = 1, the Q factor of a Householder QR of B^T (the QR variant the

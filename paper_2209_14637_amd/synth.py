@@ -28,8 +28,8 @@ the oracle reads exactly (upcast to float64) and the GPU path reads as stored.
 """
 from __future__ import annotations
 
+import contextlib
 import dataclasses
-import mmap
 import os
 from concurrent.futures import ThreadPoolExecutor
 
@@ -43,11 +43,13 @@ def _rng(*key: int) -> np.random.Generator:
 
 
 def _single_thread_blas():
+    """Context in which BLAS/OpenMP pools run one thread (no-op when
+    threadpoolctl is missing)."""
     try:
         from threadpoolctl import threadpool_limits
-        threadpool_limits(1)
+        return threadpool_limits(1)
     except Exception:
-        pass
+        return contextlib.nullcontext()
 
 
 def _orth(x: np.ndarray) -> np.ndarray:
@@ -125,17 +127,14 @@ class Stream:
             a = a + s.eta * self.noise(d)
         return a.astype(np.float32)
 
-    def slices(self, ds, out: np.ndarray | None = None, threads: int | None = None,
-               procs: int | None = None) -> np.ndarray:
-        """Slices ds as a (len(ds), m, n) float32 array.  Large requests are
-        split over forked worker processes writing into shared anonymous
-        memory (the draws are per-slice, so the result does not depend on
-        the split); call it before the process starts GPU work."""
+    def slices(self, ds, out: np.ndarray | None = None, threads: int | None = None) -> np.ndarray:
+        """Slices ds as a (len(ds), m, n) float32 array, drawn by a pool of
+        threads (the draws are per-slice, so the result does not depend on
+        the split).  Each worker's BLAS runs single-threaded meanwhile, so
+        the pool does not oversubscribe the cores; no process is forked, so
+        it is safe after GPU work has started."""
         ds = list(ds)
         s = self.spec
-        nproc = procs if procs is not None else min(16, len(os.sched_getaffinity(0)))
-        if out is None and nproc > 1 and len(ds) * s.m * s.n >= (1 << 26) and hasattr(os, "fork"):
-            return self._slices_forked(ds, nproc)
         if out is None:
             out = np.empty((len(ds), s.m, s.n), dtype=np.float32)
         nthr = threads or min(16, len(os.sched_getaffinity(0)))
@@ -147,37 +146,9 @@ class Stream:
             for i in range(len(ds)):
                 work(i)
         else:
-            with ThreadPoolExecutor(nthr) as ex:
+            with _single_thread_blas(), ThreadPoolExecutor(nthr) as ex:
                 list(ex.map(work, range(len(ds))))
         return out
-
-    def _slices_forked(self, ds, nproc):
-        s = self.spec
-        per = s.m * s.n
-        mm = mmap.mmap(-1, len(ds) * per * 4)
-        arr = np.frombuffer(mm, dtype=np.float32).reshape(len(ds), s.m, s.n)
-        nproc = min(nproc, len(ds))
-        bounds = [len(ds) * p // nproc for p in range(nproc + 1)]
-        pids = []
-        for p in range(nproc):
-            pid = os.fork()
-            if pid == 0:  # child: numpy only, then leave without cleanup
-                code = 0
-                try:
-                    _single_thread_blas()
-                    for i in range(bounds[p], bounds[p + 1]):
-                        arr[i] = self.slice(ds[i])
-                except BaseException:
-                    code = 1
-                os._exit(code)
-            pids.append(pid)
-        bad = 0
-        for pid in pids:
-            _, st = os.waitpid(pid, 0)
-            bad |= st != 0
-        if bad:
-            raise RuntimeError("slice generation worker failed")
-        return arr  # backed by the anonymous mapping, released with the array
 
     def train(self, count: int | None = None, **kw) -> np.ndarray:
         c = self.spec.n_train if count is None else count

@@ -1,7 +1,17 @@
-"""Writes the oracle's reference values for the full-size workloads to JSON.
+"""Writes the oracle's reference values for the full-size workloads.
 
 Calls only the FP64 CPU oracle (oracle/) and the seeded stream generator; no
-value here comes from the GPU path.  Usage:  python tests/golden/make_golden.py
+value here comes from the GPU path.  For each workload it writes
+  <name>.json   : spec, lambda_1..lambda_{k+1}, ||A||_F^2 of the training
+                  tensor, and the relative error and flags of EVERY test
+                  matrix (optimal rank-r tails where requested);
+  <name>_S.npy  : the oracle's sketch S (k x m, float32: the angle gates are
+                  1e-4 and looser, far above float32 rounding), or for the
+                  batch workload <name>_S.npz with one array per stream.
+The training Gram is summed over chunks of slices (FP64, chunks in order) so
+that the largest training tensors need not be held in memory at once.
+
+Usage:  python tests/golden/make_golden.py [workload ...]
 """
 import json
 import os
@@ -16,70 +26,105 @@ import numpy as np  # noqa: E402
 from oracle import oracle  # noqa: E402
 from paper_2209_14637_amd import synth  # noqa: E402
 
+CHUNK = 250  # training slices per Gram chunk
 
-def golden_stream(spec, name, n_err=64, n_opt=16):
+
+def oracle_train(st, n_train, k):
+    """S, lambda, ||A||^2 from the mode-1 Gram of the first n_train slices."""
+    G = None
+    for d0 in range(1, n_train + 1, CHUNK):
+        a = st.slices(range(d0, min(d0 + CHUNK, n_train + 1)))
+        g = oracle.gram(a)
+        G = g if G is None else G + g
+        del a
+    S, lam = oracle.train_from_gram(G, k)
+    return S, lam, float(np.trace(G))
+
+
+def oracle_errors(st, ds, S, r, chunk=100):
+    e, fl = [], []
+    for i in range(0, len(ds), chunk):
+        res = oracle.apply(st.slices(ds[i:i + chunk]), S, r, factors=False)
+        e.extend(res["relerr"].tolist())
+        fl.extend(res["flags"].tolist())
+    return e, fl
+
+
+def golden_stream(spec, name, n_opt=0):
     st = synth.Stream(spec)
     t0 = time.time()
-    tr = st.train()
-    S, lam, fro2 = oracle.train(tr, spec.k, return_fro2=True)
+    S, lam, fro2 = oracle_train(st, spec.n_train, spec.k)
     t_train = time.time() - t0
-    del tr
-    te = st.test(n_err)
-    res = oracle.apply(te, S, spec.r)
-    e = res["relerr"]
-    if n_opt:
-        tail, fro = oracle.opt_tail(te[:n_opt], spec.r)
-    else:
-        tail = fro = np.zeros(0)
+    ds = list(range(spec.n_train + 1, spec.n_train + 1 + spec.n_test))
+    t0 = time.time()
+    e, fl = oracle_errors(st, ds, S, spec.r)
+    t_apply = time.time() - t0
     out = {
         "workload": name,
         "spec": {k: v for k, v in spec.__dict__.items()},
         "source": "oracle/tsko.c via tests/golden/make_golden.py",
         "lambda": lam.tolist(),
         "train_fro2": fro2,
-        "relerr": e.tolist(),
-        "flags": res["flags"].tolist(),
-        "opt_tail": tail.tolist(),
-        "fro": fro.tolist(),
-        "metric_4_1": ((e[:n_opt] * fro - tail) / tail).tolist(),
+        "relerr": e,
+        "flags": fl,
         "oracle_train_seconds": t_train,
+        "oracle_apply_seconds": t_apply,
         "threads": oracle.threads(),
     }
+    if n_opt:
+        tail, fro = [], []
+        for i in range(0, n_opt, 50):
+            t, f = oracle.opt_tail(st.slices(ds[i:min(i + 50, n_opt)]), spec.r)
+            tail.extend(t.tolist())
+            fro.extend(f.tolist())
+        out["opt_tail"] = tail
+        out["fro"] = fro
+        ee = np.asarray(e[:n_opt])
+        out["metric_4_1"] = ((ee * np.asarray(fro) - np.asarray(tail)) / np.asarray(tail)).tolist()
     with open(os.path.join(HERE, f"{name}.json"), "w") as f:
-        json.dump(out, f, indent=1)
-    print(name, "lambda_1..3", lam[:3], "e[:3]", e[:3], f"train {t_train:.1f}s")
+        json.dump(out, f, indent=0)
+    np.save(os.path.join(HERE, f"{name}_S.npy"), S.astype(np.float32))
+    print(name, "lambda_1..3", lam[:3], "e[:3]", e[:3], f"train {t_train:.1f}s apply {t_apply:.1f}s", flush=True)
 
 
-def golden_batch(name, n_train=100, n_err=4):
+def golden_batch(name, n_train=100, count=2000):
     """The uneven-shape batch workload: per stream, the oracle's sketch from
-    its training slices and the errors of its first n_err test matrices."""
-    out = {"workload": name, "source": "oracle/tsko.c via tests/golden/make_golden.py", "streams": []}
+    its training slices and the errors of all its test matrices among the
+    `count` interleaved slots (stream s's j-th slot is its test matrix j)."""
+    order = synth.batch_order(count)
+    out = {"workload": name, "source": "oracle/tsko.c via tests/golden/make_golden.py", "count": count,
+           "streams": []}
+    Ss = {}
     t0 = time.time()
     for s in range(len(synth.BATCH_SHAPES)):
-        spec = synth.spec_batch_stream(s, n_train=n_train)
+        spec = synth.spec_batch_stream(s, n_train=n_train, n_test=count)
         st = synth.Stream(spec)
         S, lam = oracle.train(st.train(), spec.k)
-        res = oracle.apply(st.test(n_err), S, spec.r)
+        n_s = int((order == s).sum())
+        ds = list(range(spec.n_train + 1, spec.n_train + 1 + n_s))
+        e, fl = oracle_errors(st, ds, S, spec.r)
         out["streams"].append({"spec": {k: v for k, v in spec.__dict__.items()}, "lambda": lam.tolist(),
-                               "relerr": res["relerr"].tolist(), "flags": res["flags"].tolist()})
-        print(name, "stream", s, spec.m, spec.n, "e[:2]", res["relerr"][:2], flush=True)
+                               "n_test_used": n_s, "relerr": e, "flags": fl})
+        Ss[f"S{s}"] = S.astype(np.float32)
+        print(name, "stream", s, spec.m, spec.n, n_s, "e[:2]", e[:2], flush=True)
     out["oracle_seconds"] = time.time() - t0
     out["threads"] = oracle.threads()
     with open(os.path.join(HERE, f"{name}.json"), "w") as f:
-        json.dump(out, f, indent=1)
+        json.dump(out, f, indent=0)
+    np.savez(os.path.join(HERE, f"{name}_S.npz"), **Ss)
 
 
 WORKLOADS = {
     "batch_8streams_k10-40": lambda: golden_batch("batch_8streams_k10-40"),
-    "hsi_1024x768_k20_r10": lambda: golden_stream(synth.spec_hsi_fp32(), "hsi_1024x768_k20_r10"),
+    # the FP32 form's stream (the HSI shape); optimal tails of every test
+    # matrix for metric (4.1)
+    "hsi_1024x768_k20_r10": lambda: golden_stream(synth.spec_hsi_fp32(), "hsi_1024x768_k20_r10", n_opt=400),
     # the precision form's stream: 1000 training slices of 1920 x 1080; the
     # oracle's reference is on the FP32 values (the reduced-precision paths
     # are gated against it at 1e-3)
-    "stream_1920x1080_k40_r20": lambda: golden_stream(synth.spec_bf16_1920(), "stream_1920x1080_k40_r20",
-                                                      n_err=32, n_opt=0),
+    "stream_1920x1080_k40_r20": lambda: golden_stream(synth.spec_bf16_1920(), "stream_1920x1080_k40_r20"),
     # the e4m3 form's stream: 4000 training slices, Student-t(3) noise at 1e-2
-    "t3stream_1920x1080_k40_r20": lambda: golden_stream(synth.spec_fp8_1920(), "t3stream_1920x1080_k40_r20",
-                                                        n_err=32, n_opt=0),
+    "t3stream_1920x1080_k40_r20": lambda: golden_stream(synth.spec_fp8_1920(), "t3stream_1920x1080_k40_r20"),
 }
 
 if __name__ == "__main__":

@@ -366,3 +366,34 @@ def test_opt_tail_matches_lapack(orc):
         s = np.linalg.svd(a[d].astype(np.float64), compute_uv=False)
         np.testing.assert_allclose(t[d], math.sqrt((s[4:] ** 2).sum()), rtol=1e-12)
         np.testing.assert_allclose(f[d], np.linalg.norm(a[d].astype(np.float64)), rtol=1e-13)
+
+
+def test_scw_basis_spans_row_space(orc, tiny):
+    # step 1 of Algorithm 1: V has orthonormal columns, spans exactly row(SA)
+    # (SA (I - V V^T) = 0 and rank k), SVD and QR bases span the same space,
+    # and the factor R of SCW lies in span(V)
+    st, tr, te, S, lam, fro2 = tiny
+    a = te[1].astype(np.float64)
+    v, fl = orc.scw_basis(a, S)
+    vq, flq = orc.scw_basis(a, S, vmode=1)
+    b = S @ a
+    assert fl == 0 and flq == 0
+    assert np.abs(v.T @ v - np.eye(S.shape[0])).max() <= 1e-13
+    assert np.linalg.norm(b - (b @ v) @ v.T) <= 1e-13 * np.linalg.norm(b)
+    assert np.linalg.norm(vq - v @ (v.T @ vq)) <= 1e-12
+    res = orc.scw(a, S, 5)
+    assert np.linalg.norm(res["R"] - v @ (v.T @ res["R"])) <= 1e-12 * np.linalg.norm(res["R"])
+    # an independent basis: numpy's SVD of SA spans the same space
+    _, _, wt = np.linalg.svd(b, full_matrices=False)
+    assert np.linalg.norm(wt.T - v @ (v.T @ wt.T)) <= 1e-11
+
+
+def test_scw_basis_rank_deficient(orc):
+    rng = np.random.default_rng(8)
+    a = rng.standard_normal((16, 12))
+    q, _ = np.linalg.qr(rng.standard_normal((16, 6)))
+    s = q.T.copy()
+    s[5] = 0.0
+    v, fl = orc.scw_basis(a, s)
+    assert fl & orc.FLAG_RANKDEF
+    assert np.count_nonzero(np.linalg.norm(v, axis=0) > 0.5) == 5

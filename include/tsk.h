@@ -26,6 +26,13 @@
  *   TSK_E_ARG or TSK_E_SHAPE, launches nothing and sets tsk_last_error().
  * - One context per host thread; calls on one context must not overlap.
  */
+/*
+ * Diagnostics (environment, read at each call): TSK_GRAM_TILE128 makes tsk_gram use
+ * its 128 x 128-tile kernels for bf16 and e4m3 stacks (otherwise used only
+ * for slices of 4 GiB and more); TSK_FAULT_NOMEM makes every workspace
+ * allocation fail with TSK_E_NOMEM.  Both exist so tests can reach those
+ * paths.
+ */
 #ifndef TSK_H
 #define TSK_H
 
@@ -84,7 +91,10 @@ typedef struct {
  * stream. */
 tsk_status tsk_create(tsk_ctx *out, int device, void *hip_stream);
 void tsk_destroy(tsk_ctx ctx);
-/* Replace the stream used by later calls (same device). */
+/* Replace the stream used by later calls (same device).  The context's
+ * workspace is shared by all its calls, so work enqueued after the switch
+ * waits (hipStreamWaitEvent) for everything the context enqueued on the
+ * previous stream. */
 tsk_status tsk_set_stream(tsk_ctx ctx, void *hip_stream);
 /* Message of the last failure on this context ("" when none). */
 const char *tsk_last_error(tsk_ctx ctx);
@@ -147,9 +157,14 @@ tsk_status tsk_train(tsk_ctx ctx, const tsk_stack *train, int32_t k, int32_t com
  *      L_d = C_d Y_r = U_r Sigma_r (m x r), R_d = V_d Y_r (n x r).
  * Outputs (device): L (count*m*r FP32), R (count*n*r FP32),
  * sigma (count*r FP32, descending), relerr (count FP64, nullable):
- *      relerr_d = sqrt(max(0, ||A_d||^2 - sum_{i<=r} sigma_i^2)) / ||A_d||
- * (the Pythagorean identity of the proof of Theorem 1), flags (count int32,
- * nullable, TSK_FLAG_*).  Requires 1 <= r < k <= min(m, n), k <= 64.
+ *      relerr_d = ||A_d - L_d R_d^T||_F / ||A_d||_F,
+ * first from the Pythagorean identity of the proof of Theorem 1,
+ *      sqrt(max(0, ||A_d||^2 - sum_{i<=r} sigma_i^2)) / ||A_d||,
+ * whose subtraction cancels as the error shrinks (its rounding is about
+ * 2u / relerr^2 relative, u = 2^-24); where relerr^2 < 0.25 (FP32 form) or
+ * < 1e-2 (bf16, e4m3 forms) it is recomputed from the explicit residual of
+ * the stored values (FP32 products, FP64 sum), an extra pass over those
+ * matrices only.  flags (count int32, nullable, TSK_FLAG_*).  Requires 1 <= r < k <= min(m, n), k <= 64.
  * compute must match the stack's dtype:
  *   TSK_F32    : FP32 products S A_d and A_d V_d;
  *   TSK_BF16   : bf16 stack; products with bf16 A_d and S, V_d each split

@@ -2,23 +2,31 @@
 //
 //  sketch  : B_d = S A_d (k x n), the 1-mode product of Section 2 slice by
 //            slice, MFMA; also ||A_d||_F^2 in FP64.
-//  project : C_d = A_d B_d^T (m x k), MFMA (second pass over A_d).
-//  finish  : one workgroup per matrix.  Section 3.2 notes that only the
-//            orthogonalisation in Algorithm 1 matters (QR may replace the SVD), so
-//            V_d is kept implicit: with B_d B_d^T = R^T R (Cholesky, FP64),
-//            V_d = B_d^T R^-1 is an orthonormal basis of the row space of
-//            S A_d, A_d V_d = C_d R^-1, and
-//                (A_d V_d)^T (A_d V_d) = R^-T (C_d^T C_d) R^-1 = Y diag(s^2) Y^T
-//            (FP64 Jacobi).  With Z = R^-1 Y_r:
-//                L_d = C_d Z = U_r Sigma_r,  R_d = B_d^T Z = V_d Y_r,
-//            so L_d R_d^T = [A_d V_d]_r V_d^T, and the error follows from the
-//            Pythagorean identity of the proof of Theorem 1.
+//  basis   : one workgroup per matrix.  Section 3.2 notes that only the
+//            orthogonalisation in Algorithm 1 matters (a QR may replace the
+//            SVD): V_d (n x k, orthonormal columns, row space of S A_d) by
+//            CholeskyQR2 of B_d in FP64, stored as V_d^T over B_d.
+//  project : C_d = A_d V_d (m x k), MFMA (second pass over A_d), with the
+//            FP64 partial sums of C_d^T C_d per band of rows.
+//  eig     : one workgroup per matrix.  C_d^T C_d = Y diag(s^2) Y^T (FP64
+//            Jacobi), so [A_d V_d]_r = C_d Y_r Y_r^T, sigma = s_1..s_r, and the
+//            error from the Pythagorean identity of the proof of Theorem 1
+//            (recomputed from the explicit residual where it cancels: refine).
+//  outputs : L_d = C_d Y_r = U_r Sigma_r,  R_d = V_d Y_r,
+//            so L_d R_d^T = [A_d V_d]_r V_d^T.
 //  error   : explicit ||A_d - L_d R_d^T||_F / ||A_d||_F (tsk_error).
 //
+// (An implicit basis V_d = B_d^T R^-1, with L_d = C_d R^-1 Y_r and
+// R_d = B_d^T R^-1 Y_r formed in FP32, loses about kappa(B_d) u of accuracy
+// to cancellation in those products: on a stream with relative error 2e-3
+// its errors were off by a factor of 5.  With V_d explicit and orthonormal,
+// every later product is well conditioned.)
+//
 // Two forms of the streaming kernels: FP32 (FP32 MFMA) and bf16 (A_d stored
-// in bf16, B_d split into a bf16 pair hi + lo; every later use of B_d takes
-// B_d = hi + lo, so all factors refer to the same row space).  kp = k rounded
-// up to 16; rows k..kp-1 of S, B are zero, so no masking is needed on them.
+// in bf16, V_d split into a bf16 pair hi + lo; every later use of V_d takes
+// V_d = hi + lo, so all factors refer to the same row space).  kp = k rounded
+// up to 16; rows k..kp-1 of S, B_d and V_d^T are zero, so no masking is
+// needed on them.
 #include <algorithm>
 #include <cstring>
 #include <type_traits>
@@ -773,28 +781,129 @@ __device__ inline void small_mm(const double *X, const double *M, double *Y) {
     __syncthreads();
 }
 
-// factor: B B^T = R^T R (Cholesky, dead pivots dropped), X = R^-1 and
-// H = X^T (C^T C) X, written to HX[d] = [H | X] (KP x KP each, FP64); the
-// number of dead pivots among the first k to q[d].
+// X^T (KP x KP, X upper triangular with zeros below the diagonal, FP64 in
+// LDS) times column j of the KP x ldb FP32 matrix M, in place:
+//     M[a][j] = sum_{u <= a} X[u][a] M[u][j],
+// summed over u in order in FP64.  Outputs in blocks of 16 rows taken from
+// the last block down, so a block reads only rows not yet overwritten; X is
+// read as 16-byte broadcast pairs (its zeros below the diagonal make every
+// block a plain 16-wide update).  P (bf16 and e4m3 forms, else null): also
+// the bf16 pair (hi, lo) of each value (hi rows 0..KP-1, lo rows KP..2KP-1),
+// with M := hi + lo.
 template <int KP>
-__device__ __forceinline__ void factor_body(const float *__restrict__ B, int64_t ldb, int64_t n,
-                                            const float *__restrict__ C, int64_t m, int k, double *__restrict__ HX,
-                                            int *__restrict__ q, int64_t d, const double *__restrict__ ctc) {
+__device__ __forceinline__ void tri_transform_col(const double *X, float *M, int64_t ldb, int64_t j,
+                                                  uint16_t *P) {
+    for (int a0 = KP - 16; a0 >= 0; a0 -= 16) {
+        double o[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) o[t] = 0.0;
+#pragma unroll 4
+        for (int u = 0; u < a0 + 16; ++u) {
+            const double cu = (double)M[u * ldb + j];
+            const double2 *xr = reinterpret_cast<const double2 *>(X + u * KP + a0);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const double2 x = xr[t];
+                o[2 * t] = fma(x.x, cu, o[2 * t]);
+                o[2 * t + 1] = fma(x.y, cu, o[2 * t + 1]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 16; t += 2) {
+            const float v0 = (float)o[t], v1 = (float)o[t + 1];
+            if (P) {
+                const unsigned h2 = pack_bf16(v0, v1);
+                const float h0 = bf16_lo(h2), h1 = bf16_hi(h2);
+                const unsigned l2 = pack_bf16(v0 - h0, v1 - h1);
+                P[(a0 + t) * ldb + j] = (uint16_t)(h2 & 0xffffu);
+                P[(a0 + t + 1) * ldb + j] = (uint16_t)(h2 >> 16);
+                P[(KP + a0 + t) * ldb + j] = (uint16_t)(l2 & 0xffffu);
+                P[(KP + a0 + t + 1) * ldb + j] = (uint16_t)(l2 >> 16);
+                M[(a0 + t) * ldb + j] = h0 + bf16_lo(l2);
+                M[(a0 + t + 1) * ldb + j] = h1 + bf16_hi(l2);
+            } else {
+                M[(a0 + t) * ldb + j] = v0;
+                M[(a0 + t + 1) * ldb + j] = v1;
+            }
+        }
+    }
+}
+
+// basis: an orthonormal basis of the row space of B_d = S A_d by CholeskyQR2
+// (Section 3.2: Algorithm 1's SVD only orthogonalises, and a QR may take its
+// place), written over B_d as V^T (KP x ldb FP32, row i = column i of V):
+//   pass 1:  B B^T = R1^T R1 (FP64 Cholesky, dead pivots dropped),
+//            V1^T = R1^-T B;
+//   pass 2:  V1^T V1 = R2^T R2,  V^T = R2^-T V1^T,
+// the Grams by FP64 MFMA over the FP32 rows.  Pass 1 alone leaves V1
+// orthonormal to about 1e-16 kappa^2 (kappa = sigma_1 / sigma_k of B), so
+// pass 2 runs only when the smallest live pivot of pass 1 is below 1e-8 of
+// the largest (kappa > 1e4); below that V1 is orthonormal to the FP32
+// rounding of its stored values.  Bb (bf16 and e4m3 forms, else null): the
+// bf16 pair of V^T for the projection, with V^T := hi + lo so every later
+// step uses the same basis.  A direction whose pass-1 pivot is below 1e-12
+// of the largest is dropped (zero row); the count among the first k rows
+// goes to q[d] (flag RANKDEF).  Columns n .. ldb-1 of B are zero and stay so.
+template <int KP>
+__device__ __forceinline__ void basis_body(float *__restrict__ B, int64_t ldb, int64_t n, int k,
+                                           uint16_t *__restrict__ Bb, int *__restrict__ q, int64_t d) {
     constexpr int SZ = KP * KP;
-    __shared__ double buf[3 * SZ];
+    __shared__ __align__(16) double buf[3 * SZ];
     __shared__ int dead[KP];
+    __shared__ int s_second;
     const int tid = threadIdx.x;
-    const float *Bd = B + d * KP * ldb;
-    const float *Cd = C + d * m * KP;
+    float *Bd = B + d * KP * ldb;
+    uint16_t *Pd = Bb ? Bb + d * 2 * KP * ldb : nullptr;
     double *b0 = buf, *b1 = buf + SZ, *b2 = buf + 2 * SZ;
-    for (int e = tid; e < SZ; e += 256) b0[e] = 0.0;
-    __syncthreads();
-    gram_mfma_acc<KP / 16, true>(Bd, ldb, n, b0, KP);
-    const int nd = chol_factor_inverse<(KP * KP + 255) / 256>(b0, KP, KP, 1e-12, b1, b2, dead, k);  // X = R^-1 in b2
-    for (int e = tid; e < SZ; e += 256) b0[e] = 0.0;
-    __syncthreads();
+    int nd = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int e = tid; e < SZ; e += 256) b0[e] = 0.0;
+        __syncthreads();
+        gram_mfma_acc<KP / 16, true>(Bd, ldb, n, b0, KP);
+        const int ndp = chol_factor_inverse<(KP * KP + 255) / 256>(b0, KP, KP, 1e-12, b1, b2, dead, k);
+        // b1 = R (upper), b2 = R^-1; the pivots are R's squared diagonal
+        if (pass == 0) {
+            nd = ndp;
+            if (tid == 0) {
+                double pmax = 0.0, pmin = 1e300;
+                for (int i = 0; i < KP; ++i) {
+                    const double pv = b1[i * KP + i] * b1[i * KP + i];
+                    if (dead[i]) continue;
+                    pmax = fmax(pmax, pv);
+                    pmin = fmin(pmin, pv);
+                }
+                s_second = pmax > 0.0 && pmin < 1e-8 * pmax;
+            }
+        }
+        __syncthreads();
+        const bool last = pass == 1 || !s_second;
+        uint16_t *P = last ? Pd : nullptr;
+        for (int64_t j = tid; j < ldb; j += 256) tri_transform_col<KP>(b2, Bd, ldb, j, P);
+        __syncthreads();
+        if (last) break;
+    }
+    if (tid == 0) q[d] = nd;
+}
+
+// eig: H = C^T C (FP64: the projection's per-band sums added in band order,
+// or, in the FP32 form, FP64 MFMA over the rows of C), H = Y diag Y^T
+// (Jacobi), descending order, sigma, relerr, flags, and Z = Y_r (FP32, KP x KP,
+// row stride KP) to Z[d].  With C = A V and V orthonormal, H = (AV)^T (AV).
+template <int KP>
+__device__ __forceinline__ void eig_body(const float *__restrict__ C, int64_t m, const double *__restrict__ ctc,
+                                         const int *__restrict__ q, int k, int r,
+                                         const double *__restrict__ fro_part, int npanel, float *__restrict__ Z,
+                                         float *__restrict__ sigma, double *__restrict__ relerr,
+                                         int *__restrict__ flags, int *__restrict__ rf, double rf_thr,
+                                         int64_t d) {
+    constexpr int SZ = KP * KP;
+    __shared__ __align__(16) double H[SZ], Wt[SZ];
+    __shared__ __align__(16) double rot[KP];
+    __shared__ double red4[4];
+    __shared__ int perm[KP];
+    __shared__ double s_lam[KP];
+    const int tid = threadIdx.x;
     if (ctc) {
-        // C^T C from the projection's per-band sums, added in band order
         constexpr int NT = KP / 16, NPAIR = NT * (NT + 1) / 2;
         const int nb = (int)((m + PJL_ROWS - 1) / PJL_ROWS);
         const double *src = ctc + d * nb * (NPAIR * 256);
@@ -807,39 +916,14 @@ __device__ __forceinline__ void factor_body(const float *__restrict__ B, int64_t
                 ++ta;
             }
             const int tb = ta + p, a = (e >> 4) & 15, c = e & 15;
-            b0[(16 * ta + a) * KP + 16 * tb + c] = s;
-            if (ta != tb) b0[(16 * tb + c) * KP + 16 * ta + a] = s;
+            H[(16 * ta + a) * KP + 16 * tb + c] = s;
+            if (ta != tb) H[(16 * tb + c) * KP + 16 * ta + a] = s;
         }
-        __syncthreads();
     } else {
-        gram_mfma_acc<KP / 16, false>(Cd, KP, m, b0, KP);
+        for (int e = tid; e < SZ; e += 256) H[e] = 0.0;
+        __syncthreads();
+        gram_mfma_acc<KP / 16, false>(C + d * m * KP, KP, m, H, KP);
     }
-    small_mm<KP, false>(b0, b2, b1);  // b1 = (C^T C) X
-    small_mm<KP, true>(b2, b1, b0);   // b0 = X^T b1
-    double *o = HX + d * 2 * SZ;
-    for (int e = tid; e < SZ; e += 256) {
-        o[e] = b0[e];
-        o[SZ + e] = b2[e];
-    }
-    if (tid == 0) q[d] = nd;
-}
-
-// eig: H = Y diag Y^T (Jacobi), descending order, sigma, relerr, flags, and
-// Z = X Y_r (FP32, KP x KP, row stride KP) to Z[d].
-template <int KP>
-__device__ __forceinline__ void eig_body(const double *__restrict__ HX, const int *__restrict__ q, int k, int r,
-                                         const double *__restrict__ fro_part, int npanel, float *__restrict__ Z,
-                                         float *__restrict__ sigma, double *__restrict__ relerr,
-                                         int *__restrict__ flags, int64_t d) {
-    constexpr int SZ = KP * KP;
-    __shared__ __align__(16) double H[SZ], Wt[SZ];
-    __shared__ __align__(16) double rot[KP];
-    __shared__ double red4[4];
-    __shared__ int perm[KP];
-    __shared__ double s_lam[KP];
-    const int tid = threadIdx.x;
-    const double *Hg = HX + d * 2 * SZ, *Xg = Hg + SZ;
-    for (int e = tid; e < SZ; e += 256) H[e] = Hg[e];
     __syncthreads();
     const int kk = k + (k & 1);  // even size for the parallel ordering
     jacobi_eig_wg<(KP * (KP + 2) / 8 + 255) / 256, (KP * KP / 4 + 255) / 256>(H, Wt, kk, KP, rot, 40, red4);
@@ -858,10 +942,7 @@ __device__ __forceinline__ void eig_body(const double *__restrict__ HX, const in
     float *Zd = Z + d * SZ;
     for (int e = tid; e < SZ; e += 256) {
         const int i = e / KP, t = e % KP;
-        double z = 0.0;
-        if (i < k && t < r)
-            for (int u = 0; u < k; ++u) z += Xg[i * KP + u] * Wt[perm[t] * KP + u];
-        Zd[e] = (float)z;
+        Zd[e] = (i < k && t < r) ? (float)Wt[perm[t] * KP + i] : 0.f;
     }
     __syncthreads();
     double fro2 = 0.0;
@@ -878,11 +959,18 @@ __device__ __forceinline__ void eig_body(const double *__restrict__ HX, const in
         const double s1 = sqrt(fmax(s_lam[0], 0.0));
         if (sr - sr1 <= 1e-6 * s1) fl |= TSK_FLAG_TIE;
         if (flags) flags[d] = fl;
-        if (relerr) relerr[d] = !finite ? (double)qnan : (fro2 > 0.0 ? sqrt(fmax(fro2 - cap, 0.0) / fro2) : 0.0);
+        const double e2 = fro2 > 0.0 ? fmax(fro2 - cap, 0.0) / fro2 : 0.0;
+        if (relerr) relerr[d] = !finite ? (double)qnan : sqrt(e2);
+        // ||A||^2 - sum sigma_i^2 cancels: its rounding (about the FP32 unit
+        // of ||A||^2, from the FP32 accumulation of C) grows relative to the
+        // error as 1 / e^2.  Below rf_thr the error is recomputed from the
+        // explicit residual (refine_body).
+        rf[d] = (relerr && finite && fro2 > 0.0 && e2 < rf_thr) ? 1 : 0;
     }
 }
 
-// outputs: L = C Z (m x r) and R = B^T Z (n x r); NaN for a non-finite A_d.
+// outputs: L = C Z (m x r) and R = V Z (n x r), V^T stored in B's place;
+// NaN for a non-finite A_d.
 // out[t] = sum_u v[u] Z[u][t] for t < r (Z in LDS, row stride KP), four
 // columns per pass (one broadcast 16-byte LDS read per four FMAs; each sum
 // runs over u in order); NaN everywhere when the matrix was not finite.
@@ -965,6 +1053,77 @@ __device__ __forceinline__ void outputs_body(const float *__restrict__ B, int64_
 }
 
 // ---------------------------------------------------------------------------
+// refine: explicit residual ||A_d - L_d R_d^T||_F of the stored values for the
+// matrices eig_body marked (rf[d] != 0), where the Pythagorean form of the
+// error loses the form's tolerance to cancellation.  A workgroup takes
+// RF_ROWS rows of one matrix: its rows of L in LDS, one column j per thread
+// with R_d[j][0..r) in registers, each residual entry a - sum_t L[i][t] R[j][t]
+// summed over t in order in FP32 and squared into an FP64 sum; the band's sum
+// goes to part[d * nbands + band] (refine_final adds them in band order).
+// ---------------------------------------------------------------------------
+constexpr int RF_ROWS = 64;
+
+__device__ __forceinline__ float stored_value(const float *p, int64_t j, float) { return p[j]; }
+__device__ __forceinline__ float stored_value(const uint16_t *p, int64_t j, float) { return bf16_lo(p[j]); }
+__device__ __forceinline__ float stored_value(const uint8_t *p, int64_t j, float inv) {
+    return bf16_lo(e4m3x2_to_bf16((unsigned)p[j], inv, false) & 0xffffu);
+}
+
+template <int RP, typename ET>
+__device__ __forceinline__ void refine_body(const ET *__restrict__ A, const float *__restrict__ scale, int64_t m,
+                                            int64_t n, int64_t ld, int64_t stride, const float *__restrict__ L,
+                                            const float *__restrict__ R, int r, const int *__restrict__ rf,
+                                            double *__restrict__ part, int nbands, int64_t d, int band) {
+    if (!rf[d]) return;  // uniform over the workgroup
+    __shared__ __align__(16) float Ls[RF_ROWS * RP];
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)band * RF_ROWS;
+    const int rows = (int)min((int64_t)RF_ROWS, m - i0);
+    const float *Ld = L + d * m * r;
+    const float *Rd = R + d * n * r;
+    for (int e = tid; e < RF_ROWS * RP; e += 256) {
+        const int i = e / RP, t = e % RP;
+        Ls[e] = (i < rows && t < r) ? Ld[(i0 + i) * r + t] : 0.f;
+    }
+    __syncthreads();
+    const ET *Ad = A + d * stride + i0 * ld;
+    const float inv = scale ? 1.0f / scale[d] : 1.0f;
+    double acc = 0.0;
+    for (int64_t j = tid; j < n; j += 256) {
+        float rv[RP];
+#pragma unroll
+        for (int t = 0; t < RP; ++t) rv[t] = t < r ? Rd[j * r + t] : 0.f;
+        for (int i = 0; i < rows; ++i) {
+            float s = 0.f;
+#pragma unroll
+            for (int t = 0; t < RP; t += 4) {
+                const float4 l = *reinterpret_cast<const float4 *>(Ls + i * RP + t);
+                s = fmaf(l.x, rv[t], s);
+                s = fmaf(l.y, rv[t + 1], s);
+                s = fmaf(l.z, rv[t + 2], s);
+                s = fmaf(l.w, rv[t + 3], s);
+            }
+            const double res = (double)stored_value(Ad + i * ld, j, inv) - (double)s;
+            acc = fma(res, res, acc);
+        }
+    }
+    acc = block_sum_f64(acc, red);
+    if (tid == 0) part[d * nbands + band] = acc;
+}
+
+// relerr[d] = sqrt(sum of the band sums / ||A_d||^2) for the marked matrices.
+__device__ __forceinline__ void refine_final_body(const int *__restrict__ rf, const double *__restrict__ part,
+                                                  int nbands, const double *__restrict__ fro_part, int npanel,
+                                                  double *__restrict__ relerr, int64_t d) {
+    if (!rf[d]) return;
+    double r2 = 0.0, f2 = 0.0;
+    for (int b = 0; b < nbands; ++b) r2 += part[d * nbands + b];
+    for (int p = 0; p < npanel; ++p) f2 += fro_part[d * npanel + p];
+    relerr[d] = sqrt(r2 / f2);
+}
+
+// ---------------------------------------------------------------------------
 // Launch forms.  One problem (tsk_apply): grid = (tile, matrix).  A batch of
 // problems of different shapes (tsk_apply_multi): a flat grid over work
 // items (problem, matrix, tile) listed by the host, each problem's shapes
@@ -984,10 +1143,13 @@ struct ApDesc {
     uint16_t *Bb;
     float *C;
     double *fro;
-    double *HX;             // per matrix [H | X], KP x KP FP64 each
     double *ctc;            // bf16 / e4m3 forms: per-band C^T C sums; FP32 form: null
     float *Z;               // per matrix KP x KP
     int *q;                 // per matrix dead-pivot count
+    int *rf;                // per matrix: error recomputed by refine
+    double *rf_part;        // refine band sums (rf_nb per matrix)
+    int rf_nb;
+    double rf_thr;          // squared-error level below which refine runs
     float *L, *R, *sigma;
     double *relerr;
     int32_t *flags;
@@ -1070,18 +1232,32 @@ __global__ __launch_bounds__(256, 2) void project_bf16_kernel(const ET *A, const
     project_lds_body<NT, pjl_k<ET>(), ET>(A, scale, m, n, ld, stride, Bb, ldv, C, d, band, lds_dyn, ctc);
 }
 template <int KP>
-__global__ __launch_bounds__(256) void factor_kernel(const float *__restrict__ B, int64_t ldb, int64_t n,
-                                                     const float *__restrict__ C, int64_t m, int k,
-                                                     double *__restrict__ HX, int *__restrict__ q,
-                                                     const double *__restrict__ ctc) {
-    factor_body<KP>(B, ldb, n, C, m, k, HX, q, blockIdx.x, ctc);
+__global__ __launch_bounds__(256) void basis_kernel(float *__restrict__ B, int64_t ldb, int64_t n, int k,
+                                                    uint16_t *__restrict__ Bb, int *__restrict__ q) {
+    basis_body<KP>(B, ldb, n, k, Bb, q, blockIdx.x);
 }
 template <int KP>
-__global__ __launch_bounds__(256) void eig_kernel(const double *__restrict__ HX, const int *__restrict__ q, int k,
+__global__ __launch_bounds__(256) void eig_kernel(const float *__restrict__ C, int64_t m,
+                                                  const double *__restrict__ ctc, const int *__restrict__ q, int k,
                                                   int r, const double *__restrict__ fro_part, int npanel,
                                                   float *__restrict__ Z, float *__restrict__ sigma,
-                                                  double *__restrict__ relerr, int *__restrict__ flags) {
-    eig_body<KP>(HX, q, k, r, fro_part, npanel, Z, sigma, relerr, flags, blockIdx.x);
+                                                  double *__restrict__ relerr, int *__restrict__ flags,
+                                                  int *__restrict__ rf, double rf_thr) {
+    eig_body<KP>(C, m, ctc, q, k, r, fro_part, npanel, Z, sigma, relerr, flags, rf, rf_thr, blockIdx.x);
+}
+template <int RP, typename ET>
+__global__ __launch_bounds__(256) void refine_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
+                                                     int64_t m, int64_t n, int64_t ld, int64_t stride,
+                                                     const float *__restrict__ L, const float *__restrict__ R, int r,
+                                                     const int *__restrict__ rf, double *__restrict__ part,
+                                                     int nbands) {
+    refine_body<RP, ET>(A, scale, m, n, ld, stride, L, R, r, rf, part, nbands, blockIdx.y, blockIdx.x);
+}
+__global__ void refine_final_kernel(const int *__restrict__ rf, const double *__restrict__ part, int nbands,
+                                    const double *__restrict__ fro_part, int npanel, double *__restrict__ relerr,
+                                    int64_t count) {
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d < count) refine_final_body(rf, part, nbands, fro_part, npanel, relerr, d);
 }
 template <int KP>
 __global__ __launch_bounds__(256) void outputs_kernel(const float *__restrict__ B, int64_t ldb, int64_t n,
@@ -1132,16 +1308,32 @@ __global__ __launch_bounds__(256, 2) void project_bf16_multi(const ApDesc *__res
                                           it.y, it.z, lds_dyn, D.ctc);
 }
 template <int KP>
-__global__ __launch_bounds__(256) void factor_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+__global__ __launch_bounds__(256) void basis_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
-    factor_body<KP>(D.B, D.ldv, D.n, D.C, D.m, D.k, D.HX, D.q, it.y, D.ctc);
+    basis_body<KP>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y);
 }
 template <int KP>
 __global__ __launch_bounds__(256) void eig_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
-    eig_body<KP>(D.HX, D.q, D.k, D.r, D.fro, D.npanel, D.Z, D.sigma, D.relerr, D.flags, it.y);
+    eig_body<KP>(D.C, D.m, D.ctc, D.q, D.k, D.r, D.fro, D.npanel, D.Z, D.sigma, D.relerr, D.flags, D.rf, D.rf_thr,
+                 it.y);
+}
+// item = (problem, matrix, band); problems without relerr have no items
+template <int RP, typename ET>
+__global__ __launch_bounds__(256) void refine_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const ApDesc &D = P[it.x];
+    refine_body<RP, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.L, D.R, D.r, D.rf, D.rf_part,
+                        D.rf_nb, it.y, it.z);
+}
+// item = (problem, first matrix of a run of 256)
+__global__ void refine_final_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    const int4 it = items[blockIdx.x];
+    const ApDesc &D = P[it.x];
+    const int64_t d = (int64_t)it.y + threadIdx.x;
+    if (d < D.count) refine_final_body(D.rf, D.rf_part, D.rf_nb, D.fro, D.npanel, D.relerr, d);
 }
 template <int KP>
 __global__ __launch_bounds__(256) void outputs_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
@@ -1229,28 +1421,89 @@ static tsk_status allow_lds(tsk_ctx c, const void *f, size_t bytes) {
 
 // factor, eig and outputs launches of one problem (workspace grown here);
 // ctc: the projection's per-band C^T C sums, or null (computed from C)
-static tsk_status finish_enqueue(tsk_ctx c, int kp, const float *B, int64_t ldv, int64_t n, const float *Cm,
-                                 int64_t m, int k, int r, const double *fro, int npanel, int64_t count, float *L,
-                                 float *R, float *sigma, double *relerr, int32_t *flags, const double *ctc) {
-    TSK_TRY(tsk_grow(c, c->ap_HX, sizeof(double) * count * 2 * kp * kp));
-    TSK_TRY(tsk_grow(c, c->ap_Z, sizeof(float) * count * kp * kp + sizeof(int) * count));
-    double *HX = (double *)c->ap_HX.p;
-    float *Z = (float *)c->ap_Z.p;
-    int *q = (int *)(Z + count * kp * kp);
+// Squared relative error below which the reported error is recomputed from
+// the explicit residual (refine_body).  The Pythagorean form's rounding is
+// about 2u / e^2 relative (u = 2^-24, from the FP32 accumulation of C):
+// at most 5e-7 (a twentieth of the FP32 form's 1e-5) from e^2 = 0.25 up, and
+// at most 1.2e-5 (under a eightieth of 1e-3) from e^2 = 1e-2 up for the bf16
+// and e4m3 forms.
+constexpr double RF_THR_F32 = 0.25;
+constexpr double RF_THR_LOWP = 1e-2;
+
+// Per-matrix workspace after Z (count x kp x kp FP32) in ap_Z: q, rf (count
+// ints each), then the refine band sums (count x nbands FP64).
+static size_t apz_bytes(int64_t count, int kp, int nbands) {
+    return ((sizeof(float) * count * kp * kp + sizeof(int) * 2 * count + 7) & ~(size_t)7) +
+           sizeof(double) * count * nbands;
+}
+
+static tsk_status refine_enqueue(tsk_ctx c, const tsk_stack *s, int r, const float *L, const float *R,
+                                 const int *rf, double *part, int nbands, const double *fro, int npanel,
+                                 double *relerr) {
+    const int64_t m = s->m, n = s->n, count = s->count;
+    const int rp = (r + 15) / 16 * 16;
+    const dim3 g((unsigned)nbands, (unsigned)count);
+#define TSK_RF(RPV)                                                                                                do {                                                                                                               if (s->dtype == TSK_F32)                                                                                           hipLaunchKernelGGL((refine_kernel<RPV, float>), g, dim3(256), 0, c->stream, (const float *)s->A,                                  s->scale, m, n, s->ld, s->stride, L, R, r, rf, part, nbands);                           else if (s->dtype == TSK_BF16)                                                                                     hipLaunchKernelGGL((refine_kernel<RPV, uint16_t>), g, dim3(256), 0, c->stream,                                                    (const uint16_t *)s->A, s->scale, m, n, s->ld, s->stride, L, R, r, rf, part,                                   nbands);                                                                                else                                                                                                               hipLaunchKernelGGL((refine_kernel<RPV, uint8_t>), g, dim3(256), 0, c->stream,                                                     (const uint8_t *)s->A, s->scale, m, n, s->ld, s->stride, L, R, r, rf, part,                                    nbands);                                                                            } while (0)
+    TSK_LAUNCH(c, TSK_KERNEL_ERROR, TSK_KP_SWITCH(rp / 16, TSK_RF(16), TSK_RF(32), TSK_RF(48), TSK_RF(64)));
+#undef TSK_RF
+    TSK_LAUNCH(c, TSK_KERNEL_ERROR,
+               hipLaunchKernelGGL(refine_final_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, c->stream,
+                                  rf, (const double *)part, nbands, fro, npanel, relerr, count));
+    return TSK_OK;
+}
+
+// Per-matrix small workspace in ap_Z: Z (count x kp x kp FP32), q and rf
+// (count ints each), the refine band sums (count x nbands FP64).
+struct ApSmall {
+    float *Z;
+    int *q, *rf;
+    double *part;
+    int nbands;
+};
+static tsk_status small_ws(tsk_ctx c, int64_t count, int kp, int64_t m, ApSmall &w) {
+    w.nbands = (int)((m + RF_ROWS - 1) / RF_ROWS);
+    TSK_TRY(tsk_grow(c, c->ap_Z, apz_bytes(count, kp, w.nbands)));
+    w.Z = (float *)c->ap_Z.p;
+    w.q = (int *)(w.Z + count * kp * kp);
+    w.rf = w.q + count;
+    w.part = (double *)((char *)c->ap_Z.p + apz_bytes(count, kp, 0));
+    return TSK_OK;
+}
+
+// The row basis (CholeskyQR2 of B_d, written over B as V^T; Bb: its bf16
+// pair for the bf16 and e4m3 projections, else null).
+static tsk_status basis_enqueue(tsk_ctx c, int kp, float *B, int64_t ldv, int64_t n, int k, uint16_t *Bb,
+                                int64_t count, const ApSmall &w) {
+    const dim3 g((unsigned)count);
+#define TSK_BAS(KPV)                                                                                              \
+    TSK_LAUNCH(c, TSK_KERNEL_QR,                                                                                  \
+               hipLaunchKernelGGL(basis_kernel<KPV>, g, dim3(256), 0, c->stream, B, ldv, n, k, Bb, w.q))
+    TSK_KP_SWITCH(kp / 16, TSK_BAS(16), TSK_BAS(32), TSK_BAS(48), TSK_BAS(64))
+#undef TSK_BAS
+    return TSK_OK;
+}
+
+// eig, outputs and (with relerr) refine launches of one problem; ctc: the
+// projection's per-band C^T C sums, or null (computed from C)
+static tsk_status finish_enqueue(tsk_ctx c, const tsk_stack *s, int kp, const float *B, int64_t ldv,
+                                 const float *Cm, int k, int r, const double *fro, int npanel, float *L, float *R,
+                                 float *sigma, double *relerr, int32_t *flags, const double *ctc,
+                                 const ApSmall &w) {
+    const int64_t m = s->m, n = s->n, count = s->count;
+    const double thr = s->dtype == TSK_F32 ? RF_THR_F32 : RF_THR_LOWP;
     const dim3 g((unsigned)count);
 #define TSK_FIN(KPV)                                                                                              \
     do {                                                                                                          \
-        TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(factor_kernel<KPV>, g, dim3(256), 0, c->stream, B, ldv, n, \
-                                                        Cm, m, k, HX, q, ctc));                                   \
         TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                          \
-                   hipLaunchKernelGGL(eig_kernel<KPV>, g, dim3(256), 0, c->stream, (const double *)HX,            \
-                                      (const int *)q, k, r, fro, npanel, Z, sigma, relerr, flags));              \
+                   hipLaunchKernelGGL(eig_kernel<KPV>, g, dim3(256), 0, c->stream, Cm, m, ctc, (const int *)w.q,  \
+                                      k, r, fro, npanel, w.Z, sigma, relerr, flags, w.rf, thr));                 \
         TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                          \
                    hipLaunchKernelGGL(outputs_kernel<KPV>, g, dim3(256), 0, c->stream, B, ldv, n, Cm, m, k, r,    \
-                                      fro, npanel, (const float *)Z, L, R));                                      \
+                                      fro, npanel, (const float *)w.Z, L, R));                                    \
     } while (0)
     TSK_KP_SWITCH(kp / 16, TSK_FIN(16), TSK_FIN(32), TSK_FIN(48), TSK_FIN(64))
 #undef TSK_FIN
+    if (relerr) TSK_TRY(refine_enqueue(c, s, r, L, R, w.rf, w.part, w.nbands, fro, npanel, relerr));
     return TSK_OK;
 }
 
@@ -1264,6 +1517,8 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
     TSK_TRY(tsk_grow(c, c->ap_B, sizeof(float) * count * kp * ldv));
     TSK_TRY(tsk_grow(c, c->ap_C, sizeof(float) * count * m * kp));
     TSK_TRY(tsk_grow(c, c->ap_fro, sizeof(double) * count * npanel));
+    ApSmall w;
+    TSK_TRY(small_ws(c, count, kp, m, w));
     float *St = (float *)c->ap_St.p, *B = (float *)c->ap_B.p, *Cm = (float *)c->ap_C.p;
     double *fro = (double *)c->ap_fro.p;
     const float *A = (const float *)s->A;
@@ -1277,6 +1532,7 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
                                   (const float *)St, B, ldv, fro, npanel))
     TSK_KP_SWITCH(kp / 16, TSK_SK(1), TSK_SK(2), TSK_SK(3), TSK_SK(4))
 #undef TSK_SK
+    TSK_TRY(basis_enqueue(c, kp, B, ldv, n, k, nullptr, count, w));
     const int nb = (int)((m + PJ_ROWS - 1) / PJ_ROWS);
     const dim3 gp((unsigned)(nb * count));
 #define TSK_PJ(NTV)                                                                                           \
@@ -1285,8 +1541,7 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
                                   (const float *)B, ldv, Cm, count, nb))
     TSK_KP_SWITCH(kp / 16, TSK_PJ(1), TSK_PJ(2), TSK_PJ(3), TSK_PJ(4))
 #undef TSK_PJ
-    return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags,
-                          nullptr);
+    return finish_enqueue(c, s, kp, B, ldv, Cm, k, r, fro, npanel, L, R, sigma, relerr, flags, nullptr, w);
 }
 
 // bf16 form (ET = uint16_t, bf16 stack) and e4m3 form (ET = uint8_t, e4m3
@@ -1304,6 +1559,13 @@ static tsk_status apply_lowp_enqueue(tsk_ctx c, const float *S, int k, const tsk
     TSK_TRY(tsk_grow(c, c->ap_Bb, sizeof(uint16_t) * count * 2 * kp * ldv));
     TSK_TRY(tsk_grow(c, c->ap_C, sizeof(float) * count * m * kp));
     TSK_TRY(tsk_grow(c, c->ap_fro, sizeof(double) * count * npanel));
+    const int nb = (int)((m + PJL_ROWS - 1) / PJL_ROWS);
+    // the projection's per-band C^T C sums
+    const int npair = (kp / 16) * (kp / 16 + 1) / 2;
+    TSK_TRY(tsk_grow(c, c->ap_HX, sizeof(double) * count * (int64_t)nb * npair * 256));
+    ApSmall w;
+    TSK_TRY(small_ws(c, count, kp, m, w));
+    double *ctc = (double *)c->ap_HX.p;
     uint16_t *Sb = (uint16_t *)c->ap_Sb.p, *Bb = (uint16_t *)c->ap_Bb.p;
     float *B = (float *)c->ap_B.p, *Cm = (float *)c->ap_C.p;
     double *fro = (double *)c->ap_fro.p;
@@ -1319,13 +1581,9 @@ static tsk_status apply_lowp_enqueue(tsk_ctx c, const float *S, int k, const tsk
                                   s->ld, s->stride, (const uint16_t *)Sb, mp, B, Bb, ldv, fro, npanel))
     TSK_KP_SWITCH(kp / 16, TSK_SKB(1), TSK_SKB(2), TSK_SKB(3), TSK_SKB(4))
 #undef TSK_SKB
-    const int nb = (int)((m + PJL_ROWS - 1) / PJL_ROWS);
+    TSK_TRY(basis_enqueue(c, kp, B, ldv, n, k, Bb, count, w));
     const dim3 gp((unsigned)(nb * count));
     const size_t pjl = (size_t)std::max(pjl_lds_bytes(pjl_k<ET>(), (int)sizeof(ET), kp), pjl_ctc_bytes(kp));
-    // the per-band C^T C sums follow the per-matrix [H | X] in one buffer
-    const int npair = (kp / 16) * (kp / 16 + 1) / 2;
-    TSK_TRY(tsk_grow(c, c->ap_HX, sizeof(double) * count * (2 * kp * kp + (int64_t)nb * npair * 256)));
-    double *ctc = (double *)c->ap_HX.p + count * 2 * kp * kp;
 #define TSK_PJB(NTV)                                                                                          \
     {                                                                                                         \
         TSK_TRY(allow_lds(c, (const void *)project_bf16_kernel<NTV, ET>, pjl));                               \
@@ -1336,7 +1594,7 @@ static tsk_status apply_lowp_enqueue(tsk_ctx c, const float *S, int k, const tsk
     }
     TSK_KP_SWITCH(kp / 16, TSK_PJB(1), TSK_PJB(2), TSK_PJB(3), TSK_PJB(4))
 #undef TSK_PJB
-    return finish_enqueue(c, kp, B, ldv, n, Cm, m, k, r, fro, npanel, count, L, R, sigma, relerr, flags, ctc);
+    return finish_enqueue(c, s, kp, B, ldv, Cm, k, r, fro, npanel, L, R, sigma, relerr, flags, ctc, w);
 }
 
 tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
@@ -1350,14 +1608,14 @@ tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_st
 // and work-item lists into pinned memory, copies them in one transfer, then
 // launches: one sketch-preparation launch for all problems, and per
 // sketch-size class (kp / 16) one launch of each later phase (sketch,
-// project, factor, eig, outputs).
+// basis, project, eig, outputs; then refine per class of ceil(r / 16)).
 // Items are ordered largest problem first, so the long items start early.
 tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute) {
     const bool lowp = compute != TSK_F32;
     const int panel = lowp ? SKB_PANEL : SK_PANEL;
     const int band = lowp ? PJL_ROWS : PJ_ROWS;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    constexpr int NREG = 9;  // workspace regions per problem
+    constexpr int NREG = 11;  // workspace regions per problem
     std::vector<ApDesc> desc(np);
     std::vector<size_t> off(np * NREG);
     size_t ws = 0;
@@ -1383,17 +1641,21 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
         D.sigma = pr[i].sigma;
         D.relerr = pr[i].relerr;
         D.flags = pr[i].flags;
+        D.rf_nb = (int)((A.m + RF_ROWS - 1) / RF_ROWS);
+        D.rf_thr = lowp ? RF_THR_LOWP : RF_THR_F32;
         const size_t sz[NREG] = {lowp ? sizeof(uint16_t) * 2 * D.kp * D.mp : sizeof(float) * D.m * D.kp,
                                  sizeof(float) * D.count * D.kp * D.ldv,
                                  lowp ? sizeof(uint16_t) * D.count * 2 * D.kp * D.ldv : 0,
                                  sizeof(float) * D.count * D.m * D.kp,
                                  sizeof(double) * D.count * D.npanel,
-                                 sizeof(double) * D.count * 2 * D.kp * D.kp,
+                                 0,  // (unused region)
                                  sizeof(float) * D.count * D.kp * D.kp,
                                  sizeof(int) * D.count,
                                  lowp ? sizeof(double) * D.count * ((A.m + band - 1) / band) *
                                             ((D.kp / 16) * (D.kp / 16 + 1) / 2 * 256)
-                                      : 0};
+                                      : 0,
+                                 sizeof(int) * D.count,
+                                 sizeof(double) * D.count * D.rf_nb};
         for (int j = 0; j < NREG; ++j) {
             off[i * NREG + j] = ws;
             ws += al(sz[j]);
@@ -1410,10 +1672,11 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
         D.Bb = lowp ? (uint16_t *)(base + o[2]) : nullptr;
         D.C = (float *)(base + o[3]);
         D.fro = (double *)(base + o[4]);
-        D.HX = (double *)(base + o[5]);
         D.Z = (float *)(base + o[6]);
         D.q = (int *)(base + o[7]);
         D.ctc = lowp ? (double *)(base + o[8]) : nullptr;
+        D.rf = (int *)(base + o[9]);
+        D.rf_part = (double *)(base + o[10]);
     }
     // work items: problems largest first within each list
     std::vector<int> order(np);
@@ -1459,6 +1722,24 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
             }
             cnt[ph][cl] = items.size() - start[ph][cl];
         }
+    // refine of the marked matrices' errors, per class of ceil(r / 16), then
+    // its final sums (runs of 256 matrices); problems without relerr have none
+    size_t rstart[5] = {}, rcnt[5] = {};
+    for (int cl = 1; cl <= 4; ++cl) {
+        rstart[cl] = items.size();
+        for (int i : order) {
+            const ApDesc &D = desc[i];
+            if (!D.relerr || (D.r + 15) / 16 != cl) continue;
+            for (int64_t d = 0; d < D.count; ++d)
+                for (int t = 0; t < D.rf_nb; ++t) items.push_back(int4{i, (int)d, t, 0});
+        }
+        rcnt[cl] = items.size() - rstart[cl];
+    }
+    const size_t fstart = items.size();
+    for (int i : order)
+        if (desc[i].relerr)
+            for (int64_t d = 0; d < desc[i].count; d += 256) items.push_back(int4{i, (int)d, 0, 0});
+    const size_t fcnt = items.size() - fstart;
     // one transfer: descriptors then items
     const size_t dbytes = al(sizeof(ApDesc) * np), ibytes = sizeof(int4) * items.size();
     if (c->mp_ev) {
@@ -1525,7 +1806,7 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
     }
 #define TSK_MFA(CL)                                                                                          \
     if (cnt[2][CL])                                                                                          \
-        TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(factor_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),       \
+        TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(basis_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),        \
                                                         dim3(256), 0, c->stream, P, I + start[2][CL]));
 #define TSK_MEG(CL)                                                                                          \
     if (cnt[2][CL])                                                                                          \
@@ -1536,10 +1817,29 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
         TSK_LAUNCH(c, TSK_KERNEL_FINISH, hipLaunchKernelGGL(outputs_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),  \
                                                             dim3(256), 0, c->stream, P, I + start[2][CL]));
     TSK_MSK(1) TSK_MSK(2) TSK_MSK(3) TSK_MSK(4)
-    TSK_MPJ(1) TSK_MPJ(2) TSK_MPJ(3) TSK_MPJ(4)
     TSK_MFA(1) TSK_MFA(2) TSK_MFA(3) TSK_MFA(4)
+    TSK_MPJ(1) TSK_MPJ(2) TSK_MPJ(3) TSK_MPJ(4)
     TSK_MEG(1) TSK_MEG(2) TSK_MEG(3) TSK_MEG(4)
     TSK_MOU(1) TSK_MOU(2) TSK_MOU(3) TSK_MOU(4)
+#define TSK_MRF(CL)                                                                                           \
+    if (rcnt[CL]) {                                                                                           \
+        const dim3 g((unsigned)rcnt[CL]);                                                                     \
+        const int4 *It = I + rstart[CL];                                                                      \
+        if (!lowp)                                                                                            \
+            TSK_LAUNCH(c, TSK_KERNEL_ERROR,                                                                   \
+                       hipLaunchKernelGGL((refine_multi<16 * CL, float>), g, dim3(256), 0, c->stream, P, It)); \
+        else if (e4)                                                                                          \
+            TSK_LAUNCH(c, TSK_KERNEL_ERROR,                                                                   \
+                       hipLaunchKernelGGL((refine_multi<16 * CL, uint8_t>), g, dim3(256), 0, c->stream, P, It)); \
+        else                                                                                                  \
+            TSK_LAUNCH(c, TSK_KERNEL_ERROR,                                                                   \
+                       hipLaunchKernelGGL((refine_multi<16 * CL, uint16_t>), g, dim3(256), 0, c->stream, P, It)); \
+    }
+    TSK_MRF(1) TSK_MRF(2) TSK_MRF(3) TSK_MRF(4)
+    if (fcnt)
+        TSK_LAUNCH(c, TSK_KERNEL_ERROR, hipLaunchKernelGGL(refine_final_multi, dim3((unsigned)fcnt), dim3(256), 0,
+                                                           c->stream, P, I + fstart));
+#undef TSK_MRF
 #undef TSK_MSK
 #undef TSK_MPJ
 #undef TSK_MFA

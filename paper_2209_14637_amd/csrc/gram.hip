@@ -740,8 +740,12 @@ tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *
     const int T = nb * (nb + 1) / 2;
     // bf16 and e4m3 stacks (slices under 4 GiB) take the 256x256 tiles
     const int eb = s->dtype == TSK_BF16 ? 2 : 1;
+    // TSK_GRAM_TILE128 (diagnostic) forces the 128x128 kernels, which
+    // otherwise serve only slices of 4 GiB and more, so tests can check them
+    // on small stacks
+    const bool force128 = getenv("TSK_GRAM_TILE128") != nullptr;
     const bool wide = ((compute == TSK_BF16 && s->dtype == TSK_BF16) || compute == TSK_F8E4M3) &&
-                      m * s->ld * eb < ((int64_t)1 << 32);
+                      m * s->ld * eb < ((int64_t)1 << 32) && !force128;
     const int nbw = (int)((m + WT - 1) / WT);
     const int TW = nbw * (nbw + 1) / 2;
     // wide tiles: one workgroup per CU, 32 resident per XCD; 128x128 tiles:

@@ -216,12 +216,27 @@ void tsk_destroy(tsk_ctx c) {
         if (b->p) (void)hipFree(b->p);
     if (c->mp_pin) (void)hipHostFree(c->mp_pin);
     if (c->mp_ev) (void)hipEventDestroy(c->mp_ev);
+    if (c->switch_ev) (void)hipEventDestroy(c->switch_ev);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     delete c;
 }
 
 tsk_status tsk_set_stream(tsk_ctx c, void *hip_stream) {
     if (!c) return TSK_E_ARG;
+    if ((hipStream_t)hip_stream == c->stream) return TSK_OK;
+    // The workspace is shared by every call of the context: work enqueued
+    // later on the new stream waits for everything enqueued on the old one.
+    DeviceGuard g(c->device);
+    if (!c->switch_ev) {
+        hipError_t e = hipEventCreateWithFlags(&c->switch_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            c->switch_ev = nullptr;
+            return tsk_hip(c, e, "stream switch event");
+        }
+    }
+    hipError_t e = hipEventRecord(c->switch_ev, c->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)hip_stream, c->switch_ev, 0);
+    if (e != hipSuccess) return tsk_hip(c, e, "stream switch");
     c->stream = (hipStream_t)hip_stream;
     return TSK_OK;
 }
@@ -328,7 +343,7 @@ tsk_status tsk_apply_multi(tsk_ctx c, const tsk_problem *probs, int32_t nprobs, 
             c->err = "problem " + std::to_string(i) + ": " + c->err;
             return st;
         }
-        items += p.A.count * (p.A.n / 64 + p.A.m / 64 + 3);
+        items += p.A.count * (p.A.n / 64 + 2 * (p.A.m / 64) + 6);
     }
     if (items > ((int64_t)1 << 31) - 1) return tsk_fail(c, TSK_E_SHAPE, "tsk_apply_multi: batch too large");
     return tsk_apply_multi_enqueue(c, probs, nprobs, compute);

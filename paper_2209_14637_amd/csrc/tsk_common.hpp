@@ -568,6 +568,7 @@ struct tsk_ctx_s {
     void *mp_pin = nullptr;          // pinned host copy of the batch tables
     size_t mp_pin_bytes = 0;
     hipEvent_t mp_ev = nullptr;      // recorded after the last batch table copy
+    hipEvent_t switch_ev = nullptr;  // orders the old stream before a new one (tsk_set_stream)
     // eigensolver controls
     int eig_block = 0, eig_max_iter = 300, eig_check = 6;
     double eig_tol = 0.0;  // 0: TSK_EIG_TOL_F32 / TSK_EIG_TOL_BF16 by the Gram's precision

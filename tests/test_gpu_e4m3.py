@@ -9,11 +9,11 @@ Gates:
   (e4m3 value / scale) to FP32 accumulation accuracy;
 * SCW on the dequantised values: the error within 1e-4 of the oracle's on
   those same values (only FP32 accumulation and 16-bit S/B splits differ);
-* SCW error on the FP32 values against the oracle on the FP32 values is
-  REPORTED (printed), not gated: e4m3 keeps 4 significant bits, so the
-  stored matrix itself differs from the FP32 one by about 4% in Frobenius
-  norm.  On the full-size Student-t stream the e4m3 form misses the 1e-3
-  gate (reported with a loose bound); the bf16 form is gated there.
+* full-size Student-t stream, every test matrix, errors of the GPU factors
+  evaluated on the host against the FP32 inputs: the bf16-trained sketch
+  with bf16 and with e4m3 test matrices within 1e-3 of the oracle; the
+  e4m3-trained sketch at the same 1e-3, marked as an expected failure (it
+  misses: e4m3 keeps 3 mantissa bits).
 """
 import json
 import os
@@ -212,15 +212,12 @@ def test_e4m3_invalid_combinations(ctx):
         ctx.gram(a, compute="e4m3")              # FP32 stack, e4m3 compute
 
 
-def test_e4m3_full_size_golden(ctx, orc):
+@pytest.fixture(scope="module")
+def t3full(ctx, orc):
     """The 1920 x 1080 Student-t stream (4000 training slices, k = 40,
-    r = 20) against the oracle's stored errors on the FP32 values (first 32
-    test matrices).  Gated at tau = 1e-3: bf16 training and bf16 apply on
-    this stream.  Reported beside it, with a loose sanity bound of 5e-3: the
-    e4m3-trained sketch applied to bf16 and to e4m3 test matrices.  e4m3
-    keeps 3 mantissa bits; the rounding noise it adds to the training Gram
-    moves the eigenvectors near the noise bulk of this noise-dominated
-    stream by more than the gate allows."""
+    r = 20): sketches trained in e4m3 and in bf16 on the GPU, the oracle's
+    stored values (FP32 inputs, every test matrix), and the test matrices."""
+    from paper_2209_14637_amd import tsk
     path = os.path.join(HERE, "golden", "t3stream_1920x1080_k40_r20.json")
     g = json.load(open(path))
     spec = synth.spec_fp8_1920()
@@ -232,25 +229,49 @@ def test_e4m3_full_size_golden(ctx, orc):
         q8.append(ctx.stage(tr, "e4m3"))
         b16.append(ctx.stage(tr, "bf16"))
         del tr
-    from paper_2209_14637_amd import tsk
     Tq = tsk.Staged(torch.cat([x.data for x in q8]), spec.n, "e4m3", torch.cat([x.scale for x in q8]))
     Tb = tsk.Staged(torch.cat([x.data for x in b16]), spec.n, "bf16")
     del q8, b16
     S8, lam8, it8, _ = ctx.train(Tq, spec.k, compute="e4m3")
     S16, lam16, it16, _ = ctx.train(Tb, spec.k, compute="bf16")
     del Tq, Tb
+    torch.cuda.empty_cache()
     lam_orc = np.array(g["lambda"])
     for nm, lam, it in (("e4m3", lam8, it8), ("bf16", lam16, it16)):
         _say(f"  {nm} training: lambda rel dev {np.abs(np.array(lam) - lam_orc).max() / lam_orc[0]:.2e}, iters {it}")
-    n_err = len(g["relerr"])
-    te_d = dev32(st.test(n_err))
     ref = np.array(g["relerr"])
-    dev = {}
-    for tag, S, form in (("bf16/bf16", S16, "bf16"), ("e4m3/bf16", S8, "bf16"), ("e4m3/e4m3", S8, "e4m3")):
-        out = ctx.apply(S, ctx.stage(te_d, form), spec.r)
-        e = ctx.error(te_d, out["L"], out["R"])
-        torch.cuda.synchronize()
-        dev[tag] = float(np.max(np.abs(e.cpu().numpy() - ref) / ref))
-    _say("  max |de|/e over %d matrices (training/apply): %s" % (n_err, ", ".join(f"{k} {v:.2e}" for k, v in dev.items())))
-    assert dev["bf16/bf16"] <= TAU_E4M3
-    assert dev["e4m3/bf16"] <= 5e-3 and dev["e4m3/e4m3"] <= 5e-3
+    assert ref.size == spec.n_test
+    _say("generating 1000 test matrices")
+    te = st.test()
+    return spec, g, {"e4m3": S8, "bf16": S16}, te, ref
+
+
+def _t3_dev(ctx, orc, t3full, train, form):
+    spec, g, S, te, ref = t3full
+    out = ctx.apply(S[train], ctx.stage(dev32(te), form), spec.r)
+    torch.cuda.synchronize()
+    e_f = out["relerr"].cpu().numpy()
+    ev = orc.error(te, out["L"].cpu().numpy(), out["R"].cpu().numpy())
+    return float(np.max(np.abs(ev - ref) / ref)), e_f, ev
+
+
+@pytest.mark.parametrize("form", ["bf16", "e4m3"])
+def test_t3_bf16_trained_full_size(ctx, orc, t3full, form):
+    """The bf16-trained sketch applied to bf16 and to e4m3 test matrices:
+    every test matrix's error (GPU factors, evaluated on the host in FP64
+    against the FP32 inputs) within 1e-3 of the oracle's."""
+    d, e_f, ev = _t3_dev(ctx, orc, t3full, "bf16", form)
+    _say(f"  bf16 training / {form} apply: max |de|/e over {ev.size} matrices {d:.2e}")
+    assert d <= TAU_E4M3
+
+
+@pytest.mark.xfail(reason="e4m3 training misses 1e-3 on this stream (measured 1.4e-3 with the e4m3 apply, 2.8e-3 "
+                          "with the bf16 apply): e4m3 keeps 3 mantissa bits, and the rounding noise it adds to the "
+                          "training Gram moves the eigenvectors near the noise bulk of this noise-dominated stream",
+                   strict=False)
+@pytest.mark.parametrize("form", ["bf16", "e4m3"])
+def test_t3_e4m3_trained_full_size(ctx, orc, t3full, form):
+    """The e4m3-trained sketch, gated at the same 1e-3 as every other form."""
+    d, e_f, ev = _t3_dev(ctx, orc, t3full, "e4m3", form)
+    _say(f"  e4m3 training / {form} apply: max |de|/e over {ev.size} matrices {d:.2e}")
+    assert d <= TAU_E4M3

@@ -102,3 +102,72 @@ def test_multi_reuse_and_invalid(ctx, orc):
     with pytest.raises(tsk.TskError) as ei:
         ctx.apply_multi([probs[0], (S, A, S.shape[0])])  # r == k
     assert ei.value.status == tsk.TSK_E_ARG and "problem 1" in str(ei.value)
+
+
+def test_batch_full_shapes(ctx, orc):
+    """The uneven-shape batch workload at its real sizes: 8 streams of shapes
+    (256,192) .. (2048,1536), k in {10, 20, 40}, r = k/2, 2000 test matrices
+    interleaved at random and applied in batches of 256 through
+    tsk_apply_multi (bf16 storage, sketches trained on the GPU in bf16 from
+    100 slices per stream).  EVERY test matrix against the oracle's stored
+    errors (FP32 inputs, the oracle's own FP64 training): the GPU factors'
+    error evaluated on the host in FP64 and the fused error within 1e-3; the
+    resolvable leading rows of each stream's S within 1e-2."""
+    import json
+    import os
+
+    from angles import sketch_angles
+    from paper_2209_14637_amd import tsk
+    here = os.path.dirname(os.path.abspath(__file__))
+    g = json.load(open(os.path.join(here, "golden", "batch_8streams_k10-40.json")))
+    Sg = np.load(os.path.join(here, "golden", "batch_8streams_k10-40_S.npz"))
+    n_test, bsz = g["count"], 256
+    order = synth.batch_order(n_test)
+    ns = len(synth.BATCH_SHAPES)
+    specs = [synth.spec_batch_stream(s, n_test=n_test) for s in range(ns)]
+    S, te, te16 = [], [], []
+    for s, spec in enumerate(specs):
+        _say(f"batch stream {s}: {spec.m}x{spec.n}, k={spec.k}")
+        st = synth.Stream(spec)
+        tr = torch.from_numpy(st.train()).cuda()
+        Sd, lam, _, _ = ctx.train(ctx.stage(tr, "bf16"), spec.k, compute="bf16")
+        del tr
+        gs = g["streams"][s]
+        a_all, a_res = sketch_angles(Sd.cpu().numpy(), Sg[f"S{s}"], gs["lambda"])
+        _say(f"  S angle all {a_all:.2e}, resolvable {max(a_res.values()):.2e}")
+        assert max(a_res.values()) <= 1e-2
+        S.append(Sd)
+        t = st.test(gs["n_test_used"])
+        te.append(t)
+        te16.append(ctx.stage(dev32(t), "bf16"))
+    # batches of 256 slots: per stream, its next consecutive test matrices
+    outs, nxt = [[None] * len(te[s]) for s in range(ns)], [0] * ns
+    for b0 in range(0, n_test, bsz):
+        ids = order[b0:b0 + bsz]
+        probs, where = [], []
+        for s in range(ns):
+            c = int((ids == s).sum())
+            if c:
+                d0 = nxt[s]
+                probs.append((S[s], tsk.Staged(te16[s].data[d0:d0 + c], specs[s].n, "bf16"), specs[s].r))
+                where.append((s, d0, c))
+                nxt[s] += c
+        res = ctx.apply_multi(probs)
+        torch.cuda.synchronize()
+        for (s, d0, c), o in zip(where, res):
+            L, R = o["L"].cpu().numpy(), o["R"].cpu().numpy()
+            ef = o["relerr"].cpu().numpy()
+            for i in range(c):
+                outs[s][d0 + i] = (L[i], R[i], ef[i])
+    worst_v = worst_f = 0.0
+    for s in range(ns):
+        ref = np.array(g["streams"][s]["relerr"])
+        L = np.stack([x[0] for x in outs[s]])
+        R = np.stack([x[1] for x in outs[s]])
+        ef = np.array([x[2] for x in outs[s]])
+        ev = orc.error(te[s], L, R)
+        dv, df = np.max(np.abs(ev - ref) / ref), np.max(np.abs(ef - ref) / ref)
+        _say(f"  stream {s}: {ref.size} matrices, max |de|/e validator {dv:.2e}, fused {df:.2e}")
+        worst_v, worst_f = max(worst_v, dv), max(worst_f, df)
+    assert sum(len(x) for x in outs) == n_test
+    assert worst_v <= TAU["bf16"] and worst_f <= TAU["bf16"]

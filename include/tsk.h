@@ -182,6 +182,22 @@ tsk_status tsk_apply(tsk_ctx ctx, const float *S, int32_t k, const tsk_stack *te
                      int32_t compute, float *L, float *R, float *sigma, double *relerr,
                      int32_t *flags);
 
+/* tsk_apply for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, validation and results (bit for bit) as tsk_apply, but the
+ * workspace is a fixed 64 MiB device array inside the library (one per GPU,
+ * held until the process ends) instead of the context's grown workspace;
+ * nothing is allocated or freed.  The stack is processed in groups of as
+ * many matrices as fit (about 60 of 1920 x 1080 at k = 40), one after
+ * another on the context's stream.  A single matrix whose workspace exceeds
+ * the array returns TSK_E_SHAPE (launches nothing).  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other contexts or threads) race and must be serialised by the caller.
+ * Enqueue only. */
+tsk_status tsk_apply_noalloc(tsk_ctx ctx, const float *S, int32_t k, const tsk_stack *test, int32_t r,
+                             int32_t compute, float *L, float *R, float *sigma, double *relerr,
+                             int32_t *flags);
+
 /* One problem of a batch: the test matrices of one stream (any shape), its
  * sketch and outputs, exactly as the arguments of tsk_apply. */
 typedef struct {

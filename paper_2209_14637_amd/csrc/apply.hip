@@ -28,7 +28,9 @@
 // up to 16; rows k..kp-1 of S, B_d and V_d^T are zero, so no masking is
 // needed on them.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -1430,13 +1432,6 @@ static tsk_status allow_lds(tsk_ctx c, const void *f, size_t bytes) {
 constexpr double RF_THR_F32 = 0.25;
 constexpr double RF_THR_LOWP = 1e-2;
 
-// Per-matrix workspace after Z (count x kp x kp FP32) in ap_Z: q, rf (count
-// ints each), then the refine band sums (count x nbands FP64).
-static size_t apz_bytes(int64_t count, int kp, int nbands) {
-    return ((sizeof(float) * count * kp * kp + sizeof(int) * 2 * count + 7) & ~(size_t)7) +
-           sizeof(double) * count * nbands;
-}
-
 static tsk_status refine_enqueue(tsk_ctx c, const tsk_stack *s, int r, const float *L, const float *R,
                                  const int *rf, double *part, int nbands, const double *fro, int npanel,
                                  double *relerr) {
@@ -1452,22 +1447,84 @@ static tsk_status refine_enqueue(tsk_ctx c, const tsk_stack *s, int r, const flo
     return TSK_OK;
 }
 
-// Per-matrix small workspace in ap_Z: Z (count x kp x kp FP32), q and rf
-// (count ints each), the refine band sums (count x nbands FP64).
+// Workspace of one SCW call on `count` matrices of one shape, carved from
+// one buffer: the prepared sketch (FP32 form: S^T, m x kp; bf16 and e4m3
+// forms: the bf16 pair of S in MFMA lane order, kp x mp), then per matrix
+// B / V^T (kp x ldv FP32), its bf16 pair (2kp x ldv), C (m x kp FP32), the
+// ||A||^2 partials (npanel FP64), the projection's C^T C band sums (bf16
+// and e4m3 forms), Z (kp x kp FP32), q and rf (ints) and the refine band
+// sums (nbands FP64).  Every region starts on a 256-byte boundary.
 struct ApSmall {
     float *Z;
     int *q, *rf;
     double *part;
     int nbands;
 };
-static tsk_status small_ws(tsk_ctx c, int64_t count, int kp, int64_t m, ApSmall &w) {
-    w.nbands = (int)((m + RF_ROWS - 1) / RF_ROWS);
-    TSK_TRY(tsk_grow(c, c->ap_Z, apz_bytes(count, kp, w.nbands)));
-    w.Z = (float *)c->ap_Z.p;
-    w.q = (int *)(w.Z + count * kp * kp);
-    w.rf = w.q + count;
-    w.part = (double *)((char *)c->ap_Z.p + apz_bytes(count, kp, 0));
-    return TSK_OK;
+struct ApWs {
+    float *St;
+    uint16_t *Sb;
+    float *B;
+    uint16_t *Bb;
+    float *C;
+    double *fro;
+    double *ctc;
+    ApSmall w;
+};
+struct ApLayout {
+    size_t off[11];
+    size_t total;
+};
+constexpr int AP_REGIONS = 11;
+
+static ApLayout apply_layout(const tsk_stack *s, int k, int64_t count) {
+    const bool lowp = s->dtype != TSK_F32;
+    const int64_t m = s->m, n = s->n;
+    const int kp = (k + 15) / 16 * 16;
+    const int panel = lowp ? SKB_PANEL : SK_PANEL;
+    const int npanel = (int)((n + panel - 1) / panel);
+    const int64_t ldv = (int64_t)npanel * panel, mp = (m + 31) / 32 * 32;
+    const int nb = (int)((m + PJL_ROWS - 1) / PJL_ROWS);
+    const int npair = (kp / 16) * (kp / 16 + 1) / 2;
+    const int nbands = (int)((m + RF_ROWS - 1) / RF_ROWS);
+    const size_t sz[AP_REGIONS] = {
+        lowp ? sizeof(uint16_t) * 2 * kp * mp : sizeof(float) * m * kp,
+        sizeof(float) * count * kp * ldv,
+        lowp ? sizeof(uint16_t) * count * 2 * kp * ldv : 0,
+        sizeof(float) * count * m * kp,
+        sizeof(double) * count * npanel,
+        lowp ? sizeof(double) * count * nb * npair * 256 : 0,
+        sizeof(float) * count * kp * kp,
+        sizeof(int) * count,
+        sizeof(int) * count,
+        sizeof(double) * count * nbands,
+        0};
+    ApLayout L;
+    size_t o = 0;
+    for (int i = 0; i < AP_REGIONS; ++i) {
+        L.off[i] = o;
+        o += (sz[i] + 255) & ~(size_t)255;
+    }
+    L.total = o;
+    return L;
+}
+
+static ApWs apply_carve(void *base, const ApLayout &L, const tsk_stack *s) {
+    char *b = (char *)base;
+    const bool lowp = s->dtype != TSK_F32;
+    ApWs ws;
+    ws.St = lowp ? nullptr : (float *)(b + L.off[0]);
+    ws.Sb = lowp ? (uint16_t *)(b + L.off[0]) : nullptr;
+    ws.B = (float *)(b + L.off[1]);
+    ws.Bb = lowp ? (uint16_t *)(b + L.off[2]) : nullptr;
+    ws.C = (float *)(b + L.off[3]);
+    ws.fro = (double *)(b + L.off[4]);
+    ws.ctc = lowp ? (double *)(b + L.off[5]) : nullptr;
+    ws.w.Z = (float *)(b + L.off[6]);
+    ws.w.q = (int *)(b + L.off[7]);
+    ws.w.rf = (int *)(b + L.off[8]);
+    ws.w.part = (double *)(b + L.off[9]);
+    ws.w.nbands = (int)((s->m + RF_ROWS - 1) / RF_ROWS);
+    return ws;
 }
 
 // The row basis (CholeskyQR2 of B_d, written over B as V^T; Bb: its bf16
@@ -1507,24 +1564,22 @@ static tsk_status finish_enqueue(tsk_ctx c, const tsk_stack *s, int kp, const fl
     return TSK_OK;
 }
 
-tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
-                             float *sigma, double *relerr, int32_t *flags) {
+// FP32 form on workspace ws; prep: prepare the sketch (else ws holds it
+// from an earlier group of the same call).
+static tsk_status apply_f32_ws(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
+                               float *sigma, double *relerr, int32_t *flags, const ApWs &ws, bool prep) {
     const int64_t m = s->m, n = s->n, count = s->count;
     const int kp = (k + 15) / 16 * 16;
     const int npanel = (int)((n + SK_PANEL - 1) / SK_PANEL);
     const int64_t ldv = (int64_t)npanel * SK_PANEL;  // whole panels
-    TSK_TRY(tsk_grow(c, c->ap_St, sizeof(float) * m * kp));
-    TSK_TRY(tsk_grow(c, c->ap_B, sizeof(float) * count * kp * ldv));
-    TSK_TRY(tsk_grow(c, c->ap_C, sizeof(float) * count * m * kp));
-    TSK_TRY(tsk_grow(c, c->ap_fro, sizeof(double) * count * npanel));
-    ApSmall w;
-    TSK_TRY(small_ws(c, count, kp, m, w));
-    float *St = (float *)c->ap_St.p, *B = (float *)c->ap_B.p, *Cm = (float *)c->ap_C.p;
-    double *fro = (double *)c->ap_fro.p;
+    const ApSmall &w = ws.w;
+    float *St = ws.St, *B = ws.B, *Cm = ws.C;
+    double *fro = ws.fro;
     const float *A = (const float *)s->A;
-    TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
-               hipLaunchKernelGGL(transpose_sketch_kernel, dim3((unsigned)((m * kp + 255) / 256)), dim3(256), 0,
-                                  c->stream, S, k, kp, m, St));
+    if (prep)
+        TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
+                   hipLaunchKernelGGL(transpose_sketch_kernel, dim3((unsigned)((m * kp + 255) / 256)), dim3(256), 0,
+                                      c->stream, S, k, kp, m, St));
     const dim3 gs((unsigned)npanel, (unsigned)count);
 #define TSK_SK(MTV)                                                                                             \
     TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                            \
@@ -1547,33 +1602,25 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
 // bf16 form (ET = uint16_t, bf16 stack) and e4m3 form (ET = uint8_t, e4m3
 // stack with per-slice scales, widened to bf16 in registers).
 template <typename ET>
-static tsk_status apply_lowp_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
-                                     float *sigma, double *relerr, int32_t *flags) {
+static tsk_status apply_lowp_ws(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
+                                float *sigma, double *relerr, int32_t *flags, const ApWs &ws, bool prep) {
     const int64_t m = s->m, n = s->n, count = s->count;
     const int kp = (k + 15) / 16 * 16;
     const int64_t mp = (m + 31) / 32 * 32;
     const int npanel = (int)((n + SKB_PANEL - 1) / SKB_PANEL);
     const int64_t ldv = (int64_t)npanel * SKB_PANEL;  // whole panels
-    TSK_TRY(tsk_grow(c, c->ap_Sb, sizeof(uint16_t) * 2 * kp * mp));
-    TSK_TRY(tsk_grow(c, c->ap_B, sizeof(float) * count * kp * ldv));
-    TSK_TRY(tsk_grow(c, c->ap_Bb, sizeof(uint16_t) * count * 2 * kp * ldv));
-    TSK_TRY(tsk_grow(c, c->ap_C, sizeof(float) * count * m * kp));
-    TSK_TRY(tsk_grow(c, c->ap_fro, sizeof(double) * count * npanel));
     const int nb = (int)((m + PJL_ROWS - 1) / PJL_ROWS);
-    // the projection's per-band C^T C sums
-    const int npair = (kp / 16) * (kp / 16 + 1) / 2;
-    TSK_TRY(tsk_grow(c, c->ap_HX, sizeof(double) * count * (int64_t)nb * npair * 256));
-    ApSmall w;
-    TSK_TRY(small_ws(c, count, kp, m, w));
-    double *ctc = (double *)c->ap_HX.p;
-    uint16_t *Sb = (uint16_t *)c->ap_Sb.p, *Bb = (uint16_t *)c->ap_Bb.p;
-    float *B = (float *)c->ap_B.p, *Cm = (float *)c->ap_C.p;
-    double *fro = (double *)c->ap_fro.p;
+    const ApSmall &w = ws.w;
+    double *ctc = ws.ctc;
+    uint16_t *Sb = ws.Sb, *Bb = ws.Bb;
+    float *B = ws.B, *Cm = ws.C;
+    double *fro = ws.fro;
     const ET *A = (const ET *)s->A;
     const float *sc = s->scale;
-    TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
-               hipLaunchKernelGGL(prep_sketch_bf16_kernel, dim3((unsigned)((kp * mp + 255) / 256)), dim3(256), 0,
-                                  c->stream, S, k, kp, m, mp, Sb));
+    if (prep)
+        TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
+                   hipLaunchKernelGGL(prep_sketch_bf16_kernel, dim3((unsigned)((kp * mp + 255) / 256)), dim3(256), 0,
+                                      c->stream, S, k, kp, m, mp, Sb));
     const dim3 gs((unsigned)npanel, (unsigned)count);
 #define TSK_SKB(MTV)                                                                                     \
     TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                     \
@@ -1597,10 +1644,90 @@ static tsk_status apply_lowp_enqueue(tsk_ctx c, const float *S, int k, const tsk
     return finish_enqueue(c, s, kp, B, ldv, Cm, k, r, fro, npanel, L, R, sigma, relerr, flags, ctc, w);
 }
 
-tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
-                                  float *sigma, double *relerr, int32_t *flags) {
-    if (s->dtype == TSK_F8E4M3) return apply_lowp_enqueue<uint8_t>(c, S, k, s, r, L, R, sigma, relerr, flags);
-    return apply_lowp_enqueue<uint16_t>(c, S, k, s, r, L, R, sigma, relerr, flags);
+static tsk_status apply_ws(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
+                           float *sigma, double *relerr, int32_t *flags, const ApWs &ws, bool prep) {
+    if (s->dtype == TSK_F8E4M3) return apply_lowp_ws<uint8_t>(c, S, k, s, r, L, R, sigma, relerr, flags, ws, prep);
+    if (s->dtype == TSK_BF16) return apply_lowp_ws<uint16_t>(c, S, k, s, r, L, R, sigma, relerr, flags, ws, prep);
+    return apply_f32_ws(c, S, k, s, r, L, R, sigma, relerr, flags, ws, prep);
+}
+
+// tsk_apply: the whole stack on the context's workspace (grown on demand).
+tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
+                             float *sigma, double *relerr, int32_t *flags) {
+    const ApLayout lay = apply_layout(s, k, s->count);
+    TSK_TRY(tsk_grow(c, c->ap_ws, lay.total));
+    return apply_ws(c, S, k, s, r, L, R, sigma, relerr, flags, apply_carve(c->ap_ws.p, lay, s), true);
+}
+
+// ---------------------------------------------------------------------------
+// No-allocation form (tsk_apply_noalloc): the workspace is the file-scope
+// device array `scratch` (TSK_SCRATCH_BYTES on every GPU the library runs
+// on, held until the process ends).  Its device address is looked up once
+// per device (tsk_scratch_init, from tsk_create) and only that address is
+// passed to kernels; the array's name in host code is not a device address.
+// The stack is processed in groups of as many matrices as fit, one after
+// another on the stream; every call on a GPU shares its array, so calls that
+// overlap on one GPU race.  No kernel needs the scratch cleared: every
+// region is written before it is read within a call.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[TSK_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[TSK_MAX_DEVICES];
+
+// Device address of `scratch` on the current device `device` (once per device).
+tsk_status tsk_scratch_init(tsk_ctx c, int device) {
+    if (device < 0 || device >= TSK_MAX_DEVICES) return tsk_fail(c, TSK_E_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return tsk_hip(c, e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch symbol address");
+        }
+        g_scratch_ptr[device] = p;
+    }
+    c->scratch = g_scratch_ptr[device];
+    return TSK_OK;
+}
+
+// Matrices per group that fit the scratch (0: not even one).
+int64_t tsk_noalloc_group(const tsk_stack *s, int k) {
+    int64_t lo = 0, hi = s->count;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (apply_layout(s, k, mid).total <= (size_t)TSK_SCRATCH_BYTES)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+tsk_status tsk_apply_noalloc_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L,
+                                     float *R, float *sigma, double *relerr, int32_t *flags) {
+    if (!c->scratch) return tsk_fail(c, TSK_E_DEVICE, "tsk_apply_noalloc: no scratch address for this device");
+    const int64_t g = tsk_noalloc_group(s, k);
+    if (g < 1) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "tsk_apply_noalloc: one %lld x %lld matrix at k = %d needs %zu bytes of scratch, "
+                 "more than the %zu available", (long long)s->m, (long long)s->n, k, apply_layout(s, k, 1).total,
+                 (size_t)TSK_SCRATCH_BYTES);
+        return tsk_fail(c, TSK_E_SHAPE, buf);
+    }
+    const ApLayout lay = apply_layout(s, k, g);
+    const ApWs ws = apply_carve(c->scratch, lay, s);
+    const size_t es = s->dtype == TSK_F32 ? 4 : s->dtype == TSK_BF16 ? 2 : 1;
+    for (int64_t d0 = 0; d0 < s->count; d0 += g) {
+        tsk_stack sub = *s;
+        sub.count = std::min(g, s->count - d0);
+        sub.A = (const char *)s->A + (size_t)d0 * s->stride * es;
+        if (s->scale) sub.scale = s->scale + d0;
+        TSK_TRY(apply_ws(c, S, k, &sub, r, L + d0 * s->m * r, R + d0 * s->n * r, sigma + d0 * r,
+                         relerr ? relerr + d0 : nullptr, flags ? flags + d0 : nullptr, ws, d0 == 0));
+    }
+    return TSK_OK;
 }
 
 // Batched SCW over problems of different shapes (tsk_apply_multi).  The host

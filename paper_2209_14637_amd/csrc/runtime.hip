@@ -13,8 +13,9 @@ tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *
                            int32_t *iters_out, double tol_default);
 tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
                              float *sigma, double *relerr, int32_t *flags);
-tsk_status tsk_apply_bf16_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
-                                  float *sigma, double *relerr, int32_t *flags);
+tsk_status tsk_apply_noalloc_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L,
+                                     float *R, float *sigma, double *relerr, int32_t *flags);
+tsk_status tsk_scratch_init(tsk_ctx c, int device);
 tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, const float *R, int r,
                              double *relerr);
 tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute);
@@ -199,6 +200,14 @@ tsk_status tsk_create(tsk_ctx *out, int device, void *hip_stream) {
     if (!c) return TSK_E_NOMEM;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    {
+        DeviceGuard g(device);
+        const tsk_status st = tsk_scratch_init(c, device);
+        if (st != TSK_OK) {
+            delete c;
+            return st;
+        }
+    }
     *out = c;
     return TSK_OK;
 }
@@ -210,8 +219,7 @@ void tsk_destroy(tsk_ctx c) {
     drain_events(c);
     TskBuf *bufs[] = {&c->gram_part, &c->gram_G,  &c->eig_Y0,   &c->eig_Y1, &c->eig_Rinv, &c->eig_part,
                       &c->eig_C,     &c->eig_X,   &c->eig_GX,   &c->eig_small, &c->eig_U, &c->counters,
-                      &c->ap_St,     &c->ap_B,    &c->ap_C,     &c->ap_fro, &c->ap_Sb,    &c->ap_Bb,
-                      &c->ap_HX,     &c->ap_Z,    &c->er_part,  &c->st_part, &c->mp_ws,  &c->mp_tab};
+                      &c->ap_ws,     &c->er_part, &c->st_part,  &c->mp_ws,  &c->mp_tab};
     for (TskBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->mp_pin) (void)hipHostFree(c->mp_pin);
@@ -355,8 +363,16 @@ tsk_status tsk_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test
     c->err.clear();
     DeviceGuard g(c->device);
     TSK_TRY(check_apply(c, S, k, test, r, compute, L, R, sigma, relerr, flags));
-    if (compute != TSK_F32) return tsk_apply_bf16_enqueue(c, S, k, test, r, L, R, sigma, relerr, flags);
     return tsk_apply_enqueue(c, S, k, test, r, L, R, sigma, relerr, flags);
+}
+
+tsk_status tsk_apply_noalloc(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test, int32_t r,
+                             int32_t compute, float *L, float *R, float *sigma, double *relerr, int32_t *flags) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    TSK_TRY(check_apply(c, S, k, test, r, compute, L, R, sigma, relerr, flags));
+    return tsk_apply_noalloc_enqueue(c, S, k, test, r, L, R, sigma, relerr, flags);
 }
 
 tsk_status tsk_error(tsk_ctx c, const tsk_stack *A, const float *L, const float *R, int32_t r, double *relerr) {

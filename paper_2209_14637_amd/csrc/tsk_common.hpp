@@ -560,9 +560,8 @@ struct tsk_ctx_s {
     TskBuf gram_part, gram_G;
     TskBuf eig_Y0, eig_Y1, eig_Rinv, eig_part, eig_C, eig_X, eig_GX, eig_small, eig_U;
     TskBuf counters;
-    TskBuf ap_St, ap_B, ap_C, ap_fro;
-    TskBuf ap_Sb, ap_Bb;  // bf16 hi/lo pairs of S and B (bf16 path)
-    TskBuf ap_HX, ap_Z;   // per-matrix small factors
+    TskBuf ap_ws;         // workspace of tsk_apply (one buffer, carved per call)
+    void *scratch = nullptr;  // device address of the no-allocation scratch on this device
     TskBuf er_part, st_part;
     TskBuf mp_ws, mp_tab;            // batched apply: workspace, descriptors + items
     void *mp_pin = nullptr;          // pinned host copy of the batch tables
@@ -592,6 +591,11 @@ constexpr double TSK_EIG_TOL_BF16 = 1e-5;
 // 2^-8): the Gram moves about 2^4 times further, so the tolerance is 2^4
 // times looser (rounded).
 constexpr double TSK_EIG_TOL_F8 = 1e-4;
+
+// No-allocation scratch (tsk_apply_noalloc): bytes of the file-scope device
+// array, and the number of devices whose addresses are kept.
+constexpr size_t TSK_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int TSK_MAX_DEVICES = 64;
 
 // host helpers (runtime.hip)
 tsk_status tsk_fail(tsk_ctx c, tsk_status st, const std::string &msg);

@@ -23,7 +23,8 @@ _STATUS = {0: "TSK_OK", 1: "TSK_E_ARG", 2: "TSK_E_SHAPE", 3: "TSK_E_NOMEM", 4: "
            5: "TSK_E_NOCONV"}
 
 EXPORTS = ["tsk_create", "tsk_destroy", "tsk_set_stream", "tsk_last_error", "tsk_stage", "tsk_gram",
-           "tsk_eig_topk", "tsk_train", "tsk_apply", "tsk_apply_multi", "tsk_error", "tsk_set_eig_params",
+           "tsk_eig_topk", "tsk_train", "tsk_apply", "tsk_apply_noalloc", "tsk_apply_multi", "tsk_error",
+           "tsk_set_eig_params",
            "tsk_timing_enable", "tsk_timing_read"]
 
 _DTYPES = {"f32": TSK_F32, "bf16": TSK_BF16, "e4m3": TSK_F8E4M3}
@@ -71,6 +72,7 @@ def load(path: str | None = None):
         "tsk_eig_topk": ([P, P, I64, I32, P, P, P], I32),
         "tsk_train": ([P, sp, I32, I32, P, P, P], I32),
         "tsk_apply": ([P, P, I32, sp, I32, I32, P, P, P, P, P], I32),
+        "tsk_apply_noalloc": ([P, P, I32, sp, I32, I32, P, P, P, P, P], I32),
         "tsk_apply_multi": ([P, ctypes.POINTER(Problem), I32, I32], I32),
         "tsk_error": ([P, sp, P, P, I32, P], I32),
         "tsk_set_eig_params": ([P, I32, I32, D, I32], I32),
@@ -215,9 +217,12 @@ class Context:
         return S, list(lam), it.value, st
 
     def apply(self, S: torch.Tensor, A, r: int, out: dict | None = None, relerr: bool = True,
-              flags: bool = True) -> dict:
+              flags: bool = True, noalloc: bool = False) -> dict:
         """SCW on every slice; the arithmetic follows the stack's format
-        (FP32 tensor, bfloat16 tensor or a Staged stack)."""
+        (FP32 tensor, bfloat16 tensor or a Staged stack).  noalloc: through
+        tsk_apply_noalloc (the library's fixed scratch, no device allocation
+        by the library; the outputs here are still torch tensors unless
+        `out` supplies them)."""
         self._sync_stream()
         s = _stack(A)
         k = S.shape[0]
@@ -231,8 +236,9 @@ class Context:
             o["sigma"] = torch.empty((s.count, r), dtype=torch.float32, device=dev)
             o["relerr"] = torch.empty(s.count, dtype=torch.float64, device=dev) if relerr else None
             o["flags"] = torch.empty(s.count, dtype=torch.int32, device=dev) if flags else None
-        self._check(self.lib.tsk_apply(self.h, _ptr(S), k, ctypes.byref(s), r, s.dtype, _ptr(o["L"]), _ptr(o["R"]),
-                                       _ptr(o["sigma"]), _ptr(o.get("relerr")), _ptr(o.get("flags"))))
+        fn = self.lib.tsk_apply_noalloc if noalloc else self.lib.tsk_apply
+        self._check(fn(self.h, _ptr(S), k, ctypes.byref(s), r, s.dtype, _ptr(o["L"]), _ptr(o["R"]),
+                       _ptr(o["sigma"]), _ptr(o.get("relerr")), _ptr(o.get("flags"))))
         return o
 
     @staticmethod

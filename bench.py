@@ -270,6 +270,20 @@ def run(args):
             parity["s_angle_gate"] = S_ANGLE_GATE[prec]
             parity["pass"] = bool(parity["pass"] and max(a_res.values()) <= S_ANGLE_GATE[prec])
 
+    # the data-free baseline the paper argues against: SCW with a random
+    # Gaussian and a random sparse sign sketch of the same size (generated on
+    # the GPU), errors beside the trained sketch's on the same test matrices
+    e_tr = ctx.error(te, out["L"], out["R"]).cpu().numpy()
+    base = {"trained_mean_error": float(e_tr.mean())}
+    for kind in ("gaussian", "sparse"):
+        Sr = ctx.random_sketch(kind, k, m, seed=1)
+        o = ctx.apply(Sr, test_in, r)
+        e_r = ctx.error(te, o["L"], o["R"]).cpu().numpy()
+        base[kind] = {"mean_error": float(e_r.mean()), "trained_lower_fraction": float(np.mean(e_tr < e_r)),
+                      "mean_error_ratio_trained_over_random": float(np.mean(e_tr / e_r))}
+        del o
+    rec_extra["random_sketch_baseline"] = base
+
     apply_med = float(np.median(apply_ms))
     value = spec.n_test / (apply_med / 1e3)
     gram_ms = kt_gram["gram"][1] / max(kt_gram["gram"][0], 1)

@@ -146,8 +146,28 @@ tsk_status tsk_eig_topk(tsk_ctx ctx, const double *G, int64_t m, int32_t k,
 tsk_status tsk_train(tsk_ctx ctx, const tsk_stack *train, int32_t k, int32_t compute,
                      float *S, double *lambda, int32_t *iters);
 
+/* Data-free sketches for the SCW baseline: the randomly drawn sketching
+ * matrices the paper contrasts with its trained one (Section 1: entries
+ * from a distribution such as the Gaussian or the Rademacher one; Section 2:
+ * the sparse random sign matrix that initialises IVY's learned sketch).
+ * S: device FP32, k x m row-major, written; usable as the sketch of
+ * tsk_apply (whose basis step needs only that S A_d have full row rank).
+ * Counter-based: entry values are a pure function of (seed, position); the
+ * value of counter c is the c-th output (from 0) of SplitMix64 seeded with
+ * `seed`.  kind:
+ *   TSK_SKETCH_GAUSSIAN : N(0, 1/k) entries, Box-Muller on the outputs of
+ *                         counters 2c and 2c + 1 (c = i m + j), FP64,
+ *                         rounded to FP32;
+ *   TSK_SKETCH_SIGN     : +-1/sqrt(k) by the top bit of output c;
+ *   TSK_SKETCH_SPARSE   : one +-1 per column j (bit 0 of output j) in row
+ *                         (output j >> 32) mod k, zeros elsewhere.
+ * Requires 1 <= k <= m.  Enqueue only. */
+typedef enum { TSK_SKETCH_GAUSSIAN = 0, TSK_SKETCH_SIGN = 1, TSK_SKETCH_SPARSE = 2 } tsk_sketch_kind;
+tsk_status tsk_random_sketch(tsk_ctx ctx, int32_t kind, int32_t k, int64_t m, uint64_t seed, float *S);
+
 /* SCW, Algorithm 1, on every slice of `test` with the sketch S (k x m,
- * device FP32, rows orthonormal):
+ * device FP32; the trained sketch has orthonormal rows, but any S for which
+ * S A_d has full row rank serves, e.g. those of tsk_random_sketch):
  *   1. B_d = S A_d (k x n);  V_d = orthonormal basis of the row space of B_d
  *      (n x k), by CholeskyQR2 -- the QR replacement for Algorithm 1's SVD
  *      that Section 3.2 allows;

@@ -55,6 +55,7 @@ def lib():
             "tsko_train_from_gram": [_P, _I, _I, _P, _P],
             "tsko_scw": [_P, _I, _I, _P, _I, _I, ctypes.c_int, _P, _P, _P, _P, _P, _P],
             "tsko_scw_basis": [_P, _I, _I, _P, _I, ctypes.c_int, _P, _P],
+            "tsko_random_sketch": [ctypes.c_int, _I, _I, ctypes.c_uint64, _P],
             "tsko_apply_f32": [_P, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P, _P],
             "tsko_error_f32": [_P, _I, _I, _I, _P, _P, _I, _P],
             "tsko_opt_f32": [_P, _I, _I, _I, _I, _P, _P],
@@ -67,6 +68,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int
+        L.tsko_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.tsko_splitmix64.restype = ctypes.c_uint64
         _lib = L
     return _lib
 
@@ -194,6 +197,22 @@ def scw_basis(A: np.ndarray, S: np.ndarray, vmode: int = 0):
     fl = np.zeros(1, dtype=np.int32)
     _check(lib().tsko_scw_basis(_p(A), m, n, _p(S), k, vmode, _p(V), _p(fl)), "scw_basis")
     return V, int(fl[0])
+
+
+SKETCH_KINDS = {"gaussian": 0, "sign": 1, "sparse": 2}
+
+
+def splitmix64(seed: int, c: int) -> int:
+    """The c-th output (from 0) of SplitMix64 seeded with `seed`."""
+    return int(lib().tsko_splitmix64(seed, c))
+
+
+def random_sketch(kind: str, k: int, m: int, seed: int) -> np.ndarray:
+    """Data-free k x m sketch of the SCW baseline ("gaussian", "sign" or
+    "sparse"), float64."""
+    S = np.empty((k, m))
+    _check(lib().tsko_random_sketch(SKETCH_KINDS[kind], k, m, seed, _p(S)), "random_sketch")
+    return S
 
 
 def apply(A: np.ndarray, S: np.ndarray, r: int, factors: bool = True):

@@ -702,3 +702,52 @@ int tsko_opt_f32(const float *A, int64_t count, int64_t m, int64_t n, int64_t r,
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Data-free sketches for the SCW baseline (Section 1: sketching matrices
+ * drawn from a distribution such as the Gaussian or the Rademacher one;
+ * Section 2: the sparse random sign matrix that initialises IVY's sketch).
+ * Counter-based: the value of counter c is the c-th output (from 0) of the
+ * SplitMix64 generator seeded with `seed` (Steele, Lea and Flood, "Fast
+ * splittable pseudorandom number generators", OOPSLA 2014): the state
+ * advances by the odd constant 0x9E3779B97F4A7C15 and each state is mixed by
+ * two xor-shift-multiply rounds and a final xor-shift.
+ * ------------------------------------------------------------------------ */
+uint64_t tsko_splitmix64(uint64_t seed, uint64_t c) {
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+int tsko_random_sketch(int kind, int64_t k, int64_t m, uint64_t seed, double *S) {
+    if (!S || k < 1 || m < 1 || kind < 0 || kind > 2) return -1;
+    const double scale = 1.0 / sqrt((double)k);
+    if (kind == 2) {
+        /* one nonzero +-1 per column: row (h >> 32) mod k, sign from bit 0 */
+        memset(S, 0, sizeof(double) * (size_t)(k * m));
+        for (int64_t j = 0; j < m; j++) {
+            const uint64_t h = tsko_splitmix64(seed, (uint64_t)j);
+            const int64_t row = (int64_t)((h >> 32) % (uint64_t)(k - MUT(17) * (k > 1)));
+            S[row * m + j] = (h & 1u) ? -1.0 : 1.0;
+        }
+        return 0;
+    }
+    for (int64_t i = 0; i < k; i++)
+        for (int64_t j = 0; j < m; j++) {
+            const uint64_t c = (uint64_t)(i * m + j);
+            double v;
+            if (kind == 1) {
+                /* Rademacher: the sign of the top bit */
+                v = (tsko_splitmix64(seed, c) >> 63) ? -1.0 : 1.0;
+            } else {
+                /* Gaussian by the Box-Muller transform of two uniforms,
+                 * u1 in (0, 1] and u2 in [0, 1), 53 bits each */
+                const double u1 = (double)((tsko_splitmix64(seed, 2 * c) >> 11) + 1) * 0x1p-53;
+                const double u2 = (double)(tsko_splitmix64(seed, 2 * c + 1) >> 11) * 0x1p-53;
+                v = sqrt((MUT(16) ? -1.0 : -2.0) * log(u1)) * cos(6.283185307179586477 * u2);
+            }
+            S[i * m + j] = v * scale;
+        }
+    return 0;
+}

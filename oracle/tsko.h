@@ -125,6 +125,16 @@ int tsko_round_e4m3(const float *x, int64_t n, float scale, float *y);
  * unless clamped, 2 * amax * s > 448. */
 int tsko_e4m3_scale(const float *x, int64_t n, float *scale);
 
+/* Data-free sketches of the SCW baseline (Sections 1 and 2), k x m, from a
+ * counter-based generator: tsko_splitmix64(seed, c) is the c-th output (from
+ * 0) of SplitMix64 seeded with `seed`.  kind 0: Gaussian entries N(0, 1/k)
+ * (Box-Muller on the outputs of counters 2c and 2c + 1, c = i m + j);
+ * kind 1: Rademacher entries +-1/sqrt(k) (sign of the top bit of output c);
+ * kind 2: sparse random sign (CountSketch) -- column j has its one nonzero,
+ * +-1 (bit 0 of output j), in row (output j >> 32) mod k. */
+uint64_t tsko_splitmix64(uint64_t seed, uint64_t c);
+int tsko_random_sketch(int kind, int64_t k, int64_t m, uint64_t seed, double *S);
+
 /* Number of OpenMP threads the library will use. */
 int tsko_threads(void);
 

@@ -16,6 +16,7 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
 tsk_status tsk_apply_noalloc_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L,
                                      float *R, float *sigma, double *relerr, int32_t *flags);
 tsk_status tsk_scratch_init(tsk_ctx c, int device);
+tsk_status tsk_random_sketch_enqueue(tsk_ctx c, int kind, int64_t k, int64_t m, uint64_t seed, float *S);
 tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, const float *R, int r,
                              double *relerr);
 tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute);
@@ -373,6 +374,17 @@ tsk_status tsk_apply_noalloc(tsk_ctx c, const float *S, int32_t k, const tsk_sta
     DeviceGuard g(c->device);
     TSK_TRY(check_apply(c, S, k, test, r, compute, L, R, sigma, relerr, flags));
     return tsk_apply_noalloc_enqueue(c, S, k, test, r, L, R, sigma, relerr, flags);
+}
+
+tsk_status tsk_random_sketch(tsk_ctx c, int32_t kind, int32_t k, int64_t m, uint64_t seed, float *S) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    if (kind != TSK_SKETCH_GAUSSIAN && kind != TSK_SKETCH_SIGN && kind != TSK_SKETCH_SPARSE)
+        return tsk_fail(c, TSK_E_ARG, "tsk_random_sketch: unknown kind");
+    if (k < 1 || m < k || m > (1 << 24)) return tsk_fail(c, TSK_E_ARG, "tsk_random_sketch: need 1 <= k <= m <= 2^24");
+    TSK_TRY(tsk_check_dev(c, S, sizeof(float) * (size_t)k * m, "S"));
+    return tsk_random_sketch_enqueue(c, kind, k, m, seed, S);
 }
 
 tsk_status tsk_error(tsk_ctx c, const tsk_stack *A, const float *L, const float *R, int32_t r, double *relerr) {

@@ -23,11 +23,12 @@ _STATUS = {0: "TSK_OK", 1: "TSK_E_ARG", 2: "TSK_E_SHAPE", 3: "TSK_E_NOMEM", 4: "
            5: "TSK_E_NOCONV"}
 
 EXPORTS = ["tsk_create", "tsk_destroy", "tsk_set_stream", "tsk_last_error", "tsk_stage", "tsk_gram",
-           "tsk_eig_topk", "tsk_train", "tsk_apply", "tsk_apply_noalloc", "tsk_apply_multi", "tsk_error",
-           "tsk_set_eig_params",
+           "tsk_eig_topk", "tsk_train", "tsk_random_sketch", "tsk_apply", "tsk_apply_noalloc", "tsk_apply_multi",
+           "tsk_error", "tsk_set_eig_params",
            "tsk_timing_enable", "tsk_timing_read"]
 
 _DTYPES = {"f32": TSK_F32, "bf16": TSK_BF16, "e4m3": TSK_F8E4M3}
+SKETCH_KINDS = {"gaussian": 0, "sign": 1, "sparse": 2}
 
 
 class TskError(RuntimeError):
@@ -71,6 +72,7 @@ def load(path: str | None = None):
         "tsk_gram": ([P, sp, I32, P], I32),
         "tsk_eig_topk": ([P, P, I64, I32, P, P, P], I32),
         "tsk_train": ([P, sp, I32, I32, P, P, P], I32),
+        "tsk_random_sketch": ([P, I32, I32, I64, ctypes.c_uint64, P], I32),
         "tsk_apply": ([P, P, I32, sp, I32, I32, P, P, P, P, P], I32),
         "tsk_apply_noalloc": ([P, P, I32, sp, I32, I32, P, P, P, P, P], I32),
         "tsk_apply_multi": ([P, ctypes.POINTER(Problem), I32, I32], I32),
@@ -215,6 +217,14 @@ class Context:
         st = self._check(self.lib.tsk_train(self.h, ctypes.byref(s), k, _DTYPES[compute], _ptr(S), lam,
                                             ctypes.byref(it)), allow_noconv)
         return S, list(lam), it.value, st
+
+    def random_sketch(self, kind: str, k: int, m: int, seed: int = 0) -> torch.Tensor:
+        """Data-free k x m sketch ("gaussian", "sign" or "sparse") of the SCW
+        baseline, generated on the GPU (tsk_random_sketch)."""
+        self._sync_stream()
+        S = torch.empty((k, m), dtype=torch.float32, device=f"cuda:{self.device}")
+        self._check(self.lib.tsk_random_sketch(self.h, SKETCH_KINDS[kind], k, m, seed, _ptr(S)))
+        return S
 
     def apply(self, S: torch.Tensor, A, r: int, out: dict | None = None, relerr: bool = True,
               flags: bool = True, noalloc: bool = False) -> dict:

@@ -28,6 +28,8 @@ MUTANTS = {
     13: "format rounding breaks ties away from zero",
     14: "format rounding keeps one significant bit too few",
     15: "e4m3 scale one power of two too large",
+    16: "Box-Muller radius sqrt(-ln u) instead of sqrt(-2 ln u)",
+    17: "sparse sign sketch never uses its last row",
 }
 
 
@@ -37,6 +39,7 @@ def test_pins_catch_mutant(tmp_path, mutant):
     env = dict(os.environ, TSKO_LIB=so, OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_formats.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_formats.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_random.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"pins missed mutant {mutant}: {MUTANTS[mutant]}\n{r.stdout[-2000:]}"

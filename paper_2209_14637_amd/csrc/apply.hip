@@ -319,9 +319,8 @@ template <int MT, typename ET>
 __device__ __forceinline__ void sketch_bf16_body(const ET *__restrict__ A, const float *__restrict__ scale,
                                                  int64_t m, int64_t n, int64_t ld, int64_t stride,
                                                  const uint16_t *__restrict__ Sb, int64_t mp,
-                                                 float *__restrict__ B, uint16_t *__restrict__ Bb,
-                                                 int64_t ldb, double *__restrict__ fro_part, int npanel, int64_t d,
-                                                 int panel) {
+                                                 float *__restrict__ B, int64_t ldb,
+                                                 double *__restrict__ fro_part, int npanel, int64_t d, int panel) {
     constexpr int kp = MT * 16;
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, ii = lane & 15;
@@ -417,34 +416,19 @@ __device__ __forceinline__ void sketch_bf16_body(const ET *__restrict__ A, const
         }
         sketch_step<MT>(x, sh, sl, acc, fro);
     }
-    // lane holds B[a*16 + 4q + r][c8 + u] in acc[a][u][r].  Each value is
-    // split into hi = RNE(b), lo = RNE(b - hi); B' = hi + lo (exact in FP32)
-    // is what every later step uses.  The whole panel is written.
+    // lane holds B[a*16 + 4q + r][c8 + u] in acc[a][u][r]; the whole panel
+    // is written (columns >= n are zero), so B's padding is defined
     {
         float *Bd = B + d * kp * ldb + c8;
-        uint16_t *Bh = Bb + d * 2 * kp * ldb + c8;
-        uint16_t *Bl = Bh + (int64_t)kp * ldb;
 #pragma unroll
         for (int a = 0; a < MT; ++a)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = (int64_t)(a * 16 + 4 * q + r) * ldb;
-                float bp[8];
-                unsigned hw[4], lw[4];
-#pragma unroll
-                for (int u = 0; u < 8; u += 2) {
-                    const unsigned h2 = pack_bf16(acc[a][u][r], acc[a][u + 1][r]);
-                    const float h0 = bf16_lo(h2), h1 = bf16_hi(h2);
-                    const unsigned l2 = pack_bf16(acc[a][u][r] - h0, acc[a][u + 1][r] - h1);
-                    bp[u] = h0 + bf16_lo(l2);
-                    bp[u + 1] = h1 + bf16_hi(l2);
-                    hw[u >> 1] = h2;
-                    lw[u >> 1] = l2;
-                }
-                *reinterpret_cast<float4 *>(Bd + row) = float4{bp[0], bp[1], bp[2], bp[3]};
-                *reinterpret_cast<float4 *>(Bd + row + 4) = float4{bp[4], bp[5], bp[6], bp[7]};
-                *reinterpret_cast<v4u *>(Bh + row) = v4u{hw[0], hw[1], hw[2], hw[3]};
-                *reinterpret_cast<v4u *>(Bl + row) = v4u{lw[0], lw[1], lw[2], lw[3]};
+                *reinterpret_cast<float4 *>(Bd + row) =
+                    float4{acc[a][0][r], acc[a][1][r], acc[a][2][r], acc[a][3][r]};
+                *reinterpret_cast<float4 *>(Bd + row + 4) =
+                    float4{acc[a][4][r], acc[a][5][r], acc[a][6][r], acc[a][7][r]};
             }
     }
     const double tot = wave_sum_f64(fro);
@@ -783,51 +767,51 @@ __device__ inline void small_mm(const double *X, const double *M, double *Y) {
     __syncthreads();
 }
 
-// X^T (KP x KP, X upper triangular with zeros below the diagonal, FP64 in
-// LDS) times column j of the KP x ldb FP32 matrix M, in place:
-//     M[a][j] = sum_{u <= a} X[u][a] M[u][j],
-// summed over u in order in FP64.  Outputs in blocks of 16 rows taken from
-// the last block down, so a block reads only rows not yet overwritten; X is
-// read as 16-byte broadcast pairs (its zeros below the diagonal make every
-// block a plain 16-wide update).  P (bf16 and e4m3 forms, else null): also
-// the bf16 pair (hi, lo) of each value (hi rows 0..KP-1, lo rows KP..2KP-1),
+// M := X^T M for the KP x ldb FP32 matrix M (ldb a multiple of 64), X upper
+// triangular (KP x KP, FP64 in LDS, zeros below the diagonal):
+//     M[a][j] = sum_{u <= a} X[u][a] M[u][j]   (FP64 products and sums).
+// Chunks of 64 columns are staged in LDS (Ms, KP x MS_LD FP32) by
+// coalesced loads; wave w computes the chunk's columns 16w .. 16w+15 for
+// every 16-row tile by FP64 MFMA 16x16x4 (A = X^T, B = the staged columns;
+// K-steps past the tile's last row are skipped, X being zero there) and
+// writes them back in place.  P (bf16 and e4m3 forms, else null): also the
+// bf16 pair (hi, lo) of each value (hi rows 0..KP-1, lo rows KP..2KP-1),
 // with M := hi + lo.
+constexpr int MS_LD = 68;  // padded LDS row of the staged chunk (floats)
 template <int KP>
-__device__ __forceinline__ void tri_transform_col(const double *X, float *M, int64_t ldb, int64_t j,
-                                                  uint16_t *P) {
-    for (int a0 = KP - 16; a0 >= 0; a0 -= 16) {
-        double o[16];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) o[t] = 0.0;
+__device__ __forceinline__ void tri_transform(const double *X, float *M, int64_t ldb, uint16_t *P, float *Ms) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int q = lane >> 4, ii = lane & 15;
+    for (int64_t j0 = 0; j0 < ldb; j0 += 64) {
+        for (int e = tid; e < KP * 64; e += 256) Ms[(e >> 6) * MS_LD + (e & 63)] = M[(e >> 6) * ldb + j0 + (e & 63)];
+        __syncthreads();
+        for (int ta = 0; ta < KP / 16; ++ta) {
+            v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-        for (int u = 0; u < a0 + 16; ++u) {
-            const double cu = (double)M[u * ldb + j];
-            const double2 *xr = reinterpret_cast<const double2 *>(X + u * KP + a0);
+            for (int u0 = 0; u0 < 16 * (ta + 1); u0 += 4) {
+                const double a = X[(u0 + q) * KP + 16 * ta + ii];
+                const double b = (double)Ms[(u0 + q) * MS_LD + 16 * wv + ii];
+                acc = mfma16x16x4_f64(a, b, acc);
+            }
+            // lane (q, i) holds rows 16 ta + q + 4 r, column 16 wv + i
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const double2 x = xr[t];
-                o[2 * t] = fma(x.x, cu, o[2 * t]);
-                o[2 * t + 1] = fma(x.y, cu, o[2 * t + 1]);
+            for (int r = 0; r < 4; ++r) {
+                const int a = 16 * ta + q + 4 * r;
+                const int64_t col = j0 + 16 * wv + ii;
+                const float v = (float)acc[r];
+                if (P) {
+                    const unsigned h = pack_bf16(v, 0.f) & 0xffffu;
+                    const float hf = bf16_lo(h);
+                    const unsigned l = pack_bf16(v - hf, 0.f) & 0xffffu;
+                    P[a * ldb + col] = (uint16_t)h;
+                    P[(KP + a) * ldb + col] = (uint16_t)l;
+                    M[a * ldb + col] = hf + bf16_lo(l);
+                } else {
+                    M[a * ldb + col] = v;
+                }
             }
         }
-#pragma unroll
-        for (int t = 0; t < 16; t += 2) {
-            const float v0 = (float)o[t], v1 = (float)o[t + 1];
-            if (P) {
-                const unsigned h2 = pack_bf16(v0, v1);
-                const float h0 = bf16_lo(h2), h1 = bf16_hi(h2);
-                const unsigned l2 = pack_bf16(v0 - h0, v1 - h1);
-                P[(a0 + t) * ldb + j] = (uint16_t)(h2 & 0xffffu);
-                P[(a0 + t + 1) * ldb + j] = (uint16_t)(h2 >> 16);
-                P[(KP + a0 + t) * ldb + j] = (uint16_t)(l2 & 0xffffu);
-                P[(KP + a0 + t + 1) * ldb + j] = (uint16_t)(l2 >> 16);
-                M[(a0 + t) * ldb + j] = h0 + bf16_lo(l2);
-                M[(a0 + t + 1) * ldb + j] = h1 + bf16_hi(l2);
-            } else {
-                M[(a0 + t) * ldb + j] = v0;
-                M[(a0 + t + 1) * ldb + j] = v1;
-            }
-        }
+        __syncthreads();
     }
 }
 
@@ -851,6 +835,7 @@ __device__ __forceinline__ void basis_body(float *__restrict__ B, int64_t ldb, i
                                            uint16_t *__restrict__ Bb, int *__restrict__ q, int64_t d) {
     constexpr int SZ = KP * KP;
     __shared__ __align__(16) double buf[3 * SZ];
+    __shared__ __align__(16) float Ms[KP * MS_LD];
     __shared__ int dead[KP];
     __shared__ int s_second;
     const int tid = threadIdx.x;
@@ -880,8 +865,7 @@ __device__ __forceinline__ void basis_body(float *__restrict__ B, int64_t ldb, i
         __syncthreads();
         const bool last = pass == 1 || !s_second;
         uint16_t *P = last ? Pd : nullptr;
-        for (int64_t j = tid; j < ldb; j += 256) tri_transform_col<KP>(b2, Bd, ldb, j, P);
-        __syncthreads();
+        tri_transform<KP>(b2, Bd, ldb, P, Ms);
         if (last) break;
     }
     if (tid == 0) q[d] = nd;
@@ -1208,10 +1192,9 @@ template <int MT, typename ET>
 __global__ __launch_bounds__(64, 1) void sketch_bf16_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
                                                           int64_t m, int64_t n, int64_t ld, int64_t stride,
                                                           const uint16_t *__restrict__ Sb, int64_t mp,
-                                                          float *__restrict__ B, uint16_t *__restrict__ Bb,
-                                                          int64_t ldb, double *__restrict__ fro_part, int npanel) {
-    sketch_bf16_body<MT, ET>(A, scale, m, n, ld, stride, Sb, mp, B, Bb, ldb, fro_part, npanel, blockIdx.y,
-                             blockIdx.x);
+                                                          float *__restrict__ B, int64_t ldb,
+                                                          double *__restrict__ fro_part, int npanel) {
+    sketch_bf16_body<MT, ET>(A, scale, m, n, ld, stride, Sb, mp, B, ldb, fro_part, npanel, blockIdx.y, blockIdx.x);
 }
 // Columns per projection step: 64 for bf16 (LDS 37 KB and 112 VGPRs at
 // kp = 48: four workgroups per CU, 5% faster than 128 columns at two, which
@@ -1234,7 +1217,7 @@ __global__ __launch_bounds__(256, 2) void project_bf16_kernel(const ET *A, const
     project_lds_body<NT, pjl_k<ET>(), ET>(A, scale, m, n, ld, stride, Bb, ldv, C, d, band, lds_dyn, ctc);
 }
 template <int KP>
-__global__ __launch_bounds__(256) void basis_kernel(float *__restrict__ B, int64_t ldb, int64_t n, int k,
+__global__ __launch_bounds__(256, 2) void basis_kernel(float *__restrict__ B, int64_t ldb, int64_t n, int k,
                                                     uint16_t *__restrict__ Bb, int *__restrict__ q) {
     basis_body<KP>(B, ldb, n, k, Bb, q, blockIdx.x);
 }
@@ -1297,7 +1280,7 @@ template <int MT, typename ET>
 __global__ __launch_bounds__(64, 1) void sketch_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
-    sketch_bf16_body<MT, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Sb, D.mp, D.B, D.Bb, D.ldv,
+    sketch_bf16_body<MT, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Sb, D.mp, D.B, D.ldv,
                              D.fro, D.npanel, it.y, it.z);
 }
 template <int NT, typename ET>
@@ -1310,7 +1293,7 @@ __global__ __launch_bounds__(256, 2) void project_bf16_multi(const ApDesc *__res
                                           it.y, it.z, lds_dyn, D.ctc);
 }
 template <int KP>
-__global__ __launch_bounds__(256) void basis_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+__global__ __launch_bounds__(256, 2) void basis_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
     basis_body<KP>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y);
@@ -1625,7 +1608,7 @@ static tsk_status apply_lowp_ws(tsk_ctx c, const float *S, int k, const tsk_stac
 #define TSK_SKB(MTV)                                                                                     \
     TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                     \
                hipLaunchKernelGGL((sketch_bf16_kernel<MTV, ET>), gs, dim3(64), 0, c->stream, A, sc, m, n, \
-                                  s->ld, s->stride, (const uint16_t *)Sb, mp, B, Bb, ldv, fro, npanel))
+                                  s->ld, s->stride, (const uint16_t *)Sb, mp, B, ldv, fro, npanel))
     TSK_KP_SWITCH(kp / 16, TSK_SKB(1), TSK_SKB(2), TSK_SKB(3), TSK_SKB(4))
 #undef TSK_SKB
     TSK_TRY(basis_enqueue(c, kp, B, ldv, n, k, Bb, count, w));
@@ -1644,6 +1627,23 @@ static tsk_status apply_lowp_ws(tsk_ctx c, const float *S, int k, const tsk_stac
     return finish_enqueue(c, s, kp, B, ldv, Cm, k, r, fro, npanel, L, R, sigma, relerr, flags, ctc, w);
 }
 
+// The prepared sketch alone (what apply_ws launches first when prep is set).
+static tsk_status apply_prep(tsk_ctx c, const float *S, int k, const tsk_stack *s, const ApWs &ws) {
+    const int64_t m = s->m;
+    const int kp = (k + 15) / 16 * 16;
+    if (s->dtype == TSK_F32) {
+        TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
+                   hipLaunchKernelGGL(transpose_sketch_kernel, dim3((unsigned)((m * kp + 255) / 256)), dim3(256), 0,
+                                      c->stream, S, k, kp, m, ws.St));
+    } else {
+        const int64_t mp = (m + 31) / 32 * 32;
+        TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
+                   hipLaunchKernelGGL(prep_sketch_bf16_kernel, dim3((unsigned)((kp * mp + 255) / 256)), dim3(256), 0,
+                                      c->stream, S, k, kp, m, mp, ws.Sb));
+    }
+    return TSK_OK;
+}
+
 static tsk_status apply_ws(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
                            float *sigma, double *relerr, int32_t *flags, const ApWs &ws, bool prep) {
     if (s->dtype == TSK_F8E4M3) return apply_lowp_ws<uint8_t>(c, S, k, s, r, L, R, sigma, relerr, flags, ws, prep);
@@ -1651,12 +1651,82 @@ static tsk_status apply_ws(tsk_ctx c, const float *S, int k, const tsk_stack *s,
     return apply_f32_ws(c, S, k, s, r, L, R, sigma, relerr, flags, ws, prep);
 }
 
+// The workspace of matrices d0.. of a carved whole-stack workspace.
+static ApWs ws_from(const ApWs &w, const tsk_stack *s, int k, int64_t d0) {
+    const bool lowp = s->dtype != TSK_F32;
+    const int kp = (k + 15) / 16 * 16;
+    const int panel = lowp ? SKB_PANEL : SK_PANEL;
+    const int npanel = (int)((s->n + panel - 1) / panel);
+    const int64_t ldv = (int64_t)npanel * panel;
+    const int nb = (int)((s->m + PJL_ROWS - 1) / PJL_ROWS);
+    const int npair = (kp / 16) * (kp / 16 + 1) / 2;
+    ApWs o = w;
+    o.B += d0 * kp * ldv;
+    if (o.Bb) o.Bb += d0 * 2 * kp * ldv;
+    o.C += d0 * s->m * kp;
+    o.fro += d0 * npanel;
+    if (o.ctc) o.ctc += d0 * nb * npair * 256;
+    o.w.Z += d0 * kp * kp;
+    o.w.q += d0;
+    o.w.rf += d0;
+    o.w.part += d0 * o.w.nbands;
+    return o;
+}
+
+// Matrices per group of the pipelined apply: TSK_APPLY_GROUP (diagnostic)
+// or the default, two halves from 256 matrices on.  The per-matrix kernels
+// (basis, eig, outputs) are bound by their latency, and smaller groups
+// leave too few matrices in flight to hide it: on 1000 bf16 matrices of
+// 1920 x 1080 at k = 40, halves took 3.52 ms, quarters 3.66, the whole
+// stack 3.68, groups of 125 / 64 / 32 4.6 / 6.7 / 11.2 ms.
+static int64_t apply_group(const tsk_stack *s) {
+    const char *e = getenv("TSK_APPLY_GROUP");
+    if (e) {
+        const long long g = atoll(e);
+        if (g > 0) return g;
+    }
+    return s->count >= 256 ? (s->count + 1) / 2 : s->count;
+}
+
 // tsk_apply: the whole stack on the context's workspace (grown on demand).
+// With groups smaller than the stack, the groups alternate between the
+// context's two pipeline streams (forked from and joined back into the
+// caller's stream), so one group's small per-matrix kernels overlap the
+// streaming kernels of the next.
 tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
                              float *sigma, double *relerr, int32_t *flags) {
     const ApLayout lay = apply_layout(s, k, s->count);
     TSK_TRY(tsk_grow(c, c->ap_ws, lay.total));
-    return apply_ws(c, S, k, s, r, L, R, sigma, relerr, flags, apply_carve(c->ap_ws.p, lay, s), true);
+    const ApWs ws = apply_carve(c->ap_ws.p, lay, s);
+    const int64_t g = apply_group(s);
+    if (g >= s->count) return apply_ws(c, S, k, s, r, L, R, sigma, relerr, flags, ws, true);
+    TSK_TRY(tsk_pipeline_streams(c));
+    // the sketch is prepared once, on the caller's stream, then the fork
+    hipStream_t main = c->stream;
+    TSK_TRY(apply_prep(c, S, k, s, ws));
+    hipError_t e = hipEventRecord(c->pl_fork, main);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->pl[i], c->pl_fork, 0);
+    if (e != hipSuccess) return tsk_hip(c, e, "pipeline fork");
+    const size_t es = s->dtype == TSK_F32 ? 4 : s->dtype == TSK_BF16 ? 2 : 1;
+    tsk_status st = TSK_OK;
+    int64_t j = 0;
+    for (int64_t d0 = 0; d0 < s->count && st == TSK_OK; d0 += g, ++j) {
+        tsk_stack sub = *s;
+        sub.count = std::min(g, s->count - d0);
+        sub.A = (const char *)s->A + (size_t)d0 * s->stride * es;
+        if (s->scale) sub.scale = s->scale + d0;
+        c->stream = c->pl[j & 1];
+        st = apply_ws(c, S, k, &sub, r, L + d0 * s->m * r, R + d0 * s->n * r, sigma + d0 * r,
+                      relerr ? relerr + d0 : nullptr, flags ? flags + d0 : nullptr, ws_from(ws, s, k, d0), false);
+    }
+    c->stream = main;
+    e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipEventRecord(c->pl_join[i], c->pl[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(main, c->pl_join[i], 0);
+    }
+    if (st != TSK_OK) return st;
+    return e == hipSuccess ? TSK_OK : tsk_hip(c, e, "pipeline join");
 }
 
 // ---------------------------------------------------------------------------

@@ -53,6 +53,28 @@ tsk_status tsk_grow(tsk_ctx c, TskBuf &b, size_t bytes) {
     return TSK_OK;
 }
 
+// The context's two pipeline streams and their fork / join events (created
+// on first use, on the context's device, default priority).
+tsk_status tsk_pipeline_streams(tsk_ctx c) {
+    if (c->pl[0]) return TSK_OK;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&c->pl[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->pl_fork, hipEventDisableTiming);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&c->pl_join[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        for (int i = 0; i < 2; ++i) {
+            if (c->pl[i]) (void)hipStreamDestroy(c->pl[i]);
+            if (c->pl_join[i]) (void)hipEventDestroy(c->pl_join[i]);
+            c->pl[i] = nullptr;
+            c->pl_join[i] = nullptr;
+        }
+        if (c->pl_fork) (void)hipEventDestroy(c->pl_fork);
+        c->pl_fork = nullptr;
+        return tsk_hip(c, e, "pipeline streams");
+    }
+    return TSK_OK;
+}
+
 // The pointer must lie in a device allocation that holds [p, p + bytes).
 tsk_status tsk_check_dev(tsk_ctx c, const void *p, size_t bytes, const char *name) {
     if (!p) return tsk_fail(c, TSK_E_ARG, std::string(name) + ": null pointer");
@@ -226,6 +248,11 @@ void tsk_destroy(tsk_ctx c) {
     if (c->mp_pin) (void)hipHostFree(c->mp_pin);
     if (c->mp_ev) (void)hipEventDestroy(c->mp_ev);
     if (c->switch_ev) (void)hipEventDestroy(c->switch_ev);
+    for (int i = 0; i < 2; ++i) {
+        if (c->pl[i]) (void)hipStreamDestroy(c->pl[i]);
+        if (c->pl_join[i]) (void)hipEventDestroy(c->pl_join[i]);
+    }
+    if (c->pl_fork) (void)hipEventDestroy(c->pl_fork);
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     delete c;
 }

@@ -568,6 +568,10 @@ struct tsk_ctx_s {
     size_t mp_pin_bytes = 0;
     hipEvent_t mp_ev = nullptr;      // recorded after the last batch table copy
     hipEvent_t switch_ev = nullptr;  // orders the old stream before a new one (tsk_set_stream)
+    // pipelined apply: two context-owned streams (default priority), forked
+    // from and joined back into the caller's stream
+    hipStream_t pl[2] = {nullptr, nullptr};
+    hipEvent_t pl_fork = nullptr, pl_join[2] = {nullptr, nullptr};
     // eigensolver controls
     int eig_block = 0, eig_max_iter = 300, eig_check = 6;
     double eig_tol = 0.0;  // 0: TSK_EIG_TOL_F32 / TSK_EIG_TOL_BF16 by the Gram's precision
@@ -603,6 +607,7 @@ tsk_status tsk_hip(tsk_ctx c, hipError_t e, const char *what);
 tsk_status tsk_grow(tsk_ctx c, TskBuf &b, size_t bytes);
 tsk_status tsk_check_dev(tsk_ctx c, const void *p, size_t bytes, const char *name);
 tsk_status tsk_check_stack(tsk_ctx c, const tsk_stack *s, const char *name);
+tsk_status tsk_pipeline_streams(tsk_ctx c);
 void tsk_ev_begin(tsk_ctx c, int cls, hipEvent_t *a);
 void tsk_ev_end(tsk_ctx c, int cls, hipEvent_t a);
 

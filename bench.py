@@ -283,6 +283,17 @@ def run(args):
                       "mean_error_ratio_trained_over_random": float(np.mean(e_tr / e_r))}
         del o
     rec_extra["random_sketch_baseline"] = base
+    # metric (4.1) of Section 4: excess of each output's error over the best
+    # rank-r error of the same matrix, on the GPU (tsk_opt_tail), for a
+    # sample of the test matrices
+    nm = min(spec.n_test, 64 if m * n > 1 << 20 else spec.n_test)
+    t0 = time.perf_counter()
+    tail, fro = ctx.opt_tail(te[:nm], r)
+    t_opt = time.perf_counter() - t0
+    met = (e_tr[:nm] * fro - tail) / tail
+    rec_extra["metric_4_1"] = {"matrices": int(nm), "mean": float(met.mean()), "max": float(met.max()),
+                               "note": "(||A - A_hat|| - ||A - [A]_r||) / ||A - [A]_r|| with [A]_r from tsk_opt_tail "
+                                       "on the FP32 test matrices", "opt_tail_seconds": t_opt}
 
     apply_med = float(np.median(apply_ms))
     value = spec.n_test / (apply_med / 1e3)

@@ -248,6 +248,21 @@ tsk_status tsk_apply_multi(tsk_ctx ctx, const tsk_problem *probs, int32_t nprobs
 tsk_status tsk_error(tsk_ctx ctx, const tsk_stack *A, const float *L, const float *R,
                      int32_t r, double *relerr);
 
+/* The optimum that metric (4.1) of Section 4 compares each SCW output with:
+ * for every slice, tail_d = ||A_d - [A_d]_r||_F (the best rank-r error,
+ * Eckart-Young, Section 1) and fro_d = ||A_d||_F, from the Gram
+ * G_d = A_d A_d^T of the stored values (FP32 accumulation of exact products)
+ * and its top-r eigenvalues (the filtered subspace iteration of
+ * tsk_eig_topk, residual tolerance 1e-7 theta_1):
+ *     tail_d^2 = trace(G_d) - sum_{i <= r} lambda_i(G_d).
+ * Metric (4.1) of an output with relative error e_d is then
+ * (e_d fro_d - tail_d) / tail_d.  A: any stack (FP32, bf16, e4m3 with its
+ * scales: the stored values).  tail, fro: host, count doubles each.
+ * Requires 1 <= r < m, r <= 52, m <= 65536.  Processes one slice after
+ * another and synchronises the stream (an evaluation step, not the hot
+ * path). */
+tsk_status tsk_opt_tail(tsk_ctx ctx, const tsk_stack *A, int32_t r, double *tail, double *fro);
+
 /* Eigensolver controls (defaults in brackets): block = search-block width p
  * [k + max(12, k/2), at most 64 and at most m]; max_iter = cap on filtered
  * subspace steps [300]; tol = residual tolerance relative to theta_1 [by

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtsk.so")
-SOURCES = ["runtime.hip", "stage.hip", "gram.hip", "eig.hip", "apply.hip", "sketch_random.hip"]
+SOURCES = ["runtime.hip", "stage.hip", "gram.hip", "eig.hip", "apply.hip", "sketch_random.hip", "metric.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

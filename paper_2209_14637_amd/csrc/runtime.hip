@@ -17,6 +17,7 @@ tsk_status tsk_apply_noalloc_enqueue(tsk_ctx c, const float *S, int k, const tsk
                                      float *R, float *sigma, double *relerr, int32_t *flags);
 tsk_status tsk_scratch_init(tsk_ctx c, int device);
 tsk_status tsk_random_sketch_enqueue(tsk_ctx c, int kind, int64_t k, int64_t m, uint64_t seed, float *S);
+tsk_status tsk_opt_tail_enqueue(tsk_ctx c, const tsk_stack *s, int r, double *tail, double *fro);
 tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, const float *R, int r,
                              double *relerr);
 tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute);
@@ -242,7 +243,7 @@ void tsk_destroy(tsk_ctx c) {
     drain_events(c);
     TskBuf *bufs[] = {&c->gram_part, &c->gram_G,  &c->eig_Y0,   &c->eig_Y1, &c->eig_Rinv, &c->eig_part,
                       &c->eig_C,     &c->eig_X,   &c->eig_GX,   &c->eig_small, &c->eig_U, &c->counters,
-                      &c->ap_ws,     &c->er_part, &c->st_part,  &c->mp_ws,  &c->mp_tab};
+                      &c->ap_ws,     &c->er_part, &c->st_part,  &c->mp_ws,  &c->mp_tab, &c->mt_ws};
     for (TskBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->mp_pin) (void)hipHostFree(c->mp_pin);
@@ -412,6 +413,17 @@ tsk_status tsk_random_sketch(tsk_ctx c, int32_t kind, int32_t k, int64_t m, uint
     if (k < 1 || m < k || m > (1 << 24)) return tsk_fail(c, TSK_E_ARG, "tsk_random_sketch: need 1 <= k <= m <= 2^24");
     TSK_TRY(tsk_check_dev(c, S, sizeof(float) * (size_t)k * m, "S"));
     return tsk_random_sketch_enqueue(c, kind, k, m, seed, S);
+}
+
+tsk_status tsk_opt_tail(tsk_ctx c, const tsk_stack *A, int32_t r, double *tail, double *fro) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    TSK_TRY(tsk_check_stack(c, A, "A"));
+    if (!tail || !fro) return tsk_fail(c, TSK_E_ARG, "tsk_opt_tail: tail and fro are required (host)");
+    if (r < 1 || r >= A->m || r > 52) return tsk_fail(c, TSK_E_ARG, "tsk_opt_tail: need 1 <= r < m, r <= 52");
+    if (A->m > (1 << 16)) return tsk_fail(c, TSK_E_SHAPE, "tsk_opt_tail: need m <= 65536");
+    return tsk_opt_tail_enqueue(c, A, r, tail, fro);
 }
 
 tsk_status tsk_error(tsk_ctx c, const tsk_stack *A, const float *L, const float *R, int32_t r, double *relerr) {

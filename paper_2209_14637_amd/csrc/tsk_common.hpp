@@ -561,6 +561,7 @@ struct tsk_ctx_s {
     TskBuf eig_Y0, eig_Y1, eig_Rinv, eig_part, eig_C, eig_X, eig_GX, eig_small, eig_U;
     TskBuf counters;
     TskBuf ap_ws;         // workspace of tsk_apply (one buffer, carved per call)
+    TskBuf mt_ws;         // tsk_opt_tail: eigenvector block and trace
     void *scratch = nullptr;  // device address of the no-allocation scratch on this device
     TskBuf er_part, st_part;
     TskBuf mp_ws, mp_tab;            // batched apply: workspace, descriptors + items

@@ -24,7 +24,7 @@ _STATUS = {0: "TSK_OK", 1: "TSK_E_ARG", 2: "TSK_E_SHAPE", 3: "TSK_E_NOMEM", 4: "
 
 EXPORTS = ["tsk_create", "tsk_destroy", "tsk_set_stream", "tsk_last_error", "tsk_stage", "tsk_gram",
            "tsk_eig_topk", "tsk_train", "tsk_random_sketch", "tsk_apply", "tsk_apply_noalloc", "tsk_apply_multi",
-           "tsk_error", "tsk_set_eig_params",
+           "tsk_error", "tsk_opt_tail", "tsk_set_eig_params",
            "tsk_timing_enable", "tsk_timing_read"]
 
 _DTYPES = {"f32": TSK_F32, "bf16": TSK_BF16, "e4m3": TSK_F8E4M3}
@@ -77,6 +77,7 @@ def load(path: str | None = None):
         "tsk_apply_noalloc": ([P, P, I32, sp, I32, I32, P, P, P, P, P], I32),
         "tsk_apply_multi": ([P, ctypes.POINTER(Problem), I32, I32], I32),
         "tsk_error": ([P, sp, P, P, I32, P], I32),
+        "tsk_opt_tail": ([P, sp, I32, P, P], I32),
         "tsk_set_eig_params": ([P, I32, I32, D, I32], I32),
         "tsk_timing_enable": ([P, I32], I32),
         "tsk_timing_read": ([P, I32, P, P], I32),
@@ -291,6 +292,18 @@ class Context:
             relerr = torch.empty(s.count, dtype=torch.float64, device=A.device)
         self._check(self.lib.tsk_error(self.h, ctypes.byref(s), _ptr(L), _ptr(R), r, _ptr(relerr)))
         return relerr
+
+    def opt_tail(self, A, r: int):
+        """||A_d - [A_d]_r||_F and ||A_d||_F of every slice (numpy arrays),
+        for metric (4.1)."""
+        import numpy as np
+        self._sync_stream()
+        s = _stack(A)
+        tail = np.empty(s.count)
+        fro = np.empty(s.count)
+        self._check(self.lib.tsk_opt_tail(self.h, ctypes.byref(s), r, tail.ctypes.data_as(ctypes.c_void_p),
+                                          fro.ctypes.data_as(ctypes.c_void_p)))
+        return tail, fro
 
     def set_eig_params(self, block: int = 0, max_iter: int = 0, tol: float = 0.0, check: int = 0):
         self._check(self.lib.tsk_set_eig_params(self.h, block, max_iter, tol, check))

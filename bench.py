@@ -475,20 +475,33 @@ def run_batch(args):
         return out
 
     pb = problems("bf16")
-    outs = [ctx.apply_multi(p) for p in pb]  # warm-up and output buffers
+    outs_eager = [ctx.apply_multi(p) for p in pb]  # warm-up and output buffers
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    times = []
-    for _ in range(max(args.steps, 3)):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for p, o in zip(pb, outs):
-            ctx.apply_multi(p, outs=o)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    ms = float(np.median(times))
+
+    def timed(run, n):
+        ts = []
+        for _ in range(n):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    # eager: one tsk_apply_multi per batch
+    ms_eager = timed(lambda: [ctx.apply_multi(p, outs=o) for p, o in zip(pb, outs_eager)], max(args.steps, 3))
+    # the serving form: one captured plan (HIP graph) per batch, built
+    # outside the timed region, all batches launched together each step
+    plans = [ctx.plan_multi(p) for p in pb]
+    torch.cuda.synchronize()
+    ctx.launch_plans(plans)
+    torch.cuda.synchronize()
+    ms = timed(lambda: ctx.launch_plans(plans), max(args.steps, 3))
+    times = [ms]
+    outs = [pl.outs for pl in plans]
     # the plain FP32 path: one tsk_apply per (batch, stream)
     p32 = problems("f32")
     o32 = [[ctx.apply(Sx, A, r) for Sx, A, r in p] for p in p32]
@@ -523,7 +536,7 @@ def run_batch(args):
                 nmat += c
         parity = {"max_rel_dev_explicit_error": worst_v, "max_rel_dev_fused_error": worst_f, "tau": TAU["bf16"],
                   "matrices": nmat, "pass": bool(max(worst_v, worst_f) <= TAU["bf16"]),
-                  "note": "the timed tsk_apply_multi outputs; sketches trained on the GPU in bf16, oracle errors "
+                  "note": "the timed plan outputs (last replay); sketches trained on the GPU in bf16, oracle errors "
                           "from the oracle's own FP64 training"}
     apply_bytes = sum(specs[s].m * specs[s].n * 2 * need[s] for s in range(ns))
     rec = {
@@ -532,8 +545,9 @@ def run_batch(args):
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": "batch_bf16: 8 streams of shapes (256,192)..(2048,1536), k in {10,20,40}, r=k/2, "
-                               "2000 test matrices interleaved at random, batches of 256, one tsk_apply_multi per "
-                               "batch; each stream trained on 100 slices (bf16)", "streams": [list(x) for x in
+                               "2000 test matrices interleaved at random, batches of 256, one captured plan (HIP graph "
+                               "of the batched apply) per batch, the 8 plans launched together over two streams; each "
+                               "stream trained on 100 slices (bf16)", "streams": [list(x) for x in
                                                                                          synth.BATCH_SHAPES],
                    "batch": bsz, "n_test": n_test},
         "train_ms_all_streams": t_train * 1e3,
@@ -542,8 +556,12 @@ def run_batch(args):
                            "algorithmic_bytes": apply_bytes},
         "fp32_per_stream_path": {"ms": ms32, "matrices_per_s": n_test / (ms32 / 1e3), "bf16_batched_speedup":
                                  ms32 / ms},
+        "eager_apply_multi": {"ms": ms_eager, "matrices_per_s": n_test / (ms_eager / 1e3),
+                              "note": "one tsk_apply_multi per batch instead of the captured plans"},
         "parity": parity,
     }
+    for pl in plans:
+        pl.close()
     ctx.close()
     return rec
 

@@ -241,6 +241,26 @@ typedef struct {
  * waits for that copy before reusing it). */
 tsk_status tsk_apply_multi(tsk_ctx ctx, const tsk_problem *probs, int32_t nprobs, int32_t compute);
 
+/* Captured batches of the batching form, for serving loops that apply the
+ * same batch layout again and again.  tsk_apply_multi_plan builds the
+ * batch's tables and workspace in plan-owned device memory once, runs the
+ * batch once (the problems' outputs are written), and captures its launch
+ * sequence into a HIP graph; the problems' pointers are fixed in the plan,
+ * so later launches read the then-current contents of the same inputs and
+ * overwrite the same outputs.  Arguments as tsk_apply_multi.  Synchronises
+ * the context's stream.  The plan belongs to the context's device and must
+ * be destroyed with tsk_plan_destroy.
+ * tsk_plan_launch replays `nplans` plans (graph launches) after all work
+ * enqueued on the context's stream; plans alternate between two
+ * context-owned streams so consecutive batches overlap (each plan has its
+ * own workspace; plans whose outputs overlap must not be launched
+ * together), and the context's stream waits for all of them.  Enqueue only. */
+typedef struct tsk_plan_s *tsk_plan;
+tsk_status tsk_apply_multi_plan(tsk_ctx ctx, const tsk_problem *probs, int32_t nprobs, int32_t compute,
+                                tsk_plan *plan);
+tsk_status tsk_plan_launch(tsk_ctx ctx, const tsk_plan *plans, int32_t nplans);
+void tsk_plan_destroy(tsk_plan plan);
+
 /* Explicit relative error ||A_d - L_d R_d^T||_F / ||A_d||_F for every slice
  * (the quantity whose rank-r minimum is problem 1.1).  A: an FP32 stack.
  * L, R: device FP32 with the layout tsk_apply writes.  relerr: device FP64,

@@ -31,6 +31,8 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <new>
+#include <string>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -1807,15 +1809,34 @@ tsk_status tsk_apply_noalloc_enqueue(tsk_ctx c, const float *S, int k, const tsk
 // sketch-size class (kp / 16) one launch of each later phase (sketch,
 // basis, project, eig, outputs; then refine per class of ceil(r / 16)).
 // Items are ordered largest problem first, so the long items start early.
-tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute) {
-    const bool lowp = compute != TSK_F32;
+// Host side of the batching form: descriptors, workspace layout and the
+// work-item lists of every launch.
+struct MultiTables {
+    int np = 0;
+    bool lowp = false, e4 = false;
+    std::vector<ApDesc> desc;
+    std::vector<size_t> off;  // workspace offsets, AP_MREG per problem
+    size_t ws = 0;
+    std::vector<int4> items;
+    size_t n_prep = 0, start[3][5] = {}, cnt[3][5] = {}, rstart[5] = {}, rcnt[5] = {}, fstart = 0, fcnt = 0;
+};
+constexpr int AP_MREG = 11;  // workspace regions per problem
+
+static void multi_build(const tsk_problem *pr, int np, int compute, MultiTables &T) {
+    T.np = np;
+    T.lowp = compute != TSK_F32;
+    T.e4 = compute == TSK_F8E4M3;
+    const bool lowp = T.lowp;
     const int panel = lowp ? SKB_PANEL : SK_PANEL;
     const int band = lowp ? PJL_ROWS : PJ_ROWS;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    constexpr int NREG = 11;  // workspace regions per problem
-    std::vector<ApDesc> desc(np);
-    std::vector<size_t> off(np * NREG);
-    size_t ws = 0;
+    constexpr int NREG = AP_MREG;
+    std::vector<ApDesc> &desc = T.desc;
+    desc.assign(np, ApDesc{});
+    std::vector<size_t> &off = T.off;
+    off.assign(np * NREG, 0);
+    size_t &ws = T.ws;
+    ws = 0;
     for (int i = 0; i < np; ++i) {
         const tsk_stack &A = pr[i].A;
         ApDesc &D = desc[i];
@@ -1858,36 +1879,21 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
             ws += al(sz[j]);
         }
     }
-    TSK_TRY(tsk_grow(c, c->mp_ws, ws));
-    char *base = (char *)c->mp_ws.p;
-    for (int i = 0; i < np; ++i) {
-        ApDesc &D = desc[i];
-        const size_t *o = &off[i * NREG];
-        D.St = lowp ? nullptr : (float *)(base + o[0]);
-        D.Sb = lowp ? (uint16_t *)(base + o[0]) : nullptr;
-        D.B = (float *)(base + o[1]);
-        D.Bb = lowp ? (uint16_t *)(base + o[2]) : nullptr;
-        D.C = (float *)(base + o[3]);
-        D.fro = (double *)(base + o[4]);
-        D.Z = (float *)(base + o[6]);
-        D.q = (int *)(base + o[7]);
-        D.ctc = lowp ? (double *)(base + o[8]) : nullptr;
-        D.rf = (int *)(base + o[9]);
-        D.rf_part = (double *)(base + o[10]);
-    }
     // work items: problems largest first within each list
     std::vector<int> order(np);
     for (int i = 0; i < np; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return desc[a].m * desc[a].n > desc[b].m * desc[b].n;
     });
-    std::vector<int4> items;
+    std::vector<int4> &items = T.items;
+    items.clear();
     for (int i : order) {  // preparation of each sketch
         const int64_t tot = lowp ? (int64_t)desc[i].kp * desc[i].mp : desc[i].m * desc[i].kp;
         for (int64_t b = 0; b < (tot + 255) / 256; ++b) items.push_back(int4{i, (int)b, 0, 0});
     }
-    size_t n_prep = items.size();
-    size_t start[3][5] = {}, cnt[3][5] = {};  // [phase][class]
+    T.n_prep = items.size();
+    auto &start = T.start;  // [phase][class]
+    auto &cnt = T.cnt;
     for (int ph = 0; ph < 3; ++ph)
         for (int cl = 1; cl <= 4; ++cl) {
             start[ph][cl] = items.size();
@@ -1921,7 +1927,8 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
         }
     // refine of the marked matrices' errors, per class of ceil(r / 16), then
     // its final sums (runs of 256 matrices); problems without relerr have none
-    size_t rstart[5] = {}, rcnt[5] = {};
+    auto &rstart = T.rstart;
+    auto &rcnt = T.rcnt;
     for (int cl = 1; cl <= 4; ++cl) {
         rstart[cl] = items.size();
         for (int i : order) {
@@ -1932,44 +1939,48 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
         }
         rcnt[cl] = items.size() - rstart[cl];
     }
-    const size_t fstart = items.size();
+    T.fstart = items.size();
     for (int i : order)
         if (desc[i].relerr)
             for (int64_t d = 0; d < desc[i].count; d += 256) items.push_back(int4{i, (int)d, 0, 0});
-    const size_t fcnt = items.size() - fstart;
-    // one transfer: descriptors then items
-    const size_t dbytes = al(sizeof(ApDesc) * np), ibytes = sizeof(int4) * items.size();
-    if (c->mp_ev) {
-        hipError_t e = hipEventSynchronize(c->mp_ev);  // the previous transfer has read the pinned buffer
-        if (e != hipSuccess) return tsk_hip(c, e, "batch table event");
+    T.fcnt = items.size() - T.fstart;
+}
+
+// Workspace pointers of every descriptor, from the workspace base.
+static void multi_bind(MultiTables &T, char *base) {
+    const bool lowp = T.lowp;
+    constexpr int NREG = AP_MREG;
+    std::vector<ApDesc> &desc = T.desc;
+    const std::vector<size_t> &off = T.off;
+    const int np = T.np;
+    for (int i = 0; i < np; ++i) {
+        ApDesc &D = desc[i];
+        const size_t *o = &off[i * NREG];
+        D.St = lowp ? nullptr : (float *)(base + o[0]);
+        D.Sb = lowp ? (uint16_t *)(base + o[0]) : nullptr;
+        D.B = (float *)(base + o[1]);
+        D.Bb = lowp ? (uint16_t *)(base + o[2]) : nullptr;
+        D.C = (float *)(base + o[3]);
+        D.fro = (double *)(base + o[4]);
+        D.Z = (float *)(base + o[6]);
+        D.q = (int *)(base + o[7]);
+        D.ctc = lowp ? (double *)(base + o[8]) : nullptr;
+        D.rf = (int *)(base + o[9]);
+        D.rf_part = (double *)(base + o[10]);
     }
-    if (c->mp_pin_bytes < dbytes + ibytes) {
-        if (c->mp_pin) (void)hipHostFree(c->mp_pin);
-        c->mp_pin = nullptr;
-        c->mp_pin_bytes = 0;
-        const size_t nb = (dbytes + ibytes + (1 << 16) - 1) & ~(size_t)((1 << 16) - 1);
-        if (hipHostMalloc(&c->mp_pin, nb, hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            c->mp_pin = nullptr;
-            return tsk_fail(c, TSK_E_NOMEM, "pinned batch table allocation failed");
-        }
-        c->mp_pin_bytes = nb;
-    }
-    memcpy(c->mp_pin, desc.data(), sizeof(ApDesc) * np);
-    memcpy((char *)c->mp_pin + dbytes, items.data(), ibytes);
-    TSK_TRY(tsk_grow(c, c->mp_tab, dbytes + ibytes));
-    hipError_t e = hipMemcpyAsync(c->mp_tab.p, c->mp_pin, dbytes + ibytes, hipMemcpyHostToDevice, c->stream);
-    if (e != hipSuccess) return tsk_hip(c, e, "batch table copy");
-    if (!c->mp_ev && hipEventCreateWithFlags(&c->mp_ev, hipEventDisableTiming) != hipSuccess) {
-        (void)hipGetLastError();
-        c->mp_ev = nullptr;
-    }
-    if (c->mp_ev) (void)hipEventRecord(c->mp_ev, c->stream);
-    const ApDesc *P = (const ApDesc *)c->mp_tab.p;
-    const int4 *I = (const int4 *)((const char *)c->mp_tab.p + dbytes);
-    TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(prep_multi_kernel, dim3((unsigned)n_prep), dim3(256), 0,
+}
+
+// The launches of a batch, from device copies of the descriptors (P) and
+// items (I) of T.
+static tsk_status multi_launch(tsk_ctx c, const MultiTables &T, const ApDesc *P, const int4 *I) {
+    const bool lowp = T.lowp, e4 = T.e4;
+    auto &start = T.start;
+    auto &cnt = T.cnt;
+    auto &rstart = T.rstart;
+    auto &rcnt = T.rcnt;
+    const size_t fstart = T.fstart, fcnt = T.fcnt;
+    TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(prep_multi_kernel, dim3((unsigned)T.n_prep), dim3(256), 0,
                                                         c->stream, P, I, lowp ? 1 : 0));
-    const bool e4 = compute == TSK_F8E4M3;
 #define TSK_MSK(CL)                                                                                                \
     if (cnt[0][CL]) {                                                                                              \
         const dim3 g((unsigned)cnt[0][CL]);                                                                        \
@@ -2044,6 +2055,155 @@ tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
 #undef TSK_MOU
     return TSK_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Captured batches (tsk_plan): a batch's tables and workspace live in
+// plan-owned device memory, written once, and its launch sequence is
+// captured into a HIP graph; a launch replays the graph.  Plans launched
+// together alternate between the context's two pipeline streams, so one
+// batch's per-matrix kernels overlap the next batch's streaming kernels
+// (each plan has its own workspace).
+// ---------------------------------------------------------------------------
+struct tsk_plan_s {
+    int device = 0;
+    MultiTables T;
+    void *ws = nullptr, *tab = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static void plan_free(tsk_plan p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->tab) (void)hipFree(p->tab);
+    delete p;
+}
+
+tsk_status tsk_plan_create_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute, tsk_plan *out) {
+    TSK_TRY(tsk_pipeline_streams(c));
+    tsk_plan p = new (std::nothrow) tsk_plan_s();
+    if (!p) return tsk_fail(c, TSK_E_NOMEM, "plan allocation failed");
+    p->device = c->device;
+    multi_build(pr, np, compute, p->T);
+    const size_t dbytes = (sizeof(ApDesc) * np + 255) & ~(size_t)255;
+    const size_t ibytes = sizeof(int4) * p->T.items.size();
+    if (getenv("TSK_FAULT_NOMEM") || hipMalloc(&p->ws, p->T.ws ? p->T.ws : 256) != hipSuccess ||
+        hipMalloc(&p->tab, dbytes + ibytes) != hipSuccess) {
+        (void)hipGetLastError();
+        plan_free(p);
+        return tsk_fail(c, TSK_E_NOMEM, "plan workspace allocation failed");
+    }
+    multi_bind(p->T, (char *)p->ws);
+    std::vector<char> host(dbytes + ibytes, 0);
+    memcpy(host.data(), p->T.desc.data(), sizeof(ApDesc) * np);
+    memcpy(host.data() + dbytes, p->T.items.data(), ibytes);
+    // the caller's work first (inputs may still be in flight), then the copy
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(p->tab, host.data(), dbytes + ibytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return tsk_hip(c, e, "plan tables");
+    }
+    const ApDesc *P = (const ApDesc *)p->tab;
+    const int4 *I = (const int4 *)((const char *)p->tab + dbytes);
+    // one eager run on the first pipeline stream (it validates the launches
+    // and sets the kernels' LDS attributes), then the capture
+    hipStream_t saved = c->stream;
+    const uint32_t timing = c->timing;
+    c->timing = 0;
+    c->stream = c->pl[0];
+    tsk_status st = multi_launch(c, p->T, P, I);
+    if (st == TSK_OK) {
+        e = hipStreamSynchronize(c->pl[0]);
+        if (e == hipSuccess) e = hipStreamBeginCapture(c->pl[0], hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            st = multi_launch(c, p->T, P, I);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(c->pl[0], &g);
+            p->graph = g;
+            if (st == TSK_OK && e2 != hipSuccess) e = e2;
+            if (st == TSK_OK && e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        }
+        if (st == TSK_OK && e != hipSuccess) st = tsk_hip(c, e, "plan capture");
+    }
+    c->stream = saved;
+    c->timing = timing;
+    if (st != TSK_OK) {
+        (void)hipGetLastError();
+        plan_free(p);
+        return st;
+    }
+    *out = p;
+    return TSK_OK;
+}
+
+tsk_status tsk_plan_launch_enqueue(tsk_ctx c, const tsk_plan *plans, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!plans[i] || !plans[i]->exec || plans[i]->device != c->device)
+            return tsk_fail(c, TSK_E_ARG, "tsk_plan_launch: plan " + std::to_string(i) + " is not a plan of this device");
+    TSK_TRY(tsk_pipeline_streams(c));
+    hipError_t e = hipEventRecord(c->pl_fork, c->stream);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->pl[i], c->pl_fork, 0);
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = hipGraphLaunch(plans[i]->exec, c->pl[i & 1]);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipEventRecord(c->pl_join[i], c->pl[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->pl_join[i], 0);
+    }
+    return e == hipSuccess ? TSK_OK : tsk_hip(c, e, "plan launch");
+}
+
+void tsk_plan_destroy_impl(tsk_plan p) {
+    if (!p) return;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != p->device) (void)hipSetDevice(p->device);
+    plan_free(p);
+    if (prev >= 0 && prev != p->device) (void)hipSetDevice(prev);
+}
+
+tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute) {
+    MultiTables T;
+    multi_build(pr, np, compute, T);
+    TSK_TRY(tsk_grow(c, c->mp_ws, T.ws));
+    multi_bind(T, (char *)c->mp_ws.p);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const std::vector<ApDesc> &desc = T.desc;
+    const std::vector<int4> &items = T.items;
+    // one transfer: descriptors then items
+    const size_t dbytes = al(sizeof(ApDesc) * np), ibytes = sizeof(int4) * items.size();
+    if (c->mp_ev) {
+        hipError_t e = hipEventSynchronize(c->mp_ev);  // the previous transfer has read the pinned buffer
+        if (e != hipSuccess) return tsk_hip(c, e, "batch table event");
+    }
+    if (c->mp_pin_bytes < dbytes + ibytes) {
+        if (c->mp_pin) (void)hipHostFree(c->mp_pin);
+        c->mp_pin = nullptr;
+        c->mp_pin_bytes = 0;
+        const size_t nb = (dbytes + ibytes + (1 << 16) - 1) & ~(size_t)((1 << 16) - 1);
+        if (hipHostMalloc(&c->mp_pin, nb, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->mp_pin = nullptr;
+            return tsk_fail(c, TSK_E_NOMEM, "pinned batch table allocation failed");
+        }
+        c->mp_pin_bytes = nb;
+    }
+    memcpy(c->mp_pin, desc.data(), sizeof(ApDesc) * np);
+    memcpy((char *)c->mp_pin + dbytes, items.data(), ibytes);
+    TSK_TRY(tsk_grow(c, c->mp_tab, dbytes + ibytes));
+    hipError_t e = hipMemcpyAsync(c->mp_tab.p, c->mp_pin, dbytes + ibytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return tsk_hip(c, e, "batch table copy");
+    if (!c->mp_ev && hipEventCreateWithFlags(&c->mp_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        c->mp_ev = nullptr;
+    }
+    if (c->mp_ev) (void)hipEventRecord(c->mp_ev, c->stream);
+    const ApDesc *P = (const ApDesc *)c->mp_tab.p;
+    const int4 *I = (const int4 *)((const char *)c->mp_tab.p + dbytes);
+    return multi_launch(c, T, P, I);
+}
+
 
 tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, const float *R, int r, double *relerr) {
     const int64_t m = s->m, n = s->n, count = s->count;

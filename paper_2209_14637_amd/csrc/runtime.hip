@@ -21,6 +21,9 @@ tsk_status tsk_opt_tail_enqueue(tsk_ctx c, const tsk_stack *s, int r, double *ta
 tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, const float *R, int r,
                              double *relerr);
 tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute);
+tsk_status tsk_plan_create_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute, tsk_plan *out);
+tsk_status tsk_plan_launch_enqueue(tsk_ctx c, const tsk_plan *plans, int n);
+void tsk_plan_destroy_impl(tsk_plan p);
 
 tsk_status tsk_fail(tsk_ctx c, tsk_status st, const std::string &msg) {
     if (c) c->err = msg;
@@ -366,10 +369,38 @@ static tsk_status check_apply(tsk_ctx c, const float *S, int32_t k, const tsk_st
     return TSK_OK;
 }
 
+static tsk_status check_multi(tsk_ctx c, const tsk_problem *probs, int32_t nprobs, int32_t compute);
+
+tsk_status tsk_apply_multi_plan(tsk_ctx c, const tsk_problem *probs, int32_t nprobs, int32_t compute,
+                                tsk_plan *plan) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    if (!plan) return tsk_fail(c, TSK_E_ARG, "tsk_apply_multi_plan: null plan pointer");
+    *plan = nullptr;
+    TSK_TRY(check_multi(c, probs, nprobs, compute));
+    return tsk_plan_create_enqueue(c, probs, nprobs, compute, plan);
+}
+
+tsk_status tsk_plan_launch(tsk_ctx c, const tsk_plan *plans, int32_t nplans) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    if (!plans || nplans < 1) return tsk_fail(c, TSK_E_ARG, "tsk_plan_launch: need nplans >= 1");
+    return tsk_plan_launch_enqueue(c, plans, nplans);
+}
+
+void tsk_plan_destroy(tsk_plan plan) { tsk_plan_destroy_impl(plan); }
+
 tsk_status tsk_apply_multi(tsk_ctx c, const tsk_problem *probs, int32_t nprobs, int32_t compute) {
     if (!c) return TSK_E_ARG;
     c->err.clear();
     DeviceGuard g(c->device);
+    TSK_TRY(check_multi(c, probs, nprobs, compute));
+    return tsk_apply_multi_enqueue(c, probs, nprobs, compute);
+}
+
+static tsk_status check_multi(tsk_ctx c, const tsk_problem *probs, int32_t nprobs, int32_t compute) {
     if (!probs || nprobs < 1 || nprobs > (1 << 20))
         return tsk_fail(c, TSK_E_ARG, "tsk_apply_multi: need 1 <= nprobs <= 2^20 problems");
     int64_t items = 0;
@@ -383,7 +414,7 @@ tsk_status tsk_apply_multi(tsk_ctx c, const tsk_problem *probs, int32_t nprobs, 
         items += p.A.count * (p.A.n / 64 + 2 * (p.A.m / 64) + 6);
     }
     if (items > ((int64_t)1 << 31) - 1) return tsk_fail(c, TSK_E_SHAPE, "tsk_apply_multi: batch too large");
-    return tsk_apply_multi_enqueue(c, probs, nprobs, compute);
+    return TSK_OK;
 }
 
 tsk_status tsk_apply(tsk_ctx c, const float *S, int32_t k, const tsk_stack *test, int32_t r, int32_t compute,

@@ -24,7 +24,8 @@ _STATUS = {0: "TSK_OK", 1: "TSK_E_ARG", 2: "TSK_E_SHAPE", 3: "TSK_E_NOMEM", 4: "
 
 EXPORTS = ["tsk_create", "tsk_destroy", "tsk_set_stream", "tsk_last_error", "tsk_stage", "tsk_gram",
            "tsk_eig_topk", "tsk_train", "tsk_random_sketch", "tsk_apply", "tsk_apply_noalloc", "tsk_apply_multi",
-           "tsk_error", "tsk_opt_tail", "tsk_set_eig_params",
+           "tsk_apply_multi_plan", "tsk_plan_launch", "tsk_plan_destroy", "tsk_error", "tsk_opt_tail",
+           "tsk_set_eig_params",
            "tsk_timing_enable", "tsk_timing_read"]
 
 _DTYPES = {"f32": TSK_F32, "bf16": TSK_BF16, "e4m3": TSK_F8E4M3}
@@ -76,6 +77,9 @@ def load(path: str | None = None):
         "tsk_apply": ([P, P, I32, sp, I32, I32, P, P, P, P, P], I32),
         "tsk_apply_noalloc": ([P, P, I32, sp, I32, I32, P, P, P, P, P], I32),
         "tsk_apply_multi": ([P, ctypes.POINTER(Problem), I32, I32], I32),
+        "tsk_apply_multi_plan": ([P, ctypes.POINTER(Problem), I32, I32, ctypes.POINTER(P)], I32),
+        "tsk_plan_launch": ([P, ctypes.POINTER(P), I32], I32),
+        "tsk_plan_destroy": ([P], None),
         "tsk_error": ([P, sp, P, P, I32, P], I32),
         "tsk_opt_tail": ([P, sp, I32, P, P], I32),
         "tsk_set_eig_params": ([P, I32, I32, D, I32], I32),
@@ -129,6 +133,29 @@ def _stack(A) -> Stack:
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A captured batch (tsk_apply_multi_plan); `outs` are its problems'
+    output dicts, `keep` holds the inputs it reads."""
+
+    def __init__(self, ctx, h, outs, keep):
+        self.ctx, self.h, self.outs, self.keep = ctx, h, outs, keep
+
+    def launch(self):
+        self.ctx.launch_plans([self])
+        return self.outs
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.tsk_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Context:
@@ -259,6 +286,40 @@ class Context:
                 "sigma": torch.empty((s.count, r), dtype=torch.float32, device=dev),
                 "relerr": torch.empty(s.count, dtype=torch.float64, device=dev) if relerr else None,
                 "flags": torch.empty(s.count, dtype=torch.int32, device=dev) if flags else None}
+
+    def _problem_array(self, problems, outs):
+        n = len(problems)
+        arr = (Problem * n)()
+        res, keep, dts = [], [], set()
+        for i, (S, A, r) in enumerate(problems):
+            s = _stack(A)
+            dts.add(s.dtype)
+            if S.dtype != torch.float32 or not S.is_contiguous() or S.shape[1] != s.m:
+                raise ValueError("S must be a contiguous (k, m) float32 CUDA tensor")
+            o = outs[i] if outs is not None else self._outputs(s, r, S.device)
+            opt = [o[key].data_ptr() if o.get(key) is not None else None for key in ("relerr", "flags")]
+            arr[i] = Problem(s, S.data_ptr(), S.shape[0], r, o["L"].data_ptr(), o["R"].data_ptr(),
+                             o["sigma"].data_ptr(), opt[0], opt[1])
+            res.append(o)
+            keep.append((S, A))
+        if len(dts) != 1:
+            raise ValueError("all problems of a batch must have the same format")
+        return arr, res, keep, dts.pop()
+
+    def plan_multi(self, problems, outs: list | None = None) -> "Plan":
+        """Captured batch (tsk_apply_multi_plan): runs the batch once and
+        returns a Plan whose launch() replays it on the same buffers."""
+        self._sync_stream()
+        arr, res, keep, dt = self._problem_array(problems, outs)
+        h = ctypes.c_void_p()
+        self._check(self.lib.tsk_apply_multi_plan(self.h, arr, len(problems), dt, ctypes.byref(h)))
+        return Plan(self, h, res, keep)
+
+    def launch_plans(self, plans):
+        """Replay several plans together (tsk_plan_launch)."""
+        self._sync_stream()
+        arr = (ctypes.c_void_p * len(plans))(*[p.h for p in plans])
+        self._check(self.lib.tsk_plan_launch(self.h, arr, len(plans)))
 
     def apply_multi(self, problems, outs: list | None = None) -> list:
         """SCW on a batch of problems [(S, A, r), ...] of different shapes

@@ -297,6 +297,17 @@ tsk_status tsk_opt_tail(tsk_ctx ctx, const tsk_stack *A, int32_t r, double *tail
 tsk_status tsk_set_eig_params(tsk_ctx ctx, int32_t block, int32_t max_iter, double tol,
                               int32_t check);
 
+/* Tuning of the apply for one shape class (m, n, ceil(k / 16), dtype of the
+ * test stack), as chosen by an autotuner (paper_2209_14637_amd/autotune.py
+ * times the candidates and keeps a JSON cache): groups = the number of
+ * pipeline groups of tsk_apply (1..64; the groups alternate between two
+ * context streams), pj_cols = columns per projection step of the bf16 form
+ * (64 or 128; also used by the batched forms).  0 restores the default
+ * (groups: halves from 256 matrices on; pj_cols: 64).  Results do not
+ * depend on either (bit for bit).  Host only. */
+tsk_status tsk_set_tuning(tsk_ctx ctx, int64_t m, int64_t n, int32_t k, int32_t dtype, int32_t groups,
+                          int32_t pj_cols);
+
 /* Kernel timing.  mask bit i (i = TSK_KERNEL_*) brackets every launch of
  * kernel class i with HIP events on the context's stream (0: off, -1: all
  * classes).  tsk_timing_read synchronises and returns, for each kernel class,

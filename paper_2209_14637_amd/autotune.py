@@ -1,0 +1,136 @@
+"""Autotuner of the apply's launch choices per shape class.
+
+A shape class is (m, n, ceil(k / 16), storage format) of a test stack.  Two
+choices are tuned (tsk_set_tuning):
+  groups  : pipeline groups of tsk_apply (the groups alternate between two
+            context streams, so one group's per-matrix kernels overlap the
+            next group's streaming kernels);
+  pj_cols : columns per projection step of the bf16 form (64 or 128), also
+            used by the batched forms (tsk_apply_multi, captured plans).
+Every candidate is timed with HIP events on seeded Gaussian matrices of the
+class's shape and a random orthonormal sketch; the outputs of all
+candidates must be identical bit for bit (the choices change the launch
+shape only), and the fastest is kept in a JSON cache:
+  {"<m>x<n>:kp<kp>:<fmt>": {"groups": g, "pj_cols": c, "ms": t, "count": N,
+                           "timings": {"g=1,c=64": t, ...}}, ...}
+Contexts apply a cache with Context.load_tuning(path).
+
+  python -m paper_2209_14637_amd.autotune 1920x1080:40:bf16:1000 [...] [--out FILE]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tune_cache.json")
+
+
+def class_key(m: int, n: int, k: int, fmt: str) -> str:
+    return f"{m}x{n}:kp{(k + 15) // 16 * 16}:{fmt}"
+
+
+def parse_key(key: str):
+    shape, kp, fmt = key.split(":")
+    m, n = (int(x) for x in shape.split("x"))
+    return m, n, int(kp[2:]), fmt
+
+
+def load_cache(path: str | None = None) -> dict:
+    path = path or CACHE
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def apply_cache(ctx, path: str | None = None) -> int:
+    cache = load_cache(path)
+    for key, ent in cache.items():
+        m, n, kp, fmt = parse_key(key)
+        ctx.set_tuning(m, n, kp, fmt, ent.get("groups", 0), ent.get("pj_cols", 0))
+    return len(cache)
+
+
+def _candidates(fmt: str, count: int):
+    groups = [g for g in (1, 2, 4) if g == 1 or count >= 64 * g]
+    cols = (64, 128) if fmt == "bf16" else (0,)
+    return [(g, c) for g in groups for c in cols]
+
+
+def tune_class(ctx, m: int, n: int, k: int, fmt: str, count: int, reps: int = 5, seed: int = 0) -> dict:
+    """Time every candidate for one class; returns the cache entry."""
+    import torch
+    rng = np.random.default_rng([seed, m, n, k])
+    r = max(1, k // 2)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(rng.integers(1 << 62)))
+    ld = (n + 3) // 4 * 4  # rows on 16-byte boundaries
+    a = torch.randn((count, m, ld), generator=gen, device="cuda", dtype=torch.float32)[:, :, :n]
+    A = a if fmt == "f32" else ctx.stage(a, fmt)
+    q, _ = np.linalg.qr(rng.standard_normal((m, k)))
+    S = torch.from_numpy(np.ascontiguousarray(q.T, dtype=np.float32)).cuda()
+    timings, ref, best = {}, None, None
+    for g, c in _candidates(fmt, count):
+        ctx.set_tuning(m, n, k, fmt, g, c)
+        out = ctx.apply(S, A, r)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.apply(S, A, r, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        t = float(np.median(ts))
+        timings[f"g={g},c={c}"] = t
+        if ref is None:
+            ref = {key: v.clone() for key, v in out.items() if v is not None}
+        else:
+            for key in ref:
+                if not torch.equal(out[key], ref[key]):
+                    raise RuntimeError(f"tuning candidate g={g}, c={c} changed output {key}")
+        if best is None or t < best[2]:
+            best = (g, c, t)
+    ctx.set_tuning(m, n, k, fmt, best[0], best[1])
+    return {"groups": best[0], "pj_cols": best[1], "ms": best[2], "count": count, "timings": timings}
+
+
+def tune(ctx, classes, path: str | None = None, reps: int = 5) -> dict:
+    """Tune classes [(m, n, k, fmt, count), ...], merge into the cache at
+    `path` (default: the package's tune_cache.json) and write it."""
+    path = path or CACHE
+    cache = load_cache(path)
+    for m, n, k, fmt, count in classes:
+        cache[class_key(m, n, k, fmt)] = tune_class(ctx, m, n, k, fmt, count, reps)
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    return cache
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("classes", nargs="+", help="m x n : k : format : count, e.g. 1920x1080:40:bf16:1000")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args()
+    from . import tsk
+    ctx = tsk.Context(0)
+    cls = []
+    for spec in args.classes:
+        shape, k, fmt, count = spec.split(":")
+        m, n = (int(x) for x in shape.split("x"))
+        cls.append((m, n, int(k), fmt, int(count)))
+    cache = tune(ctx, cls, args.out, args.reps)
+    for key, ent in cache.items():
+        print(key, {x: ent[x] for x in ("groups", "pj_cols", "ms")}, flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

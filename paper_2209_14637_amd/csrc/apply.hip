@@ -1198,16 +1198,17 @@ __global__ __launch_bounds__(64, 1) void sketch_bf16_kernel(const ET *__restrict
                                                           double *__restrict__ fro_part, int npanel) {
     sketch_bf16_body<MT, ET>(A, scale, m, n, ld, stride, Sb, mp, B, ldb, fro_part, npanel, blockIdx.y, blockIdx.x);
 }
-// Columns per projection step: 64 for bf16 (LDS 37 KB and 112 VGPRs at
-// kp = 48: four workgroups per CU, 5% faster than 128 columns at two, which
-// measured faster than 256 at one; keeping two steps of loads in flight
-// instead of one gained nothing), 128 for e4m3 (also 128-byte segments).
+// Columns per projection step, by default: 64 for bf16 (LDS 37 KB and 112
+// VGPRs at kp = 48: four workgroups per CU, 5% faster than 128 columns at
+// two, which measured faster than 256 at one; keeping two steps of loads in
+// flight instead of one gained nothing), 128 for e4m3 (also 128-byte
+// segments).  A tuning entry (tsk_set_tuning) may choose 128 for bf16.
 template <typename ET>
 constexpr int pjl_k() { return sizeof(ET) == 2 ? 64 : 128; }
 
 // two workgroups per CU (at most 256 VGPRs, which the C^T C epilogue would
 // otherwise exceed at kp = 64)
-template <int NT, typename ET>
+template <int NT, int K, typename ET>
 __global__ __launch_bounds__(256, 2) void project_bf16_kernel(const ET *A, const float *__restrict__ scale, int64_t m,
                                                            int64_t n, int64_t ld, int64_t stride, const uint16_t *Bb,
                                                            int64_t ldv, float *__restrict__ C, int64_t count,
@@ -1216,7 +1217,7 @@ __global__ __launch_bounds__(256, 2) void project_bf16_kernel(const ET *A, const
     int64_t d;
     int band;
     xcd_band(blockIdx.x, count, nb, d, band);
-    project_lds_body<NT, pjl_k<ET>(), ET>(A, scale, m, n, ld, stride, Bb, ldv, C, d, band, lds_dyn, ctc);
+    project_lds_body<NT, K, ET>(A, scale, m, n, ld, stride, Bb, ldv, C, d, band, lds_dyn, ctc);
 }
 template <int KP>
 __global__ __launch_bounds__(256, 2) void basis_kernel(float *__restrict__ B, int64_t ldb, int64_t n, int k,
@@ -1285,13 +1286,13 @@ __global__ __launch_bounds__(64, 1) void sketch_bf16_multi(const ApDesc *__restr
     sketch_bf16_body<MT, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Sb, D.mp, D.B, D.ldv,
                              D.fro, D.npanel, it.y, it.z);
 }
-template <int NT, typename ET>
+template <int NT, int K, typename ET>
 __global__ __launch_bounds__(256, 2) void project_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int4 it = items[blockIdx.x];
     if (it.x < 0) return;  // padding of the XCD-interleaved item list
     const ApDesc &D = P[it.x];
-    project_lds_body<NT, pjl_k<ET>(), ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Bb, D.ldv, D.C,
+    project_lds_body<NT, K, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Bb, D.ldv, D.C,
                                           it.y, it.z, lds_dyn, D.ctc);
 }
 template <int KP>
@@ -1615,16 +1616,22 @@ static tsk_status apply_lowp_ws(tsk_ctx c, const float *S, int k, const tsk_stac
 #undef TSK_SKB
     TSK_TRY(basis_enqueue(c, kp, B, ldv, n, k, Bb, count, w));
     const dim3 gp((unsigned)(nb * count));
-    const size_t pjl = (size_t)std::max(pjl_lds_bytes(pjl_k<ET>(), (int)sizeof(ET), kp), pjl_ctc_bytes(kp));
-#define TSK_PJB(NTV)                                                                                          \
+    constexpr int K0 = pjl_k<ET>();
+    const bool k128 = sizeof(ET) == 2 && tsk_tuning(c, m, n, kp, s->dtype).pj_cols == 128;
+#define TSK_PJB(NTV, KV)                                                                                      \
     {                                                                                                         \
-        TSK_TRY(allow_lds(c, (const void *)project_bf16_kernel<NTV, ET>, pjl));                               \
+        const size_t pjl = (size_t)std::max(pjl_lds_bytes(KV, (int)sizeof(ET), kp), pjl_ctc_bytes(kp));      \
+        TSK_TRY(allow_lds(c, (const void *)project_bf16_kernel<NTV, KV, ET>, pjl));                           \
         TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                     \
-                   hipLaunchKernelGGL((project_bf16_kernel<NTV, ET>), gp, dim3(PJL_THREADS), pjl, c->stream,    \
-                                      A, sc, m, n, s->ld, s->stride, (const uint16_t *)Bb, ldv, Cm, count, nb, \
-                                      ctc));                                                                  \
+                   hipLaunchKernelGGL((project_bf16_kernel<NTV, KV, ET>), gp, dim3(PJL_THREADS), pjl,           \
+                                      c->stream, A, sc, m, n, s->ld, s->stride, (const uint16_t *)Bb, ldv, Cm,  \
+                                      count, nb, ctc));                                                       \
     }
-    TSK_KP_SWITCH(kp / 16, TSK_PJB(1), TSK_PJB(2), TSK_PJB(3), TSK_PJB(4))
+    if (k128) {
+        TSK_KP_SWITCH(kp / 16, TSK_PJB(1, 128), TSK_PJB(2, 128), TSK_PJB(3, 128), TSK_PJB(4, 128))
+    } else {
+        TSK_KP_SWITCH(kp / 16, TSK_PJB(1, K0), TSK_PJB(2, K0), TSK_PJB(3, K0), TSK_PJB(4, K0))
+    }
 #undef TSK_PJB
     return finish_enqueue(c, s, kp, B, ldv, Cm, k, r, fro, npanel, L, R, sigma, relerr, flags, ctc, w);
 }
@@ -1681,12 +1688,14 @@ static ApWs ws_from(const ApWs &w, const tsk_stack *s, int k, int64_t d0) {
 // leave too few matrices in flight to hide it: on 1000 bf16 matrices of
 // 1920 x 1080 at k = 40, halves took 3.52 ms, quarters 3.66, the whole
 // stack 3.68, groups of 125 / 64 / 32 4.6 / 6.7 / 11.2 ms.
-static int64_t apply_group(const tsk_stack *s) {
+static int64_t apply_group(tsk_ctx c, const tsk_stack *s, int k) {
     const char *e = getenv("TSK_APPLY_GROUP");
     if (e) {
         const long long g = atoll(e);
         if (g > 0) return g;
     }
+    const int groups = tsk_tuning(c, s->m, s->n, (k + 15) / 16 * 16, s->dtype).groups;
+    if (groups > 0) return (s->count + groups - 1) / groups;
     return s->count >= 256 ? (s->count + 1) / 2 : s->count;
 }
 
@@ -1700,7 +1709,7 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
     const ApLayout lay = apply_layout(s, k, s->count);
     TSK_TRY(tsk_grow(c, c->ap_ws, lay.total));
     const ApWs ws = apply_carve(c->ap_ws.p, lay, s);
-    const int64_t g = apply_group(s);
+    const int64_t g = apply_group(c, s, k);
     if (g >= s->count) return apply_ws(c, S, k, s, r, L, R, sigma, relerr, flags, ws, true);
     TSK_TRY(tsk_pipeline_streams(c));
     // the sketch is prepared once, on the caller's stream, then the fork
@@ -1819,13 +1828,19 @@ struct MultiTables {
     size_t ws = 0;
     std::vector<int4> items;
     size_t n_prep = 0, start[3][5] = {}, cnt[3][5] = {}, rstart[5] = {}, rcnt[5] = {}, fstart = 0, fcnt = 0;
+    size_t start128[5] = {}, cnt128[5] = {};  // projection items at 128 bf16 columns per step
+    std::vector<char> k128;                    // per problem: 128-column projection steps
 };
 constexpr int AP_MREG = 11;  // workspace regions per problem
 
-static void multi_build(const tsk_problem *pr, int np, int compute, MultiTables &T) {
+static void multi_build(tsk_ctx c, const tsk_problem *pr, int np, int compute, MultiTables &T) {
     T.np = np;
     T.lowp = compute != TSK_F32;
     T.e4 = compute == TSK_F8E4M3;
+    T.k128.assign(np, 0);
+    if (compute == TSK_BF16)
+        for (int i = 0; i < np; ++i)
+            T.k128[i] = tsk_tuning(c, pr[i].A.m, pr[i].A.n, (pr[i].k + 15) / 16 * 16, TSK_BF16).pj_cols == 128;
     const bool lowp = T.lowp;
     const int panel = lowp ? SKB_PANEL : SK_PANEL;
     const int band = lowp ? PJL_ROWS : PJ_ROWS;
@@ -1895,11 +1910,16 @@ static void multi_build(const tsk_problem *pr, int np, int compute, MultiTables 
     auto &start = T.start;  // [phase][class]
     auto &cnt = T.cnt;
     for (int ph = 0; ph < 3; ++ph)
-        for (int cl = 1; cl <= 4; ++cl) {
-            start[ph][cl] = items.size();
+        for (int cl = 1; cl <= 4; ++cl)
+            for (int kv = 0; kv < (ph == 1 ? 2 : 1); ++kv) {
+            // projection lists per step width: kv = 1 holds the problems
+            // whose tuning entry chose 128 bf16 columns per step
+            size_t &st0 = kv ? T.start128[cl] : start[ph][cl];
+            st0 = items.size();
             for (int i : order) {
                 const ApDesc &D = desc[i];
                 if (D.kp / 16 != cl) continue;
+                if (ph == 1 && (int)T.k128[i] != kv) continue;
                 const int nt = ph == 0 ? D.npanel : ph == 1 ? (int)((D.m + band - 1) / band) : 1;
                 for (int64_t d = 0; d < D.count; ++d)
                     for (int t = 0; t < nt; ++t) items.push_back(int4{i, (int)d, t, 0});
@@ -1911,7 +1931,7 @@ static void multi_build(const tsk_problem *pr, int np, int compute, MultiTables 
                 // interleaved and padded with items that do nothing
                 std::vector<int4> xl[8];
                 int64_t mi = 0;
-                for (size_t a = start[ph][cl]; a < items.size(); ++mi) {
+                for (size_t a = st0; a < items.size(); ++mi) {
                     size_t b = a;
                     while (b < items.size() && items[b].x == items[a].x && items[b].y == items[a].y) ++b;
                     xl[mi % 8].insert(xl[mi % 8].end(), items.begin() + a, items.begin() + b);
@@ -1919,11 +1939,11 @@ static void multi_build(const tsk_problem *pr, int np, int compute, MultiTables 
                 }
                 size_t len = 0;
                 for (auto &v : xl) len = std::max(len, v.size());
-                items.resize(start[ph][cl]);
+                items.resize(st0);
                 for (size_t j = 0; j < len; ++j)
                     for (auto &v : xl) items.push_back(j < v.size() ? v[j] : int4{-1, 0, 0, 0});
             }
-            cnt[ph][cl] = items.size() - start[ph][cl];
+            (kv ? T.cnt128[cl] : cnt[ph][cl]) = items.size() - st0;
         }
     // refine of the marked matrices' errors, per class of ceil(r / 16), then
     // its final sums (runs of 256 matrices); problems without relerr have none
@@ -2001,16 +2021,24 @@ static tsk_status multi_launch(tsk_ctx c, const MultiTables &T, const ApDesc *P,
         if (!lowp) {                                                                                               \
             TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_multi<CL>, g, dim3(64), 0, c->stream, P, It)); \
         } else if (e4) {                                                                                           \
-            const size_t pjl = (size_t)std::max(pjl_lds_bytes(pjl_k<uint8_t>(), 1, 16 * CL), pjl_ctc_bytes(16 * CL)); \
-            TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<CL, uint8_t>, pjl));                             \
-            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL((project_bf16_multi<CL, uint8_t>), g,             \
+            const size_t pjl = (size_t)std::max(pjl_lds_bytes(128, 1, 16 * CL), pjl_ctc_bytes(16 * CL));          \
+            TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<CL, 128, uint8_t>, pjl));                        \
+            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL((project_bf16_multi<CL, 128, uint8_t>), g,        \
                                                                  dim3(PJL_THREADS), pjl, c->stream, P, It));       \
         } else {                                                                                                   \
-            const size_t pjl = (size_t)std::max(pjl_lds_bytes(pjl_k<uint16_t>(), 2, 16 * CL), pjl_ctc_bytes(16 * CL)); \
-            TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<CL, uint16_t>, pjl));                            \
-            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL((project_bf16_multi<CL, uint16_t>), g,            \
+            const size_t pjl = (size_t)std::max(pjl_lds_bytes(64, 2, 16 * CL), pjl_ctc_bytes(16 * CL));           \
+            TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<CL, 64, uint16_t>, pjl));                        \
+            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL((project_bf16_multi<CL, 64, uint16_t>), g,        \
                                                                  dim3(PJL_THREADS), pjl, c->stream, P, It));       \
         }                                                                                                          \
+    }                                                                                                              \
+    if (T.cnt128[CL]) {                                                                                            \
+        const dim3 g((unsigned)T.cnt128[CL]);                                                                      \
+        const int4 *It = I + T.start128[CL];                                                                       \
+        const size_t pjl = (size_t)std::max(pjl_lds_bytes(128, 2, 16 * CL), pjl_ctc_bytes(16 * CL));               \
+        TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<CL, 128, uint16_t>, pjl));                           \
+        TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL((project_bf16_multi<CL, 128, uint16_t>), g,           \
+                                                             dim3(PJL_THREADS), pjl, c->stream, P, It));           \
     }
 #define TSK_MFA(CL)                                                                                          \
     if (cnt[2][CL])                                                                                          \
@@ -2086,7 +2114,7 @@ tsk_status tsk_plan_create_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int
     tsk_plan p = new (std::nothrow) tsk_plan_s();
     if (!p) return tsk_fail(c, TSK_E_NOMEM, "plan allocation failed");
     p->device = c->device;
-    multi_build(pr, np, compute, p->T);
+    multi_build(c, pr, np, compute, p->T);
     const size_t dbytes = (sizeof(ApDesc) * np + 255) & ~(size_t)255;
     const size_t ibytes = sizeof(int4) * p->T.items.size();
     if (getenv("TSK_FAULT_NOMEM") || hipMalloc(&p->ws, p->T.ws ? p->T.ws : 256) != hipSuccess ||
@@ -2165,7 +2193,7 @@ void tsk_plan_destroy_impl(tsk_plan p) {
 
 tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute) {
     MultiTables T;
-    multi_build(pr, np, compute, T);
+    multi_build(c, pr, np, compute, T);
     TSK_TRY(tsk_grow(c, c->mp_ws, T.ws));
     multi_bind(T, (char *)c->mp_ws.p);
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };

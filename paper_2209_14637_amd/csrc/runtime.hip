@@ -79,6 +79,11 @@ tsk_status tsk_pipeline_streams(tsk_ctx c) {
     return TSK_OK;
 }
 
+TskTune tsk_tuning(tsk_ctx c, int64_t m, int64_t n, int kp, int dtype) {
+    const auto it = c->tune.find(std::make_tuple(m, n, kp, dtype));
+    return it == c->tune.end() ? TskTune{} : it->second;
+}
+
 // The pointer must lie in a device allocation that holds [p, p + bytes).
 tsk_status tsk_check_dev(tsk_ctx c, const void *p, size_t bytes, const char *name) {
     if (!p) return tsk_fail(c, TSK_E_ARG, std::string(name) + ": null pointer");
@@ -477,6 +482,24 @@ tsk_status tsk_set_eig_params(tsk_ctx c, int32_t block, int32_t max_iter, double
     c->eig_max_iter = max_iter > 0 ? max_iter : 300;
     c->eig_tol = tol > 0 ? tol : 0.0;  // 0: the default for the Gram's precision
     c->eig_check = check > 0 ? check : 6;
+    return TSK_OK;
+}
+
+tsk_status tsk_set_tuning(tsk_ctx c, int64_t m, int64_t n, int32_t k, int32_t dtype, int32_t groups,
+                          int32_t pj_cols) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    if (m < 1 || n < 1 || k < 1 || k > 64) return tsk_fail(c, TSK_E_ARG, "tsk_set_tuning: need m, n >= 1, 1 <= k <= 64");
+    if (dtype != TSK_F32 && dtype != TSK_BF16 && dtype != TSK_F8E4M3)
+        return tsk_fail(c, TSK_E_ARG, "tsk_set_tuning: dtype must be TSK_F32, TSK_BF16 or TSK_F8E4M3");
+    if (groups < 0 || groups > 64) return tsk_fail(c, TSK_E_ARG, "tsk_set_tuning: need 0 <= groups <= 64");
+    if (pj_cols != 0 && !(dtype == TSK_BF16 && (pj_cols == 64 || pj_cols == 128)))
+        return tsk_fail(c, TSK_E_ARG, "tsk_set_tuning: pj_cols must be 0, or 64 or 128 for TSK_BF16");
+    const auto key = std::make_tuple(m, n, (k + 15) / 16 * 16, (int)dtype);
+    if (groups == 0 && pj_cols == 0)
+        c->tune.erase(key);
+    else
+        c->tune[key] = TskTune{groups, pj_cols};
     return TSK_OK;
 }
 

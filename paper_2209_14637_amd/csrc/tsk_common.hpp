@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/tsk.h"
@@ -547,6 +549,12 @@ struct TskBuf {
     size_t bytes = 0;
 };
 
+// Per-shape-class tuning of the apply (tsk_set_tuning): 0 = default.
+struct TskTune {
+    int groups = 0;   // pipeline groups of tsk_apply
+    int pj_cols = 0;  // bf16 projection: columns per step (64 or 128)
+};
+
 struct TskEvent {
     int cls;
     hipEvent_t a, b;
@@ -573,6 +581,8 @@ struct tsk_ctx_s {
     // from and joined back into the caller's stream
     hipStream_t pl[2] = {nullptr, nullptr};
     hipEvent_t pl_fork = nullptr, pl_join[2] = {nullptr, nullptr};
+    // tuning entries by shape class (m, n, kp, dtype)
+    std::map<std::tuple<int64_t, int64_t, int, int>, TskTune> tune;
     // eigensolver controls
     int eig_block = 0, eig_max_iter = 300, eig_check = 6;
     double eig_tol = 0.0;  // 0: TSK_EIG_TOL_F32 / TSK_EIG_TOL_BF16 by the Gram's precision
@@ -609,6 +619,7 @@ tsk_status tsk_grow(tsk_ctx c, TskBuf &b, size_t bytes);
 tsk_status tsk_check_dev(tsk_ctx c, const void *p, size_t bytes, const char *name);
 tsk_status tsk_check_stack(tsk_ctx c, const tsk_stack *s, const char *name);
 tsk_status tsk_pipeline_streams(tsk_ctx c);
+TskTune tsk_tuning(tsk_ctx c, int64_t m, int64_t n, int kp, int dtype);
 void tsk_ev_begin(tsk_ctx c, int cls, hipEvent_t *a);
 void tsk_ev_end(tsk_ctx c, int cls, hipEvent_t a);
 

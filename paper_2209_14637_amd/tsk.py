@@ -25,7 +25,7 @@ _STATUS = {0: "TSK_OK", 1: "TSK_E_ARG", 2: "TSK_E_SHAPE", 3: "TSK_E_NOMEM", 4: "
 EXPORTS = ["tsk_create", "tsk_destroy", "tsk_set_stream", "tsk_last_error", "tsk_stage", "tsk_gram",
            "tsk_eig_topk", "tsk_train", "tsk_random_sketch", "tsk_apply", "tsk_apply_noalloc", "tsk_apply_multi",
            "tsk_apply_multi_plan", "tsk_plan_launch", "tsk_plan_destroy", "tsk_error", "tsk_opt_tail",
-           "tsk_set_eig_params",
+           "tsk_set_eig_params", "tsk_set_tuning",
            "tsk_timing_enable", "tsk_timing_read"]
 
 _DTYPES = {"f32": TSK_F32, "bf16": TSK_BF16, "e4m3": TSK_F8E4M3}
@@ -83,6 +83,7 @@ def load(path: str | None = None):
         "tsk_error": ([P, sp, P, P, I32, P], I32),
         "tsk_opt_tail": ([P, sp, I32, P, P], I32),
         "tsk_set_eig_params": ([P, I32, I32, D, I32], I32),
+        "tsk_set_tuning": ([P, I64, I64, I32, I32, I32, I32], I32),
         "tsk_timing_enable": ([P, I32], I32),
         "tsk_timing_read": ([P, I32, P, P], I32),
     }
@@ -161,7 +162,9 @@ class Plan:
 class Context:
     """One libtsk context bound to a device; enqueues on torch's current stream."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tuning: str | None = "default"):
+        """tuning: an autotuner cache to apply ("default": the package's
+        tune_cache.json, measured on MI355X; None: no tuning entries)."""
         self.lib = load()
         self.device = device
         h = ctypes.c_void_p()
@@ -170,6 +173,8 @@ class Context:
         if st != TSK_OK:
             raise TskError(st, "tsk_create failed (no gfx950 device?)")
         self.h = h
+        if tuning is not None:
+            self.load_tuning(None if tuning == "default" else tuning)
 
     def close(self):
         if getattr(self, "h", None):
@@ -365,6 +370,16 @@ class Context:
         self._check(self.lib.tsk_opt_tail(self.h, ctypes.byref(s), r, tail.ctypes.data_as(ctypes.c_void_p),
                                           fro.ctypes.data_as(ctypes.c_void_p)))
         return tail, fro
+
+    def set_tuning(self, m: int, n: int, k: int, dtype: str, groups: int = 0, pj_cols: int = 0):
+        """Tuning entry of one shape class (tsk_set_tuning)."""
+        self._check(self.lib.tsk_set_tuning(self.h, m, n, k, _DTYPES[dtype], groups, pj_cols))
+
+    def load_tuning(self, path: str | None = None) -> int:
+        """Apply every entry of an autotuner cache (JSON, see autotune.py);
+        returns the number of entries applied (0 when the file is absent)."""
+        from . import autotune
+        return autotune.apply_cache(self, path)
 
     def set_eig_params(self, block: int = 0, max_iter: int = 0, tol: float = 0.0, check: int = 0):
         self._check(self.lib.tsk_set_eig_params(self.h, block, max_iter, tol, check))

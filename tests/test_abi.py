@@ -52,3 +52,10 @@ def test_null_context_is_rejected():
     assert lib.tsk_apply(None, None, 4, None, 2, tsk.TSK_F32, None, None, None, None, None) == tsk.TSK_E_ARG
     assert lib.tsk_error(None, None, None, None, 2, None) == tsk.TSK_E_ARG
     assert lib.tsk_last_error(None) == b"null context"
+
+
+def test_autotune_cache_keys():
+    from paper_2209_14637_amd import autotune
+    key = autotune.class_key(1920, 1080, 40, "bf16")
+    assert key == "1920x1080:kp48:bf16"
+    assert autotune.parse_key(key) == (1920, 1080, 48, "bf16")

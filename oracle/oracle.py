@@ -56,6 +56,10 @@ def lib():
             "tsko_scw": [_P, _I, _I, _P, _I, _I, ctypes.c_int, _P, _P, _P, _P, _P, _P],
             "tsko_scw_basis": [_P, _I, _I, _P, _I, ctypes.c_int, _P, _P],
             "tsko_random_sketch": [ctypes.c_int, _I, _I, ctypes.c_uint64, _P],
+            "tsko_gram2_f32": [_P, _I, _I, _I, _P],
+            "tsko_train2_f32": [_P, _I, _I, _I, _I, _I, _I, ctypes.c_double, _P, _P, _P, _P],
+            "tsko_scw2": [_P, _I, _I, _P, _I, _P, _I, _I, _P, _P, _P, _P, _P],
+            "tsko_apply2_f32": [_P, _I, _I, _I, _P, _I, _P, _I, _I, _P, _P, _P, _P, _P],
             "tsko_apply_f32": [_P, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P, _P],
             "tsko_error_f32": [_P, _I, _I, _I, _P, _P, _I, _P],
             "tsko_opt_f32": [_P, _I, _I, _I, _I, _P, _P],
@@ -200,6 +204,60 @@ def scw_basis(A: np.ndarray, S: np.ndarray, vmode: int = 0):
 
 
 SKETCH_KINDS = {"gaussian": 0, "sign": 1, "sparse": 2}
+
+
+def gram2(A: np.ndarray) -> np.ndarray:
+    """Mode-2 Gram sum_d A_d^T A_d of a (count, m, n) stack."""
+    A = _f32(A)
+    if A.ndim == 2:
+        A = A[None]
+    cnt, m, n = A.shape
+    G = np.empty((n, n))
+    _check(lib().tsko_gram2_f32(_p(A), cnt, m, n, _p(G)), "gram2")
+    return G
+
+
+def train2(A: np.ndarray, k: int, l: int, max_sweeps: int = 50, tol: float = 1e-10):
+    """Tucker2 by HOOI: (S (k x m), W (l x n), core2 history, sweeps)."""
+    A = _f32(A)
+    cnt, m, n = A.shape
+    S, W = np.empty((k, m)), np.empty((l, n))
+    core2 = np.zeros(max_sweeps + 1)
+    sw = np.zeros(1, dtype=np.int64)
+    _check(lib().tsko_train2_f32(_p(A), cnt, m, n, k, l, max_sweeps, tol, _p(S), _p(W), _p(core2), _p(sw)),
+           "train2")
+    return S, W, core2[:int(sw[0]) + 1], int(sw[0])
+
+
+def scw2(A: np.ndarray, S: np.ndarray, W: np.ndarray, r: int):
+    """Two-sided SCW (Algorithm 4) on one matrix."""
+    A = _f64(A)
+    S = _f64(S)
+    W = _f64(W)
+    m, n = A.shape
+    k, l = S.shape[0], W.shape[0]
+    L, R, sig = np.empty((m, r)), np.empty((n, r)), np.empty(r)
+    e = np.empty(1)
+    fl = np.zeros(1, dtype=np.int32)
+    _check(lib().tsko_scw2(_p(A), m, n, _p(S), k, _p(W), l, r, _p(L), _p(R), _p(sig), _p(e), _p(fl)), "scw2")
+    return dict(L=L, R=R, sigma=sig, relerr=float(e[0]), flags=int(fl[0]))
+
+
+def apply2(A: np.ndarray, S: np.ndarray, W: np.ndarray, r: int, factors: bool = True):
+    """Two-sided SCW over a (count, m, n) float32 stack (OpenMP across slices)."""
+    A = _f32(A)
+    S = _f64(S)
+    W = _f64(W)
+    cnt, m, n = A.shape
+    k, l = S.shape[0], W.shape[0]
+    L = np.empty((cnt, m, r)) if factors else None
+    R = np.empty((cnt, n, r)) if factors else None
+    sig = np.empty((cnt, r)) if factors else None
+    e = np.empty(cnt)
+    fl = np.zeros(cnt, dtype=np.int32)
+    _check(lib().tsko_apply2_f32(_p(A), cnt, m, n, _p(S), k, _p(W), l, r, _p(L), _p(R), _p(sig), _p(e),
+                                 _p(fl)), "apply2")
+    return dict(L=L, R=R, sigma=sig, relerr=e, flags=fl)
 
 
 def splitmix64(seed: int, c: int) -> int:

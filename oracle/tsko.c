@@ -751,3 +751,240 @@ int tsko_random_sketch(int kind, int64_t k, int64_t m, uint64_t seed, double *S)
         }
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * The two-sided method (Section 3.2, problem 3.6; Algorithms 3 and 4;
+ * Appendix, Algorithm 5).
+ * ------------------------------------------------------------------------ */
+
+/* Mode-2 Gram: sum_d A_d^T A_d (n x n), natural slice order, FP64. */
+int tsko_gram2_f32(const float *A, int64_t count, int64_t m, int64_t n, double *G) {
+    if (!A || !G || count < 0 || m <= 0 || n <= 0) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j1 = 0; j1 < n; j1++)
+        for (int64_t j2 = 0; j2 <= j1; j2++) {
+            double s = 0.0;
+            for (int64_t d = 0; d < count; d++) {
+                const float *a = A + d * m * n;
+                for (int64_t i = 0; i < m; i++) s += (double)a[i * n + j1] * (double)a[i * n + j2];
+            }
+            G[j1 * n + j2] = s;
+            G[j2 * n + j1] = s;
+        }
+    return 0;
+}
+
+/* Top-p eigenvectors of the symmetric p0 x p0 matrix G as the rows of U
+ * (p x p0) and the sum of the top-p eigenvalues. */
+static double top_rows(const double *G, int64_t p0, int64_t p, double *U) {
+    double *lam = dalloc((size_t)(p + 1));
+    tsko_train_from_gram(G, p0, p, U, lam);
+    double s = 0.0;
+    for (int64_t i = 0; i < p; i++) s += lam[i];
+    free(lam);
+    return s;
+}
+
+/* Tucker2 of the m x n x N tensor by HOOI (Algorithm 5 restricted to modes
+ * 1 and 2, the third mode left whole), from the HOSVD initial guess:
+ *   S_0 = top-k eigenvectors of sum_d A_d A_d^T,  W_0 = top-l of sum_d A_d^T A_d;
+ * one sweep updates S (mode 1, with the current W), then W (mode 2, with the
+ * new S):
+ *   S <- top-k eigenvectors of sum_d (A_d W^T)(A_d W^T)^T,
+ *   W <- top-l eigenvectors of sum_d (S A_d)^T (S A_d),
+ * and ||G||^2 = sum_d ||S A_d W^T||_F^2 is the sum of the top-l eigenvalues
+ * of the second Gram.  Stops when ||G||^2 changes by at most tol ||G||^2 or
+ * after max_sweeps sweeps.  core2: nullable, max_sweeps + 1 values (index 0:
+ * the HOSVD guess); *sweeps: the sweeps done. */
+int tsko_train2_f32(const float *A, int64_t count, int64_t m, int64_t n, int64_t k, int64_t l,
+                    int64_t max_sweeps, double tol, double *S, double *W, double *core2, int64_t *sweeps) {
+    if (!A || !S || !W || count < 1 || k < 1 || k > m || l < 1 || l > n || max_sweeps < 0) return -1;
+    double *G1 = dalloc((size_t)(m * m)), *G2 = dalloc((size_t)(n * n));
+    tsko_gram_f32(A, count, m, n, G1);
+    top_rows(G1, m, k, S);
+    tsko_gram2_f32(A, count, m, n, G2);
+    top_rows(G2, n, l, W);
+    /* ||G||^2 of the guess */
+    double c2 = 0.0;
+    for (int64_t d = 0; d < count; d++) {
+        const float *a = A + d * m * n;
+        for (int64_t s = 0; s < k; s++)
+            for (int64_t t = 0; t < l; t++) {
+                double v = 0.0;
+                for (int64_t i = 0; i < m; i++) {
+                    double ai = 0.0;
+                    for (int64_t j = 0; j < n; j++) ai += (double)a[i * n + j] * W[t * n + j];
+                    v += S[s * m + i] * ai;
+                }
+                c2 += v * v;
+            }
+    }
+    if (core2) core2[0] = c2;
+    double *Y = dalloc((size_t)(m * l)), *Z = dalloc((size_t)(k * n));
+    int64_t sw = 0;
+    while (sw < max_sweeps) {
+        /* mode 1: sum_d (A_d W^T)(A_d W^T)^T */
+        memset(G1, 0, sizeof(double) * (size_t)(m * m));
+        for (int64_t d = 0; d < count; d++) {
+            const float *a = A + d * m * n;
+            for (int64_t i = 0; i < m; i++)
+                for (int64_t t = 0; t < l; t++) {
+                    double v = 0.0;
+                    for (int64_t j = 0; j < n; j++) v += (double)a[i * n + j] * W[t * n + j];
+                    Y[i * l + t] = v;
+                }
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int64_t i1 = 0; i1 < m; i1++)
+                for (int64_t i2 = 0; i2 <= i1; i2++) {
+                    double v = 0.0;
+                    for (int64_t t = 0; t < l; t++) v += Y[i1 * l + t] * Y[i2 * l + t];
+                    G1[i1 * m + i2] += v;
+                }
+        }
+        for (int64_t i1 = 0; i1 < m; i1++)
+            for (int64_t i2 = 0; i2 < i1; i2++) G1[i2 * m + i1] = G1[i1 * m + i2];
+        if (!MUT(19)) top_rows(G1, m, k, S);
+        /* mode 2: sum_d (S A_d)^T (S A_d) */
+        memset(G2, 0, sizeof(double) * (size_t)(n * n));
+        for (int64_t d = 0; d < count; d++) {
+            const float *a = A + d * m * n;
+            for (int64_t s = 0; s < k; s++)
+                for (int64_t j = 0; j < n; j++) {
+                    double v = 0.0;
+                    for (int64_t i = 0; i < m; i++) v += S[s * m + i] * (double)a[i * n + j];
+                    Z[s * n + j] = v;
+                }
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int64_t j1 = 0; j1 < n; j1++)
+                for (int64_t j2 = 0; j2 <= j1; j2++) {
+                    double v = 0.0;
+                    for (int64_t s = 0; s < k; s++) v += Z[s * n + j1] * Z[s * n + j2];
+                    G2[j1 * n + j2] += v;
+                }
+        }
+        for (int64_t j1 = 0; j1 < n; j1++)
+            for (int64_t j2 = 0; j2 < j1; j2++) G2[j2 * n + j1] = G2[j1 * n + j2];
+        const double c2n = top_rows(G2, n, l, W);
+        sw++;
+        if (core2) core2[sw] = c2n;
+        const int done = fabs(c2n - c2) <= tol * c2n;
+        c2 = c2n;
+        if (done) break;
+    }
+    if (sweeps) *sweeps = sw;
+    free(G1); free(G2); free(Y); free(Z);
+    return 0;
+}
+
+/* Two-sided SCW (Algorithm 4) on one matrix A (m x n) with S (k x m) and
+ * W (l x n), r < min(k, l):
+ *   1. Q = Q factor of a Householder QR of A^T S^T (n x k);
+ *   2. P = Q factor of a Householder QR of A W^T (m x l);
+ *   3. M = P^T A Q (l x k), thin SVD M = U Sig Y^T, [M]_r = U_r Sig_r Y_r^T;
+ *   4. A_hat = P [M]_r Q^T = L R^T with L = P U_r Sig_r (m x r),
+ *      R = Q Y_r (n x r).
+ * relerr = ||A - A_hat||_F / ||A||_F from the dense residual.  Flags: RANKDEF
+ * when a diagonal entry of either R factor is at most 1e-13 of that
+ * factor's largest; TIE when sigma_r - sigma_{r+1} <= 1e-12 sigma_1. */
+int tsko_scw2(const double *A, int64_t m, int64_t n, const double *S, int64_t k, const double *W, int64_t l,
+              int64_t r, double *L, double *R, double *sigma, double *relerr, int32_t *flags) {
+    if (!A || !S || !W || m <= 0 || n <= 0 || r < 1 || r >= k || r >= l || k > n || l > m || k > m || l > n)
+        return -1;
+    int32_t fl = 0;
+    double fro2 = 0.0;
+    for (int64_t i = 0; i < m * n; i++) {
+        if (!isfinite(A[i])) fl |= TSKO_FLAG_NONFIN;
+        fro2 += A[i] * A[i];
+    }
+    if (fl & TSKO_FLAG_NONFIN) {
+        if (relerr) *relerr = NAN;
+        if (flags) *flags = fl;
+        return 0;
+    }
+    double *At = dalloc((size_t)(n * k)), *Q = dalloc((size_t)(n * k)), *R1 = dalloc((size_t)(k * k));
+    for (int64_t j = 0; j < n; j++)
+        for (int64_t s = 0; s < k; s++) {
+            double v = 0.0;
+            for (int64_t i = 0; i < m; i++) v += A[i * n + j] * S[s * m + i];
+            At[j * k + s] = v;
+        }
+    tsko_qr(At, n, k, Q, R1);
+    double *Aw = dalloc((size_t)(m * l)), *P = dalloc((size_t)(m * l)), *R2 = dalloc((size_t)(l * l));
+    for (int64_t i = 0; i < m; i++)
+        for (int64_t t = 0; t < l; t++) {
+            double v = 0.0;
+            for (int64_t j = 0; j < n; j++) v += A[i * n + j] * W[t * n + j];
+            Aw[i * l + t] = v;
+        }
+    tsko_qr(Aw, m, l, P, R2);
+    double d1 = 0.0, d2 = 0.0;
+    for (int64_t s = 0; s < k; s++) d1 = fmax(d1, fabs(R1[s * k + s]));
+    for (int64_t t = 0; t < l; t++) d2 = fmax(d2, fabs(R2[t * l + t]));
+    for (int64_t s = 0; s < k; s++)
+        if (fabs(R1[s * k + s]) <= 1e-13 * d1) fl |= TSKO_FLAG_RANKDEF;
+    for (int64_t t = 0; t < l; t++)
+        if (fabs(R2[t * l + t]) <= 1e-13 * d2) fl |= TSKO_FLAG_RANKDEF;
+    /* M = P^T A Q */
+    double *AQ = dalloc((size_t)(m * k)), *M = dalloc((size_t)(l * k));
+    for (int64_t i = 0; i < m; i++)
+        for (int64_t s = 0; s < k; s++) {
+            double v = 0.0;
+            for (int64_t j = 0; j < n; j++) v += A[i * n + j] * Q[j * k + s];
+            AQ[i * k + s] = v;
+        }
+    for (int64_t t = 0; t < l; t++)
+        for (int64_t s = 0; s < k; s++) {
+            double v = 0.0;
+            for (int64_t i = 0; i < m; i++) v += P[i * l + t] * AQ[i * k + s];
+            M[t * k + s] = v;
+        }
+    const int64_t p = l < k ? l : k;
+    double *Um = dalloc((size_t)(l * p)), *sm = dalloc((size_t)p), *Yt = dalloc((size_t)(p * k));
+    tsko_svd(M, l, k, Um, sm, Yt);
+    if (r < p && sm[r - 1] - sm[r] <= 1e-12 * sm[0]) fl |= TSKO_FLAG_TIE;
+    double *Lm = dalloc((size_t)(m * r)), *Rm = dalloc((size_t)(n * r));
+    for (int64_t i = 0; i < m; i++)
+        for (int64_t c = 0; c < r; c++) {
+            double v = 0.0;
+            for (int64_t t = 0; t < l; t++) v += P[i * l + t] * Um[t * p + c];
+            Lm[i * r + c] = MUT(18) ? v : v * sm[c];
+        }
+    for (int64_t j = 0; j < n; j++)
+        for (int64_t c = 0; c < r; c++) {
+            double v = 0.0;
+            for (int64_t s = 0; s < k; s++) v += Q[j * k + s] * Yt[c * k + s];
+            Rm[j * r + c] = v;
+        }
+    double res2 = 0.0;
+    for (int64_t i = 0; i < m; i++)
+        for (int64_t j = 0; j < n; j++) {
+            double ah = 0.0;
+            for (int64_t c = 0; c < r; c++) ah += Lm[i * r + c] * Rm[j * r + c];
+            const double dl = A[i * n + j] - ah;
+            res2 += dl * dl;
+        }
+    if (L) memcpy(L, Lm, sizeof(double) * (size_t)(m * r));
+    if (R) memcpy(R, Rm, sizeof(double) * (size_t)(n * r));
+    if (sigma) memcpy(sigma, sm, sizeof(double) * (size_t)r);
+    if (relerr) *relerr = fro2 > 0.0 ? sqrt(res2 / fro2) : 0.0;
+    if (flags) *flags = fl;
+    free(At); free(Q); free(R1); free(Aw); free(P); free(R2); free(AQ); free(M);
+    free(Um); free(sm); free(Yt); free(Lm); free(Rm);
+    return 0;
+}
+
+int tsko_apply2_f32(const float *A, int64_t count, int64_t m, int64_t n, const double *S, int64_t k,
+                    const double *W, int64_t l, int64_t r, double *L, double *R, double *sigma, double *relerr,
+                    int32_t *flags) {
+    if (!A || !S || !W || count < 0) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (int64_t d = 0; d < count; d++) {
+        double *a = dalloc((size_t)(m * n));
+        for (int64_t i = 0; i < m * n; i++) a[i] = (double)A[d * m * n + i];
+        bad |= tsko_scw2(a, m, n, S, k, W, l, r, L ? L + d * m * r : NULL, R ? R + d * n * r : NULL,
+                         sigma ? sigma + d * r : NULL, relerr ? relerr + d : NULL, flags ? flags + d : NULL) != 0;
+        free(a);
+    }
+    return bad ? -1 : 0;
+}

@@ -135,6 +135,24 @@ int tsko_e4m3_scale(const float *x, int64_t n, float *scale);
 uint64_t tsko_splitmix64(uint64_t seed, uint64_t c);
 int tsko_random_sketch(int kind, int64_t k, int64_t m, uint64_t seed, double *S);
 
+/* The two-sided method (Section 3.2, problem 3.6; Algorithms 3-5).
+ * tsko_gram2_f32: mode-2 Gram sum_d A_d^T A_d (n x n).
+ * tsko_train2_f32: Tucker2 by HOOI from the HOSVD guess (see tsko.c):
+ *   S (k x m) and W (l x n) with orthonormal rows; core2 (nullable,
+ *   max_sweeps + 1 values): ||G||^2 after each sweep (index 0: the guess);
+ *   *sweeps (nullable): sweeps done (stop when ||G||^2 changes by <= tol).
+ * tsko_scw2: two-sided SCW (Algorithm 4) on one matrix, factors as tsko_scw
+ *   (L = P U_r Sig_r, R = Q Y_r), explicit relerr, flags.
+ * tsko_apply2_f32: tsko_scw2 over a stack of float slices (OpenMP). */
+int tsko_gram2_f32(const float *A, int64_t count, int64_t m, int64_t n, double *G);
+int tsko_train2_f32(const float *A, int64_t count, int64_t m, int64_t n, int64_t k, int64_t l,
+                    int64_t max_sweeps, double tol, double *S, double *W, double *core2, int64_t *sweeps);
+int tsko_scw2(const double *A, int64_t m, int64_t n, const double *S, int64_t k, const double *W, int64_t l,
+              int64_t r, double *L, double *R, double *sigma, double *relerr, int32_t *flags);
+int tsko_apply2_f32(const float *A, int64_t count, int64_t m, int64_t n, const double *S, int64_t k,
+                    const double *W, int64_t l, int64_t r, double *L, double *R, double *sigma, double *relerr,
+                    int32_t *flags);
+
 /* Number of OpenMP threads the library will use. */
 int tsko_threads(void);
 

@@ -30,6 +30,8 @@ MUTANTS = {
     15: "e4m3 scale one power of two too large",
     16: "Box-Muller radius sqrt(-ln u) instead of sqrt(-2 ln u)",
     17: "sparse sign sketch never uses its last row",
+    18: "two-sided SCW drops Sigma_r from L",
+    19: "HOOI never updates S (mode 1 stays at the HOSVD guess)",
 }
 
 
@@ -40,6 +42,7 @@ def test_pins_catch_mutant(tmp_path, mutant):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle.py"),
                         os.path.join(ROOT, "tests", "test_oracle_formats.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_random.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_random.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_twosided.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"pins missed mutant {mutant}: {MUTANTS[mutant]}\n{r.stdout[-2000:]}"

@@ -261,6 +261,40 @@ tsk_status tsk_apply_multi_plan(tsk_ctx ctx, const tsk_problem *probs, int32_t n
 tsk_status tsk_plan_launch(tsk_ctx ctx, const tsk_plan *plans, int32_t nplans);
 void tsk_plan_destroy(tsk_plan plan);
 
+/* The two-sided method (Section 3.2, problem 3.6).
+ *
+ * tsk_train2 (Algorithm 3, line 2): the Tucker2 decomposition of the
+ * training tensor along modes 1 and 2 by HOOI (Appendix, Algorithm 5) from
+ * the HOSVD guess (S = top-k eigenvectors of sum_d A_d A_d^T, W = top-l of
+ * sum_d A_d^T A_d); a sweep updates S to the top-k eigenvectors of
+ * sum_d (A_d W^T)(A_d W^T)^T, then W to the top-l of sum_d (S A_d)^T (S A_d),
+ * and stops when ||G||^2 = sum_d ||S A_d W^T||_F^2 (the top-l eigenvalue sum
+ * of the second Gram) changes by at most tol ||G||^2 (tol <= 0: 1e-10) or
+ * after max_sweeps sweeps.  train: FP32 stack.  S: device FP32 k x m,
+ * W: device FP32 l x n (rows orthonormal, descending, sign-canonical).
+ * core2: host, nullable, max_sweeps doubles: ||G||^2 after each sweep.
+ * sweeps: host, nullable.  Requires 1 <= k < m, 1 <= l < n, k, l <= 52.
+ * Every Gram as tsk_gram (FP32), every eigensolve as tsk_eig_topk
+ * (residual 1e-7 theta_1).  Synchronises the stream.
+ *
+ * tsk_apply2 (Algorithm 4, two-sided SCW) on every slice of `test` with S
+ * (k x m) and W (l x n), device FP32:
+ *   Q = orthonormal basis of the row space of S A_d (CholeskyQR2 of S A_d,
+ *       as tsk_apply; Algorithm 4 takes a QR of A_d^T S^T, which spans the
+ *       same space);
+ *   P = orthonormal basis of the columns of A_d W^T (Cholesky QR, a second
+ *       pass when ill-conditioned);
+ *   M = P^T A_d Q (l x k), M^T M = Y diag(sigma^2) Y^T (FP64 Jacobi);
+ *   A_hat_d = P [M]_r Q^T = L_d R_d^T, L_d = P M Y_r (m x r), R_d = Q Y_r.
+ * Outputs, forms and relerr (with its exact recomputation where the
+ * Pythagorean form cancels) as tsk_apply.  Requires 1 <= r < min(k, l),
+ * k, l <= min(m, n), k, l <= 64.  Enqueue only. */
+tsk_status tsk_train2(tsk_ctx ctx, const tsk_stack *train, int32_t k, int32_t l, int32_t max_sweeps, double tol,
+                      float *S, float *W, double *core2, int32_t *sweeps);
+tsk_status tsk_apply2(tsk_ctx ctx, const float *S, int32_t k, const float *W, int32_t l, const tsk_stack *test,
+                      int32_t r, int32_t compute, float *L, float *R, float *sigma, double *relerr,
+                      int32_t *flags);
+
 /* Explicit relative error ||A_d - L_d R_d^T||_F / ||A_d||_F for every slice
  * (the quantity whose rank-r minimum is problem 1.1).  A: an FP32 stack.
  * L, R: device FP32 with the layout tsk_apply writes.  relerr: device FP64,

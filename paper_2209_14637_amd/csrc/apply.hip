@@ -1390,6 +1390,289 @@ __global__ void error_final_kernel(const double *__restrict__ part, int nblk, in
     relerr[d] = f2 > 0.0 ? sqrt(r2 / f2) : 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// The two-sided method (Section 3.2, problem 3.6; Algorithms 3 and 4).
+// ---------------------------------------------------------------------------
+
+// Slices of an FP32 stack transposed: out[d] (n x ldo, ldo >= m) = A_d^T,
+// columns m .. ldo-1 zero.  32 x 32 tiles through LDS; grid (tiles of n,
+// tiles of m, count).
+__global__ __launch_bounds__(256) void transpose_stack_kernel(const float *__restrict__ A, int64_t m, int64_t n,
+                                                              int64_t ld, int64_t stride, float *__restrict__ out,
+                                                              int64_t ldo, int64_t ostride) {
+    __shared__ float t[32][33];
+    const int64_t d = blockIdx.z;
+    const int64_t j0 = (int64_t)blockIdx.x * 32, i0 = (int64_t)blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int y = ty; y < 32; y += 8) {
+        const int64_t i = i0 + y, j = j0 + tx;
+        t[y][tx] = (i < m && j < n) ? A[d * stride + i * ld + j] : 0.f;
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int64_t j = j0 + y, i = i0 + tx;
+        if (j < n && i < ldo) out[d * ostride + j * ldo + i] = t[tx][y];
+    }
+}
+
+// W (l x n FP32, rows orthonormal) copied into the B slot of every matrix:
+// B[d] (kp x ldv) = W with zero rows l .. kp-1 and zero columns n .. ldv-1;
+// with Bb (bf16 and e4m3 forms) also its bf16 pair (hi rows, then lo rows),
+// and B := hi + lo.  One thread per entry of one matrix's slot.
+__global__ void broadcast_w_kernel(const float *__restrict__ W, int l, int kp, int64_t n, int64_t ldv,
+                                   int64_t count, float *__restrict__ B, uint16_t *__restrict__ Bb) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)kp * ldv) return;
+    const int a = (int)(e / ldv);
+    const int64_t j = e % ldv;
+    float v = (a < l && j < n) ? W[a * n + j] : 0.f;
+    uint16_t hi = 0, lo = 0;
+    if (Bb) {
+        const unsigned h = pack_bf16(v, 0.f) & 0xffffu;
+        const float hf = bf16_lo(h);
+        const unsigned lw = pack_bf16(v - hf, 0.f) & 0xffffu;
+        hi = (uint16_t)h;
+        lo = (uint16_t)lw;
+        v = hf + bf16_lo(lw);
+    }
+    for (int64_t d = 0; d < count; ++d) {
+        B[d * kp * ldv + e] = v;
+        if (Bb) {
+            Bb[d * 2 * kp * ldv + e] = hi;
+            Bb[d * 2 * kp * ldv + (int64_t)kp * ldv + e] = lo;
+        }
+    }
+}
+
+// T (KP x KP, LDS, ld KP) += X^T Y for the rows of X and Y (len x KP FP32,
+// row strides ldx, ldy): FP64 MFMA 16x16x4 with K over 4 rows at a time, the
+// four waves splitting the rows, their tiles added in wave order.
+template <int NT>
+__device__ inline void cross_mfma_acc(const float *__restrict__ X, int64_t ldx, const float *__restrict__ Y,
+                                      int64_t ldy, int64_t len, double *T) {
+    constexpr int KP = NT * 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = lane >> 4, ii = lane & 15;
+    v4d acc[NT][NT];
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int64_t nst = (len + 3) / 4;
+    const int64_t s0 = nst * wv / 4, s1 = nst * (wv + 1) / 4;
+    for (int64_t st = s0; st < s1; ++st) {
+        const int64_t row = st * 4 + q;
+        double xv[NT], yv[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            xv[t] = row < len ? (double)X[row * ldx + t * 16 + ii] : 0.0;
+            yv[t] = row < len ? (double)Y[row * ldy + t * 16 + ii] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+            for (int b = 0; b < NT; ++b) acc[a][b] = mfma16x16x4_f64(xv[a], yv[b], acc[a][b]);
+    }
+    for (int w = 0; w < 4; ++w) {
+        if (wv == w) {
+#pragma unroll
+            for (int a = 0; a < NT; ++a)
+#pragma unroll
+                for (int b = 0; b < NT; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) T[(a * 16 + q + 4 * r) * KP + b * 16 + ii] += acc[a][b][r];
+        }
+        __syncthreads();
+    }
+}
+
+// M := M X for the rows of M (len x KP FP32, row-major, stride KP), X upper
+// triangular (KP x KP, FP64 in LDS, zeros below the diagonal):
+//     M[i][a] = sum_{u <= a} M[i][u] X[u][a]   (FP64 products and sums).
+// Chunks of 64 rows staged in LDS (Ms, 64 x MS_LD floats); wave w computes
+// rows 16w .. 16w+15 of the chunk for every 16-column tile by FP64 MFMA
+// 16x16x4 (K-steps past the tile's last column skipped) and writes them
+// back in place.
+template <int KP>
+__device__ __forceinline__ void tri_transform_rows(const double *X, float *M, int64_t len, float *Ms) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int q = lane >> 4, ii = lane & 15;
+    static_assert(KP <= MS_LD, "row chunk fits the staging rows");
+    for (int64_t i0 = 0; i0 < len; i0 += 64) {
+        for (int e = tid; e < 64 * KP; e += 256) {
+            const int64_t i = i0 + e / KP;
+            Ms[(e / KP) * MS_LD + e % KP] = i < len ? M[i * KP + e % KP] : 0.f;
+        }
+        __syncthreads();
+        for (int ta = 0; ta < KP / 16; ++ta) {
+            v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+            for (int u0 = 0; u0 < 16 * (ta + 1); u0 += 4) {
+                const double a = (double)Ms[(16 * wv + ii) * MS_LD + u0 + q];
+                const double b = X[(u0 + q) * KP + 16 * ta + ii];
+                acc = mfma16x16x4_f64(a, b, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + 16 * wv + q + 4 * r;
+                if (i < len) M[i * KP + 16 * ta + ii] = (float)acc[r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// finish2: the small steps of two-sided SCW for matrix d.
+//   P  = orthonormal basis of the columns of C1 = A W^T (m x KP, in place),
+//        by Cholesky QR of C1^T C1 (FP64; a second pass when the smallest
+//        live pivot is below 1e-8 of the largest); Algorithm 4 takes a QR,
+//        any orthonormal basis of the same span gives the same A_hat;
+//   M  = P^T C2 (l x k), C2 = A Q with Q = V (the basis kernel's row basis);
+//   M^T M = Y diag(sigma^2) Y^T (Jacobi), descending;
+//   Zl = M Y_r (KP x KP FP32, L = P Zl = U_r Sigma_r), Zr = Y_r (R = V Zr);
+//   sigma, relerr (Pythagorean form, refine mark as eig_body), flags.
+template <int KP>
+__device__ __forceinline__ void finish2_body(float *__restrict__ C1, const float *__restrict__ C2, int64_t m,
+                                             int k, int l, int r, const int *__restrict__ q,
+                                             const double *__restrict__ fro_part, int npanel,
+                                             float *__restrict__ Zl, float *__restrict__ Zr,
+                                             float *__restrict__ sigma, double *__restrict__ relerr,
+                                             int *__restrict__ flags, int *__restrict__ rf, double rf_thr, int64_t d) {
+    constexpr int SZ = KP * KP;
+    __shared__ __align__(16) double buf[3 * SZ];
+    __shared__ __align__(16) float Ms[64 * MS_LD];
+    __shared__ __align__(16) double rot[KP];
+    __shared__ double red4[4];
+    __shared__ int dead[KP];
+    __shared__ int perm[KP];
+    __shared__ double s_lam[KP];
+    __shared__ int s_second, s_nd;
+    const int tid = threadIdx.x;
+    float *C1d = C1 + d * m * KP;
+    const float *C2d = C2 + d * m * KP;
+    double *b0 = buf, *b1 = buf + SZ, *b2 = buf + 2 * SZ;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int e = tid; e < SZ; e += 256) b0[e] = 0.0;
+        __syncthreads();
+        gram_mfma_acc<KP / 16, false>(C1d, KP, m, b0, KP);
+        const int nd = chol_factor_inverse<(KP * KP + 255) / 256>(b0, KP, KP, 1e-12, b1, b2, dead, l);
+        if (pass == 0 && tid == 0) {
+            s_nd = nd;
+            double pmax = 0.0, pmin = 1e300;
+            for (int i = 0; i < KP; ++i) {
+                if (dead[i]) continue;
+                const double pv = b1[i * KP + i] * b1[i * KP + i];
+                pmax = fmax(pmax, pv);
+                pmin = fmin(pmin, pv);
+            }
+            s_second = pmax > 0.0 && pmin < 1e-8 * pmax;
+        }
+        __syncthreads();
+        tri_transform_rows<KP>(b2, C1d, m, Ms);
+        if (pass == 1 || !s_second) break;
+    }
+    // M = P^T C2 (b0), H = M^T M (b1), Jacobi with eigenvectors in b2
+    for (int e = tid; e < SZ; e += 256) b0[e] = 0.0;
+    __syncthreads();
+    cross_mfma_acc<KP / 16>(C1d, KP, C2d, KP, m, b0);
+    small_mm<KP, true>(b0, b0, b1);
+    const int kk = k + (k & 1);
+    jacobi_eig_wg<(KP * (KP + 2) / 8 + 255) / 256, (KP * KP / 4 + 255) / 256>(b1, b2, kk, KP, rot, 40, red4);
+    for (int i = tid; i < kk; i += 256) {
+        const double hi = b1[i * KP + i];
+        int rank = 0;
+        for (int j = 0; j < kk; ++j) {
+            const double hj = b1[j * KP + j];
+            rank += (hj > hi) || (hj == hi && j < i);
+        }
+        perm[rank] = i;
+    }
+    __syncthreads();
+    for (int t = tid; t < kk; t += 256) s_lam[t] = b1[perm[t] * KP + perm[t]];
+    float *Zld = Zl + d * SZ, *Zrd = Zr + d * SZ;
+    for (int e = tid; e < SZ; e += 256) {
+        const int i = e / KP, t = e % KP;
+        Zrd[e] = (i < k && t < r) ? (float)b2[perm[t] * KP + i] : 0.f;
+        double z = 0.0;
+        if (i < l && t < r)
+            for (int u = 0; u < k; ++u) z += b0[i * KP + u] * b2[perm[t] * KP + u];
+        Zld[e] = (float)z;
+    }
+    __syncthreads();
+    double fro2 = 0.0;
+    for (int p = 0; p < npanel; ++p) fro2 += fro_part[d * npanel + p];
+    const bool finite = isfinite(fro2);
+    const float qnan = __builtin_nanf("");
+    if (tid < r) sigma[d * r + tid] = finite ? (float)sqrt(fmax(s_lam[tid], 0.0)) : qnan;
+    if (tid == 0) {
+        double cap = 0.0;
+        for (int t = 0; t < r; ++t) cap += fmax(s_lam[t], 0.0);
+        int fl = (q[d] > 0 || s_nd > 0) ? TSK_FLAG_RANKDEF : 0;
+        if (!finite) fl |= TSK_FLAG_NONFIN;
+        const double sr = sqrt(fmax(s_lam[r - 1], 0.0)), sr1 = sqrt(fmax(s_lam[r], 0.0));
+        const double s1 = sqrt(fmax(s_lam[0], 0.0));
+        if (sr - sr1 <= 1e-6 * s1) fl |= TSK_FLAG_TIE;
+        if (flags) flags[d] = fl;
+        const double e2 = fro2 > 0.0 ? fmax(fro2 - cap, 0.0) / fro2 : 0.0;
+        if (relerr) relerr[d] = !finite ? (double)qnan : sqrt(e2);
+        rf[d] = (relerr && finite && fro2 > 0.0 && e2 < rf_thr) ? 1 : 0;
+    }
+}
+
+template <int KP>
+__global__ __launch_bounds__(256, 2) void finish2_kernel(float *__restrict__ C1, const float *__restrict__ C2,
+                                                      int64_t m, int k, int l, int r, const int *__restrict__ q,
+                                                      const double *__restrict__ fro_part, int npanel,
+                                                      float *__restrict__ Zl, float *__restrict__ Zr,
+                                                      float *__restrict__ sigma, double *__restrict__ relerr,
+                                                      int *__restrict__ flags, int *__restrict__ rf, double rf_thr) {
+    finish2_body<KP>(C1, C2, m, k, l, r, q, fro_part, npanel, Zl, Zr, sigma, relerr, flags, rf, rf_thr, blockIdx.x);
+}
+
+// L = P Zl (m x r) and R = V Zr (n x r): outputs_body with separate Z for
+// the two factors.
+template <int KP>
+__global__ __launch_bounds__(256) void outputs2_kernel(const float *__restrict__ B, int64_t ldb, int64_t n,
+                                                       const float *__restrict__ P, int64_t m, int k, int r,
+                                                       const double *__restrict__ fro_part, int npanel,
+                                                       const float *__restrict__ Zl, const float *__restrict__ Zr,
+                                                       float *__restrict__ L, float *__restrict__ R) {
+    __shared__ __align__(16) float Zls[KP * KP], Zrs[KP * KP];
+    const int64_t d = blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < KP * KP; e += 256) {
+        Zls[e] = Zl[d * KP * KP + e];
+        Zrs[e] = Zr[d * KP * KP + e];
+    }
+    double fro2 = 0.0;
+    for (int p = 0; p < npanel; ++p) fro2 += fro_part[d * npanel + p];
+    const bool finite = isfinite(fro2);
+    const bool vec = r % 4 == 0 && ((reinterpret_cast<uintptr_t>(L) | reinterpret_cast<uintptr_t>(R)) & 15) == 0;
+    __syncthreads();
+    const float *Bd = B + d * KP * ldb;
+    const float *Pd = P + d * m * KP;
+    float *Ld = L + d * m * r;
+    for (int64_t i = tid; i < m; i += 256) {
+        float cv[KP];
+#pragma unroll
+        for (int u = 0; u < KP; u += 4) {
+            const float4 f = *reinterpret_cast<const float4 *>(Pd + i * KP + u);
+            cv[u] = f.x;
+            cv[u + 1] = f.y;
+            cv[u + 2] = f.z;
+            cv[u + 3] = f.w;
+        }
+        outputs_row<KP>(cv, Zls, r, finite, vec, Ld + i * r);
+    }
+    float *Rd = R + d * n * r;
+    for (int64_t j = tid; j < n; j += 256) {
+        float vv[KP];
+#pragma unroll
+        for (int u = 0; u < KP; ++u) vv[u] = u < k ? Bd[u * ldb + j] : 0.f;
+        outputs_row<KP>(vv, Zrs, r, finite, vec, Rd + j * r);
+    }
+}
+
 }  // namespace
 
 #define TSK_KP_SWITCH(KP16, M1, M2, M3, M4) \
@@ -2244,5 +2527,242 @@ tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, cons
     TSK_LAUNCH(c, TSK_KERNEL_ERROR,
                hipLaunchKernelGGL(error_final_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, c->stream,
                                   (const double *)part, nblk, count, relerr));
+    return TSK_OK;
+}
+
+tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *G);
+tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *S, double *lambda,
+                           int32_t *iters_out, double tol_default);
+
+// ---------------------------------------------------------------------------
+// Two-sided SCW (Algorithm 4) on a stack: the one-sided sketch and basis give
+// Q = V (row basis of S A_d); two projections give C2 = A_d V and
+// C1 = A_d W^T; finish2 turns C1 into P and solves the small problem;
+// outputs2 writes L = P Zl and R = V Zr.  Sketch sizes k (S) and l (W)
+// share one padded size KP = ceil16(max(k, l)).
+// ---------------------------------------------------------------------------
+tsk_status tsk_apply2_enqueue(tsk_ctx c, const float *S, int k, const float *W, int l, const tsk_stack *s, int r,
+                              float *L, float *R, float *sigma, double *relerr, int32_t *flags) {
+    const int kmax = k > l ? k : l;
+    const int KP = (kmax + 15) / 16 * 16;
+    const int64_t m = s->m, n = s->n, count = s->count;
+    const bool lowp = s->dtype != TSK_F32;
+    const ApLayout lay = apply_layout(s, kmax, count);
+    TSK_TRY(tsk_grow(c, c->ap_ws, lay.total));
+    const ApWs ws = apply_carve(c->ap_ws.p, lay, s);
+    const int panel = lowp ? SKB_PANEL : SK_PANEL;
+    const int npanel = (int)((n + panel - 1) / panel);
+    const int64_t ldv = (int64_t)npanel * panel;
+    // second workspace: C1, the W slots (FP32 and bf16 pair), Zl, Zr
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t szC1 = al(sizeof(float) * count * m * KP), szBw = al(sizeof(float) * count * KP * ldv);
+    const size_t szBwb = lowp ? al(sizeof(uint16_t) * count * 2 * KP * ldv) : 0;
+    const size_t szZ = al(sizeof(float) * count * KP * KP);
+    TSK_TRY(tsk_grow(c, c->ap2_ws, szC1 + szBw + szBwb + 2 * szZ));
+    char *b2 = (char *)c->ap2_ws.p;
+    float *C1 = (float *)b2, *Bw = (float *)(b2 + szC1);
+    uint16_t *Bwb = lowp ? (uint16_t *)(b2 + szC1 + szBw) : nullptr;
+    float *Zl = (float *)(b2 + szC1 + szBw + szBwb), *Zr = (float *)(b2 + szC1 + szBw + szBwb + szZ);
+    // sketch, basis and C2 = A V: the one-sided launches up to the
+    // projection (S has k live rows of KP)
+    TSK_TRY(apply_prep(c, S, k, s, ws));
+    const ApSmall &w = ws.w;
+    const dim3 gs((unsigned)npanel, (unsigned)count);
+    if (!lowp) {
+        const float *A = (const float *)s->A;
+#define TSK_SK2(MTV)                                                                                            \
+    TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                            \
+               hipLaunchKernelGGL(sketch_f32_kernel<MTV>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, \
+                                  (const float *)ws.St, ws.B, ldv, ws.fro, npanel))
+        TSK_KP_SWITCH(KP / 16, TSK_SK2(1), TSK_SK2(2), TSK_SK2(3), TSK_SK2(4))
+#undef TSK_SK2
+    } else {
+        const int64_t mp = (m + 31) / 32 * 32;
+#define TSK_SKB2(MTV)                                                                                               \
+    {                                                                                                              \
+        if (s->dtype == TSK_F8E4M3)                                                                                \
+            TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                       \
+                       hipLaunchKernelGGL((sketch_bf16_kernel<MTV, uint8_t>), gs, dim3(64), 0, c->stream,           \
+                                          (const uint8_t *)s->A, s->scale, m, n, s->ld, s->stride,                  \
+                                          (const uint16_t *)ws.Sb, mp, ws.B, ldv, ws.fro, npanel));                 \
+        else                                                                                                       \
+            TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                       \
+                       hipLaunchKernelGGL((sketch_bf16_kernel<MTV, uint16_t>), gs, dim3(64), 0, c->stream,          \
+                                          (const uint16_t *)s->A, s->scale, m, n, s->ld, s->stride,                 \
+                                          (const uint16_t *)ws.Sb, mp, ws.B, ldv, ws.fro, npanel));                 \
+    }
+        TSK_KP_SWITCH(KP / 16, TSK_SKB2(1), TSK_SKB2(2), TSK_SKB2(3), TSK_SKB2(4))
+#undef TSK_SKB2
+    }
+    TSK_TRY(basis_enqueue(c, KP, ws.B, ldv, n, k, ws.Bb, count, w));
+    // W into every matrix's slot, then the two projections
+    TSK_LAUNCH(c, TSK_KERNEL_PROJECT,
+               hipLaunchKernelGGL(broadcast_w_kernel, dim3((unsigned)(((int64_t)KP * ldv + 255) / 256)), dim3(256), 0,
+                                  c->stream, W, l, KP, n, ldv, count, Bw, Bwb));
+    auto project = [&](const float *Bsrc, const uint16_t *Bpair, float *Cout) -> tsk_status {
+        if (!lowp) {
+            const int nb = (int)((m + PJ_ROWS - 1) / PJ_ROWS);
+            const dim3 gp((unsigned)(nb * count));
+            const float *A = (const float *)s->A;
+#define TSK_PJ2(NTV)                                                                                             \
+    TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                            \
+               hipLaunchKernelGGL(project_f32_kernel<NTV>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, \
+                                  Bsrc, ldv, Cout, count, nb))
+            TSK_KP_SWITCH(KP / 16, TSK_PJ2(1), TSK_PJ2(2), TSK_PJ2(3), TSK_PJ2(4))
+#undef TSK_PJ2
+        } else {
+            const int nb = (int)((m + PJL_ROWS - 1) / PJL_ROWS);
+            const dim3 gp((unsigned)(nb * count));
+#define TSK_PJB2(NTV)                                                                                               \
+    {                                                                                                              \
+        if (s->dtype == TSK_F8E4M3) {                                                                              \
+            const size_t pjl = (size_t)pjl_lds_bytes(128, 1, KP);                                                  \
+            TSK_TRY(allow_lds(c, (const void *)project_bf16_kernel<NTV, 128, uint8_t>, pjl));                      \
+            TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                      \
+                       hipLaunchKernelGGL((project_bf16_kernel<NTV, 128, uint8_t>), gp, dim3(PJL_THREADS), pjl,      \
+                                          c->stream, (const uint8_t *)s->A, s->scale, m, n, s->ld, s->stride, Bpair, \
+                                          ldv, Cout, count, nb, nullptr));                                        \
+        } else {                                                                                                   \
+            const size_t pjl = (size_t)pjl_lds_bytes(64, 2, KP);                                                   \
+            TSK_TRY(allow_lds(c, (const void *)project_bf16_kernel<NTV, 64, uint16_t>, pjl));                      \
+            TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                      \
+                       hipLaunchKernelGGL((project_bf16_kernel<NTV, 64, uint16_t>), gp, dim3(PJL_THREADS), pjl,      \
+                                          c->stream, (const uint16_t *)s->A, s->scale, m, n, s->ld, s->stride,      \
+                                          Bpair, ldv, Cout, count, nb, nullptr));                                 \
+        }                                                                                                          \
+    }
+            TSK_KP_SWITCH(KP / 16, TSK_PJB2(1), TSK_PJB2(2), TSK_PJB2(3), TSK_PJB2(4))
+#undef TSK_PJB2
+        }
+        return TSK_OK;
+    };
+    TSK_TRY(project(ws.B, ws.Bb, ws.C));  // C2 = A V
+    TSK_TRY(project(Bw, Bwb, C1));        // C1 = A W^T
+    const double thr = lowp ? RF_THR_LOWP : RF_THR_F32;
+    const dim3 g((unsigned)count);
+#define TSK_FIN2(KPV)                                                                                            \
+    do {                                                                                                         \
+        TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                         \
+                   hipLaunchKernelGGL(finish2_kernel<KPV>, g, dim3(256), 0, c->stream, C1, (const float *)ws.C, m, \
+                                      k, l, r, (const int *)w.q, (const double *)ws.fro, npanel, Zl, Zr, sigma,   \
+                                      relerr, flags, w.rf, thr));                                               \
+        TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                         \
+                   hipLaunchKernelGGL(outputs2_kernel<KPV>, g, dim3(256), 0, c->stream, (const float *)ws.B, ldv, \
+                                      n, (const float *)C1, m, k, r, (const double *)ws.fro, npanel,             \
+                                      (const float *)Zl, (const float *)Zr, L, R));                             \
+    } while (0)
+    TSK_KP_SWITCH(KP / 16, TSK_FIN2(16), TSK_FIN2(32), TSK_FIN2(48), TSK_FIN2(64))
+#undef TSK_FIN2
+    if (relerr) TSK_TRY(refine_enqueue(c, s, r, L, R, w.rf, w.part, w.nbands, ws.fro, npanel, relerr));
+    return TSK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Two-sided training (Algorithm 3, line 2): Tucker2 of the training tensor
+// by HOOI (Appendix, Algorithm 5, on modes 1 and 2) from the HOSVD guess.
+//   guess : S = top-k eigenvectors of sum_d A_d A_d^T (tsk_gram),
+//           W = top-l eigenvectors of sum_d A_d^T A_d (tsk_gram on the
+//               transposed slices);
+//   sweep : S <- top-k of sum_d (A_d W^T)(A_d W^T)^T  (projection by W, then
+//               the Gram of those m x l slices);
+//           W <- top-l of sum_d (S A_d)^T (S A_d)      (sketch by S, slices
+//               transposed, then their Gram);
+//           ||G||^2 = sum of the top-l eigenvalues of the second Gram.
+// FP32 stacks; every Gram by tsk_gram's FP32 kernels, every eigensolve by
+// tsk_eig_topk's solver (residual 1e-7 theta_1).  Host-driven: one
+// synchronisation per eigensolve.
+// ---------------------------------------------------------------------------
+tsk_status tsk_train2_enqueue(tsk_ctx c, const tsk_stack *s, int k, int l, int max_sweeps, double tol, float *S,
+                              float *W, double *core2, int32_t *sweeps_out) {
+    const int64_t m = s->m, n = s->n, count = s->count;
+    const int KPS = (k + 15) / 16 * 16, KPW = (l + 15) / 16 * 16;
+    const int npanel = (int)((n + SK_PANEL - 1) / SK_PANEL);
+    const int64_t ldv = (int64_t)npanel * SK_PANEL;
+    const int64_t ldt = std::max<int64_t>((m + 3) / 4 * 4, KPS);  // transposed slices' row stride
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t szG = al(sizeof(double) * std::max(m, n) * std::max(m, n));
+    const size_t szT = al(sizeof(float) * count * n * ldt);
+    const size_t szBw = al(sizeof(float) * count * KPW * ldv), szC = al(sizeof(float) * count * m * KPW);
+    const size_t szB = al(sizeof(float) * count * KPS * ldv), szSt = al(sizeof(float) * m * KPS);
+    const size_t szF = al(sizeof(double) * count * npanel);
+    TSK_TRY(tsk_grow(c, c->t2_ws, szG + szT + szBw + szC + szB + szSt + szF));
+    char *b = (char *)c->t2_ws.p;
+    double *G = (double *)b;
+    float *T = (float *)(b + szG), *Bw = (float *)(b + szG + szT), *Cw = (float *)(b + szG + szT + szBw);
+    float *Bs = (float *)(b + szG + szT + szBw + szC), *St = (float *)(b + szG + szT + szBw + szC + szB);
+    double *fro = (double *)(b + szG + szT + szBw + szC + szB + szSt);
+    double lam[65];
+    auto eig_top = [&](int64_t dim, int p, float *U, double *sum) -> tsk_status {
+        const tsk_status st = tsk_eig_enqueue(c, G, dim, p, U, lam, nullptr, TSK_EIG_TOL_F32);
+        if (st != TSK_OK) return st;
+        if (sum) {
+            double t = 0.0;
+            for (int i = 0; i < p; ++i) t += lam[i];
+            *sum = t;
+        }
+        return TSK_OK;
+    };
+    // Gram of the transposed slices (n x rows of each slice) into G (n x n)
+    auto gram_transposed = [&](const float *src, int64_t rows, int64_t ld, int64_t stride) -> tsk_status {
+        const dim3 gt((unsigned)((n + 31) / 32), (unsigned)((ldt + 31) / 32), (unsigned)count);
+        TSK_LAUNCH(c, TSK_KERNEL_STAGE, hipLaunchKernelGGL(transpose_stack_kernel, gt, dim3(256), 0, c->stream, src,
+                                                           rows, n, ld, stride, T, ldt, n * ldt));
+        tsk_stack t = *s;
+        t.A = T;
+        t.m = n;
+        t.n = rows;
+        t.ld = ldt;
+        t.stride = n * ldt;
+        return tsk_gram_enqueue(c, &t, TSK_F32, G);
+    };
+    // the HOSVD guess
+    TSK_TRY(tsk_gram_enqueue(c, s, TSK_F32, G));
+    TSK_TRY(eig_top(m, k, S, nullptr));
+    TSK_TRY(gram_transposed((const float *)s->A, m, s->ld, s->stride));
+    TSK_TRY(eig_top(n, l, W, nullptr));
+    double prev = -1.0;
+    int sw = 0;
+    const float *A = (const float *)s->A;
+    const int nb = (int)((m + PJ_ROWS - 1) / PJ_ROWS);
+    while (sw < max_sweeps) {
+        // mode 1: C_d = A_d W^T (m x KPW), the Gram of those slices, top-k
+        TSK_LAUNCH(c, TSK_KERNEL_PROJECT,
+                   hipLaunchKernelGGL(broadcast_w_kernel, dim3((unsigned)(((int64_t)KPW * ldv + 255) / 256)),
+                                      dim3(256), 0, c->stream, (const float *)W, l, KPW, n, ldv, count, Bw, nullptr));
+        const dim3 gp((unsigned)(nb * count));
+#define TSK_PJT(NTV)                                                                                             \
+    TSK_LAUNCH(c, TSK_KERNEL_PROJECT,                                                                            \
+               hipLaunchKernelGGL(project_f32_kernel<NTV>, gp, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, \
+                                  (const float *)Bw, ldv, Cw, count, nb))
+        TSK_KP_SWITCH(KPW / 16, TSK_PJT(1), TSK_PJT(2), TSK_PJT(3), TSK_PJT(4))
+#undef TSK_PJT
+        tsk_stack cs = *s;
+        cs.A = Cw;
+        cs.n = KPW;
+        cs.ld = KPW;
+        cs.stride = m * KPW;
+        TSK_TRY(tsk_gram_enqueue(c, &cs, TSK_F32, G));
+        TSK_TRY(eig_top(m, k, S, nullptr));
+        // mode 2: B_d = S A_d (KPS x n), transposed, their Gram, top-l
+        TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
+                   hipLaunchKernelGGL(transpose_sketch_kernel, dim3((unsigned)((m * KPS + 255) / 256)), dim3(256), 0,
+                                      c->stream, (const float *)S, k, KPS, m, St));
+        const dim3 gs((unsigned)npanel, (unsigned)count);
+#define TSK_SKT(MTV)                                                                                            \
+    TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                            \
+               hipLaunchKernelGGL(sketch_f32_kernel<MTV>, gs, dim3(64), 0, c->stream, A, m, n, s->ld, s->stride, \
+                                  (const float *)St, Bs, ldv, fro, npanel))
+        TSK_KP_SWITCH(KPS / 16, TSK_SKT(1), TSK_SKT(2), TSK_SKT(3), TSK_SKT(4))
+#undef TSK_SKT
+        TSK_TRY(gram_transposed(Bs, KPS, ldv, (int64_t)KPS * ldv));
+        double c2 = 0.0;
+        TSK_TRY(eig_top(n, l, W, &c2));
+        if (core2) core2[sw] = c2;
+        ++sw;
+        const bool done = prev >= 0.0 && fabs(c2 - prev) <= tol * c2;
+        prev = c2;
+        if (done) break;
+    }
+    if (sweeps_out) *sweeps_out = sw;
     return TSK_OK;
 }

@@ -18,6 +18,10 @@ tsk_status tsk_apply_noalloc_enqueue(tsk_ctx c, const float *S, int k, const tsk
 tsk_status tsk_scratch_init(tsk_ctx c, int device);
 tsk_status tsk_random_sketch_enqueue(tsk_ctx c, int kind, int64_t k, int64_t m, uint64_t seed, float *S);
 tsk_status tsk_opt_tail_enqueue(tsk_ctx c, const tsk_stack *s, int r, double *tail, double *fro);
+tsk_status tsk_apply2_enqueue(tsk_ctx c, const float *S, int k, const float *W, int l, const tsk_stack *s, int r,
+                              float *L, float *R, float *sigma, double *relerr, int32_t *flags);
+tsk_status tsk_train2_enqueue(tsk_ctx c, const tsk_stack *s, int k, int l, int max_sweeps, double tol, float *S,
+                              float *W, double *core2, int32_t *sweeps_out);
 tsk_status tsk_error_enqueue(tsk_ctx c, const tsk_stack *s, const float *L, const float *R, int r,
                              double *relerr);
 tsk_status tsk_apply_multi_enqueue(tsk_ctx c, const tsk_problem *pr, int np, int compute);
@@ -251,7 +255,7 @@ void tsk_destroy(tsk_ctx c) {
     drain_events(c);
     TskBuf *bufs[] = {&c->gram_part, &c->gram_G,  &c->eig_Y0,   &c->eig_Y1, &c->eig_Rinv, &c->eig_part,
                       &c->eig_C,     &c->eig_X,   &c->eig_GX,   &c->eig_small, &c->eig_U, &c->counters,
-                      &c->ap_ws,     &c->er_part, &c->st_part,  &c->mp_ws,  &c->mp_tab, &c->mt_ws};
+                      &c->ap_ws,     &c->er_part, &c->st_part,  &c->mp_ws,  &c->mp_tab, &c->mt_ws, &c->ap2_ws, &c->t2_ws};
     for (TskBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->mp_pin) (void)hipHostFree(c->mp_pin);
@@ -449,6 +453,35 @@ tsk_status tsk_random_sketch(tsk_ctx c, int32_t kind, int32_t k, int64_t m, uint
     if (k < 1 || m < k || m > (1 << 24)) return tsk_fail(c, TSK_E_ARG, "tsk_random_sketch: need 1 <= k <= m <= 2^24");
     TSK_TRY(tsk_check_dev(c, S, sizeof(float) * (size_t)k * m, "S"));
     return tsk_random_sketch_enqueue(c, kind, k, m, seed, S);
+}
+
+tsk_status tsk_train2(tsk_ctx c, const tsk_stack *train, int32_t k, int32_t l, int32_t max_sweeps, double tol,
+                      float *S, float *W, double *core2, int32_t *sweeps) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    TSK_TRY(tsk_check_stack(c, train, "train"));
+    if (train->dtype != TSK_F32) return tsk_fail(c, TSK_E_ARG, "tsk_train2: the training stack must be FP32");
+    const int64_t m = train->m, n = train->n;
+    if (k < 1 || k >= m || l < 1 || l >= n) return tsk_fail(c, TSK_E_ARG, "tsk_train2: need 1 <= k < m, 1 <= l < n");
+    if (k > 52 || l > 52) return tsk_fail(c, TSK_E_ARG, "tsk_train2: k, l <= 52");
+    if (m > (1 << 16) || n > (1 << 16)) return tsk_fail(c, TSK_E_SHAPE, "tsk_train2: need m, n <= 65536");
+    if (max_sweeps < 0 || max_sweeps > 1000) return tsk_fail(c, TSK_E_ARG, "tsk_train2: need 0 <= max_sweeps <= 1000");
+    TSK_TRY(tsk_check_dev(c, S, sizeof(float) * k * m, "S"));
+    TSK_TRY(tsk_check_dev(c, W, sizeof(float) * l * n, "W"));
+    return tsk_train2_enqueue(c, train, k, l, max_sweeps, tol > 0 ? tol : 1e-10, S, W, core2, sweeps);
+}
+
+tsk_status tsk_apply2(tsk_ctx c, const float *S, int32_t k, const float *W, int32_t l, const tsk_stack *test,
+                      int32_t r, int32_t compute, float *L, float *R, float *sigma, double *relerr, int32_t *flags) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    TSK_TRY(check_apply(c, S, k, test, r, compute, L, R, sigma, relerr, flags));
+    if (l < 1 || r >= l) return tsk_fail(c, TSK_E_ARG, "tsk_apply2: need 1 <= r < l");
+    if (l > test->m || l > test->n || l > 64) return tsk_fail(c, TSK_E_ARG, "tsk_apply2: need l <= min(m, n), l <= 64");
+    TSK_TRY(tsk_check_dev(c, W, sizeof(float) * l * test->n, "W"));
+    return tsk_apply2_enqueue(c, S, k, W, l, test, r, L, R, sigma, relerr, flags);
 }
 
 tsk_status tsk_opt_tail(tsk_ctx c, const tsk_stack *A, int32_t r, double *tail, double *fro) {

@@ -570,6 +570,8 @@ struct tsk_ctx_s {
     TskBuf counters;
     TskBuf ap_ws;         // workspace of tsk_apply (one buffer, carved per call)
     TskBuf mt_ws;         // tsk_opt_tail: eigenvector block and trace
+    TskBuf ap2_ws;        // tsk_apply2: C1, W slots, Zl, Zr
+    TskBuf t2_ws;         // tsk_train2: Grams, transposed slices, projections
     void *scratch = nullptr;  // device address of the no-allocation scratch on this device
     TskBuf er_part, st_part;
     TskBuf mp_ws, mp_tab;            // batched apply: workspace, descriptors + items

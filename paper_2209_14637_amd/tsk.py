@@ -25,7 +25,7 @@ _STATUS = {0: "TSK_OK", 1: "TSK_E_ARG", 2: "TSK_E_SHAPE", 3: "TSK_E_NOMEM", 4: "
 EXPORTS = ["tsk_create", "tsk_destroy", "tsk_set_stream", "tsk_last_error", "tsk_stage", "tsk_gram",
            "tsk_eig_topk", "tsk_train", "tsk_random_sketch", "tsk_apply", "tsk_apply_noalloc", "tsk_apply_multi",
            "tsk_apply_multi_plan", "tsk_plan_launch", "tsk_plan_destroy", "tsk_error", "tsk_opt_tail",
-           "tsk_set_eig_params", "tsk_set_tuning",
+           "tsk_set_eig_params", "tsk_set_tuning", "tsk_train2", "tsk_apply2",
            "tsk_timing_enable", "tsk_timing_read"]
 
 _DTYPES = {"f32": TSK_F32, "bf16": TSK_BF16, "e4m3": TSK_F8E4M3}
@@ -84,6 +84,8 @@ def load(path: str | None = None):
         "tsk_opt_tail": ([P, sp, I32, P, P], I32),
         "tsk_set_eig_params": ([P, I32, I32, D, I32], I32),
         "tsk_set_tuning": ([P, I64, I64, I32, I32, I32, I32], I32),
+        "tsk_train2": ([P, sp, I32, I32, I32, D, P, P, P, P], I32),
+        "tsk_apply2": ([P, P, I32, P, I32, sp, I32, I32, P, P, P, P, P], I32),
         "tsk_timing_enable": ([P, I32], I32),
         "tsk_timing_read": ([P, I32, P, P], I32),
     }
@@ -370,6 +372,32 @@ class Context:
         self._check(self.lib.tsk_opt_tail(self.h, ctypes.byref(s), r, tail.ctypes.data_as(ctypes.c_void_p),
                                           fro.ctypes.data_as(ctypes.c_void_p)))
         return tail, fro
+
+    def train2(self, A: torch.Tensor, k: int, l: int, max_sweeps: int = 50, tol: float = 1e-10):
+        """Two-sided training (tsk_train2): (S, W, core2 per sweep, sweeps)."""
+        import numpy as np
+        self._sync_stream()
+        s = _stack(A)
+        S = torch.empty((k, s.m), dtype=torch.float32, device=A.device)
+        W = torch.empty((l, s.n), dtype=torch.float32, device=A.device)
+        core2 = np.zeros(max(max_sweeps, 1))
+        sw = ctypes.c_int32(0)
+        self._check(self.lib.tsk_train2(self.h, ctypes.byref(s), k, l, max_sweeps, tol, _ptr(S), _ptr(W),
+                                        core2.ctypes.data_as(ctypes.c_void_p), ctypes.byref(sw)))
+        return S, W, core2[:sw.value], sw.value
+
+    def apply2(self, S: torch.Tensor, W: torch.Tensor, A, r: int, out: dict | None = None) -> dict:
+        """Two-sided SCW on every slice (tsk_apply2)."""
+        self._sync_stream()
+        s = _stack(A)
+        for X, dim in ((S, s.m), (W, s.n)):
+            if X.dtype != torch.float32 or not X.is_contiguous() or X.shape[1] != dim:
+                raise ValueError("S (k x m) and W (l x n) must be contiguous float32 CUDA tensors")
+        o = out if out is not None else self._outputs(s, r, S.device)
+        self._check(self.lib.tsk_apply2(self.h, _ptr(S), S.shape[0], _ptr(W), W.shape[0], ctypes.byref(s), r, s.dtype,
+                                        _ptr(o["L"]), _ptr(o["R"]), _ptr(o["sigma"]), _ptr(o.get("relerr")),
+                                        _ptr(o.get("flags"))))
+        return o
 
     def set_tuning(self, m: int, n: int, k: int, dtype: str, groups: int = 0, pj_cols: int = 0):
         """Tuning entry of one shape class (tsk_set_tuning)."""

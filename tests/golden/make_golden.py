@@ -114,7 +114,29 @@ def golden_batch(name, n_train=100, count=2000):
     np.savez(os.path.join(HERE, f"{name}_S.npz"), **Ss)
 
 
+def golden_twosided(spec, name, l, max_sweeps=50, tol=1e-10):
+    """The two-sided method on a stream: the oracle's Tucker2 (HOOI from the
+    HOSVD guess) of the training slices and two-sided SCW on every test
+    matrix."""
+    st = synth.Stream(spec)
+    t0 = time.time()
+    S, W, core2, sweeps = oracle.train2(st.train(), spec.k, l, max_sweeps, tol)
+    t_train = time.time() - t0
+    ds = list(range(spec.n_train + 1, spec.n_train + 1 + spec.n_test))
+    res = oracle.apply2(st.slices(ds), S, W, spec.r, factors=False)
+    out = {"workload": name, "spec": {k: v for k, v in spec.__dict__.items()}, "l": l,
+           "source": "oracle/tsko.c via tests/golden/make_golden.py", "core2": core2.tolist(), "sweeps": sweeps,
+           "relerr": res["relerr"].tolist(), "flags": res["flags"].tolist(), "oracle_train_seconds": t_train,
+           "threads": oracle.threads()}
+    with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+        json.dump(out, f, indent=0)
+    np.savez(os.path.join(HERE, f"{name}_SW.npz"), S=S.astype(np.float32), W=W.astype(np.float32))
+    print(name, "sweeps", sweeps, "core2", core2[-1], "e[:3]", res["relerr"][:3], f"train {t_train:.1f}s", flush=True)
+
+
 WORKLOADS = {
+    # the two-sided method on the 1024x768 stream, k = l = 20, r = 10
+    "hsi_twosided_k20_l20_r10": lambda: golden_twosided(synth.spec_hsi_fp32(), "hsi_twosided_k20_l20_r10", 20),
     "batch_8streams_k10-40": lambda: golden_batch("batch_8streams_k10-40"),
     # the FP32 form's stream (the HSI shape); optimal tails of every test
     # matrix for metric (4.1)

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "tsk.h")
 def declared_symbols():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(tsk_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(tsk_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_declares_the_boundary():
@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
     assert set(declared_symbols()) == set(tsk.EXPORTS)
     out = subprocess.run(["nm", "-D", "--defined-only", tsk.LIB_PATH], capture_output=True, text=True).stdout
-    exported = set(re.findall(r"\b(tsk_[a-z_]+)\b", out))
+    exported = set(re.findall(r"\b(tsk_[a-z0-9_]+)\b", out))
     assert set(declared_symbols()) <= exported
 
 

@@ -269,8 +269,9 @@ void tsk_plan_destroy(tsk_plan plan);
  * sum_d A_d^T A_d); a sweep updates S to the top-k eigenvectors of
  * sum_d (A_d W^T)(A_d W^T)^T, then W to the top-l of sum_d (S A_d)^T (S A_d),
  * and stops when ||G||^2 = sum_d ||S A_d W^T||_F^2 (the top-l eigenvalue sum
- * of the second Gram) changes by at most tol ||G||^2 (tol <= 0: 1e-10) or
- * after max_sweeps sweeps.  train: FP32 stack.  S: device FP32 k x m,
+ * of the second Gram) changes by at most max(tol, 1e-8) ||G||^2 (tol <= 0:
+ * 1e-10; the FP32 Grams and the eigensolver's tolerance fix ||G||^2 to about
+ * 1e-8) or after max_sweeps sweeps.  train: FP32 stack.  S: device FP32 k x m,
  * W: device FP32 l x n (rows orthonormal, descending, sign-canonical).
  * core2: host, nullable, max_sweeps doubles: ||G||^2 after each sweep.
  * sweeps: host, nullable.  Requires 1 <= k < m, 1 <= l < n, k, l <= 52.

@@ -2759,7 +2759,10 @@ tsk_status tsk_train2_enqueue(tsk_ctx c, const tsk_stack *s, int k, int l, int m
         TSK_TRY(eig_top(n, l, W, &c2));
         if (core2) core2[sw] = c2;
         ++sw;
-        const bool done = prev >= 0.0 && fabs(c2 - prev) <= tol * c2;
+        // the FP32 Grams and the eigensolver's 1e-7 residual tolerance fix
+        // ||G||^2 to about 1e-8 relative: a smaller threshold would only
+        // wait for rounding noise to line up
+        const bool done = prev >= 0.0 && fabs(c2 - prev) <= std::max(tol, 1e-8) * c2;
         prev = c2;
         if (done) break;
     }

@@ -44,22 +44,55 @@ COPY_BYTES = 256 << 20  # calibration copy of the counter pass
 # below); otherwise traffic is reported as null.
 TRAFFIC_SOURCES = ("paper_2209_14637_amd/csrc/gram.hip", "paper_2209_14637_amd/csrc/tsk_common.hpp")
 MEASURED_TRAFFIC = {
-    "stream_bf16": {"kernel": "gram_wide_kernel<uint16_t>", "fetch_kib": 9768671.2, "write_kib": 509954.0,
-                    "copy_fetch_kib": 131086.1, "copy_write_kib": 262144.0,
-                    "sha256": "1391695caab097565e6c0dbaf06c749548737c4b224c7b3776a06e811ddcd241"},
-    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1119450.8, "write_kib": 294920.2,
-                 "copy_fetch_kib": 131086.1, "copy_write_kib": 262144.0,
-                 "sha256": "1391695caab097565e6c0dbaf06c749548737c4b224c7b3776a06e811ddcd241"},
+    "stream_bf16": {"kernel": "gram_wide_kernel<uint16_t>", "fetch_kib": 9767457.1, "write_kib": 509953.4,
+                    "copy_fetch_kib": 131086.0, "copy_write_kib": 262144.0,
+                    "sha256": "dc97ba130852e3cb46cf8ea5dfebe7e885ca3fa0ef4ea61971298d909dfcf9b1"},
+    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1117562.8, "write_kib": 294921.2,
+                 "copy_fetch_kib": 131086.2, "copy_write_kib": 262144.0,
+                 "sha256": "dc97ba130852e3cb46cf8ea5dfebe7e885ca3fa0ef4ea61971298d909dfcf9b1"},
+}
+# HBM traffic of the apply's kernels from the same counter runs (the counter
+# pass applies the test stack twice; KiB per dispatch, the mean over the
+# dispatches; each dispatch covers `matrices` test matrices: the apply runs
+# in two pipeline groups), valid for the apply sources they were taken on.
+APPLY_TRAFFIC_SOURCES = ("paper_2209_14637_amd/csrc/apply.hip", "paper_2209_14637_amd/csrc/tsk_common.hpp")
+MEASURED_APPLY_TRAFFIC = {
+    "stream_bf16": {"matrices": 500, "copy_fetch_kib": 131086.0, "copy_write_kib": 262144.0,
+                    "fetch_kib": {"sketch": 1030490.6, "basis": 111359.6, "project": 1149256.0, "eig": 45152.1,
+                                  "outputs": 134929.1},
+                    "write_kib": {"sketch": 108172.9, "basis": 228016.4, "project": 270003.3, "eig": 4599.3,
+                                  "outputs": 152210.3},
+                    "sha256": "b6a91e30a31fd32974ef6ed0b47b9c7524e63efee00708975a8126ed504f8e41"},
+    "hsi_fp32": {"matrices": 200, "copy_fetch_kib": 131086.2, "copy_write_kib": 262144.0,
+                 "fetch_kib": {"sketch": 307769.8, "basis": 9727.2, "project": 380482.0, "eig": 12932.7,
+                               "outputs": 19287.8},
+                 "write_kib": {"sketch": 19280.9, "basis": 19206.2, "project": 25600.1, "eig": 831.2,
+                               "outputs": 14000.3},
+                 "sha256": "b6a91e30a31fd32974ef6ed0b47b9c7524e63efee00708975a8126ed504f8e41"},
 }
 
 
-def traffic_sha():
+def _sha(files):
     import hashlib
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def measured_apply_traffic(workload):
+    """Calibrated HBM bytes per test matrix of the apply, by kernel, or None
+    when the counters were taken on other kernel sources."""
+    t = MEASURED_APPLY_TRAFFIC.get(workload)
+    if t is None or t["sha256"] != _sha(APPLY_TRAFFIC_SOURCES):
+        return None
+    ff, fw = COPY_BYTES / (t["copy_fetch_kib"] * 1024), COPY_BYTES / (t["copy_write_kib"] * 1024)
+    return {k: (t["fetch_kib"][k] * ff + t["write_kib"][k] * fw) * 1024 / t["matrices"] for k in t["fetch_kib"]}
+
+
+def traffic_sha():
+    return _sha(TRAFFIC_SOURCES)
 
 
 def measured_traffic(workload):
@@ -216,13 +249,19 @@ def run(args):
         for _ in range(2):
             ctx.gram(train_in, compute=compute)
         torch.cuda.synchronize()
+        # two applies of the test stack (a data-free sketch: traffic does
+        # not depend on its values)
+        Sr = ctx.random_sketch("gaussian", k, m, seed=1)
+        for _ in range(2):
+            ctx.apply(Sr, test_in, r)
+        torch.cuda.synchronize()
         x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         for _ in range(2):
             y.copy_(x)
         torch.cuda.synchronize()
         ctx.close()
-        return {"counter_pass": wl, "gram_launches": 2, "copy_bytes": COPY_BYTES, "copies": 2}, spec
+        return {"counter_pass": wl, "gram_launches": 2, "apply_calls": 2, "copy_bytes": COPY_BYTES, "copies": 2}, spec
 
     outbuf = {}
 
@@ -329,6 +368,16 @@ def run(args):
     for name in ("sketch", "project"):
         if name in per_kernel_ms:
             roof_apply[f"{name}_kernel_gbs"] = apply_bytes / (per_kernel_ms[name] / 1e3) / 1e9
+    at = measured_apply_traffic(wl)
+    if at is not None:
+        per_matrix = sum(at.values())
+        roof_apply["traffic"] = per_matrix * spec.n_test
+        roof_apply["traffic_per_matrix_by_kernel"] = at
+        roof_apply["traffic_note"] = ("HBM bytes of one apply of the stack (FETCH_SIZE + WRITE_SIZE per kernel, "
+                                      "rocprofv3 --pmc on bench.py --counter-pass, calibrated by a 256 MiB copy); "
+                                      "null when taken on other kernel sources")
+    else:
+        roof_apply["traffic"] = None
 
     Tq = rec_extra.pop("_q8", None)
     if Tq is not None and parity is not None:

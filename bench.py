@@ -113,6 +113,11 @@ WORKLOADS = {
 
 
 S_ANGLE_GATE = {"f32": 1e-4, "bf16": 1e-2, "e4m3": 1e-2}
+# smallest eigengap (relative to lambda_1) whose leading block is gated: the
+# rounding of the training slices to bf16 perturbs the Gram by about 2e-5
+# lambda_1 on the Student-t stream (its gap of 1.7e-3 lambda_1 at j = 12 gives
+# an angle of 1.3e-2), so the reduced-precision forms gate gaps of 1e-2 and up
+S_ANGLE_GAP = {"f32": 1e-3, "bf16": 1e-2, "e4m3": 1e-2}
 
 
 def sketch_angles(S_gpu, S_orc, lam, rel_gap=1e-3):
@@ -303,8 +308,9 @@ def run(args):
                   "pass": bool(dev <= TAU[prec] and dev_f <= TAU[prec])}
         spath = os.path.join(ROOT, "tests", "golden", gname + "_S.npy")
         if os.path.exists(spath):
-            a_all, a_res = sketch_angles(S.cpu().numpy(), np.load(spath), lam_g)
+            a_all, a_res = sketch_angles(S.cpu().numpy(), np.load(spath), lam_g, S_ANGLE_GAP[prec])
             parity["s_angle_all_k"] = a_all
+            parity["s_angle_min_rel_gap"] = S_ANGLE_GAP[prec]
             parity["s_angle_resolvable"] = {str(j): v for j, v in sorted(a_res.items())}
             parity["s_angle_gate"] = S_ANGLE_GATE[prec]
             parity["pass"] = bool(parity["pass"] and max(a_res.values()) <= S_ANGLE_GATE[prec])

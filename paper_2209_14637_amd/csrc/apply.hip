@@ -877,7 +877,10 @@ __device__ __forceinline__ void basis_body(float *__restrict__ B, int64_t ldb, i
 // or, in the FP32 form, FP64 MFMA over the rows of C), H = Y diag Y^T
 // (Jacobi), descending order, sigma, relerr, flags, and Z = Y_r (FP32, KP x KP,
 // row stride KP) to Z[d].  With C = A V and V orthonormal, H = (AV)^T (AV).
-template <int KP>
+// FROM_C selects the source of H at compile time: the MFMA loop over C needs
+// far more registers than the rest, and a kernel that only adds band sums
+// keeps the occupancy of its LDS use.
+template <int KP, bool FROM_C>
 __device__ __forceinline__ void eig_body(const float *__restrict__ C, int64_t m, const double *__restrict__ ctc,
                                          const int *__restrict__ q, int k, int r,
                                          const double *__restrict__ fro_part, int npanel, float *__restrict__ Z,
@@ -891,7 +894,7 @@ __device__ __forceinline__ void eig_body(const float *__restrict__ C, int64_t m,
     __shared__ int perm[KP];
     __shared__ double s_lam[KP];
     const int tid = threadIdx.x;
-    if (ctc) {
+    if constexpr (!FROM_C) {
         constexpr int NT = KP / 16, NPAIR = NT * (NT + 1) / 2;
         const int nb = (int)((m + PJL_ROWS - 1) / PJL_ROWS);
         const double *src = ctc + d * nb * (NPAIR * 256);
@@ -1224,14 +1227,14 @@ __global__ __launch_bounds__(256, 2) void basis_kernel(float *__restrict__ B, in
                                                     uint16_t *__restrict__ Bb, int *__restrict__ q) {
     basis_body<KP>(B, ldb, n, k, Bb, q, blockIdx.x);
 }
-template <int KP>
+template <int KP, bool FROM_C>
 __global__ __launch_bounds__(256) void eig_kernel(const float *__restrict__ C, int64_t m,
                                                   const double *__restrict__ ctc, const int *__restrict__ q, int k,
                                                   int r, const double *__restrict__ fro_part, int npanel,
                                                   float *__restrict__ Z, float *__restrict__ sigma,
                                                   double *__restrict__ relerr, int *__restrict__ flags,
                                                   int *__restrict__ rf, double rf_thr) {
-    eig_body<KP>(C, m, ctc, q, k, r, fro_part, npanel, Z, sigma, relerr, flags, rf, rf_thr, blockIdx.x);
+    eig_body<KP, FROM_C>(C, m, ctc, q, k, r, fro_part, npanel, Z, sigma, relerr, flags, rf, rf_thr, blockIdx.x);
 }
 template <int RP, typename ET>
 __global__ __launch_bounds__(256) void refine_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
@@ -1301,11 +1304,11 @@ __global__ __launch_bounds__(256, 2) void basis_multi(const ApDesc *__restrict__
     const ApDesc &D = P[it.x];
     basis_body<KP>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y);
 }
-template <int KP>
+template <int KP, bool FROM_C>
 __global__ __launch_bounds__(256) void eig_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
-    eig_body<KP>(D.C, D.m, D.ctc, D.q, D.k, D.r, D.fro, D.npanel, D.Z, D.sigma, D.relerr, D.flags, D.rf, D.rf_thr,
+    eig_body<KP, FROM_C>(D.C, D.m, D.ctc, D.q, D.k, D.r, D.fro, D.npanel, D.Z, D.sigma, D.relerr, D.flags, D.rf, D.rf_thr,
                  it.y);
 }
 // item = (problem, matrix, band); problems without relerr have no items
@@ -1820,9 +1823,16 @@ static tsk_status finish_enqueue(tsk_ctx c, const tsk_stack *s, int kp, const fl
     const dim3 g((unsigned)count);
 #define TSK_FIN(KPV)                                                                                              \
     do {                                                                                                          \
-        TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                          \
-                   hipLaunchKernelGGL(eig_kernel<KPV>, g, dim3(256), 0, c->stream, Cm, m, ctc, (const int *)w.q,  \
-                                      k, r, fro, npanel, w.Z, sigma, relerr, flags, w.rf, thr));                 \
+        if (ctc)                                                                                                  \
+            TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                      \
+                       hipLaunchKernelGGL((eig_kernel<KPV, false>), g, dim3(256), 0, c->stream, Cm, m, ctc,       \
+                                          (const int *)w.q, k, r, fro, npanel, w.Z, sigma, relerr, flags, w.rf,   \
+                                          thr));                                                                  \
+        else                                                                                                      \
+            TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                      \
+                       hipLaunchKernelGGL((eig_kernel<KPV, true>), g, dim3(256), 0, c->stream, Cm, m, ctc,        \
+                                          (const int *)w.q, k, r, fro, npanel, w.Z, sigma, relerr, flags, w.rf,   \
+                                          thr));                                                                  \
         TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                          \
                    hipLaunchKernelGGL(outputs_kernel<KPV>, g, dim3(256), 0, c->stream, B, ldv, n, Cm, m, k, r,    \
                                       fro, npanel, (const float *)w.Z, L, R));                                    \
@@ -2328,9 +2338,16 @@ static tsk_status multi_launch(tsk_ctx c, const MultiTables &T, const ApDesc *P,
         TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(basis_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),        \
                                                         dim3(256), 0, c->stream, P, I + start[2][CL]));
 #define TSK_MEG(CL)                                                                                          \
-    if (cnt[2][CL])                                                                                          \
-        TSK_LAUNCH(c, TSK_KERNEL_FINISH, hipLaunchKernelGGL(eig_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),      \
-                                                            dim3(256), 0, c->stream, P, I + start[2][CL]));
+    if (cnt[2][CL]) {                                                                                        \
+        if (lowp)                                                                                            \
+            TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                 \
+                       hipLaunchKernelGGL((eig_multi<16 * CL, false>), dim3((unsigned)cnt[2][CL]), dim3(256), 0, \
+                                          c->stream, P, I + start[2][CL]));                                 \
+        else                                                                                                 \
+            TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                 \
+                       hipLaunchKernelGGL((eig_multi<16 * CL, true>), dim3((unsigned)cnt[2][CL]), dim3(256), 0,  \
+                                          c->stream, P, I + start[2][CL]));                                 \
+    }
 #define TSK_MOU(CL)                                                                                          \
     if (cnt[2][CL])                                                                                          \
         TSK_LAUNCH(c, TSK_KERNEL_FINISH, hipLaunchKernelGGL(outputs_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),  \

@@ -338,7 +338,7 @@ tsk_status tsk_set_eig_params(tsk_ctx ctx, int32_t block, int32_t max_iter, doub
  * pipeline groups of tsk_apply (1..64; the groups alternate between two
  * context streams), pj_cols = columns per projection step of the bf16 form
  * (64 or 128; also used by the batched forms).  0 restores the default
- * (groups: halves from 256 matrices on; pj_cols: 64).  Results do not
+ * (groups: 1, the whole stack; pj_cols: 64).  Results do not
  * depend on either (bit for bit).  Host only. */
 tsk_status tsk_set_tuning(tsk_ctx ctx, int64_t m, int64_t n, int32_t k, int32_t dtype, int32_t groups,
                           int32_t pj_cols);

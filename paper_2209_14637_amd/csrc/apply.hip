@@ -1975,12 +1975,13 @@ static ApWs ws_from(const ApWs &w, const tsk_stack *s, int k, int64_t d0) {
     return o;
 }
 
-// Matrices per group of the pipelined apply: TSK_APPLY_GROUP (diagnostic)
-// or the default, two halves from 256 matrices on.  The per-matrix kernels
-// (basis, eig, outputs) are bound by their latency, and smaller groups
-// leave too few matrices in flight to hide it: on 1000 bf16 matrices of
-// 1920 x 1080 at k = 40, halves took 3.52 ms, quarters 3.66, the whole
-// stack 3.68, groups of 125 / 64 / 32 4.6 / 6.7 / 11.2 ms.
+// Matrices per group of the pipelined apply: TSK_APPLY_GROUP (diagnostic),
+// the shape class's tuning entry, or by default the whole stack.  The
+// per-matrix kernels (basis, eig, outputs) fill a CU's registers and LDS by
+// themselves, so a group's per-matrix kernels do not run beside the next
+// group's streaming kernels, and each group pays their latency again: on
+// 1000 bf16 matrices of 1920 x 1080 at k = 40 the whole stack took 3.16 ms,
+// halves 3.23-3.28 ms and quarters 3.39-3.49 ms.
 static int64_t apply_group(tsk_ctx c, const tsk_stack *s, int k) {
     const char *e = getenv("TSK_APPLY_GROUP");
     if (e) {
@@ -1989,7 +1990,7 @@ static int64_t apply_group(tsk_ctx c, const tsk_stack *s, int k) {
     }
     const int groups = tsk_tuning(c, s->m, s->n, (k + 15) / 16 * 16, s->dtype).groups;
     if (groups > 0) return (s->count + groups - 1) / groups;
-    return s->count >= 256 ? (s->count + 1) / 2 : s->count;
+    return s->count;
 }
 
 // tsk_apply: the whole stack on the context's workspace (grown on demand).

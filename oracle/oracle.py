@@ -67,6 +67,7 @@ def lib():
             "tsko_round_bf16": [_P, _I, _P],
             "tsko_round_e4m3": [_P, _I, ctypes.c_float, _P],
             "tsko_e4m3_scale": [_P, _I, _P],
+            "tsko_round_e4m3_mx": [_P, _I, _I, _P, _P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -327,6 +328,23 @@ def round_e4m3(x: np.ndarray, scale: float = 1.0) -> np.ndarray:
     y = np.empty_like(x)
     _check(lib().tsko_round_e4m3(_p(x), x.size, ctypes.c_float(scale), _p(y)), "round_e4m3")
     return y
+
+
+MX_BLOCK = 32
+
+
+def round_e4m3_mx(x: np.ndarray):
+    """Block-scaled e4m3 of x (..., n): one power-of-two scale per block of
+    32 consecutive elements of a row.  Returns (decoded values as float32,
+    E8M0 exponent bytes (..., ceil(n / 32)))."""
+    x = _f32(x)
+    n = x.shape[-1]
+    rows = x.size // n if n else 0
+    nb = (n + MX_BLOCK - 1) // MX_BLOCK
+    y = np.empty_like(x)
+    e = np.empty(x.shape[:-1] + (nb,), dtype=np.uint8)
+    _check(lib().tsko_round_e4m3_mx(_p(x), rows, n, _p(y), _p(e)), "round_e4m3_mx")
+    return y, e
 
 
 def e4m3_scale(x: np.ndarray) -> float:

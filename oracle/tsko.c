@@ -681,6 +681,25 @@ int tsko_e4m3_scale(const float *x, int64_t n, float *scale) {
     return 0;
 }
 
+int tsko_round_e4m3_mx(const float *x, int64_t rows, int64_t n, float *y, uint8_t *e) {
+    if (rows < 0 || n < 0 || ((!x || !y || !e) && rows * n > 0)) return -1;
+    const int64_t bw = 32 - 16 * MUT(20);           /* block width along a row */
+    const int64_t nb = (n + bw - 1) / bw;
+    for (int64_t i = 0; i < rows; i++)
+        for (int64_t b = 0; b < nb; b++) {
+            const int64_t c0 = b * bw, w = n - c0 < bw ? n - c0 : bw;
+            const float *xb = x + i * n + c0;
+            float *yb = y + i * n + c0, s;
+            tsko_e4m3_scale(xb, w, &s);
+            tsko_round_e4m3(xb, w, s, yb);
+            for (int64_t j = 0; j < w; j++) yb[j] = (float)((double)yb[j] / (double)s);
+            int ex;
+            frexp((double)s, &ex);                  /* s = 2^(ex - 1) */
+            e[i * nb + b] = (uint8_t)(127 - (ex - 1));
+        }
+    return 0;
+}
+
 int tsko_opt_f32(const float *A, int64_t count, int64_t m, int64_t n, int64_t r,
                  double *tail, double *fro) {
     if (!A || !tail || count < 0 || m <= 0 || n <= 0 || r < 0) return -1;

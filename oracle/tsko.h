@@ -125,6 +125,17 @@ int tsko_round_e4m3(const float *x, int64_t n, float scale, float *y);
  * unless clamped, 2 * amax * s > 448. */
 int tsko_e4m3_scale(const float *x, int64_t n, float *scale);
 
+/* e4m3 with block scales (the MX layout: one power-of-two scale per block of
+ * 32 consecutive elements of a row; the last block of a row may be
+ * shorter).  x: rows x n.  Each block is scaled by its own tsko_e4m3_scale
+ * and rounded by tsko_round_e4m3.  y (rows x n): the decoded values,
+ * rounded value / scale.  e (rows x ceil(n / 32) bytes): the E8M0 exponent
+ * of each block, 127 - log2(scale), so that a stored code times
+ * 2^(e - 127) is the decoded value.  Pinned by exhaustive nearest-value
+ * search per element, block independence and power-of-two equivariance,
+ * the scale's defining inequality per block, and block boundaries (tests). */
+int tsko_round_e4m3_mx(const float *x, int64_t rows, int64_t n, float *y, uint8_t *e);
+
 /* Data-free sketches of the SCW baseline (Sections 1 and 2), k x m, from a
  * counter-based generator: tsko_splitmix64(seed, c) is the c-th output (from
  * 0) of SplitMix64 seeded with `seed`.  kind 0: Gaussian entries N(0, 1/k)

@@ -122,3 +122,61 @@ def test_integer_inputs_exact(orc, fmt):
         s = orc.e4m3_scale(x)
         assert s == 128.0
         np.testing.assert_array_equal(orc.round_e4m3(x, s), x * s)
+
+
+def test_e4m3_mx_nearest_per_block(orc):
+    """Block-scaled e4m3 (one power-of-two scale per 32 consecutive elements
+    of a row): every element is its value times its block's scale, rounded to
+    the nearest e4m3 value (exhaustive search), divided by that scale; the
+    scale is the largest power of two that keeps the block's amax within
+    448; the last block of a row is the ragged rest."""
+    vals, codes = e4m3_values()
+    rng = np.random.default_rng(4)
+    m, n = 5, 77                                    # blocks of 32, 32 and 13
+    x = samples(rng, -12, 6, m * n).reshape(m, n)
+    for i in range(m):
+        for b in range(3):
+            x[i, 32 * b:32 * b + 32] *= np.float32(2.0 ** int(rng.integers(-20, 20)))
+    y, e = orc.round_e4m3_mx(x)
+    assert e.shape == (m, 3) and e.dtype == np.uint8
+    for i in range(m):
+        for b in range(3):
+            sl = slice(32 * b, min(32 * b + 32, n))
+            blk = x[i, sl].astype(np.float64)
+            s = 2.0 ** (127 - int(e[i, b]))
+            a = np.abs(blk).max()
+            assert a * s <= 448.0 < 2 * a * s, (i, b)
+            for xv, yv in zip(blk, y[i, sl]):
+                want = nearest_even(xv * s, vals, codes, 0x07) / s
+                assert yv == np.float32(want), (i, b, xv, yv, want)
+                if abs(xv * s) >= 2.0 ** -6:                 # normal range: 3 mantissa bits
+                    assert abs(yv - xv) <= 2.0 ** -4 * abs(xv)
+
+
+def test_e4m3_mx_blocks_independent(orc):
+    """Scaling one block by a power of two scales exactly its decoded values
+    and shifts exactly its exponent; no other block changes, even in the
+    same row; an all-zero block has exponent 127 (scale 1)."""
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((3, 96)).astype(np.float32)
+    y, e = orc.round_e4m3_mx(x)
+    x2 = x.copy()
+    x2[1, 32:64] *= np.float32(2.0 ** 9)
+    y2, e2 = orc.round_e4m3_mx(x2)
+    mask = np.zeros(x.shape, bool)
+    mask[1, 32:64] = True
+    np.testing.assert_array_equal(y2[~mask], y[~mask])
+    np.testing.assert_array_equal(y2[mask], y[mask] * np.float32(2.0 ** 9))
+    assert int(e2[1, 1]) == int(e[1, 1]) + 9
+    keep = np.ones(e.shape, bool)
+    keep[1, 1] = False
+    np.testing.assert_array_equal(e2[keep], e[keep])
+    x3 = x.copy()
+    x3[0, 32] = 1e4                                  # first column of block 1
+    y3, e3 = orc.round_e4m3_mx(x3)
+    np.testing.assert_array_equal(y3[0, :32], y[0, :32])
+    assert e3[0, 0] == e[0, 0] and e3[0, 1] != e[0, 1]
+    z = x.copy()
+    z[2, 64:] = 0.0
+    yz, ez = orc.round_e4m3_mx(z)
+    assert ez[2, 2] == 127 and not yz[2, 64:].any()

@@ -32,6 +32,7 @@ MUTANTS = {
     17: "sparse sign sketch never uses its last row",
     18: "two-sided SCW drops Sigma_r from L",
     19: "HOOI never updates S (mode 1 stays at the HOSVD guess)",
+    20: "block-scaled e4m3 with blocks of 16 instead of 32 elements",
 }
 
 

@@ -238,6 +238,7 @@ def run(args):
         if wl == "t3stream_e4m3":
             # the e4m3 form beside the gated bf16 one
             rec_extra["_q8"] = ctx.stage(tr, "e4m3")
+            rec_extra["_mx"] = ctx.stage(tr, "mxe4m3")
         del tr
         torch.cuda.empty_cache()
         stage_bytes = spec.n_test * m * n * (4 + 2)
@@ -386,6 +387,7 @@ def run(args):
         roof_apply["traffic"] = None
 
     Tq = rec_extra.pop("_q8", None)
+    Tmx = rec_extra.pop("_mx", None)
     if Tq is not None and parity is not None:
         # the e4m3 form: e4m3 Gram (timed), its sketch applied to e4m3 and
         # bf16 test matrices; errors against the oracle side by side with the
@@ -399,12 +401,24 @@ def run(args):
         kt8 = ctx.timing_read(reset=True)
         ctx.timing(False)
         g8 = kt8["gram"][1] / max(kt8["gram"][0], 1)
+        # block-scaled e4m3 (one scale per 32 elements of a row) training
+        ctx.timing(["gram"])
+        ctx.timing_read(reset=True)
+        Smx, lammx, itmx, _ = ctx.train(Tmx, k, compute="mxe4m3")
+        Smx, lammx, itmx, _ = ctx.train(Tmx, k, compute="mxe4m3")
+        ktm = ctx.timing_read(reset=True)
+        ctx.timing(False)
+        gmx = ktm["gram"][1] / max(ktm["gram"][0], 1)
+        del Tmx
         q8t = ctx.stage(te, "e4m3")
         side = {"gram_e4m3_ms": g8, "gram_e4m3_tflops": gram_flops / (g8 / 1e3) / 1e12,
                 "gram_e4m3_frac_of_5000": gram_flops / (g8 / 1e3) / 1e12 / PEAK_TFLOPS["e4m3"],
-                "eig_iterations": it8}
+                "eig_iterations": it8,
+                "gram_mx_e4m3_ms": gmx, "gram_mx_e4m3_tflops": gram_flops / (gmx / 1e3) / 1e12,
+                "gram_mx_e4m3_frac_of_5000": gram_flops / (gmx / 1e3) / 1e12 / PEAK_TFLOPS["e4m3"],
+                "mx_eig_iterations": itmx}
         for tag, Sx, A in (("e4m3_sketch_e4m3_apply", S8, q8t), ("e4m3_sketch_bf16_apply", S8, test_in),
-                           ("bf16_sketch_bf16_apply", S, test_in)):
+                           ("mx_e4m3_sketch_bf16_apply", Smx, test_in), ("bf16_sketch_bf16_apply", S, test_in)):
             o = ctx.apply(Sx, A, r)
             e_exp = ctx.error(te[:ne], o["L"][:ne], o["R"][:ne]).cpu().numpy()
             tt = []

@@ -55,7 +55,8 @@ typedef enum {
     TSK_F64 = 0,
     TSK_F32 = 1,
     TSK_BF16 = 2,
-    TSK_F8E4M3 = 3
+    TSK_F8E4M3 = 3,
+    TSK_MXE4M3 = 4
 } tsk_dtype;
 
 /* Per-matrix condition bits written to `flags` by tsk_apply. */
@@ -74,10 +75,17 @@ typedef struct tsk_ctx_s *tsk_ctx;
  * (4 FP32, 8 bf16 or 16 e4m3 elements).  A row stride that is a multiple of
  * 128 bytes (a cache line) lets the streaming kernels read whole lines: at
  * 1920 x 1080 bf16 they run 5-8% faster than at a 2160-byte stride.
- * dtype: TSK_F32, TSK_BF16 (bfloat16 bits), or TSK_F8E4M3 (OCP e4m3 bytes,
- * largest finite 448); scale: NULL except for TSK_F8E4M3, where it is a
- * device array of `count` floats and slice d holds A_d * scale[d]
- * (tsk_stage writes such stacks). */
+ * dtype: TSK_F32, TSK_BF16 (bfloat16 bits), TSK_F8E4M3 (OCP e4m3 bytes,
+ * largest finite 448) or TSK_MXE4M3 (e4m3 bytes with one power-of-two scale
+ * per block of 32 consecutive elements of a row, the MX layout; the last
+ * block of a row is the ragged rest).  scale: NULL for TSK_F32 and TSK_BF16.
+ * TSK_F8E4M3: a device array of `count` floats, slice d holds A_d * scale[d]
+ * (tsk_stage writes such stacks).  TSK_MXE4M3: the pointer holds bytes, not
+ * floats -- count * m * ceil(n / 32) E8M0 exponents, byte
+ * (d * m + i) * ceil(n / 32) + b for block b of row i of slice d; element
+ * (i, j) holds A_d(i, j) * 2^(127 - e) for its block's exponent e
+ * (tsk_stage_mx writes such stacks).  Block-scaled stacks are accepted by
+ * tsk_gram, tsk_train and tsk_opt_tail only. */
 typedef struct {
     const void *A;     /* device */
     int32_t dtype;     /* tsk_dtype of the stored elements */
@@ -113,6 +121,19 @@ const char *tsk_last_error(tsk_ctx ctx);
 tsk_status tsk_stage(tsk_ctx ctx, const tsk_stack *src, int32_t dtype, void *dst, int64_t ld,
                      int64_t stride, float *scale, double *norm2);
 
+/* Staging into block-scaled e4m3 (TSK_MXE4M3; the reading of the e4m3 form
+ * with one scale per block of 32 consecutive elements of a row, the MX
+ * layout).  Block b of row i of slice d is multiplied by its own power of
+ * two 2^j, j = floor(log2(448 / max|block|)) clamped to [-126, 127] (0 for an
+ * all-zero block), and rounded to nearest even e4m3; no value saturates.
+ * src: an FP32 stack.  dst: device, codes at dst[d * stride + i * ld + c]
+ * (ld >= n, stride >= m * ld, both multiples of 16, dst 16-byte aligned;
+ * columns n..ld-1 not written).  bscale: device, count * m * ceil(n / 32)
+ * bytes, written 127 - j per block in (slice, row, block) order.  Enqueue
+ * only. */
+tsk_status tsk_stage_mx(tsk_ctx ctx, const tsk_stack *src, void *dst, int64_t ld, int64_t stride,
+                        uint8_t *bscale);
+
 /* Mode-1 Gram (Section 3.1, eqs. 3.2-3.3; tensor basics in Section 2):
  *     G = A_(1) A_(1)^T = sum_{d<count} A_d A_d^T,   A_(1) = [A_1|...|A_N].
  * G: device, m x m FP64, full symmetric matrix.  Products accumulate in FP32
@@ -121,7 +142,11 @@ tsk_status tsk_stage(tsk_ctx ctx, const tsk_stack *src, int32_t dtype, void *dst
  *   TSK_BF16   : bf16 products, from a TSK_BF16 stack as stored or from an
  *                FP32 stack rounded to bf16 (nearest even) as it is loaded;
  *   TSK_F8E4M3 : e4m3 products of a TSK_F8E4M3 stack, each slice's products
- *                multiplied exactly by 1/scale[d]^2 (power of two).
+ *                multiplied exactly by 1/scale[d]^2 (power of two);
+ *   TSK_MXE4M3 : e4m3 products of a TSK_MXE4M3 stack, every 32-element
+ *                block of each operand multiplied exactly by its own
+ *                2^(e - 127) through the MFMA's per-lane operand scales
+ *                (128 x 128 tiles).
  * Enqueue only. */
 tsk_status tsk_gram(tsk_ctx ctx, const tsk_stack *train, int32_t compute, double *G);
 

@@ -600,10 +600,18 @@ __device__ __forceinline__ void qstash(uint8_t *buf, const v4u (&v)[8]) {
     }
 }
 
+// MX: a block-scaled stack (one E8M0 exponent per 32 consecutive elements of
+// a row, bscale[(d m + i) nbk + b]); every lane loads the exponents of its
+// four A rows and four B rows at its 32-column block of a stage together
+// with the stage's data, packs them one byte per operand tile once they
+// have landed, and hands them to the MFMA, which selects the byte.
+template <bool MX>
 __global__ __launch_bounds__(256, 2) void gram_e4m3_kernel(const uint8_t *__restrict__ A,
-                                                           const float *__restrict__ scale, int64_t m, int64_t n,
-                                                           int64_t ld, int64_t stride, int64_t count, int T,
-                                                           int nchunks, int per_xcd, float *__restrict__ part) {
+                                                           const float *__restrict__ scale,
+                                                           const uint8_t *__restrict__ bscale, int nbk, int64_t m,
+                                                           int64_t n, int64_t ld, int64_t stride, int64_t count,
+                                                           int T, int nchunks, int per_xcd,
+                                                           float *__restrict__ part) {
     constexpr int QLD = 2 * HLD;        // padded LDS row, bytes (144)
     constexpr int QBUF = 2 * GT * QLD;  // bytes per stage buffer
     __shared__ uint8_t lds[2 * QBUF];
@@ -633,9 +641,51 @@ __global__ __launch_bounds__(256, 2) void gram_e4m3_kernel(const uint8_t *__rest
     };
     // E8M0 operand scale 2^-j of the stage's slice (scale[d] = 2^j)
     auto escale = [&](int64_t s1) {
+        if constexpr (MX) return 0;
         int j;
         frexpf(scale[d0 + s1 / spd], &j);
         return 127 - (j - 1);
+    };
+    // block-scaled form: this lane's exponents of stage s1 (rows past m read
+    // row m - 1, blocks past n the last block: their data is zero)
+    auto sfetch = [&](int64_t s1, unsigned (&sr)[8]) {
+        const int64_t d = d0 + s1 / spd;
+        const int64_t blk = min((s1 % spd) * (QK / 32) + q, (int64_t)nbk - 1);
+        const uint8_t *base = bscale + d * m * nbk + blk;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t row = min((u < 4 ? rb0 + wr : cb0 + (wc - GT)) + 16 * (u & 3) + ii, m - 1);
+            sr[u] = base[row * nbk];
+        }
+    };
+    auto spack = [&](const unsigned (&sr)[8], unsigned &pa, unsigned &pb) {
+        pa = sr[0] | (sr[1] << 8) | (sr[2] << 16) | (sr[3] << 24);
+        pb = sr[4] | (sr[5] << 8) | (sr[6] << 16) | (sr[7] << 24);
+    };
+    // The MFMA's K blocks (measured): block g, whose scale lane group g
+    // supplies, is bytes 0..15 of lane groups 2(g & 1) and 2(g & 1) + 1 for
+    // g < 2 and their bytes 16..31 for g >= 2.  So lane group q takes the
+    // stage's 16-byte chunks q (bytes 0..15) and q + 4 (bytes 16..31): block
+    // g then holds columns 32g .. 32g + 31 of the stage, the MX block whose
+    // exponent lane group g passes.
+    auto mma_mx = [&](const uint8_t *cur, unsigned pa, unsigned pb) {
+        v8i a[4], b[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const uint8_t *ra = cur + (wr + x * 16 + ii) * QLD + 16 * q;
+            const uint8_t *rc = cur + (wc + x * 16 + ii) * QLD + 16 * q;
+            const v4u a0 = *reinterpret_cast<const v4u *>(ra), a1 = *reinterpret_cast<const v4u *>(ra + 64);
+            const v4u b0 = *reinterpret_cast<const v4u *>(rc), b1 = *reinterpret_cast<const v4u *>(rc + 64);
+            a[x] = v8i{(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+            b[x] = v8i{(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+        }
+        const int sa = (int)pa, sb = (int)pb;
+#define TSK_MXM(X, Y) acc[X][Y] = mfma16x16x128_e4m3_sel<X, Y>(a[X], b[Y], acc[X][Y], sa, sb);
+        TSK_MXM(0, 0) TSK_MXM(0, 1) TSK_MXM(0, 2) TSK_MXM(0, 3)
+        TSK_MXM(1, 0) TSK_MXM(1, 1) TSK_MXM(1, 2) TSK_MXM(1, 3)
+        TSK_MXM(2, 0) TSK_MXM(2, 1) TSK_MXM(2, 2) TSK_MXM(2, 3)
+        TSK_MXM(3, 0) TSK_MXM(3, 1) TSK_MXM(3, 2) TSK_MXM(3, 3)
+#undef TSK_MXM
     };
     auto mma_stage = [&](const uint8_t *cur, int es) {
         v8i a[4], b[4];
@@ -654,22 +704,58 @@ __global__ __launch_bounds__(256, 2) void gram_e4m3_kernel(const uint8_t *__rest
             for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x128_e4m3(a[x], b[y], acc[x][y], es, es);
     };
     v4u p0[8], p1[8];
-    fetch(0, p0);
-    qstash(lds, p0);
-    if (nst > 1) fetch(1, p1);
-    __syncthreads();
-    int64_t st = 0;
-    for (; st + 1 < nst; st += 2) {
-        if (st + 2 < nst) fetch(st + 2, p0);
-        mma_stage(lds, escale(st));
-        qstash(lds + QBUF, p1);
+    if constexpr (MX) {
+        // the pipeline below, with each stage's exponents beside its data
+        unsigned s0[8], s1[8], pa0, pb0, pa1 = 0u, pb1 = 0u;
+        fetch(0, p0);
+        sfetch(0, s0);
+        qstash(lds, p0);
+        spack(s0, pa0, pb0);
+        if (nst > 1) {
+            fetch(1, p1);
+            sfetch(1, s1);
+        }
         __syncthreads();
-        if (st + 3 < nst) fetch(st + 3, p1);
-        mma_stage(lds + QBUF, escale(st + 1));
-        if (st + 2 < nst) qstash(lds, p0);
+        int64_t st = 0;
+        for (; st + 1 < nst; st += 2) {
+            if (st + 2 < nst) {
+                fetch(st + 2, p0);
+                sfetch(st + 2, s0);
+            }
+            mma_mx(lds, pa0, pb0);
+            qstash(lds + QBUF, p1);
+            spack(s1, pa1, pb1);
+            __syncthreads();
+            if (st + 3 < nst) {
+                fetch(st + 3, p1);
+                sfetch(st + 3, s1);
+            }
+            mma_mx(lds + QBUF, pa1, pb1);
+            if (st + 2 < nst) {
+                qstash(lds, p0);
+                spack(s0, pa0, pb0);
+            }
+            __syncthreads();
+        }
+        if (st < nst) mma_mx(lds, pa0, pb0);
+    } else {
+        fetch(0, p0);
+        qstash(lds, p0);
+        if (nst > 1) fetch(1, p1);
         __syncthreads();
+        int64_t st = 0;
+        for (; st + 1 < nst; st += 2) {
+            if (st + 2 < nst) fetch(st + 2, p0);
+            mma_stage(lds, escale(st));
+            qstash(lds + QBUF, p1);
+            __syncthreads();
+            if (st + 3 < nst) fetch(st + 3, p1);
+            mma_stage(lds + QBUF, escale(st + 1));
+            if (st + 2 < nst) qstash(lds, p0);
+            __syncthreads();
+        }
+        if (st < nst) mma_stage(lds, escale(st));
     }
-    if (st < nst) mma_stage(lds, escale(st));
     float *P = part + ((int64_t)chunk * T + t) * (GT * GT);
 #pragma unroll
     for (int x = 0; x < 4; ++x)
@@ -778,9 +864,15 @@ tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *
                                       per_xcd, part));
     } else if (compute == TSK_F8E4M3) {
         TSK_LAUNCH(c, TSK_KERNEL_GRAM,
-                   hipLaunchKernelGGL(gram_e4m3_kernel, dim3(grid), dim3(256), 0, c->stream,
-                                      (const uint8_t *)s->A, s->scale, m, s->n, s->ld, s->stride, count, T, nchunks,
-                                      per_xcd, part));
+                   hipLaunchKernelGGL(gram_e4m3_kernel<false>, dim3(grid), dim3(256), 0, c->stream,
+                                      (const uint8_t *)s->A, s->scale, (const uint8_t *)nullptr, 0, m, s->n, s->ld,
+                                      s->stride, count, T, nchunks, per_xcd, part));
+    } else if (compute == TSK_MXE4M3) {
+        TSK_LAUNCH(c, TSK_KERNEL_GRAM,
+                   hipLaunchKernelGGL(gram_e4m3_kernel<true>, dim3(grid), dim3(256), 0, c->stream,
+                                      (const uint8_t *)s->A, (const float *)nullptr,
+                                      reinterpret_cast<const uint8_t *>(s->scale), (int)((s->n + 31) / 32), m,
+                                      s->n, s->ld, s->stride, count, T, nchunks, per_xcd, part));
     } else if (s->dtype == TSK_F32) {
         TSK_LAUNCH(c, TSK_KERNEL_GRAM,
                    hipLaunchKernelGGL(gram_bf16_kernel<float>, dim3(grid), dim3(256), 0, c->stream,

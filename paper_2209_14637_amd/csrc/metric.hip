@@ -27,7 +27,7 @@ __global__ void trace_kernel(const double *__restrict__ G, int64_t m, double *__
 
 tsk_status tsk_opt_tail_enqueue(tsk_ctx c, const tsk_stack *s, int r, double *tail, double *fro) {
     const int64_t m = s->m;
-    const int compute = s->dtype == TSK_F32 ? TSK_F32 : s->dtype == TSK_BF16 ? TSK_BF16 : TSK_F8E4M3;
+    const int compute = s->dtype == TSK_F32 ? TSK_F32 : s->dtype == TSK_BF16 ? TSK_BF16 : s->dtype;
     TSK_TRY(tsk_grow(c, c->gram_G, sizeof(double) * m * m));
     TSK_TRY(tsk_grow(c, c->mt_ws, sizeof(float) * (size_t)r * m + 256));
     double *G = (double *)c->gram_G.p;
@@ -39,7 +39,10 @@ tsk_status tsk_opt_tail_enqueue(tsk_ctx c, const tsk_stack *s, int r, double *ta
         tsk_stack one = *s;
         one.count = 1;
         one.A = (const char *)s->A + (size_t)d * s->stride * es;
-        if (s->scale) one.scale = s->scale + d;
+        if (s->dtype == TSK_F8E4M3) one.scale = s->scale + d;
+        if (s->dtype == TSK_MXE4M3)  // the slice's block exponents
+            one.scale = reinterpret_cast<const float *>(reinterpret_cast<const uint8_t *>(s->scale) +
+                                                        (size_t)d * s->m * ((s->n + 31) / 32));
         TSK_TRY(tsk_gram_enqueue(c, &one, compute, G));
         TSK_LAUNCH(c, TSK_KERNEL_ERROR, hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 0, c->stream,
                                                            (const double *)G, m, tr));

@@ -9,6 +9,8 @@
 tsk_status tsk_gram_enqueue(tsk_ctx c, const tsk_stack *s, int compute, double *G);
 tsk_status tsk_stage_enqueue(tsk_ctx c, const tsk_stack *s, int dtype, void *dst, int64_t ldd, int64_t strided,
                              float *scale, double *norm2);
+tsk_status tsk_stage_mx_enqueue(tsk_ctx c, const tsk_stack *s, void *dst, int64_t ldd, int64_t strided,
+                                uint8_t *bscale);
 tsk_status tsk_eig_enqueue(tsk_ctx c, const double *G, int64_t m, int k, float *S, double *lambda,
                            int32_t *iters_out, double tol_default);
 tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
@@ -121,6 +123,7 @@ static size_t dtype_size(int32_t dt) {
         case TSK_F32: return 4;
         case TSK_BF16: return 2;
         case TSK_F8E4M3: return 1;
+        case TSK_MXE4M3: return 1;
         default: return 0;
     }
 }
@@ -130,10 +133,11 @@ tsk_status tsk_check_stack(tsk_ctx c, const tsk_stack *s, const char *name) {
     if (!s) return tsk_fail(c, TSK_E_ARG, nm + ": null stack");
     if (!s->A) return tsk_fail(c, TSK_E_ARG, nm + ": null data pointer");
     const size_t es = dtype_size(s->dtype);
-    if (s->dtype != TSK_F32 && s->dtype != TSK_BF16 && s->dtype != TSK_F8E4M3)
-        return tsk_fail(c, TSK_E_ARG, nm + ": dtype must be TSK_F32, TSK_BF16 or TSK_F8E4M3");
-    if (s->dtype == TSK_F8E4M3 && !s->scale) return tsk_fail(c, TSK_E_ARG, nm + ": TSK_F8E4M3 needs scale");
-    if (s->dtype != TSK_F8E4M3 && s->scale) return tsk_fail(c, TSK_E_ARG, nm + ": scale must be NULL");
+    const bool scaled = s->dtype == TSK_F8E4M3 || s->dtype == TSK_MXE4M3;
+    if (s->dtype != TSK_F32 && s->dtype != TSK_BF16 && !scaled)
+        return tsk_fail(c, TSK_E_ARG, nm + ": dtype must be TSK_F32, TSK_BF16, TSK_F8E4M3 or TSK_MXE4M3");
+    if (scaled && !s->scale) return tsk_fail(c, TSK_E_ARG, nm + ": e4m3 stacks need scale");
+    if (!scaled && s->scale) return tsk_fail(c, TSK_E_ARG, nm + ": scale must be NULL");
     if (s->m < 1 || s->n < 1 || s->count < 1) return tsk_fail(c, TSK_E_SHAPE, nm + ": m, n, count must be >= 1");
     if (s->ld < s->n) return tsk_fail(c, TSK_E_SHAPE, nm + ": ld < n");
     if (s->stride < s->m * s->ld) return tsk_fail(c, TSK_E_SHAPE, nm + ": stride < m*ld");
@@ -144,7 +148,11 @@ tsk_status tsk_check_stack(tsk_ctx c, const tsk_stack *s, const char *name) {
         return tsk_fail(c, TSK_E_SHAPE, nm + ": dimension too large");
     const size_t need = ((size_t)(s->count - 1) * s->stride + (size_t)(s->m - 1) * s->ld + s->n) * es;
     TSK_TRY(tsk_check_dev(c, s->A, need, (nm + ".A").c_str()));
-    if (s->scale) TSK_TRY(tsk_check_dev(c, s->scale, sizeof(float) * s->count, (nm + ".scale").c_str()));
+    if (s->dtype == TSK_F8E4M3)
+        TSK_TRY(tsk_check_dev(c, s->scale, sizeof(float) * s->count, (nm + ".scale").c_str()));
+    if (s->dtype == TSK_MXE4M3)
+        TSK_TRY(tsk_check_dev(c, s->scale, (size_t)(s->count * s->m * ((s->n + 31) / 32)),
+                              (nm + ".scale").c_str()));
     return TSK_OK;
 }
 
@@ -164,7 +172,12 @@ static tsk_status check_gram_compute(tsk_ctx c, const tsk_stack *s, int32_t comp
         if (s->dtype != TSK_F8E4M3) return tsk_fail(c, TSK_E_ARG, w + ": compute TSK_F8E4M3 needs an e4m3 stack");
         return TSK_OK;
     }
-    return tsk_fail(c, TSK_E_ARG, w + ": compute must be TSK_F32, TSK_BF16 or TSK_F8E4M3");
+    if (compute == TSK_MXE4M3) {
+        if (s->dtype != TSK_MXE4M3)
+            return tsk_fail(c, TSK_E_ARG, w + ": compute TSK_MXE4M3 needs a block-scaled e4m3 stack");
+        return TSK_OK;
+    }
+    return tsk_fail(c, TSK_E_ARG, w + ": compute must be TSK_F32, TSK_BF16, TSK_F8E4M3 or TSK_MXE4M3");
 }
 
 void tsk_ev_begin(tsk_ctx c, int cls, hipEvent_t *a) {
@@ -310,7 +323,7 @@ tsk_status tsk_stage(tsk_ctx c, const tsk_stack *src, int32_t dtype, void *dst, 
     TSK_TRY(tsk_check_stack(c, src, "src"));
     if (src->dtype != TSK_F32) return tsk_fail(c, TSK_E_ARG, "tsk_stage: src must be an FP32 stack");
     if (dtype != TSK_BF16 && dtype != TSK_F8E4M3)
-        return tsk_fail(c, TSK_E_ARG, "tsk_stage: dtype must be TSK_BF16 or TSK_F8E4M3");
+        return tsk_fail(c, TSK_E_ARG, "tsk_stage: dtype must be TSK_BF16 or TSK_F8E4M3 (block scales: tsk_stage_mx)");
     if (dtype == TSK_F8E4M3 && !scale) return tsk_fail(c, TSK_E_ARG, "tsk_stage: TSK_F8E4M3 needs scale");
     if (dtype == TSK_BF16 && scale) return tsk_fail(c, TSK_E_ARG, "tsk_stage: scale must be NULL for TSK_BF16");
     tsk_stack d = *src;
@@ -322,6 +335,23 @@ tsk_status tsk_stage(tsk_ctx c, const tsk_stack *src, int32_t dtype, void *dst, 
     TSK_TRY(tsk_check_stack(c, &d, "dst"));
     if (norm2) TSK_TRY(tsk_check_dev(c, norm2, sizeof(double) * src->count, "norm2"));
     return tsk_stage_enqueue(c, src, dtype, dst, ld, stride, scale, norm2);
+}
+
+tsk_status tsk_stage_mx(tsk_ctx c, const tsk_stack *src, void *dst, int64_t ld, int64_t stride, uint8_t *bscale) {
+    if (!c) return TSK_E_ARG;
+    c->err.clear();
+    DeviceGuard g(c->device);
+    TSK_TRY(tsk_check_stack(c, src, "src"));
+    if (src->dtype != TSK_F32) return tsk_fail(c, TSK_E_ARG, "tsk_stage_mx: src must be an FP32 stack");
+    if (!bscale) return tsk_fail(c, TSK_E_ARG, "tsk_stage_mx: bscale is required");
+    tsk_stack d = *src;
+    d.A = dst;
+    d.dtype = TSK_MXE4M3;
+    d.scale = reinterpret_cast<const float *>(bscale);
+    d.ld = ld;
+    d.stride = stride;
+    TSK_TRY(tsk_check_stack(c, &d, "dst"));
+    return tsk_stage_mx_enqueue(c, src, dst, ld, stride, bscale);
 }
 
 tsk_status tsk_eig_topk(tsk_ctx c, const double *G, int64_t m, int32_t k, float *S, double *lambda,
@@ -354,7 +384,9 @@ tsk_status tsk_train(tsk_ctx c, const tsk_stack *train, int32_t k, int32_t compu
     TSK_TRY(tsk_grow(c, c->gram_G, sizeof(double) * m * m));
     double *G = (double *)c->gram_G.p;
     TSK_TRY(tsk_gram_enqueue(c, train, compute, G));
-    const double tol = compute == TSK_F8E4M3 ? TSK_EIG_TOL_F8 : compute == TSK_BF16 ? TSK_EIG_TOL_BF16 : TSK_EIG_TOL_F32;
+    const double tol = compute == TSK_F8E4M3 || compute == TSK_MXE4M3 ? TSK_EIG_TOL_F8
+                       : compute == TSK_BF16                          ? TSK_EIG_TOL_BF16
+                                                                      : TSK_EIG_TOL_F32;
     return tsk_eig_enqueue(c, G, m, k, S, lambda, iters, tol);
 }
 

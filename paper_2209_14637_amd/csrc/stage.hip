@@ -152,7 +152,73 @@ __global__ __launch_bounds__(256) void stage_e4m3_kernel(const float *__restrict
     }
 }
 
+// Block-scaled e4m3 (the MX layout: one power of two per 32 consecutive
+// elements of a row).  A group of 8 lanes takes one block, 4 values per
+// lane; the block's amax by a 3-step exchange within the group; its
+// exponent j as in stage_final_kernel (0 for an all-zero block); the values
+// times 2^j (exact) rounded to nearest even; bscale[block] = 127 - j.
+// Blocks are numbered (slice, row, block) in row-major order.
+__global__ __launch_bounds__(256) void stage_mx_kernel(const float *__restrict__ src, int64_t m, int64_t n,
+                                                       int64_t ld, int64_t stride, int64_t count,
+                                                       uint8_t *__restrict__ dst, int64_t ldd, int64_t strided,
+                                                       uint8_t *__restrict__ bscale, int64_t nbk) {
+    const int64_t g = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3;
+    const int l = threadIdx.x & 7;
+    const bool live = g < count * m * nbk;
+    const int64_t b = live ? g % nbk : 0, row = live ? (g / nbk) % m : 0, d = live ? g / (nbk * m) : 0;
+    const int64_t c = b * 32 + 4 * l;
+    float x[4] = {0.f, 0.f, 0.f, 0.f};
+    if (live && c < n) {
+        const float *p = src + d * stride + row * ld + c;
+        if (c + 3 < n) {
+            const float4 v = *reinterpret_cast<const float4 *>(p);
+            x[0] = v.x;
+            x[1] = v.y;
+            x[2] = v.z;
+            x[3] = v.w;
+        } else {
+            for (int e = 0; c + e < n; ++e) x[e] = p[e];
+        }
+    }
+    float amax = fmaxf(fmaxf(fabsf(x[0]), fabsf(x[1])), fmaxf(fabsf(x[2]), fabsf(x[3])));
+    amax = fmaxf(amax, __shfl_xor(amax, 1));
+    amax = fmaxf(amax, __shfl_xor(amax, 2));
+    amax = fmaxf(amax, __shfl_xor(amax, 4));
+    int j = 0;
+    if (amax > 0.f && isfinite(amax)) {
+        int ea;
+        const float fa = frexpf(amax, &ea);
+        j = fa <= 0.875f ? 9 - ea : 8 - ea;
+        j = j > 127 ? 127 : (j < -126 ? -126 : j);
+    }
+    const float sc = ldexpf(1.f, j);
+    unsigned w = __builtin_amdgcn_cvt_pk_fp8_f32(x[0] * sc, x[1] * sc, 0u, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(x[2] * sc, x[3] * sc, w, true);
+    if (!live) return;
+    if (c < n) {
+        uint8_t *q = dst + d * strided + row * ldd + c;
+        if (c + 3 < n) {
+            *reinterpret_cast<unsigned *>(q) = w;
+        } else {
+            for (int e = 0; c + e < n; ++e) q[e] = (uint8_t)(w >> (8 * e));
+        }
+    }
+    if (l == 0) bscale[g] = (uint8_t)(127 - j);
+}
+
 }  // namespace
+
+tsk_status tsk_stage_mx_enqueue(tsk_ctx c, const tsk_stack *s, void *dst, int64_t ldd, int64_t strided,
+                                uint8_t *bscale) {
+    const int64_t nbk = (s->n + 31) / 32;
+    const int64_t groups = s->count * s->m * nbk;
+    const int64_t blocks = (groups * 8 + 255) / 256;
+    TSK_LAUNCH(c, TSK_KERNEL_STAGE,
+               hipLaunchKernelGGL(stage_mx_kernel, dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                                  (const float *)s->A, s->m, s->n, s->ld, s->stride, s->count, (uint8_t *)dst, ldd,
+                                  strided, bscale, nbk));
+    return TSK_OK;
+}
 
 tsk_status tsk_stage_enqueue(tsk_ctx c, const tsk_stack *s, int dtype, void *dst, int64_t ldd, int64_t strided,
                              float *scale, double *norm2) {

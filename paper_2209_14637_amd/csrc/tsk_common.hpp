@@ -50,6 +50,14 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ v4f mfma16x16x128_e4m3(v8i a, v8i b, v4f c, int sa, int sb) {
     return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, sa, 0, sb);
 }
+// The same with per-lane scales taken from byte OA of sa and byte OB of sb:
+// lane (q, i) supplies the E8M0 scale of row i of A (column i of B) for the
+// MFMA's K block q, and K block g is bytes 0..15 of lane groups 2(g & 1)
+// and 2(g & 1) + 1 for g < 2, their bytes 16..31 for g >= 2 (measured).
+template <int OA, int OB>
+__device__ __forceinline__ v4f mfma16x16x128_e4m3_sel(v8i a, v8i b, v4f c, int sa, int sb) {
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, OA, sa, OB, sb);
+}
 // Two e4m3 bytes of w (bytes 0,1, or 2,3 when hi) to two bf16 packed in a
 // dword, multiplied by the power of two sc (exact: e4m3 values are bf16
 // values).

@@ -15,20 +15,20 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtsk.so")
 
 TSK_OK, TSK_E_ARG, TSK_E_SHAPE, TSK_E_NOMEM, TSK_E_DEVICE, TSK_E_NOCONV = range(6)
-TSK_F64, TSK_F32, TSK_BF16, TSK_F8E4M3 = range(4)
+TSK_F64, TSK_F32, TSK_BF16, TSK_F8E4M3, TSK_MXE4M3 = range(5)
 FLAG_RANKDEF, FLAG_TIE, FLAG_NONFIN = 1, 2, 4
 KERNELS = ["gram", "gram_reduce", "eig_iter", "eig_rr", "sketch", "qr", "project", "finish", "error", "stage"]
 
 _STATUS = {0: "TSK_OK", 1: "TSK_E_ARG", 2: "TSK_E_SHAPE", 3: "TSK_E_NOMEM", 4: "TSK_E_DEVICE",
            5: "TSK_E_NOCONV"}
 
-EXPORTS = ["tsk_create", "tsk_destroy", "tsk_set_stream", "tsk_last_error", "tsk_stage", "tsk_gram",
+EXPORTS = ["tsk_create", "tsk_destroy", "tsk_set_stream", "tsk_last_error", "tsk_stage", "tsk_stage_mx", "tsk_gram",
            "tsk_eig_topk", "tsk_train", "tsk_random_sketch", "tsk_apply", "tsk_apply_noalloc", "tsk_apply_multi",
            "tsk_apply_multi_plan", "tsk_plan_launch", "tsk_plan_destroy", "tsk_error", "tsk_opt_tail",
            "tsk_set_eig_params", "tsk_set_tuning", "tsk_train2", "tsk_apply2",
            "tsk_timing_enable", "tsk_timing_read"]
 
-_DTYPES = {"f32": TSK_F32, "bf16": TSK_BF16, "e4m3": TSK_F8E4M3}
+_DTYPES = {"f32": TSK_F32, "bf16": TSK_BF16, "e4m3": TSK_F8E4M3, "mxe4m3": TSK_MXE4M3}
 SKETCH_KINDS = {"gaussian": 0, "sign": 1, "sparse": 2}
 
 
@@ -70,6 +70,7 @@ def load(path: str | None = None):
         "tsk_set_stream": ([P, P], I32),
         "tsk_last_error": ([P], ctypes.c_char_p),
         "tsk_stage": ([P, sp, I32, P, I64, I64, P, P], I32),
+        "tsk_stage_mx": ([P, sp, P, I64, I64, P], I32),
         "tsk_gram": ([P, sp, I32, P], I32),
         "tsk_eig_topk": ([P, P, I64, I32, P, P, P], I32),
         "tsk_train": ([P, sp, I32, I32, P, P, P], I32),
@@ -99,8 +100,10 @@ def load(path: str | None = None):
 
 class Staged:
     """A stack in a reduced-precision storage format: `data` holds the raw
-    elements (torch.bfloat16 for bf16, torch.uint8 bytes for e4m3) as
-    (count, m, ld); `scale` is the per-slice e4m3 scale (None for bf16)."""
+    elements (torch.bfloat16 for bf16, torch.uint8 bytes for e4m3 and
+    mxe4m3) as (count, m, ld); `scale` is the per-slice e4m3 scale (float32),
+    the per-block exponents of mxe4m3 (uint8, (count, m, ceil(n / 32))), or
+    None for bf16."""
 
     def __init__(self, data: torch.Tensor, n: int, dtype: str, scale: torch.Tensor | None = None):
         self.data, self.n, self.dtype, self.scale = data, n, dtype, scale
@@ -199,8 +202,10 @@ class Context:
 
     # --- entry points -----------------------------------------------------
     def stage(self, A: torch.Tensor, dtype: str = "bf16", norm2: bool = False):
-        """Round an FP32 stack into a storage format ("bf16" or "e4m3");
-        returns a Staged stack (and ||A_d||^2 of the source when norm2)."""
+        """Round an FP32 stack into a storage format ("bf16", "e4m3", or
+        "mxe4m3": e4m3 with a scale per 32 elements of a row); returns a
+        Staged stack (and ||A_d||^2 of the source when norm2; not for
+        mxe4m3)."""
         self._sync_stream()
         s = _stack(A)
         if s.dtype != TSK_F32:
@@ -213,6 +218,12 @@ class Context:
         tdt = torch.bfloat16 if dtype == "bf16" else torch.uint8
         dev = A.device
         out = torch.empty((s.count, s.m, ld), dtype=tdt, device=dev)
+        if dtype == "mxe4m3":
+            if norm2:
+                raise ValueError("norm2 is not available for mxe4m3 staging")
+            bs = torch.empty((s.count, s.m, (s.n + 31) // 32), dtype=torch.uint8, device=dev)
+            self._check(self.lib.tsk_stage_mx(self.h, ctypes.byref(s), _ptr(out), ld, s.m * ld, _ptr(bs)))
+            return Staged(out, s.n, dtype, bs)
         scale = torch.empty(s.count, dtype=torch.float32, device=dev) if dtype == "e4m3" else None
         nrm = torch.empty(s.count, dtype=torch.float64, device=dev) if norm2 else None
         self._check(self.lib.tsk_stage(self.h, ctypes.byref(s), _DTYPES[dtype], _ptr(out), ld, s.m * ld,

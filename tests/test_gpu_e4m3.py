@@ -223,27 +223,30 @@ def t3full(ctx, orc):
     spec = synth.spec_fp8_1920()
     st = synth.Stream(spec)
     _say("generating 4000 training slices of 1920x1080 in 4 parts")
-    q8, b16 = [], []
+    q8, b16, mx = [], [], []
     for p in range(4):
         tr = dev32(st.slices(range(1 + 1000 * p, 1 + 1000 * (p + 1))))
         q8.append(ctx.stage(tr, "e4m3"))
         b16.append(ctx.stage(tr, "bf16"))
+        mx.append(ctx.stage(tr, "mxe4m3"))
         del tr
     Tq = tsk.Staged(torch.cat([x.data for x in q8]), spec.n, "e4m3", torch.cat([x.scale for x in q8]))
     Tb = tsk.Staged(torch.cat([x.data for x in b16]), spec.n, "bf16")
-    del q8, b16
+    Tm = tsk.Staged(torch.cat([x.data for x in mx]), spec.n, "mxe4m3", torch.cat([x.scale for x in mx]))
+    del q8, b16, mx
     S8, lam8, it8, _ = ctx.train(Tq, spec.k, compute="e4m3")
     S16, lam16, it16, _ = ctx.train(Tb, spec.k, compute="bf16")
-    del Tq, Tb
+    Smx, lammx, itmx, _ = ctx.train(Tm, spec.k, compute="mxe4m3")
+    del Tq, Tb, Tm
     torch.cuda.empty_cache()
     lam_orc = np.array(g["lambda"])
-    for nm, lam, it in (("e4m3", lam8, it8), ("bf16", lam16, it16)):
+    for nm, lam, it in (("e4m3", lam8, it8), ("bf16", lam16, it16), ("mxe4m3", lammx, itmx)):
         _say(f"  {nm} training: lambda rel dev {np.abs(np.array(lam) - lam_orc).max() / lam_orc[0]:.2e}, iters {it}")
     ref = np.array(g["relerr"])
     assert ref.size == spec.n_test
     _say("generating 1000 test matrices")
     te = st.test()
-    return spec, g, {"e4m3": S8, "bf16": S16}, te, ref
+    return spec, g, {"e4m3": S8, "bf16": S16, "mxe4m3": Smx}, te, ref
 
 
 def _t3_dev(ctx, orc, t3full, train, form):
@@ -296,4 +299,17 @@ def test_t3_e4m3_trained_full_size(ctx, orc, t3full, form):
     """The e4m3-trained sketch, gated at the same 1e-3 as every other form."""
     d, e_f, ev = _t3_dev(ctx, orc, t3full, "e4m3", form)
     _say(f"  e4m3 training / {form} apply: max |de|/e over {ev.size} matrices {d:.2e}")
+    assert d <= TAU_E4M3
+
+
+@pytest.mark.xfail(reason="block scales (one power of two per 32 elements of a row) leave e4m3's rounding error "
+                          "unchanged: a power-of-two scale moves values between binades, and the per-matrix "
+                          "scale already keeps them normal, so the MX-trained sketch misses 1e-3 like the "
+                          "e4m3-trained one", strict=False)
+def test_t3_mx_trained_full_size(ctx, orc, t3full):
+    """The sketch trained on block-scaled e4m3 slices (MX layout, 128 x 128
+    MFMA tiles with per-lane block scales), applied in bf16, gated at the
+    same 1e-3."""
+    d, e_f, ev = _t3_dev(ctx, orc, t3full, "mxe4m3", "bf16")
+    _say(f"  MX e4m3 training / bf16 apply: max |de|/e over {ev.size} matrices {d:.2e}")
     assert d <= TAU_E4M3

@@ -27,7 +27,8 @@
  * - One context per host thread; calls on one context must not overlap.
  */
 /*
- * Diagnostics (environment, read at each call): TSK_GRAM_TILE128 makes tsk_gram use
+ * Diagnostics (environment; TSK_PIPELINE_STREAMS is described at
+ * tsk_plan_launch, the others are read at each call): TSK_GRAM_TILE128 makes tsk_gram use
  * its 128 x 128-tile kernels for bf16 and e4m3 stacks (otherwise used only
  * for slices of 4 GiB and more); TSK_FAULT_NOMEM makes every workspace
  * allocation fail with TSK_E_NOMEM.  Both exist so tests can reach those
@@ -276,8 +277,10 @@ tsk_status tsk_apply_multi(tsk_ctx ctx, const tsk_problem *probs, int32_t nprobs
  * the context's stream.  The plan belongs to the context's device and must
  * be destroyed with tsk_plan_destroy.
  * tsk_plan_launch replays `nplans` plans (graph launches) after all work
- * enqueued on the context's stream; plans alternate between two
- * context-owned streams so consecutive batches overlap (each plan has its
+ * enqueued on the context's stream; plans go in turn to three
+ * context-owned streams (TSK_PIPELINE_STREAMS, 2..4, read when the context
+ * first needs them, overrides the number) so consecutive batches overlap
+ * (each plan has its
  * own workspace; plans whose outputs overlap must not be launched
  * together), and the context's stream waits for all of them.  Enqueue only. */
 typedef struct tsk_plan_s *tsk_plan;
@@ -360,8 +363,8 @@ tsk_status tsk_set_eig_params(tsk_ctx ctx, int32_t block, int32_t max_iter, doub
 /* Tuning of the apply for one shape class (m, n, ceil(k / 16), dtype of the
  * test stack), as chosen by an autotuner (paper_2209_14637_amd/autotune.py
  * times the candidates and keeps a JSON cache): groups = the number of
- * pipeline groups of tsk_apply (1..64; the groups alternate between two
- * context streams), pj_cols = columns per projection step of the bf16 form
+ * pipeline groups of tsk_apply (1..64; the groups go in turn to the
+ * context-owned streams of tsk_plan_launch), pj_cols = columns per projection step of the bf16 form
  * (64 or 128; also used by the batched forms).  0 restores the default
  * (groups: 1, the whole stack; pj_cols: 64).  Results do not
  * depend on either (bit for bit).  Host only. */

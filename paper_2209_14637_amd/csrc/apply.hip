@@ -1995,7 +1995,7 @@ static int64_t apply_group(tsk_ctx c, const tsk_stack *s, int k) {
 
 // tsk_apply: the whole stack on the context's workspace (grown on demand).
 // With groups smaller than the stack, the groups alternate between the
-// context's two pipeline streams (forked from and joined back into the
+// context's pipeline streams in turn (forked from and joined back into the
 // caller's stream), so one group's small per-matrix kernels overlap the
 // streaming kernels of the next.
 tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *s, int r, float *L, float *R,
@@ -2010,7 +2010,7 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
     hipStream_t main = c->stream;
     TSK_TRY(apply_prep(c, S, k, s, ws));
     hipError_t e = hipEventRecord(c->pl_fork, main);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->pl[i], c->pl_fork, 0);
+    for (int i = 0; i < c->npl && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->pl[i], c->pl_fork, 0);
     if (e != hipSuccess) return tsk_hip(c, e, "pipeline fork");
     const size_t es = s->dtype == TSK_F32 ? 4 : s->dtype == TSK_BF16 ? 2 : 1;
     tsk_status st = TSK_OK;
@@ -2020,13 +2020,13 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
         sub.count = std::min(g, s->count - d0);
         sub.A = (const char *)s->A + (size_t)d0 * s->stride * es;
         if (s->scale) sub.scale = s->scale + d0;
-        c->stream = c->pl[j & 1];
+        c->stream = c->pl[j % c->npl];
         st = apply_ws(c, S, k, &sub, r, L + d0 * s->m * r, R + d0 * s->n * r, sigma + d0 * r,
                       relerr ? relerr + d0 : nullptr, flags ? flags + d0 : nullptr, ws_from(ws, s, k, d0), false);
     }
     c->stream = main;
     e = hipSuccess;
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    for (int i = 0; i < c->npl && e == hipSuccess; ++i) {
         e = hipEventRecord(c->pl_join[i], c->pl[i]);
         if (e == hipSuccess) e = hipStreamWaitEvent(main, c->pl_join[i], 0);
     }
@@ -2389,7 +2389,7 @@ static tsk_status multi_launch(tsk_ctx c, const MultiTables &T, const ApDesc *P,
 // Captured batches (tsk_plan): a batch's tables and workspace live in
 // plan-owned device memory, written once, and its launch sequence is
 // captured into a HIP graph; a launch replays the graph.  Plans launched
-// together alternate between the context's two pipeline streams, so one
+// together go to the context's pipeline streams in turn (three by default), so one
 // batch's per-matrix kernels overlap the next batch's streaming kernels
 // (each plan has its own workspace).
 // ---------------------------------------------------------------------------
@@ -2474,9 +2474,9 @@ tsk_status tsk_plan_launch_enqueue(tsk_ctx c, const tsk_plan *plans, int n) {
             return tsk_fail(c, TSK_E_ARG, "tsk_plan_launch: plan " + std::to_string(i) + " is not a plan of this device");
     TSK_TRY(tsk_pipeline_streams(c));
     hipError_t e = hipEventRecord(c->pl_fork, c->stream);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->pl[i], c->pl_fork, 0);
-    for (int i = 0; i < n && e == hipSuccess; ++i) e = hipGraphLaunch(plans[i]->exec, c->pl[i & 1]);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    for (int i = 0; i < c->npl && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->pl[i], c->pl_fork, 0);
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = hipGraphLaunch(plans[i]->exec, c->pl[i % c->npl]);
+    for (int i = 0; i < c->npl && e == hipSuccess; ++i) {
         e = hipEventRecord(c->pl_join[i], c->pl[i]);
         if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->pl_join[i], 0);
     }

@@ -65,14 +65,21 @@ tsk_status tsk_grow(tsk_ctx c, TskBuf &b, size_t bytes) {
 
 // The context's two pipeline streams and their fork / join events (created
 // on first use, on the context's device, default priority).
+// TSK_PIPELINE_STREAMS (diagnostic, read when the streams are created): their
+// number, 2..TSK_MAX_PIPE (default TSK_DEFAULT_PIPE).
 tsk_status tsk_pipeline_streams(tsk_ctx c) {
     if (c->pl[0]) return TSK_OK;
+    int np = TSK_DEFAULT_PIPE;
+    if (const char *v = getenv("TSK_PIPELINE_STREAMS")) np = atoi(v);
+    np = np < 2 ? 2 : (np > TSK_MAX_PIPE ? TSK_MAX_PIPE : np);
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&c->pl[i], hipStreamNonBlocking);
+    for (int i = 0; i < np && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&c->pl[i], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->pl_fork, hipEventDisableTiming);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&c->pl_join[i], hipEventDisableTiming);
+    for (int i = 0; i < np && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&c->pl_join[i], hipEventDisableTiming);
+    c->npl = np;
     if (e != hipSuccess) {
-        for (int i = 0; i < 2; ++i) {
+        c->npl = 0;
+        for (int i = 0; i < TSK_MAX_PIPE; ++i) {
             if (c->pl[i]) (void)hipStreamDestroy(c->pl[i]);
             if (c->pl_join[i]) (void)hipEventDestroy(c->pl_join[i]);
             c->pl[i] = nullptr;
@@ -274,7 +281,7 @@ void tsk_destroy(tsk_ctx c) {
     if (c->mp_pin) (void)hipHostFree(c->mp_pin);
     if (c->mp_ev) (void)hipEventDestroy(c->mp_ev);
     if (c->switch_ev) (void)hipEventDestroy(c->switch_ev);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < TSK_MAX_PIPE; ++i) {
         if (c->pl[i]) (void)hipStreamDestroy(c->pl[i]);
         if (c->pl_join[i]) (void)hipEventDestroy(c->pl_join[i]);
     }

@@ -568,6 +568,14 @@ struct TskEvent {
     hipEvent_t a, b;
 };
 
+// Pipeline streams.  HIP maps streams onto a few hardware queues (four by
+// default), and the caller's stream takes one: with three pipeline streams
+// every stream has a queue of its own.  On the 8-stream batch (8 captured
+// plans of 256 matrices) two streams gave 326k matrices/s, three 386k and
+// four 324k (two of them then share a queue).
+constexpr int TSK_MAX_PIPE = 4;      // pipeline streams at most
+constexpr int TSK_DEFAULT_PIPE = 3;  // pipeline streams by default
+
 struct tsk_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -587,10 +595,12 @@ struct tsk_ctx_s {
     size_t mp_pin_bytes = 0;
     hipEvent_t mp_ev = nullptr;      // recorded after the last batch table copy
     hipEvent_t switch_ev = nullptr;  // orders the old stream before a new one (tsk_set_stream)
-    // pipelined apply: two context-owned streams (default priority), forked
-    // from and joined back into the caller's stream
-    hipStream_t pl[2] = {nullptr, nullptr};
-    hipEvent_t pl_fork = nullptr, pl_join[2] = {nullptr, nullptr};
+    // pipelined apply and plan launches: npl (2..TSK_MAX_PIPE) context-owned
+    // streams (default priority), forked from and joined back into the
+    // caller's stream
+    hipStream_t pl[TSK_MAX_PIPE] = {};
+    hipEvent_t pl_fork = nullptr, pl_join[TSK_MAX_PIPE] = {};
+    int npl = 0;
     // tuning entries by shape class (m, n, kp, dtype)
     std::map<std::tuple<int64_t, int64_t, int, int>, TskTune> tune;
     // eigensolver controls

@@ -448,16 +448,20 @@ __device__ __forceinline__ v4u bytemask16(int nb) {
     return k;
 }
 
-// C_d = A_d B_d^T through LDS.  A workgroup (4 waves) takes 128 rows of one
-// matrix; wave w computes rows 32w .. 32w+31 (two row tiles) against all kp
-// columns.  Each step covers K columns: the workgroup reads the 128 row
+// C_d = A_d B_d^T through LDS.  A workgroup (4 waves) takes PJL_ROWS = 192
+// rows of one matrix; wave w computes rows 48w .. 48w+47 (PJL_RT = 3 row
+// tiles) against all kp columns (on 1000 bf16 matrices of 1920 x 1080 at
+// k = 40: 128-row bands 3.22 ms per apply, 192 rows 3.11, 256 rows 3.16;
+// the projection itself barely changes, the eig kernel adds fewer band
+// partials).  Each step covers K columns: the workgroup reads the 128 row
 // segments of A and the 2kp row segments of the B pair with coalesced
 // 16-byte loads, keeps them in registers while the previous step's MFMAs
 // run, and stores them into LDS; the waves read their MFMA operands from
 // there (lane (q, i): 8 consecutive columns of row i of a tile).  Rows past
 // m and columns past n enter as zeros; B is read only up to its padded
 // width ldv (its columns n .. ldv-1 are zero).
-constexpr int PJL_ROWS = 128;
+constexpr int PJL_RT = 3;                 // row tiles of 16 per wave
+constexpr int PJL_ROWS = 4 * 16 * PJL_RT; // rows per workgroup (4 waves)
 constexpr int PJL_THREADS = 256;
 __host__ __device__ constexpr int pjl_lds_bytes(int K, int eb, int kp) {
     return PJL_ROWS * (K * eb + 16) + 2 * kp * (2 * K + 16);
@@ -502,9 +506,9 @@ __device__ __forceinline__ void project_lds_body(const ET *A, const float *__res
     const int ca = tid % CPA, ra0 = tid / CPA;
     const int cb = tid % CPB, rb0 = tid / CPB;
     const int64_t nst = (n + K - 1) / K;
-    v4f acc[2][NT];
+    v4f acc[PJL_RT][NT];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < PJL_RT; ++t)
 #pragma unroll
         for (int b = 0; b < NT; ++b) acc[t][b] = v4f{0.f, 0.f, 0.f, 0.f};
     // fetch issues the loads of a step, unconditionally and in range: rows
@@ -560,10 +564,10 @@ __device__ __forceinline__ void project_lds_body(const ET *A, const float *__res
         fetch(more ? c0 + K : c0, sa, sb);
 #pragma unroll
         for (int kb = 0; kb < K / 32; ++kb) {  // (columns past n are zeros)
-            v4u xa[2], vh[NT], vl[NT];
+            v4u xa[PJL_RT], vh[NT], vl[NT];
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const unsigned char *p = la + (32 * w + 16 * t + ii) * RA + (kb * 32 + 8 * q) * EB;
+            for (int t = 0; t < PJL_RT; ++t) {
+                const unsigned char *p = la + (16 * PJL_RT * w + 16 * t + ii) * RA + (kb * 32 + 8 * q) * EB;
                 if constexpr (EB == 2)
                     xa[t] = *reinterpret_cast<const v4u *>(p);
                 else
@@ -575,11 +579,11 @@ __device__ __forceinline__ void project_lds_body(const ET *A, const float *__res
                 vl[b] = *reinterpret_cast<const v4u *>(lb + (kp + 16 * b + ii) * RB + (kb * 32 + 8 * q) * 2);
             }
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
+            for (int t = 0; t < PJL_RT; ++t)
 #pragma unroll
                 for (int b = 0; b < NT; ++b) acc[t][b] = mfma16x16x32_bf16(xa[t], vh[b], acc[t][b]);
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
+            for (int t = 0; t < PJL_RT; ++t)
 #pragma unroll
                 for (int b = 0; b < NT; ++b) acc[t][b] = mfma16x16x32_bf16(xa[t], vl[b], acc[t][b]);
         }
@@ -591,10 +595,10 @@ __device__ __forceinline__ void project_lds_body(const ET *A, const float *__res
     }
     float *Cd = C + d * m * kp;
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < PJL_RT; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int64_t row = r0 + 32 * w + 16 * t + 4 * q + r;
+            const int64_t row = r0 + 16 * PJL_RT * w + 16 * t + 4 * q + r;
             if (row < m) {
 #pragma unroll
                 for (int b = 0; b < NT; ++b) Cd[row * kp + b * 16 + ii] = acc[t][b][r];
@@ -606,7 +610,7 @@ __device__ __forceinline__ void project_lds_body(const ET *A, const float *__res
 #pragma unroll
         for (int p = 0; p < NPAIR; ++p) g[p] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
+        for (int t = 0; t < PJL_RT; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 double xv[NT];

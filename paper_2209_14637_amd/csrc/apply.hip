@@ -777,20 +777,43 @@ __device__ inline void small_mm(const double *X, const double *M, double *Y) {
 // triangular (KP x KP, FP64 in LDS, zeros below the diagonal):
 //     M[a][j] = sum_{u <= a} X[u][a] M[u][j]   (FP64 products and sums).
 // Chunks of 64 columns are staged in LDS (Ms, KP x MS_LD FP32) by
-// coalesced loads; wave w computes the chunk's columns 16w .. 16w+15 for
-// every 16-row tile by FP64 MFMA 16x16x4 (A = X^T, B = the staged columns;
-// K-steps past the tile's last row are skipped, X being zero there) and
-// writes them back in place.  P (bf16 and e4m3 forms, else null): also the
-// bf16 pair (hi, lo) of each value (hi rows 0..KP-1, lo rows KP..2KP-1),
-// with M := hi + lo.
-constexpr int MS_LD = 68;  // padded LDS row of the staged chunk (floats)
+// coalesced 16-byte loads, the next chunk's loads in flight (registers)
+// while the current chunk is transformed (staging one chunk at a time left
+// every chunk waiting for its loads: 0.24 of the 0.45 ms the basis took on
+// 1000 matrices of 1920 x 1080 at k = 40); wave w computes the chunk's
+// columns 16w .. 16w+15 for every 16-row tile by FP64 MFMA 16x16x4 (A =
+// X^T, B = the staged columns; K-steps past the tile's last row are
+// skipped, X being zero there) and writes them back in place (the next
+// chunk's columns are disjoint).  P (bf16 and e4m3 forms, else null): also
+// the bf16 pair (hi, lo) of each value (hi rows 0..KP-1, lo rows
+// KP..2KP-1), with M := hi + lo.
+constexpr int MS_LD = 68;  // padded LDS row of the staged chunk (floats; 16-byte rows)
 template <int KP>
 __device__ __forceinline__ void tri_transform(const double *X, float *M, int64_t ldb, uint16_t *P, float *Ms) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int q = lane >> 4, ii = lane & 15;
+    constexpr int NL = KP / 16;  // 16-byte loads per thread per chunk (KP rows x 16 of them)
+    float4 nx[NL];
+    auto load = [&](int64_t j0) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = tid + 256 * i;
+            nx[i] = *reinterpret_cast<const float4 *>(M + (int64_t)(e >> 4) * ldb + j0 + 4 * (e & 15));
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = tid + 256 * i;
+            *reinterpret_cast<float4 *>(Ms + (e >> 4) * MS_LD + 4 * (e & 15)) = nx[i];
+        }
+    };
+    load(0);
+    stash();
+    __syncthreads();
     for (int64_t j0 = 0; j0 < ldb; j0 += 64) {
-        for (int e = tid; e < KP * 64; e += 256) Ms[(e >> 6) * MS_LD + (e & 63)] = M[(e >> 6) * ldb + j0 + (e & 63)];
-        __syncthreads();
+        const bool more = j0 + 64 < ldb;
+        if (more) load(j0 + 64);
         for (int ta = 0; ta < KP / 16; ++ta) {
             v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
@@ -818,6 +841,10 @@ __device__ __forceinline__ void tri_transform(const double *X, float *M, int64_t
             }
         }
         __syncthreads();
+        if (more) {
+            stash();
+            __syncthreads();
+        }
     }
 }
 

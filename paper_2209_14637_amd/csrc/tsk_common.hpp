@@ -156,7 +156,9 @@ __device__ __forceinline__ void jacobi_rot(const double *H, int ld, int a, int b
     const double haa = H[a * ld + a], hbb = H[b * ld + b], hab = H[a * ld + b];
     c = 1.0;
     s = 0.0;
-    if (hab != 0.0 && fabs(hab) > 1e-18 * sqrt(fabs(haa * hbb))) {
+    // |hab| > 1e-18 sqrt(|haa hbb|), compared squared (no square root on the
+    // round's critical path)
+    if (hab != 0.0 && hab * hab > 1e-36 * fabs(haa * hbb)) {
         // t from the hardware estimates (an angle that is slightly off still
         // shrinks H[a][b] by the estimates' relative error, so the sweeps
         // converge); c refined so that c^2 + s^2 = 1 to rounding
@@ -291,8 +293,9 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
                 *reinterpret_cast<double2 *>(rot + 2 * tid) = double2{cc, ss};
             }
             __syncthreads();
-            // blocks: gather (unused slots read block (0, 0): in bounds,
-            // never stored), then compute and write
+            // gather the blocks' entries (unused slots read block (0, 0): in
+            // bounds, never stored) and the W items' rows together, so the
+            // round waits for one set of LDS reads; then compute and write
             double hv[MAXB][4], rv[MAXB][4];
 #pragma unroll
             for (int u = 0; u < MAXB; ++u) {
@@ -304,6 +307,14 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
                 rv[u][2] = rq.x; rv[u][3] = rq.y;
                 hv[u][0] = H[a * ld + x]; hv[u][1] = H[a * ld + y];
                 hv[u][2] = H[b * ld + x]; hv[u][3] = H[b * ld + y];
+            }
+            double2 w0v[MAXW], w1v[MAXW], wr[MAXW];
+#pragma unroll
+            for (int u = 0; u < MAXW; ++u) {
+                if (u >= nwu) break;
+                wr[u] = *reinterpret_cast<const double2 *>(rot + 2 * wQ[u]);
+                w0v[u] = *reinterpret_cast<const double2 *>(Wt + wX[u] * ld + wI[u]);
+                w1v[u] = *reinterpret_cast<const double2 *>(Wt + wY[u] * ld + wI[u]);
             }
 #pragma unroll
             for (int u = 0; u < MAXB; ++u) {
@@ -328,15 +339,7 @@ __device__ inline void jacobi_eig_wg(double *H, double *Wt, int p, int ld, doubl
                     }
                 }
             }
-            // W items: gather, compute, write (two adjacent entries of each row)
-            double2 w0v[MAXW], w1v[MAXW], wr[MAXW];
-#pragma unroll
-            for (int u = 0; u < MAXW; ++u) {
-                if (u >= nwu) break;
-                wr[u] = *reinterpret_cast<const double2 *>(rot + 2 * wQ[u]);
-                w0v[u] = *reinterpret_cast<const double2 *>(Wt + wX[u] * ld + wI[u]);
-                w1v[u] = *reinterpret_cast<const double2 *>(Wt + wY[u] * ld + wI[u]);
-            }
+            // W items: compute, write (two adjacent entries of each row)
 #pragma unroll
             for (int u = 0; u < MAXW; ++u) {
                 if (u >= nwu) break;

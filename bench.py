@@ -340,6 +340,37 @@ def run(args):
     rec_extra["metric_4_1"] = {"matrices": int(nm), "mean": float(met.mean()), "max": float(met.max()),
                                "note": "(||A - A_hat|| - ||A - [A]_r||) / ||A - [A]_r|| with [A]_r from tsk_opt_tail "
                                        "on the FP32 test matrices", "opt_tail_seconds": t_opt}
+    g2path = os.path.join(ROOT, "tests", "golden", "hsi_twosided_k20_l20_r10.json")
+    if wl == "hsi_fp32" and os.path.exists(g2path):
+        # the two-sided method (Section 3.2, Algorithms 3-5) on the same
+        # stream, k = l = 20: Tucker2 training by HOOI and two-sided SCW,
+        # timed, every test error against the oracle's stored values
+        g2 = json.load(open(g2path))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S2, W2, core2, sweeps = ctx.train2(train_in, k, g2["l"])
+        torch.cuda.synchronize()
+        t_tr2 = (time.perf_counter() - t0) * 1e3
+        o2 = ctx.apply2(S2, W2, test_in, r)
+        tt = []
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.apply2(S2, W2, test_in, r, out=o2)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tt.append(e0.elapsed_time(e1))
+        e2 = ctx.error(te, o2["L"], o2["R"]).cpu().numpy()
+        ref2 = np.array(g2["relerr"])
+        dev2 = float(np.max(np.abs(e2[:ref2.size] - ref2) / ref2))
+        rec_extra["twosided"] = {"k": k, "l": g2["l"], "r": r, "train_ms": t_tr2, "hooi_sweeps": int(sweeps),
+                                 "apply_ms": float(np.median(tt)),
+                                 "matrices_per_s": spec.n_test / (float(np.median(tt)) / 1e3),
+                                 "mean_error": float(e2.mean()), "one_sided_mean_error": float(e_tr.mean()),
+                                 "max_rel_dev_explicit_error": dev2, "matrices": int(ref2.size),
+                                 "pass_1e-5": bool(dev2 <= TAU["f32"])}
+        del o2
 
     apply_med = float(np.median(apply_ms))
     value = spec.n_test / (apply_med / 1e3)

@@ -303,3 +303,29 @@ def test_gram_tile128_integer_exact(ctx, orc, fmt, shape):
     finally:
         del os.environ["TSK_GRAM_TILE128"]
     assert np.array_equal(G.cpu().numpy(), orc.gram(a))
+
+
+# --------------------------------------------------------------------------
+# Empty inputs: a stack with no slices (or no rows / columns) is refused with
+# TSK_E_SHAPE before anything is launched, by every entry point that takes one
+# --------------------------------------------------------------------------
+def test_empty_stacks_refused(ctx):
+    from paper_2209_14637_amd import tsk
+    lib = ctx.lib
+    buf = torch.zeros((4, 64, 48), dtype=torch.float32, device="cuda")
+    S = torch.from_numpy(np.eye(8, 64, dtype=np.float32)).cuda()
+    G = torch.empty((64, 64), dtype=torch.float64, device="cuda")
+    out = torch.empty(4096, dtype=torch.float32, device="cuda")
+    for field, val in (("count", 0), ("m", 0), ("n", 0)):
+        s = tsk._stack(buf)
+        setattr(s, field, val)
+        assert lib.tsk_gram(ctx.h, tsk.ctypes.byref(s), tsk.TSK_F32, tsk._ptr(G)) == tsk.TSK_E_SHAPE, field
+        st = lib.tsk_apply(ctx.h, tsk._ptr(S), 8, tsk.ctypes.byref(s), 4, tsk.TSK_F32, tsk._ptr(out),
+                           tsk._ptr(out), tsk._ptr(out), None, None)
+        assert st == tsk.TSK_E_SHAPE, field
+        st = lib.tsk_stage(ctx.h, tsk.ctypes.byref(s), tsk.TSK_BF16, tsk._ptr(out), 64, 64 * 64, None, None)
+        assert st == tsk.TSK_E_SHAPE, field
+    # the context still works
+    o = ctx.apply(S, buf + 1.0, 4)
+    torch.cuda.synchronize()
+    assert np.isfinite(o["relerr"].cpu().numpy()).all()

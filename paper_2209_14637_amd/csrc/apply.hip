@@ -48,13 +48,24 @@ constexpr int SK_PANEL = 64;   // columns of A_d per sketch workgroup (one wave)
 constexpr int PJ_ROWS = 64;    // rows of A_d per project workgroup (one wave)
 constexpr int MAXK = 64;
 
-// St (m x kp) = S^T with zero columns k..kp-1
-__device__ __forceinline__ void transpose_sketch_body(const float *__restrict__ S, int k, int kp, int64_t m,
-                                        float *__restrict__ St, int64_t e) {
-    if (e >= m * kp) return;
-    const int64_t i = e / kp;
-    const int s = (int)(e % kp);
-    St[e] = s < k ? S[(int64_t)s * m + i] : 0.f;
+// The FP32 sketch in the order the FP32 sketch kernel's MFMA lanes read it
+// (mp = m rounded up to 32, zeros past k and m): for 16-row block R of the
+// rows of A_d and 16-row tile a of S, lane 16q + j holds the four values
+// S[16a + j][16R + 4u + q], u = 0..3, at ((R kp/16 + a) 64 + lane) 4 + u, so
+// one 16-byte load per lane (one 1 KB piece per instruction) serves four
+// row groups.  (S^T read one value per lane per row group took 28% of the
+// kernel's time on 400 matrices of 1024 x 768.)
+__device__ __forceinline__ void prep_sketch_f32_body(const float *__restrict__ S, int k, int kp, int64_t m,
+                                                     int64_t mp, float *__restrict__ St, int64_t e) {
+    if (e >= (int64_t)kp * mp) return;
+    const int u = (int)(e & 3), lane = (int)((e >> 2) & 63);
+    const int64_t t = e >> 8;  // R kp/16 + a
+    const int mt = kp / 16;
+    const int a = (int)(t % mt);
+    const int64_t R = t / mt;
+    const int srow = 16 * a + (lane & 15);
+    const int64_t col = 16 * R + 4 * u + (lane >> 4);
+    St[e] = (srow < k && col < m) ? S[(int64_t)srow * m + col] : 0.f;
 }
 
 template <int MT>
@@ -75,8 +86,16 @@ __device__ __forceinline__ void sketch_f32_body(const float *__restrict__ A, int
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[a][t] = v4f{0.f, 0.f, 0.f, 0.f};
     double fro = 0.0;
-    constexpr int U = 8;  // row groups of 4 in flight
+    constexpr int U = 8;  // row groups of 4 in flight (two 16-row blocks)
     for (int64_t i0 = 0; i0 < m; i0 += 4 * U) {
+        // this step's S values: 16-row blocks i0 / 16 and i0 / 16 + 1 (St holds
+        // m rounded up to 32 rows, so both exist)
+        float4 sv[2][MT];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int a = 0; a < MT; ++a)
+                sv[h][a] = *reinterpret_cast<const float4 *>(St + (((i0 / 16 + h) * MT + a) * 64 + lane) * 4);
         float4 x[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -100,7 +119,10 @@ __device__ __forceinline__ void sketch_f32_body(const float *__restrict__ A, int
                    (double)x[u].w * x[u].w;
             float s[MT];
 #pragma unroll
-            for (int a = 0; a < MT; ++a) s[a] = row < m ? St[row * kp + a * 16 + jj] : 0.f;
+            for (int a = 0; a < MT; ++a) {
+                const float4 &v = sv[u >> 2][a];
+                s[a] = (u & 3) == 0 ? v.x : (u & 3) == 1 ? v.y : (u & 3) == 2 ? v.z : v.w;
+            }
 #pragma unroll
             for (int a = 0; a < MT; ++a) {
                 acc[a][0] = mfma16x16x4_f32(s[a], x[u].x, acc[a][0]);
@@ -1177,9 +1199,9 @@ struct ApDesc {
     int32_t *flags;
 };
 
-__global__ void transpose_sketch_kernel(const float *__restrict__ S, int k, int kp, int64_t m,
-                                        float *__restrict__ St) {
-    transpose_sketch_body(S, k, kp, m, St, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void prep_sketch_f32_kernel(const float *__restrict__ S, int k, int kp, int64_t m, int64_t mp,
+                                      float *__restrict__ St) {
+    prep_sketch_f32_body(S, k, kp, m, mp, St, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 __global__ void prep_sketch_bf16_kernel(const float *__restrict__ S, int k, int kp, int64_t m, int64_t mp,
                                         uint16_t *__restrict__ Sb) {
@@ -1298,7 +1320,7 @@ __global__ void prep_multi_kernel(const ApDesc *__restrict__ P, const int4 *__re
     if (lowp)
         prep_sketch_bf16_body(D.S, D.k, D.kp, D.m, D.mp, D.Sb, e);
     else
-        transpose_sketch_body(D.S, D.k, D.kp, D.m, D.St, e);
+        prep_sketch_f32_body(D.S, D.k, D.kp, D.m, D.mp, D.St, e);
 }
 template <int MT>
 __global__ __launch_bounds__(64) void sketch_f32_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
@@ -1790,7 +1812,7 @@ static ApLayout apply_layout(const tsk_stack *s, int k, int64_t count) {
     const int npair = (kp / 16) * (kp / 16 + 1) / 2;
     const int nbands = (int)((m + RF_ROWS - 1) / RF_ROWS);
     const size_t sz[AP_REGIONS] = {
-        lowp ? sizeof(uint16_t) * 2 * kp * mp : sizeof(float) * m * kp,
+        lowp ? sizeof(uint16_t) * 2 * kp * mp : sizeof(float) * mp * kp,
         sizeof(float) * count * kp * ldv,
         lowp ? sizeof(uint16_t) * count * 2 * kp * ldv : 0,
         sizeof(float) * count * m * kp,
@@ -1888,8 +1910,8 @@ static tsk_status apply_f32_ws(tsk_ctx c, const float *S, int k, const tsk_stack
     const float *A = (const float *)s->A;
     if (prep)
         TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
-                   hipLaunchKernelGGL(transpose_sketch_kernel, dim3((unsigned)((m * kp + 255) / 256)), dim3(256), 0,
-                                      c->stream, S, k, kp, m, St));
+                   hipLaunchKernelGGL(prep_sketch_f32_kernel, dim3((unsigned)((kp * ((m + 31) / 32 * 32) + 255) / 256)),
+                                      dim3(256), 0, c->stream, S, k, kp, m, (m + 31) / 32 * 32, St));
     const dim3 gs((unsigned)npanel, (unsigned)count);
 #define TSK_SK(MTV)                                                                                             \
     TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                            \
@@ -1960,14 +1982,15 @@ static tsk_status apply_lowp_ws(tsk_ctx c, const float *S, int k, const tsk_stac
     return finish_enqueue(c, s, kp, B, ldv, Cm, k, r, fro, npanel, L, R, sigma, relerr, flags, ctc, w);
 }
 
-// The prepared sketch alone (what apply_ws launches first when prep is set).
-static tsk_status apply_prep(tsk_ctx c, const float *S, int k, const tsk_stack *s, const ApWs &ws) {
+// The prepared sketch alone (what apply_ws launches first when prep is set),
+// for sketch kernels of padded size kp >= ceil16(k) (the two-sided apply
+// pads S to the size of the larger of its two sketches).
+static tsk_status apply_prep(tsk_ctx c, const float *S, int k, int kp, const tsk_stack *s, const ApWs &ws) {
     const int64_t m = s->m;
-    const int kp = (k + 15) / 16 * 16;
     if (s->dtype == TSK_F32) {
         TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
-                   hipLaunchKernelGGL(transpose_sketch_kernel, dim3((unsigned)((m * kp + 255) / 256)), dim3(256), 0,
-                                      c->stream, S, k, kp, m, ws.St));
+                   hipLaunchKernelGGL(prep_sketch_f32_kernel, dim3((unsigned)((kp * ((m + 31) / 32 * 32) + 255) / 256)),
+                                      dim3(256), 0, c->stream, S, k, kp, m, (m + 31) / 32 * 32, ws.St));
     } else {
         const int64_t mp = (m + 31) / 32 * 32;
         TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
@@ -2039,7 +2062,7 @@ tsk_status tsk_apply_enqueue(tsk_ctx c, const float *S, int k, const tsk_stack *
     TSK_TRY(tsk_pipeline_streams(c));
     // the sketch is prepared once, on the caller's stream, then the fork
     hipStream_t main = c->stream;
-    TSK_TRY(apply_prep(c, S, k, s, ws));
+    TSK_TRY(apply_prep(c, S, k, (k + 15) / 16 * 16, s, ws));
     hipError_t e = hipEventRecord(c->pl_fork, main);
     for (int i = 0; i < c->npl && e == hipSuccess; ++i) e = hipStreamWaitEvent(c->pl[i], c->pl_fork, 0);
     if (e != hipSuccess) return tsk_hip(c, e, "pipeline fork");
@@ -2201,7 +2224,7 @@ static void multi_build(tsk_ctx c, const tsk_problem *pr, int np, int compute, M
         D.flags = pr[i].flags;
         D.rf_nb = (int)((A.m + RF_ROWS - 1) / RF_ROWS);
         D.rf_thr = lowp ? RF_THR_LOWP : RF_THR_F32;
-        const size_t sz[NREG] = {lowp ? sizeof(uint16_t) * 2 * D.kp * D.mp : sizeof(float) * D.m * D.kp,
+        const size_t sz[NREG] = {lowp ? sizeof(uint16_t) * 2 * D.kp * D.mp : sizeof(float) * D.mp * D.kp,
                                  sizeof(float) * D.count * D.kp * D.ldv,
                                  lowp ? sizeof(uint16_t) * D.count * 2 * D.kp * D.ldv : 0,
                                  sizeof(float) * D.count * D.m * D.kp,
@@ -2228,7 +2251,7 @@ static void multi_build(tsk_ctx c, const tsk_problem *pr, int np, int compute, M
     std::vector<int4> &items = T.items;
     items.clear();
     for (int i : order) {  // preparation of each sketch
-        const int64_t tot = lowp ? (int64_t)desc[i].kp * desc[i].mp : desc[i].m * desc[i].kp;
+        const int64_t tot = (int64_t)desc[i].kp * desc[i].mp;
         for (int64_t b = 0; b < (tot + 255) / 256; ++b) items.push_back(int4{i, (int)b, 0, 0});
     }
     T.n_prep = items.size();
@@ -2614,7 +2637,7 @@ tsk_status tsk_apply2_enqueue(tsk_ctx c, const float *S, int k, const float *W, 
     float *Zl = (float *)(b2 + szC1 + szBw + szBwb), *Zr = (float *)(b2 + szC1 + szBw + szBwb + szZ);
     // sketch, basis and C2 = A V: the one-sided launches up to the
     // projection (S has k live rows of KP)
-    TSK_TRY(apply_prep(c, S, k, s, ws));
+    TSK_TRY(apply_prep(c, S, k, KP, s, ws));
     const ApSmall &w = ws.w;
     const dim3 gs((unsigned)npanel, (unsigned)count);
     if (!lowp) {
@@ -2732,7 +2755,7 @@ tsk_status tsk_train2_enqueue(tsk_ctx c, const tsk_stack *s, int k, int l, int m
     const size_t szG = al(sizeof(double) * std::max(m, n) * std::max(m, n));
     const size_t szT = al(sizeof(float) * count * n * ldt);
     const size_t szBw = al(sizeof(float) * count * KPW * ldv), szC = al(sizeof(float) * count * m * KPW);
-    const size_t szB = al(sizeof(float) * count * KPS * ldv), szSt = al(sizeof(float) * m * KPS);
+    const size_t szB = al(sizeof(float) * count * KPS * ldv), szSt = al(sizeof(float) * ((m + 31) / 32 * 32) * KPS);
     const size_t szF = al(sizeof(double) * count * npanel);
     TSK_TRY(tsk_grow(c, c->t2_ws, szG + szT + szBw + szC + szB + szSt + szF));
     char *b = (char *)c->t2_ws.p;
@@ -2794,8 +2817,8 @@ tsk_status tsk_train2_enqueue(tsk_ctx c, const tsk_stack *s, int k, int l, int m
         TSK_TRY(eig_top(m, k, S, nullptr));
         // mode 2: B_d = S A_d (KPS x n), transposed, their Gram, top-l
         TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
-                   hipLaunchKernelGGL(transpose_sketch_kernel, dim3((unsigned)((m * KPS + 255) / 256)), dim3(256), 0,
-                                      c->stream, (const float *)S, k, KPS, m, St));
+                   hipLaunchKernelGGL(prep_sketch_f32_kernel, dim3((unsigned)((KPS * ((m + 31) / 32 * 32) + 255) / 256)),
+                                      dim3(256), 0, c->stream, (const float *)S, k, KPS, m, (m + 31) / 32 * 32, St));
         const dim3 gs((unsigned)npanel, (unsigned)count);
 #define TSK_SKT(MTV)                                                                                            \
     TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                            \

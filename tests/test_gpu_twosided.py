@@ -73,10 +73,13 @@ def test_train2_small(ctx, orc, small):
     assert np.max(np.abs(e - ref) / ref) <= 1e-4
 
 
+# (10, 20): W's sketch tile (32 rows) is larger than S's (16), so S is padded
+# to the larger tile for the shared kernels
+@pytest.mark.parametrize("kl", [(14, 12), (10, 20)])
 @pytest.mark.parametrize("fmt", ["f32", "bf16", "e4m3"])
-def test_apply2_with_oracle_sketches(ctx, orc, small, fmt):
+def test_apply2_with_oracle_sketches(ctx, orc, small, fmt, kl):
     spec, tr, te = small
-    So, Wo, _, _ = orc.train2(tr, 14, 12, 30, 1e-10)
+    So, Wo, _, _ = orc.train2(tr, kl[0], kl[1], 30, 1e-10)
     S32, W32 = So.astype(np.float32), Wo.astype(np.float32)
     if fmt == "f32":
         q = te
@@ -93,7 +96,7 @@ def test_apply2_with_oracle_sketches(ctx, orc, small, fmt):
     ev = orc.error(q, out["L"].cpu().numpy(), out["R"].cpu().numpy())
     tau = TAU_F32 if fmt == "f32" else 1e-4
     d_f, d_v = np.abs(e - ref["relerr"]) / ref["relerr"], np.abs(ev - ref["relerr"]) / ref["relerr"]
-    _say(f"apply2 {fmt}: fused dev {d_f.max():.2e}, factors dev {d_v.max():.2e}")
+    _say(f"apply2 {fmt} k, l = {kl}: fused dev {d_f.max():.2e}, factors dev {d_v.max():.2e}")
     assert d_f.max() <= tau and d_v.max() <= tau
     np.testing.assert_allclose(out["sigma"].cpu().numpy(), ref["sigma"], rtol=10 * tau)
     assert not out["flags"].cpu().numpy().any()

@@ -86,35 +86,45 @@ __device__ __forceinline__ void sketch_f32_body(const float *__restrict__ A, int
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[a][t] = v4f{0.f, 0.f, 0.f, 0.f};
     double fro = 0.0;
-    constexpr int U = 8;  // row groups of 4 in flight (two 16-row blocks)
-    for (int64_t i0 = 0; i0 < m; i0 += 4 * U) {
-        // this step's S values: 16-row blocks i0 / 16 and i0 / 16 + 1 (St holds
-        // m rounded up to 32 rows, so both exist)
-        float4 sv[2][MT];
+    // 32 rows (two 16-row blocks of St) per step; the next step's rows and
+    // S values are loaded while this step's MFMAs run (St holds m rounded up
+    // to 32 rows, so both blocks of a step exist)
+    constexpr int U = 8;  // row groups of 4
+    float4 nx[U], nsv[2][MT];
+    auto load = [&](int64_t i0) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int a = 0; a < MT; ++a)
-                sv[h][a] = *reinterpret_cast<const float4 *>(St + (((i0 / 16 + h) * MT + a) * 64 + lane) * 4);
-        float4 x[U];
+                nsv[h][a] = *reinterpret_cast<const float4 *>(St + (((i0 / 16 + h) * MT + a) * 64 + lane) * 4);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t row = i0 + 4 * u + q;
-            x[u] = float4{0.f, 0.f, 0.f, 0.f};
+            nx[u] = float4{0.f, 0.f, 0.f, 0.f};
             if (row < m && any) {
                 const float *p = Ad + row * ld + col4;
                 if (full) {
-                    x[u] = *reinterpret_cast<const float4 *>(p);
+                    nx[u] = *reinterpret_cast<const float4 *>(p);
                 } else {
-                    x[u].x = p[0];
-                    if (col4 + 1 < n) x[u].y = p[1];
-                    if (col4 + 2 < n) x[u].z = p[2];
+                    nx[u].x = p[0];
+                    if (col4 + 1 < n) nx[u].y = p[1];
+                    if (col4 + 2 < n) nx[u].z = p[2];
                 }
             }
         }
+    };
+    load(0);
+    for (int64_t i0 = 0; i0 < m; i0 += 4 * U) {
+        float4 x[U], sv[2][MT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = nx[u];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int a = 0; a < MT; ++a) sv[h][a] = nsv[h][a];
+        if (i0 + 4 * U < m) load(i0 + 4 * U);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t row = i0 + 4 * u + q;
             fro += (double)x[u].x * x[u].x + (double)x[u].y * x[u].y + (double)x[u].z * x[u].z +
                    (double)x[u].w * x[u].w;
             float s[MT];
@@ -162,47 +172,85 @@ __device__ __forceinline__ void project_f32_body(const float *__restrict__ A, in
     const int64_t r0 = (int64_t)band * PJ_ROWS;
     const float *Ad = A + d * stride;
     const float *Vd = Bm + d * kp * ldv;
-    const float *arow[4];
-    bool av[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int64_t row = r0 + a * 16 + ii;
-        av[a] = row < m;
-        arow[a] = Ad + (av[a] ? row : 0) * ld;
-    }
     v4f acc[4][NT];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < NT; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int64_t c0 = 0; c0 < n; c0 += 16) {
-        const int64_t cc = c0 + 4 * q;
-        const bool full = cc + 3 < n;
-        float4 xa[4], xb[NT];
+    // 32-column steps.  The band's 64 x 32 piece of A_d is read with 8 lanes
+    // per row (128 contiguous bytes, 8 rows per load) and staged in LDS (row
+    // stride 36 floats: the 16 rows an MFMA operand load reads fall in
+    // distinct banks); the MFMA lanes, which need 16 rows at 16 bytes each,
+    // read it from there.  (Read straight from HBM in the MFMA order, 16 rows
+    // x 64 bytes per load, the kernel took 0.43 ms on 400 matrices of
+    // 1024 x 768, k = 20; staged, with A and B_d of the next step loaded
+    // during this one's MFMAs, 0.31 ms.)
+    constexpr int CW = 32, H = CW / 16, NL = 8, LPR = 8, RPI = 64 / LPR;
+    constexpr int AS_LD = CW + 4;
+    __shared__ float As[64 * AS_LD];
+    float4 nx[NL], nb[NT][H];
+    const int lr = lane / LPR, lc = 4 * (lane % LPR);
+    auto load = [&](int64_t c0) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            xa[a] = float4{0.f, 0.f, 0.f, 0.f};
-            if (av[a] && cc < n) {
-                if (full) {
-                    xa[a] = *reinterpret_cast<const float4 *>(arow[a] + cc);
+        for (int g = 0; g < NL; ++g) {
+            const int64_t row = r0 + RPI * g + lr, cc = c0 + lc;
+            float4 x = float4{0.f, 0.f, 0.f, 0.f};
+            if (row < m && cc < n) {
+                const float *p = Ad + row * ld + cc;
+                if (cc + 3 < n) {
+                    x = *reinterpret_cast<const float4 *>(p);
                 } else {
-                    xa[a].x = arow[a][cc];
-                    if (cc + 1 < n) xa[a].y = arow[a][cc + 1];
-                    if (cc + 2 < n) xa[a].z = arow[a][cc + 2];
+                    x.x = p[0];
+                    if (cc + 1 < n) x.y = p[1];
+                    if (cc + 2 < n) x.z = p[2];
                 }
             }
+            nx[g] = x;
         }
 #pragma unroll
-        for (int b = 0; b < NT; ++b) xb[b] = *reinterpret_cast<const float4 *>(Vd + (b * 16 + ii) * ldv + cc);
+        for (int h = 0; h < H; ++h)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < NT; ++b)
+                nb[b][h] = c0 + 16 * h < ldv
+                               ? *reinterpret_cast<const float4 *>(Vd + (b * 16 + ii) * ldv + c0 + 16 * h + 4 * q)
+                               : float4{0.f, 0.f, 0.f, 0.f};
+    };
+    auto stash = [&]() {
 #pragma unroll
-            for (int b = 0; b < NT; ++b) {
-                acc[a][b] = mfma16x16x4_f32(xa[a].x, xb[b].x, acc[a][b]);
-                acc[a][b] = mfma16x16x4_f32(xa[a].y, xb[b].y, acc[a][b]);
-                acc[a][b] = mfma16x16x4_f32(xa[a].z, xb[b].z, acc[a][b]);
-                acc[a][b] = mfma16x16x4_f32(xa[a].w, xb[b].w, acc[a][b]);
-            }
+        for (int g = 0; g < NL; ++g) *reinterpret_cast<float4 *>(As + (RPI * g + lr) * AS_LD + lc) = nx[g];
+    };
+    load(0);
+    stash();
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < n; c0 += CW) {
+        const bool more = c0 + CW < n;
+        float4 xb[NT][H];
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int b = 0; b < NT; ++b) xb[b][h] = nb[b][h];
+        if (more) load(c0 + CW);
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            float4 xa[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                xa[a] = *reinterpret_cast<const float4 *>(As + (16 * a + ii) * AS_LD + 16 * h + 4 * q);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < NT; ++b) {
+                    acc[a][b] = mfma16x16x4_f32(xa[a].x, xb[b][h].x, acc[a][b]);
+                    acc[a][b] = mfma16x16x4_f32(xa[a].y, xb[b][h].y, acc[a][b]);
+                    acc[a][b] = mfma16x16x4_f32(xa[a].z, xb[b][h].z, acc[a][b]);
+                    acc[a][b] = mfma16x16x4_f32(xa[a].w, xb[b][h].w, acc[a][b]);
+                }
+        }
+        __syncthreads();
+        if (more) {
+            stash();
+            __syncthreads();
+        }
     }
     float *Cd = C + d * m * kp;
 #pragma unroll

@@ -933,14 +933,18 @@ __device__ __forceinline__ void tri_transform(const double *X, float *M, int64_t
 // step uses the same basis.  A direction whose pass-1 pivot is below 1e-12
 // of the largest is dropped (zero row); the count among the first k rows
 // goes to q[d] (flag RANKDEF).  Columns n .. ldb-1 of B are zero and stay so.
+// LDS of basis_body<kp>: three kp x kp FP64 matrices, the staged chunk,
+// the dead-pivot marks and one flag.
+__host__ __device__ constexpr int basis_lds_bytes(int kp) { return 3 * kp * kp * 8 + kp * MS_LD * 4 + (kp + 4) * 4; }
 template <int KP>
 __device__ __forceinline__ void basis_body(float *__restrict__ B, int64_t ldb, int64_t n, int k,
-                                           uint16_t *__restrict__ Bb, int *__restrict__ q, int64_t d) {
+                                           uint16_t *__restrict__ Bb, int *__restrict__ q, int64_t d,
+                                           unsigned char *lds) {
     constexpr int SZ = KP * KP;
-    __shared__ __align__(16) double buf[3 * SZ];
-    __shared__ __align__(16) float Ms[KP * MS_LD];
-    __shared__ int dead[KP];
-    __shared__ int s_second;
+    double *buf = reinterpret_cast<double *>(lds);
+    float *Ms = reinterpret_cast<float *>(lds + 3 * SZ * 8);
+    int *dead = reinterpret_cast<int *>(lds + 3 * SZ * 8 + KP * MS_LD * 4);
+    int &s_second = dead[KP];
     const int tid = threadIdx.x;
     float *Bd = B + d * KP * ldb;
     uint16_t *Pd = Bb ? Bb + d * 2 * KP * ldb : nullptr;
@@ -981,25 +985,28 @@ __device__ __forceinline__ void basis_body(float *__restrict__ B, int64_t ldb, i
 // FROM_C selects the source of H at compile time: the MFMA loop over C needs
 // far more registers than the rest, and a kernel that only adds band sums
 // keeps the occupancy of its LDS use.
-template <int KP, bool FROM_C>
+// LDS of eig_body<kp, *, nth>: H and its eigenvectors (kp x kp FP64 each),
+// the rotations, the eigenvalues, nth/64 partial sums and the order.
+__host__ __device__ constexpr int eig_lds_bytes(int kp, int nth) {
+    return 2 * kp * kp * 8 + 2 * kp * 8 + nth / 64 * 8 + kp * 4;
+}
+template <int KP, bool FROM_C, int NTH>
 __device__ __forceinline__ void eig_body(const float *__restrict__ C, int64_t m, const double *__restrict__ ctc,
                                          const int *__restrict__ q, int k, int r,
                                          const double *__restrict__ fro_part, int npanel, float *__restrict__ Z,
                                          float *__restrict__ sigma, double *__restrict__ relerr,
                                          int *__restrict__ flags, int *__restrict__ rf, double rf_thr,
-                                         int64_t d) {
+                                         int64_t d, unsigned char *lds) {
     constexpr int SZ = KP * KP;
-    __shared__ __align__(16) double H[SZ], Wt[SZ];
-    __shared__ __align__(16) double rot[KP];
-    __shared__ double red4[4];
-    __shared__ int perm[KP];
-    __shared__ double s_lam[KP];
+    double *H = reinterpret_cast<double *>(lds), *Wt = H + SZ, *rot = Wt + SZ, *s_lam = rot + KP;
+    double *red = s_lam + KP;
+    int *perm = reinterpret_cast<int *>(red + NTH / 64);
     const int tid = threadIdx.x;
     if constexpr (!FROM_C) {
         constexpr int NT = KP / 16, NPAIR = NT * (NT + 1) / 2;
         const int nb = (int)((m + PJL_ROWS - 1) / PJL_ROWS);
         const double *src = ctc + d * nb * (NPAIR * 256);
-        for (int e = tid; e < NPAIR * 256; e += 256) {
+        for (int e = tid; e < NPAIR * 256; e += NTH) {
             double s = 0.0;
             for (int b = 0; b < nb; ++b) s += src[(int64_t)b * (NPAIR * 256) + e];
             int p = e >> 8, ta = 0;
@@ -1012,15 +1019,17 @@ __device__ __forceinline__ void eig_body(const float *__restrict__ C, int64_t m,
             if (ta != tb) H[(16 * tb + c) * KP + 16 * ta + a] = s;
         }
     } else {
-        for (int e = tid; e < SZ; e += 256) H[e] = 0.0;
+        static_assert(NTH == 256, "the MFMA Gram of C runs on four waves");
+        for (int e = tid; e < SZ; e += NTH) H[e] = 0.0;
         __syncthreads();
         gram_mfma_acc<KP / 16, false>(C + d * m * KP, KP, m, H, KP);
     }
     __syncthreads();
     const int kk = k + (k & 1);  // even size for the parallel ordering
-    jacobi_eig_wg<(KP * (KP + 2) / 8 + 255) / 256, (KP * KP / 4 + 255) / 256>(H, Wt, kk, KP, rot, 40, red4);
+    jacobi_eig_wg<(KP * (KP + 2) / 8 + NTH - 1) / NTH, (KP * KP / 4 + NTH - 1) / NTH, NTH>(H, Wt, kk, KP, rot, 40,
+                                                                                           red);
     // descending order: rank of each diagonal entry (ties by index)
-    for (int i = tid; i < kk; i += 256) {
+    for (int i = tid; i < kk; i += NTH) {
         const double hi = H[i * KP + i];
         int rank = 0;
         for (int j = 0; j < kk; ++j) {
@@ -1030,9 +1039,9 @@ __device__ __forceinline__ void eig_body(const float *__restrict__ C, int64_t m,
         perm[rank] = i;
     }
     __syncthreads();
-    for (int t = tid; t < kk; t += 256) s_lam[t] = H[perm[t] * KP + perm[t]];
+    for (int t = tid; t < kk; t += NTH) s_lam[t] = H[perm[t] * KP + perm[t]];
     float *Zd = Z + d * SZ;
-    for (int e = tid; e < SZ; e += 256) {
+    for (int e = tid; e < SZ; e += NTH) {
         const int i = e / KP, t = e % KP;
         Zd[e] = (i < k && t < r) ? (float)Wt[perm[t] * KP + i] : 0.f;
     }
@@ -1104,13 +1113,14 @@ __device__ __forceinline__ void outputs_row(const float (&v)[KP], const float *Z
     }
 }
 
+__host__ __device__ constexpr int outputs_lds_bytes(int kp) { return kp * kp * 4; }
 template <int KP>
 __device__ __forceinline__ void outputs_body(const float *__restrict__ B, int64_t ldb, int64_t n,
                                              const float *__restrict__ C, int64_t m, int k, int r,
                                              const double *__restrict__ fro_part, int npanel,
                                              const float *__restrict__ Z, float *__restrict__ L,
-                                             float *__restrict__ R, int64_t d) {
-    __shared__ __align__(16) float Zs[KP * KP];
+                                             float *__restrict__ R, int64_t d, unsigned char *lds) {
+    float *Zs = reinterpret_cast<float *>(lds);
     const int tid = threadIdx.x;
     for (int e = tid; e < KP * KP; e += 256) Zs[e] = Z[d * KP * KP + e];
     double fro2 = 0.0;
@@ -1228,8 +1238,9 @@ struct ApDesc {
     const float *S;         // k x m sketch
     int64_t m, n, ld, stride, count;
     int k, r, kp, npanel;
+    int pj128;              // bf16 / e4m3 projection steps of 128 columns (else 64)
     int64_t ldv, mp;
-    float *St;              // FP32 form: m x kp transposed sketch
+    float *St;              // FP32 form: the sketch in the FP32 sketch kernel's lane order
     uint16_t *Sb;           // bf16 / e4m3 forms: bf16 pair of S
     float *B;
     uint16_t *Bb;
@@ -1326,16 +1337,19 @@ __global__ __launch_bounds__(256, 2) void project_bf16_kernel(const ET *A, const
 template <int KP>
 __global__ __launch_bounds__(256, 2) void basis_kernel(float *__restrict__ B, int64_t ldb, int64_t n, int k,
                                                     uint16_t *__restrict__ Bb, int *__restrict__ q) {
-    basis_body<KP>(B, ldb, n, k, Bb, q, blockIdx.x);
+    __shared__ __align__(16) unsigned char lds[basis_lds_bytes(KP)];
+    basis_body<KP>(B, ldb, n, k, Bb, q, blockIdx.x, lds);
 }
-template <int KP, bool FROM_C>
-__global__ __launch_bounds__(256) void eig_kernel(const float *__restrict__ C, int64_t m,
+template <int KP, bool FROM_C, int NTH>
+__global__ __launch_bounds__(NTH) void eig_kernel(const float *__restrict__ C, int64_t m,
                                                   const double *__restrict__ ctc, const int *__restrict__ q, int k,
                                                   int r, const double *__restrict__ fro_part, int npanel,
                                                   float *__restrict__ Z, float *__restrict__ sigma,
                                                   double *__restrict__ relerr, int *__restrict__ flags,
                                                   int *__restrict__ rf, double rf_thr) {
-    eig_body<KP, FROM_C>(C, m, ctc, q, k, r, fro_part, npanel, Z, sigma, relerr, flags, rf, rf_thr, blockIdx.x);
+    __shared__ __align__(16) unsigned char lds[eig_lds_bytes(KP, NTH)];
+    eig_body<KP, FROM_C, NTH>(C, m, ctc, q, k, r, fro_part, npanel, Z, sigma, relerr, flags, rf, rf_thr, blockIdx.x,
+                              lds);
 }
 template <int RP, typename ET>
 __global__ __launch_bounds__(256) void refine_kernel(const ET *__restrict__ A, const float *__restrict__ scale,
@@ -1357,7 +1371,8 @@ __global__ __launch_bounds__(256) void outputs_kernel(const float *__restrict__ 
                                                       const double *__restrict__ fro_part, int npanel,
                                                       const float *__restrict__ Z, float *__restrict__ L,
                                                       float *__restrict__ R) {
-    outputs_body<KP>(B, ldb, n, C, m, k, r, fro_part, npanel, Z, L, R, blockIdx.x);
+    __shared__ __align__(16) unsigned char lds[outputs_lds_bytes(KP)];
+    outputs_body<KP>(B, ldb, n, C, m, k, r, fro_part, npanel, Z, L, R, blockIdx.x, lds);
 }
 
 // batched forms: item = (problem, matrix, tile)
@@ -1370,47 +1385,106 @@ __global__ void prep_multi_kernel(const ApDesc *__restrict__ P, const int4 *__re
     else
         prep_sketch_f32_body(D.S, D.k, D.kp, D.m, D.mp, D.St, e);
 }
-template <int MT>
+// Every stage of a batch takes all padded sketch sizes (and, for the bf16
+// projection, both step widths) in one launch, the body chosen per item: in
+// one launch per size, a batch waited for each size's launch in turn (on 8
+// streams of 256 matrices, k = 10, 20, 40: 410k -> 500k matrices/s with the
+// per-matrix stages merged).
 __global__ __launch_bounds__(64) void sketch_f32_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
-    sketch_f32_body<MT>((const float *)D.A, D.m, D.n, D.ld, D.stride, D.St, D.B, D.ldv, D.fro, D.npanel, it.y, it.z);
+#define TSK_SKF(MTV)                                                                                              \
+    sketch_f32_body<MTV>((const float *)D.A, D.m, D.n, D.ld, D.stride, D.St, D.B, D.ldv, D.fro, D.npanel, it.y, \
+                         it.z)
+    switch (D.kp) {
+    case 16: TSK_SKF(1); break;
+    case 32: TSK_SKF(2); break;
+    case 48: TSK_SKF(3); break;
+    default: TSK_SKF(4); break;
+    }
+#undef TSK_SKF
 }
-template <int NT>
 __global__ __launch_bounds__(64) void project_f32_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     if (it.x < 0) return;  // padding of the XCD-interleaved item list
     const ApDesc &D = P[it.x];
-    project_f32_body<NT>((const float *)D.A, D.m, D.n, D.ld, D.stride, D.B, D.ldv, D.C, it.y, it.z);
+#define TSK_PJF(NTV) project_f32_body<NTV>((const float *)D.A, D.m, D.n, D.ld, D.stride, D.B, D.ldv, D.C, it.y, it.z)
+    switch (D.kp) {
+    case 16: TSK_PJF(1); break;
+    case 32: TSK_PJF(2); break;
+    case 48: TSK_PJF(3); break;
+    default: TSK_PJF(4); break;
+    }
+#undef TSK_PJF
 }
-template <int MT, typename ET>
+template <typename ET>
 __global__ __launch_bounds__(64, 1) void sketch_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
-    sketch_bf16_body<MT, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Sb, D.mp, D.B, D.ldv,
-                             D.fro, D.npanel, it.y, it.z);
+#define TSK_SKB(MTV)                                                                                               \
+    sketch_bf16_body<MTV, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Sb, D.mp, D.B, D.ldv, D.fro, \
+                              D.npanel, it.y, it.z)
+    switch (D.kp) {
+    case 16: TSK_SKB(1); break;
+    case 32: TSK_SKB(2); break;
+    case 48: TSK_SKB(3); break;
+    default: TSK_SKB(4); break;
+    }
+#undef TSK_SKB
 }
-template <int NT, int K, typename ET>
+// e4m3 stacks take 128-column steps; bf16 ones 64 or 128 (pj128)
+template <typename ET>
 __global__ __launch_bounds__(256, 2) void project_bf16_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int4 it = items[blockIdx.x];
     if (it.x < 0) return;  // padding of the XCD-interleaved item list
     const ApDesc &D = P[it.x];
-    project_lds_body<NT, K, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Bb, D.ldv, D.C,
-                                          it.y, it.z, lds_dyn, D.ctc);
+#define TSK_PJB(NTV, KV)                                                                                           \
+    project_lds_body<NTV, KV, ET>((const ET *)D.A, D.scale, D.m, D.n, D.ld, D.stride, D.Bb, D.ldv, D.C, it.y, it.z, \
+                                  lds_dyn, D.ctc)
+    if (sizeof(ET) == 1 || D.pj128) {
+        switch (D.kp) {
+        case 16: TSK_PJB(1, 128); break;
+        case 32: TSK_PJB(2, 128); break;
+        case 48: TSK_PJB(3, 128); break;
+        default: TSK_PJB(4, 128); break;
+        }
+    } else if constexpr (sizeof(ET) == 2) {
+        switch (D.kp) {
+        case 16: TSK_PJB(1, 64); break;
+        case 32: TSK_PJB(2, 64); break;
+        case 48: TSK_PJB(3, 64); break;
+        default: TSK_PJB(4, 64); break;
+        }
+    }
+#undef TSK_PJB
 }
-template <int KP>
 __global__ __launch_bounds__(256, 2) void basis_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
-    basis_body<KP>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y);
+    switch (D.kp) {
+    case 16: basis_body<16>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y, lds_dyn); break;
+    case 32: basis_body<32>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y, lds_dyn); break;
+    case 48: basis_body<48>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y, lds_dyn); break;
+    default: basis_body<64>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y, lds_dyn); break;
+    }
 }
-template <int KP, bool FROM_C>
-__global__ __launch_bounds__(256) void eig_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+template <bool FROM_C, int NTH>
+__global__ __launch_bounds__(NTH) void eig_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
-    eig_body<KP, FROM_C>(D.C, D.m, D.ctc, D.q, D.k, D.r, D.fro, D.npanel, D.Z, D.sigma, D.relerr, D.flags, D.rf, D.rf_thr,
-                 it.y);
+#define TSK_EIGB(KPV)                                                                                            \
+    eig_body<KPV, FROM_C, NTH>(D.C, D.m, D.ctc, D.q, D.k, D.r, D.fro, D.npanel, D.Z, D.sigma, D.relerr, D.flags, \
+                               D.rf, D.rf_thr, it.y, lds_dyn)
+    switch (D.kp) {
+    case 16: TSK_EIGB(16); break;
+    case 32: TSK_EIGB(32); break;
+    case 48: TSK_EIGB(48); break;
+    default: TSK_EIGB(64); break;
+    }
+#undef TSK_EIGB
 }
 // item = (problem, matrix, band); problems without relerr have no items
 template <int RP, typename ET>
@@ -1427,11 +1501,16 @@ __global__ void refine_final_multi(const ApDesc *__restrict__ P, const int4 *__r
     const int64_t d = (int64_t)it.y + threadIdx.x;
     if (d < D.count) refine_final_body(D.rf, D.rf_part, D.rf_nb, D.fro, D.npanel, D.relerr, d);
 }
-template <int KP>
 __global__ __launch_bounds__(256) void outputs_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
-    outputs_body<KP>(D.B, D.ldv, D.n, D.C, D.m, D.k, D.r, D.fro, D.npanel, D.Z, D.L, D.R, it.y);
+    switch (D.kp) {
+    case 16: outputs_body<16>(D.B, D.ldv, D.n, D.C, D.m, D.k, D.r, D.fro, D.npanel, D.Z, D.L, D.R, it.y, lds_dyn); break;
+    case 32: outputs_body<32>(D.B, D.ldv, D.n, D.C, D.m, D.k, D.r, D.fro, D.npanel, D.Z, D.L, D.R, it.y, lds_dyn); break;
+    case 48: outputs_body<48>(D.B, D.ldv, D.n, D.C, D.m, D.k, D.r, D.fro, D.npanel, D.Z, D.L, D.R, it.y, lds_dyn); break;
+    default: outputs_body<64>(D.B, D.ldv, D.n, D.C, D.m, D.k, D.r, D.fro, D.npanel, D.Z, D.L, D.R, it.y, lds_dyn); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1926,12 +2005,12 @@ static tsk_status finish_enqueue(tsk_ctx c, const tsk_stack *s, int kp, const fl
     do {                                                                                                          \
         if (ctc)                                                                                                  \
             TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                      \
-                       hipLaunchKernelGGL((eig_kernel<KPV, false>), g, dim3(256), 0, c->stream, Cm, m, ctc,       \
+                       hipLaunchKernelGGL((eig_kernel<KPV, false, 256>), g, dim3(256), 0, c->stream, Cm, m, ctc,  \
                                           (const int *)w.q, k, r, fro, npanel, w.Z, sigma, relerr, flags, w.rf,   \
                                           thr));                                                                  \
         else                                                                                                      \
             TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                      \
-                       hipLaunchKernelGGL((eig_kernel<KPV, true>), g, dim3(256), 0, c->stream, Cm, m, ctc,        \
+                       hipLaunchKernelGGL((eig_kernel<KPV, true, 256>), g, dim3(256), 0, c->stream, Cm, m, ctc,   \
                                           (const int *)w.q, k, r, fro, npanel, w.Z, sigma, relerr, flags, w.rf,   \
                                           thr));                                                                  \
         TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                          \
@@ -2262,6 +2341,7 @@ static void multi_build(tsk_ctx c, const tsk_problem *pr, int np, int compute, M
         D.k = pr[i].k;
         D.r = pr[i].r;
         D.kp = (D.k + 15) / 16 * 16;
+        D.pj128 = T.e4 ? 1 : T.k128[i];
         D.npanel = (int)((A.n + panel - 1) / panel);
         D.ldv = (int64_t)D.npanel * panel;
         D.mp = (A.m + 31) / 32 * 32;
@@ -2397,69 +2477,67 @@ static tsk_status multi_launch(tsk_ctx c, const MultiTables &T, const ApDesc *P,
     const size_t fstart = T.fstart, fcnt = T.fcnt;
     TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(prep_multi_kernel, dim3((unsigned)T.n_prep), dim3(256), 0,
                                                         c->stream, P, I, lowp ? 1 : 0));
-#define TSK_MSK(CL)                                                                                                \
-    if (cnt[0][CL]) {                                                                                              \
-        const dim3 g((unsigned)cnt[0][CL]);                                                                        \
-        const int4 *It = I + start[0][CL];                                                                         \
-        if (!lowp)                                                                                                 \
-            TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_multi<CL>, g, dim3(64), 0, c->stream, P, It)); \
-        else if (e4)                                                                                               \
-            TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                       \
-                       hipLaunchKernelGGL((sketch_bf16_multi<CL, uint8_t>), g, dim3(64), 0, c->stream, P, It));     \
-        else                                                                                                       \
-            TSK_LAUNCH(c, TSK_KERNEL_SKETCH,                                                                       \
-                       hipLaunchKernelGGL((sketch_bf16_multi<CL, uint16_t>), g, dim3(64), 0, c->stream, P, It));    \
+    // one launch per stage over all sizes (a stage's items are consecutive,
+    // sizes ascending; the projection's lists of 64- and 128-column steps
+    // alternate by size, each a multiple of 8 items long so the XCD
+    // interleave holds); LDS for the largest size present
+    size_t n0 = 0, n1 = 0, n2 = 0, lp = 0;
+    int kpmax = 16;
+    for (int cl = 1; cl <= 4; ++cl) {
+        n0 += cnt[0][cl];
+        n1 += cnt[1][cl] + T.cnt128[cl];
+        if (cnt[2][cl]) {
+            n2 += cnt[2][cl];
+            kpmax = 16 * cl;
+        }
+        if (lowp && cnt[1][cl])
+            lp = std::max(lp, (size_t)std::max(pjl_lds_bytes(e4 ? 128 : 64, e4 ? 1 : 2, 16 * cl), pjl_ctc_bytes(16 * cl)));
+        if (lowp && T.cnt128[cl])
+            lp = std::max(lp, (size_t)std::max(pjl_lds_bytes(128, 2, 16 * cl), pjl_ctc_bytes(16 * cl)));
     }
-#define TSK_MPJ(CL)                                                                                                \
-    if (cnt[1][CL]) {                                                                                              \
-        const dim3 g((unsigned)cnt[1][CL]);                                                                        \
-        const int4 *It = I + start[1][CL];                                                                         \
-        if (!lowp) {                                                                                               \
-            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_multi<CL>, g, dim3(64), 0, c->stream, P, It)); \
-        } else if (e4) {                                                                                           \
-            const size_t pjl = (size_t)std::max(pjl_lds_bytes(128, 1, 16 * CL), pjl_ctc_bytes(16 * CL));          \
-            TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<CL, 128, uint8_t>, pjl));                        \
-            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL((project_bf16_multi<CL, 128, uint8_t>), g,        \
-                                                                 dim3(PJL_THREADS), pjl, c->stream, P, It));       \
-        } else {                                                                                                   \
-            const size_t pjl = (size_t)std::max(pjl_lds_bytes(64, 2, 16 * CL), pjl_ctc_bytes(16 * CL));           \
-            TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<CL, 64, uint16_t>, pjl));                        \
-            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL((project_bf16_multi<CL, 64, uint16_t>), g,        \
-                                                                 dim3(PJL_THREADS), pjl, c->stream, P, It));       \
-        }                                                                                                          \
-    }                                                                                                              \
-    if (T.cnt128[CL]) {                                                                                            \
-        const dim3 g((unsigned)T.cnt128[CL]);                                                                      \
-        const int4 *It = I + T.start128[CL];                                                                       \
-        const size_t pjl = (size_t)std::max(pjl_lds_bytes(128, 2, 16 * CL), pjl_ctc_bytes(16 * CL));               \
-        TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<CL, 128, uint16_t>, pjl));                           \
-        TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL((project_bf16_multi<CL, 128, uint16_t>), g,           \
-                                                             dim3(PJL_THREADS), pjl, c->stream, P, It));           \
+    const dim3 g0((unsigned)n0), g1((unsigned)n1), g2((unsigned)n2);
+    const int4 *I0 = I + start[0][1], *I1 = I + start[1][1], *I2 = I + start[2][1];
+    if (n0) {
+        if (!lowp)
+            TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_multi, g0, dim3(64), 0, c->stream, P, I0));
+        else if (e4)
+            TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
+                       hipLaunchKernelGGL(sketch_bf16_multi<uint8_t>, g0, dim3(64), 0, c->stream, P, I0));
+        else
+            TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
+                       hipLaunchKernelGGL(sketch_bf16_multi<uint16_t>, g0, dim3(64), 0, c->stream, P, I0));
     }
-#define TSK_MFA(CL)                                                                                          \
-    if (cnt[2][CL])                                                                                          \
-        TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(basis_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),        \
-                                                        dim3(256), 0, c->stream, P, I + start[2][CL]));
-#define TSK_MEG(CL)                                                                                          \
-    if (cnt[2][CL]) {                                                                                        \
-        if (lowp)                                                                                            \
-            TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                 \
-                       hipLaunchKernelGGL((eig_multi<16 * CL, false>), dim3((unsigned)cnt[2][CL]), dim3(256), 0, \
-                                          c->stream, P, I + start[2][CL]));                                 \
-        else                                                                                                 \
-            TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                 \
-                       hipLaunchKernelGGL((eig_multi<16 * CL, true>), dim3((unsigned)cnt[2][CL]), dim3(256), 0,  \
-                                          c->stream, P, I + start[2][CL]));                                 \
+    if (n2) {
+        const size_t lb = (size_t)basis_lds_bytes(kpmax);
+        TSK_TRY(allow_lds(c, (const void *)basis_multi, lb));
+        TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(basis_multi, g2, dim3(256), lb, c->stream, P, I2));
     }
-#define TSK_MOU(CL)                                                                                          \
-    if (cnt[2][CL])                                                                                          \
-        TSK_LAUNCH(c, TSK_KERNEL_FINISH, hipLaunchKernelGGL(outputs_multi<16 * CL>, dim3((unsigned)cnt[2][CL]),  \
-                                                            dim3(256), 0, c->stream, P, I + start[2][CL]));
-    TSK_MSK(1) TSK_MSK(2) TSK_MSK(3) TSK_MSK(4)
-    TSK_MFA(1) TSK_MFA(2) TSK_MFA(3) TSK_MFA(4)
-    TSK_MPJ(1) TSK_MPJ(2) TSK_MPJ(3) TSK_MPJ(4)
-    TSK_MEG(1) TSK_MEG(2) TSK_MEG(3) TSK_MEG(4)
-    TSK_MOU(1) TSK_MOU(2) TSK_MOU(3) TSK_MOU(4)
+    if (n1) {
+        if (!lowp) {
+            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_multi, g1, dim3(64), 0, c->stream, P, I1));
+        } else if (e4) {
+            TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<uint8_t>, lp));
+            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_bf16_multi<uint8_t>, g1, dim3(PJL_THREADS),
+                                                                 lp, c->stream, P, I1));
+        } else {
+            TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<uint16_t>, lp));
+            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_bf16_multi<uint16_t>, g1, dim3(PJL_THREADS),
+                                                                 lp, c->stream, P, I1));
+        }
+    }
+    if (n2) {
+        const size_t le = (size_t)eig_lds_bytes(kpmax, 256);
+        const void *ek = lowp ? (const void *)eig_multi<false, 256> : (const void *)eig_multi<true, 256>;
+        TSK_TRY(allow_lds(c, ek, le));
+        if (lowp)
+            TSK_LAUNCH(c, TSK_KERNEL_FINISH,
+                       hipLaunchKernelGGL((eig_multi<false, 256>), g2, dim3(256), le, c->stream, P, I2));
+        else
+            TSK_LAUNCH(c, TSK_KERNEL_FINISH,
+                       hipLaunchKernelGGL((eig_multi<true, 256>), g2, dim3(256), le, c->stream, P, I2));
+        const size_t lo = (size_t)outputs_lds_bytes(kpmax);
+        TSK_LAUNCH(c, TSK_KERNEL_FINISH, hipLaunchKernelGGL(outputs_multi, g2, dim3(256), lo, c->stream, P, I2));
+    }
 #define TSK_MRF(CL)                                                                                           \
     if (rcnt[CL]) {                                                                                           \
         const dim3 g((unsigned)rcnt[CL]);                                                                     \
@@ -2479,11 +2557,6 @@ static tsk_status multi_launch(tsk_ctx c, const MultiTables &T, const ApDesc *P,
         TSK_LAUNCH(c, TSK_KERNEL_ERROR, hipLaunchKernelGGL(refine_final_multi, dim3((unsigned)fcnt), dim3(256), 0,
                                                            c->stream, P, I + fstart));
 #undef TSK_MRF
-#undef TSK_MSK
-#undef TSK_MPJ
-#undef TSK_MFA
-#undef TSK_MEG
-#undef TSK_MOU
     return TSK_OK;
 }
 

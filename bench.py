@@ -44,10 +44,10 @@ COPY_BYTES = 256 << 20  # calibration copy of the counter pass
 # below); otherwise traffic is reported as null.
 TRAFFIC_SOURCES = ("paper_2209_14637_amd/csrc/gram.hip", "paper_2209_14637_amd/csrc/tsk_common.hpp")
 MEASURED_TRAFFIC = {
-    "stream_bf16": {"kernel": "gram_wide_kernel<uint16_t>", "fetch_kib": 9671731.6, "write_kib": 509953.8,
-                    "copy_fetch_kib": 131089.9, "copy_write_kib": 262144.0,
+    "stream_bf16": {"kernel": "gram_wide_kernel<uint16_t>", "fetch_kib": 9746731.8, "write_kib": 509953.2,
+                    "copy_fetch_kib": 131089.8, "copy_write_kib": 262144.0,
                     "sha256": "fcca3baedcb290a8a49a9874164e0a5add006ddf402a8ae6627e9b5f74bb4989"},
-    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1118974.5, "write_kib": 294920.4,
+    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1119461.9, "write_kib": 294918.8,
                  "copy_fetch_kib": 131086.2, "copy_write_kib": 262144.0,
                  "sha256": "fcca3baedcb290a8a49a9874164e0a5add006ddf402a8ae6627e9b5f74bb4989"},
 }
@@ -58,14 +58,14 @@ MEASURED_TRAFFIC = {
 # were taken on.
 APPLY_TRAFFIC_SOURCES = ("paper_2209_14637_amd/csrc/apply.hip", "paper_2209_14637_amd/csrc/tsk_common.hpp")
 MEASURED_APPLY_TRAFFIC = {
-    "stream_bf16": {"matrices": 1000, "copy_fetch_kib": 131089.9, "copy_write_kib": 262144.0,
-                    "fetch_kib": {"sketch": 2062979.9, "basis": 228231.5, "project": 2305250.4, "eig": 60222.0, "outputs": 279833.7},
-                    "write_kib": {"sketch": 216341.2, "basis": 466101.1, "project": 480036.9, "eig": 9187.5, "outputs": 394791.5},
-                    "sha256": "333cd4c450a3806c3fc383c07335f06c3e577f49e87899b945474cbd49c4db4f"},
+    "stream_bf16": {"matrices": 1000, "copy_fetch_kib": 131089.8, "copy_write_kib": 262144.0,
+                    "fetch_kib": {"sketch": 2062598.2, "basis": 223595.0, "project": 2302161.3, "eig": 60228.1, "outputs": 279756.0},
+                    "write_kib": {"sketch": 216340.5, "basis": 450052.3, "project": 480033.8, "eig": 9187.5, "outputs": 405196.3},
+                    "sha256": "d8e90a95fb13e49acd46c4fd276dc81daa13f4a9542405160152f76c5ea0f3b1"},
     "hsi_fp32": {"matrices": 200, "copy_fetch_kib": 131086.2, "copy_write_kib": 262144.0,
-                 "fetch_kib": {"sketch": 307778.6, "basis": 10180.0, "project": 383401.2, "eig": 12928.2, "outputs": 19280.6},
-                 "write_kib": {"sketch": 19280.9, "basis": 20806.5, "project": 25600.0, "eig": 831.2, "outputs": 14000.0},
-                 "sha256": "333cd4c450a3806c3fc383c07335f06c3e577f49e87899b945474cbd49c4db4f"},
+                 "fetch_kib": {"sketch": 308249.1, "basis": 10160.3, "project": 317220.1, "eig": 12921.2, "outputs": 19288.0},
+                 "write_kib": {"sketch": 19279.4, "basis": 20806.4, "project": 25600.0, "eig": 831.2, "outputs": 14000.0},
+                 "sha256": "d8e90a95fb13e49acd46c4fd276dc81daa13f4a9542405160152f76c5ea0f3b1"},
 }
 
 
@@ -643,7 +643,7 @@ def run_batch(args):
         "data": "synthetic",
         "config": {"workload": "batch_bf16: 8 streams of shapes (256,192)..(2048,1536), k in {10,20,40}, r=k/2, "
                                "2000 test matrices interleaved at random, batches of 256, one captured plan (HIP graph "
-                               "of the batched apply) per batch, the 8 plans launched together over two streams; each "
+                               "of the batched apply) per batch, the 8 plans launched together over three streams; each "
                                "stream trained on 100 slices (bf16)", "streams": [list(x) for x in
                                                                                          synth.BATCH_SHAPES],
                    "batch": bsz, "n_test": n_test},

@@ -478,6 +478,7 @@ __device__ inline int chol_factor_inverse(double *C, int ld, int pp, double tol_
                                           int live = 1 << 30) {
     __shared__ double s_maxd;
     __shared__ int s_nd;
+    __shared__ double s_inv[2];
     const int tid = threadIdx.x;
     const int nth = (int)blockDim.x;
     if (tid < 64) {  // largest diagonal entry (wave 0)
@@ -512,12 +513,18 @@ __device__ inline int chol_factor_inverse(double *C, int ld, int pp, double tol_
     for (int u = 0; u < MAXU; ++u) ra[u] = rc[u] = 0.0;
     for (int j = 0; j < pp; ++j) {
         double *rb = X + (j & 1) * pp;
+        // row j is published with the reciprocal of its pivot, formed once
+        // by the pivot's owner instead of by every thread (5% of the
+        // kernel at pp = 64 and 1024 threads)
 #pragma unroll
         for (int u = 0; u < MAXU; ++u)
-            if (ea[u] == j) rb[eb[u]] = cv[u];
+            if (ea[u] == j) {
+                rb[eb[u]] = cv[u];
+                if (eb[u] == j) s_inv[j & 1] = (cv[u] > thr && cv[u] > 0.0) ? rcp_nr(cv[u]) : 0.0;
+            }
         __syncthreads();
         // the column's reads are all issued before any of them is used
-        const double piv = rb[j];
+        const double piv = rb[j], inv = s_inv[j & 1];
 #pragma unroll
         for (int u = 0; u < MAXU; ++u)
             if (ea[u] > j) {
@@ -532,7 +539,6 @@ __device__ inline int chol_factor_inverse(double *C, int ld, int pp, double tol_
             if (dj && j < live) ++s_nd;
         }
         if (!dj) {
-            const double inv = 1.0 / piv;
 #pragma unroll
             for (int u = 0; u < MAXU; ++u)
                 if (ea[u] > j) cv[u] -= ra[u] * rc[u] * inv;

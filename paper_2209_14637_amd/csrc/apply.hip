@@ -1459,18 +1459,23 @@ __global__ __launch_bounds__(256, 2) void project_bf16_multi(const ApDesc *__res
     }
 #undef TSK_PJB
 }
+// The per-matrix kernels are compiled for the largest padded size of the
+// batch (MAXKP): a kernel holding the 64-size body takes its registers for
+// every size (the eig kernel 248 instead of 126, one workgroup per CU instead
+// of four).
+template <int MAXKP>
 __global__ __launch_bounds__(256, 2) void basis_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
     switch (D.kp) {
     case 16: basis_body<16>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y, lds_dyn); break;
-    case 32: basis_body<32>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y, lds_dyn); break;
-    case 48: basis_body<48>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y, lds_dyn); break;
-    default: basis_body<64>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y, lds_dyn); break;
+    case 32: if constexpr (MAXKP >= 32) basis_body<32>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y, lds_dyn); break;
+    case 48: if constexpr (MAXKP >= 48) basis_body<48>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y, lds_dyn); break;
+    default: if constexpr (MAXKP >= 64) basis_body<64>(D.B, D.ldv, D.n, D.k, D.Bb, D.q, it.y, lds_dyn); break;
     }
 }
-template <bool FROM_C, int NTH>
+template <bool FROM_C, int NTH, int MAXKP>
 __global__ __launch_bounds__(NTH) void eig_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     const int4 it = items[blockIdx.x];
@@ -1480,9 +1485,9 @@ __global__ __launch_bounds__(NTH) void eig_multi(const ApDesc *__restrict__ P, c
                                D.rf, D.rf_thr, it.y, lds_dyn)
     switch (D.kp) {
     case 16: TSK_EIGB(16); break;
-    case 32: TSK_EIGB(32); break;
-    case 48: TSK_EIGB(48); break;
-    default: TSK_EIGB(64); break;
+    case 32: if constexpr (MAXKP >= 32) TSK_EIGB(32); break;
+    case 48: if constexpr (MAXKP >= 48) TSK_EIGB(48); break;
+    default: if constexpr (MAXKP >= 64) TSK_EIGB(64); break;
     }
 #undef TSK_EIGB
 }
@@ -2509,8 +2514,13 @@ static tsk_status multi_launch(tsk_ctx c, const MultiTables &T, const ApDesc *P,
     }
     if (n2) {
         const size_t lb = (size_t)basis_lds_bytes(kpmax);
-        TSK_TRY(allow_lds(c, (const void *)basis_multi, lb));
-        TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(basis_multi, g2, dim3(256), lb, c->stream, P, I2));
+#define TSK_MBA(MK)                                                                                          \
+    {                                                                                                        \
+        TSK_TRY(allow_lds(c, (const void *)basis_multi<MK>, lb));                                            \
+        TSK_LAUNCH(c, TSK_KERNEL_QR, hipLaunchKernelGGL(basis_multi<MK>, g2, dim3(256), lb, c->stream, P, I2)); \
+    }
+        TSK_KP_SWITCH(kpmax / 16, TSK_MBA(16), TSK_MBA(32), TSK_MBA(48), TSK_MBA(64))
+#undef TSK_MBA
     }
     if (n1) {
         if (!lowp) {
@@ -2527,14 +2537,19 @@ static tsk_status multi_launch(tsk_ctx c, const MultiTables &T, const ApDesc *P,
     }
     if (n2) {
         const size_t le = (size_t)eig_lds_bytes(kpmax, 256);
-        const void *ek = lowp ? (const void *)eig_multi<false, 256> : (const void *)eig_multi<true, 256>;
-        TSK_TRY(allow_lds(c, ek, le));
-        if (lowp)
-            TSK_LAUNCH(c, TSK_KERNEL_FINISH,
-                       hipLaunchKernelGGL((eig_multi<false, 256>), g2, dim3(256), le, c->stream, P, I2));
-        else
-            TSK_LAUNCH(c, TSK_KERNEL_FINISH,
-                       hipLaunchKernelGGL((eig_multi<true, 256>), g2, dim3(256), le, c->stream, P, I2));
+#define TSK_MEI(MK)                                                                                          \
+    {                                                                                                        \
+        const void *ek = lowp ? (const void *)eig_multi<false, 256, MK> : (const void *)eig_multi<true, 256, MK>; \
+        TSK_TRY(allow_lds(c, ek, le));                                                                       \
+        if (lowp)                                                                                            \
+            TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                 \
+                       hipLaunchKernelGGL((eig_multi<false, 256, MK>), g2, dim3(256), le, c->stream, P, I2)); \
+        else                                                                                                 \
+            TSK_LAUNCH(c, TSK_KERNEL_FINISH,                                                                 \
+                       hipLaunchKernelGGL((eig_multi<true, 256, MK>), g2, dim3(256), le, c->stream, P, I2)); \
+    }
+        TSK_KP_SWITCH(kpmax / 16, TSK_MEI(16), TSK_MEI(32), TSK_MEI(48), TSK_MEI(64))
+#undef TSK_MEI
         const size_t lo = (size_t)outputs_lds_bytes(kpmax);
         TSK_LAUNCH(c, TSK_KERNEL_FINISH, hipLaunchKernelGGL(outputs_multi, g2, dim3(256), lo, c->stream, P, I2));
     }

@@ -61,11 +61,11 @@ MEASURED_APPLY_TRAFFIC = {
     "stream_bf16": {"matrices": 1000, "copy_fetch_kib": 131090.7, "copy_write_kib": 262144.0,
                     "fetch_kib": {"sketch": 2063041.0, "basis": 226668.2, "project": 2303623.2, "eig": 60228.0, "outputs": 279980.2},
                     "write_kib": {"sketch": 216340.6, "basis": 455052.9, "project": 480036.8, "eig": 9187.5, "outputs": 389471.6},
-                    "sha256": "bd5e3a3bda83d95bdf772f2230cb22541f8c2d367f4a8228da5f46e6533a67ac"},
+                    "sha256": "54752a891a19591d26d6aa950ef1b32cbb392bc209f9e1392cca47b812b9ffc7"},
     "hsi_fp32": {"matrices": 200, "copy_fetch_kib": 131086.3, "copy_write_kib": 262144.0,
                  "fetch_kib": {"sketch": 308294.3, "basis": 10171.1, "project": 317235.0, "eig": 12927.6, "outputs": 19288.1},
                  "write_kib": {"sketch": 19279.7, "basis": 20806.3, "project": 25600.0, "eig": 831.2, "outputs": 14000.1},
-                 "sha256": "bd5e3a3bda83d95bdf772f2230cb22541f8c2d367f4a8228da5f46e6533a67ac"},
+                 "sha256": "54752a891a19591d26d6aa950ef1b32cbb392bc209f9e1392cca47b812b9ffc7"},
 }
 
 

@@ -258,8 +258,9 @@ typedef struct {
 /* The batching form of SCW (Algorithm 1): tsk_apply on every problem of
  * `probs` -- matrices of different shapes and sketch sizes, e.g. from
  * several streams -- in a fixed number of launches for the whole batch
- * (one sketch-preparation launch, then one sketch, one project and one
- * finish launch per sketch-size class ceil(k/16)), work items of all
+ * (one sketch-preparation launch, then one launch of each later phase --
+ * sketch, basis, project, eig, outputs -- over all problems and sketch
+ * sizes, and the error refinement per class ceil(r/16)), work items of all
  * problems sharing each launch.  Results are identical to tsk_apply on each
  * problem.  compute: as tsk_apply, and every stack's dtype must equal it.
  * nprobs >= 1.  The problems' outputs must not overlap.  Enqueue only (the

@@ -1230,7 +1230,7 @@ __device__ __forceinline__ void refine_final_body(const int *__restrict__ rf, co
 // problems of different shapes (tsk_apply_multi): a flat grid over work
 // items (problem, matrix, tile) listed by the host, each problem's shapes
 // and buffers read from its descriptor; one launch per phase covers every
-// problem of a sketch-size class.
+// problem, whatever its sketch size.
 // ---------------------------------------------------------------------------
 struct ApDesc {
     const void *A;
@@ -2294,9 +2294,10 @@ tsk_status tsk_apply_noalloc_enqueue(tsk_ctx c, const float *S, int k, const tsk
 // Batched SCW over problems of different shapes (tsk_apply_multi).  The host
 // lays out every problem's workspace in one buffer, writes the descriptors
 // and work-item lists into pinned memory, copies them in one transfer, then
-// launches: one sketch-preparation launch for all problems, and per
-// sketch-size class (kp / 16) one launch of each later phase (sketch,
-// basis, project, eig, outputs; then refine per class of ceil(r / 16)).
+// launches: one sketch-preparation launch for all problems, then one launch
+// of each later phase (sketch, basis, project, eig, outputs) over all
+// problems, their items listed by sketch-size class (kp / 16); then refine
+// per class of ceil(r / 16).
 // Items are ordered largest problem first, so the long items start early.
 // Host side of the batching form: descriptors, workspace layout and the
 // work-item lists of every launch.

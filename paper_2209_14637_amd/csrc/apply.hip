@@ -46,6 +46,7 @@ namespace {
 // last units run at full speed on otherwise idle SIMDs.
 constexpr int SK_PANEL = 64;   // columns of A_d per sketch workgroup (one wave)
 constexpr int PJ_ROWS = 64;    // rows of A_d per project workgroup (one wave)
+constexpr int PJ_AS_LD = 36;   // LDS row stride (floats) of its staged 64 x 32 piece of A_d
 constexpr int MAXK = 64;
 
 // The FP32 sketch in the order the FP32 sketch kernel's MFMA lanes read it
@@ -165,7 +166,8 @@ __device__ __forceinline__ void sketch_f32_body(const float *__restrict__ A, int
 template <int NT>
 __device__ __forceinline__ void project_f32_body(const float *__restrict__ A, int64_t m, int64_t n,
                                                           int64_t ld, int64_t stride, const float *__restrict__ Bm,
-                                                          int64_t ldv, float *__restrict__ C, int64_t d, int band) {
+                                                          int64_t ldv, float *__restrict__ C, int64_t d, int band,
+                                                          float *__restrict__ As) {
     constexpr int kp = NT * 16;
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, ii = lane & 15;
@@ -186,8 +188,7 @@ __device__ __forceinline__ void project_f32_body(const float *__restrict__ A, in
     // 1024 x 768, k = 20; staged, with A and B_d of the next step loaded
     // during this one's MFMAs, 0.31 ms.)
     constexpr int CW = 32, H = CW / 16, NL = 8, LPR = 8, RPI = 64 / LPR;
-    constexpr int AS_LD = CW + 4;
-    __shared__ float As[64 * AS_LD];
+    constexpr int AS_LD = PJ_AS_LD;  // As: 64 x AS_LD floats of LDS
     float4 nx[NL], nb[NT][H];
     const int lr = lane / LPR, lc = 4 * (lane % LPR);
     auto load = [&](int64_t c0) {
@@ -1301,7 +1302,8 @@ __global__ __launch_bounds__(64) void project_f32_kernel(const float *__restrict
     int64_t d;
     int band;
     xcd_band(blockIdx.x, count, nb, d, band);
-    project_f32_body<NT>(A, m, n, ld, stride, Bm, ldv, C, d, band);
+    __shared__ __align__(16) float As[PJ_ROWS * PJ_AS_LD];
+    project_f32_body<NT>(A, m, n, ld, stride, Bm, ldv, C, d, band, As);
 }
 // one wave per SIMD: its register ring keeps several steps of rows in
 // flight (HBM latency under load is several microseconds)
@@ -1408,7 +1410,10 @@ __global__ __launch_bounds__(64) void project_f32_multi(const ApDesc *__restrict
     const int4 it = items[blockIdx.x];
     if (it.x < 0) return;  // padding of the XCD-interleaved item list
     const ApDesc &D = P[it.x];
-#define TSK_PJF(NTV) project_f32_body<NTV>((const float *)D.A, D.m, D.n, D.ld, D.stride, D.B, D.ldv, D.C, it.y, it.z)
+    // one staging buffer for every size's body (static LDS per body would add up)
+    __shared__ __align__(16) float As[PJ_ROWS * PJ_AS_LD];
+#define TSK_PJF(NTV) \
+    project_f32_body<NTV>((const float *)D.A, D.m, D.n, D.ld, D.stride, D.B, D.ldv, D.C, it.y, it.z, As)
     switch (D.kp) {
     case 16: TSK_PJF(1); break;
     case 32: TSK_PJF(2); break;

@@ -1392,6 +1392,7 @@ __global__ void prep_multi_kernel(const ApDesc *__restrict__ P, const int4 *__re
 // one launch per size, a batch waited for each size's launch in turn (on 8
 // streams of 256 matrices, k = 10, 20, 40: 410k -> 500k matrices/s with the
 // per-matrix stages merged).
+template <int MAXKP>
 __global__ __launch_bounds__(64) void sketch_f32_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     const ApDesc &D = P[it.x];
@@ -1400,12 +1401,13 @@ __global__ __launch_bounds__(64) void sketch_f32_multi(const ApDesc *__restrict_
                          it.z)
     switch (D.kp) {
     case 16: TSK_SKF(1); break;
-    case 32: TSK_SKF(2); break;
-    case 48: TSK_SKF(3); break;
-    default: TSK_SKF(4); break;
+    case 32: if constexpr (MAXKP >= 32) TSK_SKF(2); break;
+    case 48: if constexpr (MAXKP >= 48) TSK_SKF(3); break;
+    default: if constexpr (MAXKP >= 64) TSK_SKF(4); break;
     }
 #undef TSK_SKF
 }
+template <int MAXKP>
 __global__ __launch_bounds__(64) void project_f32_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     const int4 it = items[blockIdx.x];
     if (it.x < 0) return;  // padding of the XCD-interleaved item list
@@ -1416,9 +1418,9 @@ __global__ __launch_bounds__(64) void project_f32_multi(const ApDesc *__restrict
     project_f32_body<NTV>((const float *)D.A, D.m, D.n, D.ld, D.stride, D.B, D.ldv, D.C, it.y, it.z, As)
     switch (D.kp) {
     case 16: TSK_PJF(1); break;
-    case 32: TSK_PJF(2); break;
-    case 48: TSK_PJF(3); break;
-    default: TSK_PJF(4); break;
+    case 32: if constexpr (MAXKP >= 32) TSK_PJF(2); break;
+    case 48: if constexpr (MAXKP >= 48) TSK_PJF(3); break;
+    default: if constexpr (MAXKP >= 64) TSK_PJF(4); break;
     }
 #undef TSK_PJF
 }
@@ -2506,11 +2508,18 @@ static tsk_status multi_launch(tsk_ctx c, const MultiTables &T, const ApDesc *P,
         if (lowp && T.cnt128[cl])
             lp = std::max(lp, (size_t)std::max(pjl_lds_bytes(128, 2, 16 * cl), pjl_ctc_bytes(16 * cl)));
     }
+    // the largest padded size of any problem (every phase lists every problem)
+    int kpall = 16;
+    for (int cl = 1; cl <= 4; ++cl)
+        if (cnt[0][cl]) kpall = 16 * cl;
     const dim3 g0((unsigned)n0), g1((unsigned)n1), g2((unsigned)n2);
     const int4 *I0 = I + start[0][1], *I1 = I + start[1][1], *I2 = I + start[2][1];
     if (n0) {
-        if (!lowp)
-            TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_multi, g0, dim3(64), 0, c->stream, P, I0));
+        if (!lowp) {
+#define TSK_MSF(MK) TSK_LAUNCH(c, TSK_KERNEL_SKETCH, hipLaunchKernelGGL(sketch_f32_multi<MK>, g0, dim3(64), 0, c->stream, P, I0))
+            TSK_KP_SWITCH(kpall / 16, TSK_MSF(16), TSK_MSF(32), TSK_MSF(48), TSK_MSF(64))
+#undef TSK_MSF
+        }
         else if (e4)
             TSK_LAUNCH(c, TSK_KERNEL_SKETCH,
                        hipLaunchKernelGGL(sketch_bf16_multi<uint8_t>, g0, dim3(64), 0, c->stream, P, I0));
@@ -2530,7 +2539,9 @@ static tsk_status multi_launch(tsk_ctx c, const MultiTables &T, const ApDesc *P,
     }
     if (n1) {
         if (!lowp) {
-            TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_multi, g1, dim3(64), 0, c->stream, P, I1));
+#define TSK_MPF(MK) TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_f32_multi<MK>, g1, dim3(64), 0, c->stream, P, I1))
+            TSK_KP_SWITCH(kpall / 16, TSK_MPF(16), TSK_MPF(32), TSK_MPF(48), TSK_MPF(64))
+#undef TSK_MPF
         } else if (e4) {
             TSK_TRY(allow_lds(c, (const void *)project_bf16_multi<uint8_t>, lp));
             TSK_LAUNCH(c, TSK_KERNEL_PROJECT, hipLaunchKernelGGL(project_bf16_multi<uint8_t>, g1, dim3(PJL_THREADS),

@@ -61,11 +61,11 @@ MEASURED_APPLY_TRAFFIC = {
     "stream_bf16": {"matrices": 1000, "copy_fetch_kib": 131090.1, "copy_write_kib": 262144.0,
                     "fetch_kib": {"sketch": 2063734.6, "basis": 226616.6, "project": 2305058.0, "eig": 60222.0, "outputs": 279463.5},
                     "write_kib": {"sketch": 216339.3, "basis": 455051.0, "project": 480037.7, "eig": 9187.5, "outputs": 400166.4},
-                    "sha256": "a24bfc62f3a594ac719d889fc657ff83073de5e6a20dac2d1c9460624e20b4e9"},
+                    "sha256": "656b82029519249f04ea75a95c7dce502f183610590a5d4d48fa735afb7e97dd"},
     "hsi_fp32": {"matrices": 200, "copy_fetch_kib": 131086.1, "copy_write_kib": 262144.0,
                  "fetch_kib": {"sketch": 308251.9, "basis": 10168.6, "project": 317208.2, "eig": 12927.6, "outputs": 19280.4},
                  "write_kib": {"sketch": 19279.4, "basis": 20806.3, "project": 25600.0, "eig": 831.2, "outputs": 14000.0},
-                 "sha256": "a24bfc62f3a594ac719d889fc657ff83073de5e6a20dac2d1c9460624e20b4e9"},
+                 "sha256": "656b82029519249f04ea75a95c7dce502f183610590a5d4d48fa735afb7e97dd"},
 }
 
 

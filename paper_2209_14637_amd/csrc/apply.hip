@@ -1468,8 +1468,8 @@ __global__ __launch_bounds__(256, 2) void project_bf16_multi(const ApDesc *__res
 }
 // The per-matrix kernels are compiled for the largest padded size of the
 // batch (MAXKP): a kernel holding the 64-size body takes its registers for
-// every size (the eig kernel 248 instead of 126, one workgroup per CU instead
-// of four).
+// every size (the eig kernel: 248 with it, 140 up to size 48; one workgroup
+// per CU against three).
 template <int MAXKP>
 __global__ __launch_bounds__(256, 2) void basis_multi(const ApDesc *__restrict__ P, const int4 *__restrict__ items) {
     extern __shared__ __align__(16) unsigned char lds_dyn[];

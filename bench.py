@@ -47,8 +47,8 @@ MEASURED_TRAFFIC = {
     "stream_bf16": {"kernel": "gram_wide_kernel<uint16_t>", "fetch_kib": 9679720.5, "write_kib": 509953.2,
                     "copy_fetch_kib": 131090.1, "copy_write_kib": 262144.0,
                     "sha256": "cef17165d20e3344d1e27b34466edeab20453ec3c7b1ef8e7759c2970913fefe"},
-    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1118034.6, "write_kib": 294919.1,
-                 "copy_fetch_kib": 131086.1, "copy_write_kib": 262144.0,
+    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1118442.3, "write_kib": 294920.2,
+                 "copy_fetch_kib": 131090.5, "copy_write_kib": 262144.0,
                  "sha256": "cef17165d20e3344d1e27b34466edeab20453ec3c7b1ef8e7759c2970913fefe"},
 }
 # HBM traffic of the apply's kernels from the same counter runs (the counter
@@ -62,9 +62,9 @@ MEASURED_APPLY_TRAFFIC = {
                     "fetch_kib": {"sketch": 2063734.6, "basis": 226616.6, "project": 2305058.0, "eig": 60222.0, "outputs": 279463.5},
                     "write_kib": {"sketch": 216339.3, "basis": 455051.0, "project": 480037.7, "eig": 9187.5, "outputs": 400166.4},
                     "sha256": "656b82029519249f04ea75a95c7dce502f183610590a5d4d48fa735afb7e97dd"},
-    "hsi_fp32": {"matrices": 200, "copy_fetch_kib": 131086.1, "copy_write_kib": 262144.0,
-                 "fetch_kib": {"sketch": 308251.9, "basis": 10168.6, "project": 317208.2, "eig": 12927.6, "outputs": 19280.4},
-                 "write_kib": {"sketch": 19279.4, "basis": 20806.3, "project": 25600.0, "eig": 831.2, "outputs": 14000.0},
+    "hsi_fp32": {"matrices": 400, "copy_fetch_kib": 131090.5, "copy_write_kib": 262144.0,
+                 "fetch_kib": {"sketch": 616677.5, "basis": 32175.3, "project": 635725.6, "eig": 25758.5, "outputs": 38507.0},
+                 "write_kib": {"sketch": 38568.1, "basis": 41791.6, "project": 51200.1, "eig": 1662.5, "outputs": 28088.5},
                  "sha256": "656b82029519249f04ea75a95c7dce502f183610590a5d4d48fa735afb7e97dd"},
 }
 

@@ -1,4 +1,5 @@
-"""Captured batches (tsk_apply_multi_plan / tsk_plan_launch): every replay
+"""Captured batches (tsk_apply_multi_plan / tsk_plan_launch) of FP32, bf16 and
+e4m3 stacks: every replay
 of a plan equals, bit for bit, the eager tsk_apply_multi on the then-current
 inputs, over several replays with other work and new inputs in between, and
 plans launched together (two streams) equal their eager batches."""
@@ -41,7 +42,7 @@ def _same(a, b):
         assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), key
 
 
-@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+@pytest.mark.parametrize("fmt", ["f32", "bf16", "e4m3"])
 def test_plan_replays_equal_eager(ctx, fmt):
     data = _inputs(1)
     A32 = [torch.from_numpy(a).cuda() for a, _, _, _ in data]
@@ -50,7 +51,7 @@ def test_plan_replays_equal_eager(ctx, fmt):
     def stacks():
         if fmt == "f32":
             return [x[:, :, :n] for x, (_, _, n, _) in zip(A32, data)]
-        return [ctx.stage(x[:, :, :n], "bf16") for x, (_, _, n, _) in zip(A32, data)]
+        return [ctx.stage(x[:, :, :n], fmt) for x, (_, _, n, _) in zip(A32, data)]
 
     A = stacks()
     probs = [(S, a, r) for S, a, (_, _, _, r) in zip(Ss, A, data)]
@@ -61,9 +62,12 @@ def test_plan_replays_equal_eager(ctx, fmt):
         new = _inputs(10 + rep)
         for x, (a, _, _, _) in zip(A32, new):
             x.copy_(torch.from_numpy(a).cuda())
-        if fmt == "bf16":
+        if fmt != "f32":
             for st, x, (_, _, n, _) in zip(A, A32, data):
-                st.data.copy_(ctx.stage(x[:, :, :n], "bf16").data)
+                fresh = ctx.stage(x[:, :, :n], fmt)
+                st.data.copy_(fresh.data)
+                if fmt == "e4m3":
+                    st.scale.copy_(fresh.scale)  # the per-matrix scales change with the data
         torch.cuda.synchronize()
         outs = plan.launch()
         torch.cuda.synchronize()

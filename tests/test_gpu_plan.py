@@ -1,8 +1,8 @@
 """Captured batches (tsk_apply_multi_plan / tsk_plan_launch) of FP32, bf16 and
-e4m3 stacks: every replay
-of a plan equals, bit for bit, the eager tsk_apply_multi on the then-current
-inputs, over several replays with other work and new inputs in between, and
-plans launched together (two streams) equal their eager batches."""
+e4m3 stacks: every replay of a plan equals, bit for bit, the eager
+tsk_apply_multi on the then-current inputs, over several replays with other
+work and new inputs in between, and plans launched together (two streams)
+equal their eager batches."""
 import numpy as np
 import pytest
 

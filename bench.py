@@ -44,12 +44,12 @@ COPY_BYTES = 256 << 20  # calibration copy of the counter pass
 # below); otherwise traffic is reported as null.
 TRAFFIC_SOURCES = ("paper_2209_14637_amd/csrc/gram.hip", "paper_2209_14637_amd/csrc/tsk_common.hpp")
 MEASURED_TRAFFIC = {
-    "stream_bf16": {"kernel": "gram_wide_kernel<uint16_t>", "fetch_kib": 9679720.5, "write_kib": 509953.2,
-                    "copy_fetch_kib": 131090.1, "copy_write_kib": 262144.0,
-                    "sha256": "cef17165d20e3344d1e27b34466edeab20453ec3c7b1ef8e7759c2970913fefe"},
-    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1118442.3, "write_kib": 294920.2,
-                 "copy_fetch_kib": 131090.5, "copy_write_kib": 262144.0,
-                 "sha256": "cef17165d20e3344d1e27b34466edeab20453ec3c7b1ef8e7759c2970913fefe"},
+    "stream_bf16": {"kernel": "gram_wide_kernel<uint16_t>", "fetch_kib": 9690524.7, "write_kib": 701186.4,
+                    "copy_fetch_kib": 131085.9, "copy_write_kib": 262144.0,
+                    "sha256": "94ceaf19bb10198825ed671d20ba27abc449ed8f40323f61f9b0a677b573e863"},
+    "hsi_fp32": {"kernel": "gram_f32_kernel", "fetch_kib": 1120319.5, "write_kib": 294921.2,
+                 "copy_fetch_kib": 131086.1, "copy_write_kib": 262144.0,
+                 "sha256": "94ceaf19bb10198825ed671d20ba27abc449ed8f40323f61f9b0a677b573e863"},
 }
 # HBM traffic of the apply's kernels from the same counter runs (the counter
 # pass applies the test stack twice; KiB per dispatch, the mean over the
@@ -58,13 +58,13 @@ MEASURED_TRAFFIC = {
 # were taken on.
 APPLY_TRAFFIC_SOURCES = ("paper_2209_14637_amd/csrc/apply.hip", "paper_2209_14637_amd/csrc/tsk_common.hpp")
 MEASURED_APPLY_TRAFFIC = {
-    "stream_bf16": {"matrices": 1000, "copy_fetch_kib": 131090.1, "copy_write_kib": 262144.0,
-                    "fetch_kib": {"sketch": 2063734.6, "basis": 226616.6, "project": 2305058.0, "eig": 60222.0, "outputs": 279463.5},
-                    "write_kib": {"sketch": 216339.3, "basis": 455051.0, "project": 480037.7, "eig": 9187.5, "outputs": 400166.4},
+    "stream_bf16": {"matrices": 1000, "copy_fetch_kib": 131085.9, "copy_write_kib": 262144.0,
+                    "fetch_kib": {"sketch": 2062224.8, "basis": 226619.8, "project": 2306618.6, "eig": 60222.1, "outputs": 280329.4},
+                    "write_kib": {"sketch": 216342.0, "basis": 455052.2, "project": 480039.2, "eig": 9187.5, "outputs": 388450.8},
                     "sha256": "656b82029519249f04ea75a95c7dce502f183610590a5d4d48fa735afb7e97dd"},
-    "hsi_fp32": {"matrices": 400, "copy_fetch_kib": 131090.5, "copy_write_kib": 262144.0,
-                 "fetch_kib": {"sketch": 616677.5, "basis": 32175.3, "project": 635725.6, "eig": 25758.5, "outputs": 38507.0},
-                 "write_kib": {"sketch": 38568.1, "basis": 41791.6, "project": 51200.1, "eig": 1662.5, "outputs": 28088.5},
+    "hsi_fp32": {"matrices": 400, "copy_fetch_kib": 131086.1, "copy_write_kib": 262144.0,
+                 "fetch_kib": {"sketch": 616668.0, "basis": 32124.1, "project": 635686.8, "eig": 25758.5, "outputs": 38505.6},
+                 "write_kib": {"sketch": 38569.9, "basis": 41806.5, "project": 51200.1, "eig": 1662.5, "outputs": 28057.5},
                  "sha256": "656b82029519249f04ea75a95c7dce502f183610590a5d4d48fa735afb7e97dd"},
 }
 

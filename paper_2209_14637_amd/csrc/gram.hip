@@ -817,8 +817,10 @@ static int pick_per_xcd(int tiles, int res, int64_t count) {
 }
 
 // Chunks per XCD for the 256x256 tiles: chunks of about W_CHUNK_STAGES
-// stages (128 bytes of every row each), at least the 2048-workgroup minimum
-// above, at most count / 8.  A workgroup's 256 rows drift away from those of
+// stages (128 bytes of every row each), between the 2048-workgroup minimum
+// above and four times it (the bound the rule above keeps: a chunk writes
+// about 2 m^2 bytes of partials, so large m keeps chunks long), and at most
+// count / 8.  A workgroup's 256 rows drift away from those of
 // the other tiles of its chunk as it runs, so a long chunk is fetched from
 // beyond the XCD's L2 more often; short chunks add partial tiles to write and
 // reduce.  On 1920 x 1080 bf16 slices (17 stages each) the Gram with its
@@ -830,6 +832,7 @@ static int pick_per_xcd_wide(int tiles, int64_t count, int64_t stages_per_slice)
     const int64_t pmin = (2048 + 8 * tiles - 1) / (8 * tiles);
     int64_t pc = (count * stages_per_slice + 4 * W_CHUNK_STAGES) / (8 * W_CHUNK_STAGES);
     if (pc < pmin) pc = pmin;
+    if (pc > 4 * pmin) pc = 4 * pmin;
     const int64_t cap = count / 8;
     if (pc > cap) pc = cap;
     return pc < 1 ? 1 : (int)pc;

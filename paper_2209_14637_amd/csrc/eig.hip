@@ -37,7 +37,10 @@
 namespace {
 
 constexpr int MV_RB = 16;      // rows per matvec workgroup (one MFMA tile)
-constexpr int RW_RB = 64;      // rows per row-kernel workgroup
+// Rows per row-kernel workgroup: 60 workgroups at m = 1920.  64 rows (30
+// workgroups) took 10.20 / 5.45 ms per 1920 x 1080 bf16 / 1024 x 768 FP32
+// training, 32 rows 9.85 / 5.26, 16 rows 9.92 / 5.20.
+constexpr int RW_RB = 32;
 constexpr int RR_THREADS = 1024;  // threads of the one-workgroup small-matrix kernels
 constexpr int EIG_MAXPP = 64;  // largest padded block
 constexpr int NT_MAX = EIG_MAXPP / 16;
@@ -257,17 +260,19 @@ __device__ inline void block_gram(const double *As, const double *Bs, int pp, do
 }
 
 // Sum nparts upper-triangle partials into the full symmetric C (LDS), in
-// partial order; the first 32 partials of an entry are loaded before any add.
+// partial order; an entry's partials are loaded 32 at a time, each group
+// before any of its adds.
 __device__ inline void reduce_tri(const double *__restrict__ part, int nparts, int pp, double *C) {
     const int ntri = pp * (pp + 1) / 2;
     for (int e = threadIdx.x; e < ntri; e += blockDim.x) {
-        double v[32];
-#pragma unroll
-        for (int w = 0; w < 32; ++w) v[w] = (w < nparts) ? part[(int64_t)w * ntri + e] : 0.0;
         double s = 0.0;
+        for (int w0 = 0; w0 < nparts; w0 += 32) {
+            double v[32];
 #pragma unroll
-        for (int w = 0; w < 32; ++w) s += v[w];
-        for (int w = 32; w < nparts; ++w) s += part[(int64_t)w * ntri + e];
+            for (int w = 0; w < 32; ++w) v[w] = (w0 + w < nparts) ? part[(int64_t)(w0 + w) * ntri + e] : 0.0;
+#pragma unroll
+            for (int w = 0; w < 32; ++w) s += v[w];
+        }
         int a, b;
         tri_index(e, pp, a, b);
         C[a * pp + b] = s;
